@@ -1,0 +1,208 @@
+"""CPU tests: the FP64 oracle against what the paper and mathematics fix.
+
+No GPU.  The checks themselves live in ``pins.py``; here they are run on the
+loop oracle (``oracle.forward``), on the exact table encoding
+(``oracle.bruteforce``) and on mutated tables, and the adjoint and tangent
+operators are pinned by exact finite differences and inner-product identities.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle
+import pins
+from oracle import bruteforce as bf
+from paper_2301_13016_amd import workloads as wl
+
+
+def F_oracle(u, v, w, c):
+    return oracle.forward(u, v, w, c)
+
+
+@pytest.mark.parametrize("check", pins.ALL_CHECKS, ids=lambda c: c.__name__)
+def test_pins_hold_on_oracle(check):
+    name, ok = check(F_oracle)
+    assert ok, name
+
+
+@pytest.mark.parametrize("check", pins.ALL_CHECKS, ids=lambda c: c.__name__)
+def test_pins_hold_on_exact_table(check):
+    name, ok = check(pins.table_evaluator(bf.TERMS))
+    assert ok, name
+
+
+def _mutants(table):
+    coefs = ("tcx", "tcy", "tzc1", "tzc2", "tzd1", "tzd2")
+    T = list(table)
+    for r, (o, c, s, A, B, D) in enumerate(T):
+        yield "drop%d" % r, T[:r] + T[r + 1:]
+        yield "sign%d" % r, T[:r] + [(o, c, -s, A, B, D)] + T[r + 1:]
+        for c2 in coefs:
+            if c2 != c:
+                yield "coef%d:%s" % (r, c2), T[:r] + [(o, c2, s, A, B, D)] + T[r + 1:]
+        for role in range(3):
+            f, off = (A, B, D)[role]
+            for dim, dd in itertools.product(range(3), (-1, 1)):
+                no = list(off)
+                no[dim] += dd
+                if abs(no[dim]) > 1:
+                    continue
+                new = [A, B, D]
+                new[role] = (f, tuple(no))
+                yield "off%d%s%d%+d" % (r, "abd"[role], dim, dd), T[:r] + [(o, c, s, *new)] + T[r + 1:]
+            for f2 in "uvw":
+                if f2 != f:
+                    new = [A, B, D]
+                    new[role] = (f2, off)
+                    yield "field%d%s:%s" % (r, "abd"[role], f2), T[:r] + [(o, c, s, *new)] + T[r + 1:]
+
+
+def test_every_plausible_table_mistake_is_caught():
+    """A dropped term, flipped sign, wrong coefficient, stencil index moved by
+    one in any direction, or wrong field in any operand of any of the 18 terms
+    makes at least one pin fail (510 mutants)."""
+    survivors = []
+    n = 0
+    for name, table in _mutants(bf.TERMS):
+        n += 1
+        if all(ok for _, ok in pins.run_all(pins.table_evaluator(table))):
+            survivors.append(name)
+    assert n == 510
+    assert survivors == []
+
+
+def test_table_structure_matches_paper_counts():
+    """Per field and cell: six face sums (twelve addition operands), six
+    products with one neighbour each (six multiplication operands), and the
+    same coefficient/sign pattern for all three fields (paper Sec. 4); every
+    operand lies inside the 27-point box of a depth-one stencil (Sec. 2.2)."""
+    for o in bf.OUTPUTS:
+        rows = [t for t in bf.TERMS if t[0] == o]
+        assert len(rows) == 6
+        assert [r[2] for r in rows] == [+1, -1, +1, -1, +1, -1]
+        kinds = ["z" if r[1].startswith("tz") else r[1] for r in rows]
+        assert kinds == ["tcx", "tcx", "tcy", "tcy", "z", "z"]
+        operands = [x for r in rows for x in r[3:]]
+        assert len(operands) == 18   # 6 multiplicands + 12 face operands
+        for _, off in operands:
+            assert all(abs(d) <= 1 for d in off)
+        # the advected field is always the multiplicand a
+        assert {r[3][0] for r in rows} == {o[1]}
+        # face operands are one component per direction: u for x, v for y, w for z
+        assert [r[4][0] for r in rows] == [r[5][0] for r in rows]
+
+
+@pytest.mark.parametrize("shape", [(4, 4, 4), (5, 3, 2), (1, 1, 1)])
+def test_bruteforce_equals_oracle_bitwise(shape):
+    """Integer winds + dyadic coefficients make every intermediate exact, so the
+    rational table evaluation and the FP64 loops must agree bit for bit at every
+    point (the 4^3 case covers all 64 points of a 4^3 grid)."""
+    nx, ny, nz = shape
+    g = wl.integer_grid(nx, ny, nz, seed=11, dtype=np.float64)
+    exact = bf.forward_exact(dict(u=g.u, v=g.v, w=g.w), g.coeffs)
+    got = oracle.forward(g.u, g.v, g.w, g.coeffs)
+    for o, x in zip(bf.OUTPUTS, got):
+        assert np.array_equal(bf.to_float_array(exact[o]), x), o
+
+
+def test_magnitude_bounds_outputs():
+    g = wl.make_grid(9, 7, 5, seed=12, dtype=np.float64)
+    out, mag = oracle.forward(g.u, g.v, g.w, g.coeffs, magnitude=True)
+    absF = oracle.forward(np.abs(g.u), np.abs(g.v), np.abs(g.w),
+                          dict(g.coeffs, tcx=abs(g.tcx), tcy=abs(g.tcy)), magnitude=True)[1]
+    for o, m, a in zip(out, mag, absF):
+        assert np.all(np.abs(o) <= m * (1 + 1e-12))
+        assert np.allclose(m, a, rtol=1e-14, atol=0)
+
+
+def test_threads_do_not_change_results():
+    g = wl.make_grid(17, 13, 11, seed=13, dtype=np.float64)
+    a = oracle.forward(g.u, g.v, g.w, g.coeffs, nthreads=1)
+    b = oracle.forward(g.u, g.v, g.w, g.coeffs, nthreads=4)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
+# ---------------------------------------------------------------- adjoint / tangent
+
+def test_adjoint_equals_exact_rational_differences():
+    """J^T r from the scatter oracle equals, bit for bit, the exact central
+    differences of the rational forward operator (F is quadratic, so the
+    difference quotient is exact), on a ragged 3x2x2 grid, halo included."""
+    g = wl.integer_grid(3, 2, 2, seed=14, dtype=np.float64)
+    rng = np.random.default_rng(15)
+    r = [rng.integers(-3, 4, (2, 2, 3)).astype(np.float64) for _ in range(3)]
+    exact = bf.adjoint_exact(dict(u=g.u, v=g.v, w=g.w), g.coeffs, dict(su=r[0], sv=r[1], sw=r[2]))
+    got = oracle.adjoint(g.u, g.v, g.w, g.coeffs, *r)
+    for f, x in zip(bf.FIELDS, got):
+        assert np.array_equal(bf.to_float_array(exact[f]), x), f
+
+
+def _dot(a, b):
+    return float(sum(np.sum(np.asarray(x, np.float64) * np.asarray(y, np.float64)) for x, y in zip(a, b)))
+
+
+def test_adjoint_finite_difference_fp64():
+    """FP64 central finite differences on a 16^3 grid (eps = 1e-6, seed 40):
+    <(F(x + eps d) - F(x - eps d)) / 2eps, y> = <d, J^T y>.  F is quadratic,
+    so the quotient has no truncation error and only roundoff remains."""
+    cfg = wl.C4_FD
+    g = wl.make_grid(cfg["nx"], cfg["ny"], cfg["nz"], cfg["seed"], dtype=np.float64)
+    d = wl.direction(cfg["nx"], cfg["ny"], cfg["nz"], cfg["seed"] + 1)
+    y = wl.cotangents(cfg["nx"], cfg["ny"], cfg["nz"], cfg["seed"] + 2, dtype=np.float64)
+    eps = cfg["eps"]
+    x = (g.u, g.v, g.w)
+    fp = oracle.forward(*(a + eps * b for a, b in zip(x, d)), g.coeffs)
+    fm = oracle.forward(*(a - eps * b for a, b in zip(x, d)), g.coeffs)
+    jd_fd = [(p - m) / (2 * eps) for p, m in zip(fp, fm)]
+    jty = oracle.adjoint(*x, g.coeffs, *y)
+    lhs, rhs = _dot(jd_fd, y), _dot(d, jty)
+    assert abs(lhs - rhs) <= 1e-8 * abs(rhs)
+    # element-wise against the tangent-linear operator
+    jd = oracle.tangent(*x, *d, g.coeffs)
+    for a, b in zip(jd_fd, jd):
+        assert np.max(np.abs(a - b)) <= 1e-8 * np.max(np.abs(b))
+
+
+def test_tangent_polarisation_and_dot_product():
+    """For a homogeneous quadratic F: J(x) d = F(x + d) - F(x) - F(d), and
+    <J d, y> = <d, J^T y> (the dot-product test)."""
+    g = wl.make_grid(12, 9, 7, seed=16, dtype=np.float64)
+    d = wl.direction(12, 9, 7, seed=17)
+    y = wl.cotangents(12, 9, 7, seed=18, dtype=np.float64)
+    x = (g.u, g.v, g.w)
+    jd = oracle.tangent(*x, *d, g.coeffs)
+    pol = [a - b - c for a, b, c in zip(oracle.forward(*(p + q for p, q in zip(x, d)), g.coeffs),
+                                        oracle.forward(*x, g.coeffs), oracle.forward(*d, g.coeffs))]
+    for a, b in zip(jd, pol):
+        assert np.max(np.abs(a - b)) <= 1e-12 * np.max(np.abs(a))
+    jty = oracle.adjoint(*x, g.coeffs, *y)
+    assert abs(_dot(jd, y) - _dot(d, jty)) <= 1e-12 * abs(_dot(d, jty))
+
+
+def test_adjoint_euler_and_symmetry_identities():
+    """F(x) = B(x, x) with B symmetric bilinear, so J(x)^T y is linear in x:
+    Euler <x, J^T(x) y> = 2 <F(x), y>, and symmetry <d, J^T(x) y> = <x, J^T(d) y>."""
+    g = wl.make_grid(10, 8, 6, seed=19, dtype=np.float64)
+    d = wl.direction(10, 8, 6, seed=20)
+    y = wl.cotangents(10, 8, 6, seed=21, dtype=np.float64)
+    x = (g.u, g.v, g.w)
+    jx = oracle.adjoint(*x, g.coeffs, *y)
+    fx = oracle.forward(*x, g.coeffs)
+    assert abs(_dot(x, jx) - 2 * _dot(fx, y)) <= 1e-12 * abs(_dot(x, jx))
+    jd = oracle.adjoint(*d, g.coeffs, *y)
+    assert abs(_dot(d, jx) - _dot(x, jd)) <= 1e-12 * abs(_dot(d, jx))
+
+
+def test_adjoint_gradient_halo_is_written():
+    """The gradient covers the padded arrays: halo entries that some interior
+    output reads get non-zero gradient, the 3-D corners of the halo (read by no
+    output) get exactly zero."""
+    g = wl.make_grid(5, 4, 3, seed=22, dtype=np.float64)
+    y = wl.cotangents(5, 4, 3, seed=23, dtype=np.float64)
+    gu, gv, gw = oracle.adjoint(g.u, g.v, g.w, g.coeffs, *y)
+    for gr in (gu, gv, gw):
+        for k, j, i in itertools.product((0, -1), (0, -1), (0, -1)):
+            assert gr[k, j, i] == 0.0
+        assert np.any(gr[0] != 0) or np.any(gr[-1] != 0)

@@ -1,0 +1,192 @@
+"""Benchmark of PW advection on one MI355X.
+
+One step = one forward launch of the PW stencil (face sums, products,
+differences, reduction, store: the whole hot path) over the FP32 grid
+512 x 512 x 64 (16.8 M interior points, 1-cell halo), with inputs resident in
+HBM.  K steps are timed between two device synchronisations; consecutive steps
+use different buffer sets (4 x 410 MB) so the 256 MB MALL cannot serve a
+repeat.  The dominant kernel's average duration comes from HIP events around
+each launch on the launch stream.
+
+Also measured in the same run:
+  * BF16 / FP16 storage vs FP32 on 1024 x 1024 x 256 (268 M points) ("forms");
+    their errors against the FP64 oracle are measured by the GPU test suite;
+  * the FP64 oracle on the host cores ("cpu_baseline", the only use of the
+    oracle here).
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def algo_bytes(nx, ny, nz, halo, in_bytes, out_bytes=4):
+    """Algorithmic HBM bytes of one forward launch: every padded input element
+    read once, every interior output written once."""
+    padded = (nx + 2 * halo) * (ny + 2 * halo) * (nz + 2 * halo)
+    return 3 * padded * in_bytes + 3 * nx * ny * nz * out_bytes
+
+
+def time_launches(torch, launch, nsets, steps, warmup, stream):
+    """Run ``launch(i)`` for warmup + steps iterations (i = buffer set), time
+    the steps region with a wall clock between synchronisations and each
+    launch with HIP events on ``stream``.  Returns (ms_per_step, mean kernel ms,
+    list of per-launch ms)."""
+    for i in range(warmup):
+        launch(i % nsets)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for i in range(steps):
+        ev[i][0].record(stream)
+        launch(i % nsets)
+        ev[i][1].record(stream)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3
+    per = [a.elapsed_time(b) for a, b in ev]
+    return wall / steps, float(np.mean(per)), per
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="approximate host time spent timing the oracle")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on exactly one GPU (the stencil's multi-GPU halo "
+              "exchange is a design, not an implementation); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import oracle
+    from paper_2301_13016_amd import binding as B
+    from paper_2301_13016_amd import workloads as wl
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    log("device:", torch.cuda.get_device_name(dev), "lib:", B.pw_version())
+
+    # ------------------------------------------------------------ headline: c1 FP32
+    cfg = wl.C1
+    nx, ny, nz, h = cfg["nx"], cfg["ny"], cfg["nz"], 1
+    g = wl.config_grid(cfg)
+    coeffs = B.Coeffs.from_host(g.coeffs, device=dev)
+    nsets = 4
+    host = [torch.from_numpy(x) for x in (g.u, g.v, g.w)]
+    sets = []
+    for _ in range(nsets):
+        ins = [x.to(dev) for x in host]
+        outs = tuple(torch.empty((nz, ny, nx), device=dev) for _ in range(3))
+        sets.append((ins, outs))
+
+    def launch(i):
+        ins, outs = sets[i]
+        B.advect(*ins, coeffs, out=outs)
+
+    ms_step, k_ms, per = time_launches(torch, launch, nsets, args.steps, args.warmup, stream)
+    pts = nx * ny * nz
+    gpts = pts / (ms_step * 1e-3) / 1e9
+    nbytes = algo_bytes(nx, ny, nz, h, 4)
+    achieved = nbytes / (k_ms * 1e-3) / 1e9
+    log("c1 fp32: %.4f ms/step, kernel %.4f ms, %.1f Gpt/s, %.0f GB/s algorithmic"
+        % (ms_step, k_ms, gpts, achieved))
+
+    # plain copy kernel of the same byte count (reachable-bandwidth reference)
+    cbytes = (nbytes // 2) // 16 * 16
+    src = torch.empty(cbytes // 4, device=dev)
+    dst = [torch.empty_like(src) for _ in range(4)]
+    srcs = [src] + [torch.empty_like(src) for _ in range(3)]
+    _, copy_ms, _ = time_launches(torch, lambda i: B.stream_copy(srcs[i], dst[i]), 4, 200, 10, stream)
+    copy_gbs = 2 * cbytes / (copy_ms * 1e-3) / 1e9
+    log("copy %d MB each way: %.4f ms, %.0f GB/s" % (cbytes >> 20, copy_ms, copy_gbs))
+    del sets, src, dst, srcs
+    torch.cuda.empty_cache()
+
+    # ------------------------------------------------------------ CPU baseline (oracle)
+    ncpu = len(os.sched_getaffinity(0))
+    u64, v64, w64 = (x.astype(np.float64) for x in (g.u, g.v, g.w))
+    reps, t_cpu = 0, 0.0
+    while t_cpu < args.cpu_seconds and reps < 1000:
+        t0 = time.perf_counter()
+        oracle.forward(u64, v64, w64, g.coeffs, nthreads=ncpu)
+        t_cpu += time.perf_counter() - t0
+        reps += 1
+    cpu_gpts = reps * pts / t_cpu / 1e9
+    log("oracle on %d host threads: %.3f Gpt/s (%d reps of the full grid)" % (ncpu, cpu_gpts, reps))
+    del u64, v64, w64
+
+    # ------------------------------------------------------------ precision form: c2
+    forms = {}
+    c2 = wl.C2
+    n2 = (c2["nx"], c2["ny"], c2["nz"])
+    log("generating the 1024x1024x256 grid ...")
+    g2 = wl.config_grid(c2)
+    co2 = B.Coeffs.from_host(g2.coeffs, device=dev)
+    f32 = [torch.from_numpy(x).to(dev) for x in (g2.u, g2.v, g2.w)]
+    outs2 = tuple(torch.empty((n2[2], n2[1], n2[0]), device=dev) for _ in range(3))
+    pts2 = n2[0] * n2[1] * n2[2]
+    res2 = {}
+    for name, dt in (("fp32", torch.float32), ("bf16", torch.bfloat16), ("fp16", torch.float16)):
+        ins = f32 if dt == torch.float32 else [x.to(dt) for x in f32]
+        ms2, kms2, _ = time_launches(torch, lambda i: B.advect(*ins, co2, out=outs2), 1, 30, 3, stream)
+        eb = 2 if dt != torch.float32 else 4
+        res2[name] = dict(gpts=pts2 / (kms2 * 1e-3) / 1e9, kernel_ms=kms2,
+                          hbm_gbs=algo_bytes(*n2, 1, eb) / (kms2 * 1e-3) / 1e9)
+        log("c2 %s: kernel %.4f ms, %.1f Gpt/s" % (name, kms2, res2[name]["gpts"]))
+        if dt != torch.float32:
+            del ins
+    for name in ("bf16", "fp16"):
+        res2[name]["speed_vs_fp32"] = res2["fp32"]["kernel_ms"] / res2[name]["kernel_ms"]
+    forms["precision_1024x1024x256"] = res2
+    del f32, outs2
+
+    line = {
+        "metric": "PW advection Gpoints/s + % HBM roofline; FP32 vs BF16-store vs adjoint",
+        "value": round(gpts, 3),
+        "unit": "Gpoints/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 6),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded uniform winds in [-10,10], per-level coefficients)",
+        "config": {"workload": cfg["name"], "nx": nx, "ny": ny, "nz": nz, "halo": h,
+                   "points": pts, "buffer_sets": nsets},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "algorithmic_bytes_per_launch": nbytes, "kernel_ms": round(k_ms, 6),
+                     "copy_kernel_gbs": round(copy_gbs, 1)},
+        "cpu_baseline": {"value": round(cpu_gpts, 4), "unit": "Gpoints/s", "cores": ncpu, "kind": "oracle",
+                         "sample": "FP64 oracle on the full 512x512x64 grid, %d repetitions (%.1f s)"
+                                   % (reps, t_cpu)},
+        "forms": forms,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

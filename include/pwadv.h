@@ -1,0 +1,175 @@
+/*
+ * libpwadv -- Piacsek-Williams (PW) advection source terms on AMD MI355X (gfx950).
+ *
+ * The operation (paper, Sec. 2.2): from the three wind fields u, v, w on a
+ * halo-padded 3-D grid, compute one advective "source term" per field and
+ * interior cell -- su, sv, sw -- with a depth-one stencil that reaches the
+ * neighbouring cells in all three dimensions.  Per field and cell the scheme
+ * forms six face sums of advecting velocities, six products of a neighbouring
+ * value with a face sum, and their signed reduction (Sec. 4, Fig. 2); the
+ * three fields share that arithmetic and differ only in stencil locations.
+ *
+ * Reading of the scheme (the paper prints no equations): the energy-
+ * conserving PW form on a staggered grid, u on east faces, v on north faces,
+ * w on top faces, upstream face minus downstream face.  In padded coordinates
+ * (k, j, i), x fastest, interior level index kk = k - halo:
+ *
+ *   su = tcx*( u[k,j,i-1]*(u[k,j,i]+u[k,j,i-1]) - u[k,j,i+1]*(u[k,j,i]+u[k,j,i+1]) )
+ *      + tcy*( u[k,j-1,i]*(v[k,j-1,i]+v[k,j-1,i+1]) - u[k,j+1,i]*(v[k,j,i]+v[k,j,i+1]) )
+ *      + tzc1[kk]*u[k-1,j,i]*(w[k-1,j,i]+w[k-1,j,i+1]) - tzc2[kk]*u[k+1,j,i]*(w[k,j,i]+w[k,j,i+1])
+ *   sv = tcx*( v[k,j,i-1]*(u[k,j,i-1]+u[k,j+1,i-1]) - v[k,j,i+1]*(u[k,j,i]+u[k,j+1,i]) )
+ *      + tcy*( v[k,j-1,i]*(v[k,j,i]+v[k,j-1,i]) - v[k,j+1,i]*(v[k,j,i]+v[k,j+1,i]) )
+ *      + tzc1[kk]*v[k-1,j,i]*(w[k-1,j,i]+w[k-1,j+1,i]) - tzc2[kk]*v[k+1,j,i]*(w[k,j,i]+w[k,j+1,i])
+ *   sw = tcx*( w[k,j,i-1]*(u[k,j,i-1]+u[k+1,j,i-1]) - w[k,j,i+1]*(u[k,j,i]+u[k+1,j,i]) )
+ *      + tcy*( w[k,j-1,i]*(v[k,j-1,i]+v[k+1,j-1,i]) - w[k,j+1,i]*(v[k,j,i]+v[k+1,j,i]) )
+ *      + tzd1[kk]*w[k-1,j,i]*(w[k,j,i]+w[k-1,j,i]) - tzd2[kk]*w[k+1,j,i]*(w[k,j,i]+w[k+1,j,i])
+ *
+ * Conventions shared by every call below
+ * --------------------------------------
+ * Memory:    every array argument is a caller-owned DEVICE buffer on the
+ *            current HIP device.  The library never frees or keeps them.
+ * Inputs:    u, v, w have the padded shape (nz+2h, ny+2h, nx+2h); element
+ *            (k, j, i) lives at  base[k*in_sz + j*in_sy + i]  (x stride 1).
+ * Outputs:   su, sv, sw are interior-shaped (nz, ny, nx); element (kk, jj, ii)
+ *            at  base[kk*out_sz + jj*out_sy + ii].
+ * Vertical:  tzc1, tzc2, tzd1, tzd2 are device arrays of nz entries indexed by
+ *            the interior level.  Element type: float for PW_F32/PW_BF16/PW_F16,
+ *            double for PW_F64.  tcx, tcy are passed as double and rounded
+ *            (to nearest even) to float for the float-family dtypes.
+ * Precision: PW_F32  -- float storage, float arithmetic, float outputs.
+ *            PW_BF16 / PW_F16 -- 16-bit storage of u, v, w only; values are
+ *            widened exactly to float in registers, float arithmetic and float
+ *            outputs.  PW_F64 -- double throughout.
+ * Streams:   work is enqueued on `hip_stream` (a hipStream_t; NULL = the
+ *            default stream) and the call returns without synchronising.
+ *            Faults inside a kernel surface at the caller's next
+ *            synchronisation.
+ * Errors:    every call returns a pw_status; nothing aborts or throws across
+ *            the ABI.  On a non-OK status nothing was enqueued, and
+ *            pw_last_error() holds a message (per thread).  Arguments are
+ *            validated before any HIP call, so argument errors are reported
+ *            the same way on a machine with no GPU; with valid arguments and no
+ *            usable device the status is PW_ERR_NO_DEVICE.
+ * Threads:   all calls are reentrant; distinct calls may run concurrently.
+ */
+#ifndef PWADV_H
+#define PWADV_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PW_OK = 0,
+    PW_ERR_INVALID_ARG = 1,   /* null/misaligned pointer, bad size, stride or alias */
+    PW_ERR_UNSUPPORTED = 2,   /* valid arguments, combination not implemented      */
+    PW_ERR_NO_DEVICE = 3,     /* no usable HIP device                               */
+    PW_ERR_HIP = 4,           /* a HIP runtime call failed (message in last_error)  */
+    PW_ERR_ALLOC = 5          /* host or device allocation failed                   */
+} pw_status;
+
+typedef enum {
+    PW_F32 = 0,
+    PW_F64 = 1,
+    PW_BF16 = 2,
+    PW_F16 = 3
+} pw_dtype;
+
+/* Interior extent and halo width.  nx, ny, nz >= 1; halo >= 1 (the stencil
+ * has depth one, Sec. 2.2; a wider halo is just padding).  nx*ny*nz < 2^40. */
+typedef struct {
+    int64_t nx, ny, nz;
+    int32_t halo;
+} pw_grid;
+
+/* Element strides.  Input strides must be at least the dense padded ones
+ * (in_sy >= nx+2h, in_sz >= in_sy*(ny+2h)), output strides at least the dense
+ * interior ones (out_sy >= nx, out_sz >= out_sy*ny).  A NULL pw_layout* means
+ * dense in both. */
+typedef struct {
+    int64_t in_sy, in_sz;
+    int64_t out_sy, out_sz;
+} pw_layout;
+
+/* Coefficients: tcx, tcy scalars; tz* device pointers to nz elements. */
+typedef struct {
+    double tcx, tcy;
+    const void *tzc1, *tzc2, *tzd1, *tzd2;
+} pw_coeffs;
+
+/* Forward operator (the equations above): writes su, sv, sw at every
+ * interior cell.  Inputs of element type `in_dtype`; outputs float (double
+ * for PW_F64).  Outputs must not overlap any input.  Halo cells of u, v, w
+ * are read, never written. */
+pw_status pw_advect(const pw_grid *grid, const pw_layout *layout, pw_dtype in_dtype,
+                    const void *u, const void *v, const void *w,
+                    const pw_coeffs *coeffs,
+                    void *su, void *sv, void *sw,
+                    void *hip_stream);
+
+/* Launch shape of the stencil kernels (a performance choice; results are
+ * bit-identical across shapes).  A wavefront owns a strip of 62 x
+ * rows_per_strip interior cells and marches through zlen levels;
+ * waves_per_group strips are stacked in y per workgroup.
+ *   rows_per_strip in {1, 2, 4, 8} (PW_F64: {1, 2, 4}), zlen >= 1,
+ *   waves_per_group in 1..8.  Other values give PW_ERR_INVALID_ARG. */
+typedef struct {
+    int32_t rows_per_strip;
+    int32_t zlen;
+    int32_t waves_per_group;
+} pw_tile;
+
+/* pw_advect with an explicit launch shape; tile == NULL means the library's
+ * choice (the tuned shape for this grid class if pw_tune has run, else a
+ * fixed default).  Same contract and results as pw_advect. */
+pw_status pw_advect_ex(const pw_grid *grid, const pw_layout *layout, pw_dtype in_dtype,
+                       const void *u, const void *v, const void *w,
+                       const pw_coeffs *coeffs,
+                       void *su, void *sv, void *sw,
+                       const pw_tile *tile, void *hip_stream);
+
+/* Adjoint (vector-Jacobian product) of the forward operator:
+ *   (gu, gv, gw) = J(u, v, w)^T (gsu, gsv, gsw)
+ * i.e. the gradient of <su, gsu> + <sv, gsv> + <sw, gsw> with respect to every
+ * padded entry of u, v, w, halo included.  gsu/gsv/gsw are interior-shaped
+ * (output layout); gu/gv/gw are padded-shaped (input layout) and fully
+ * overwritten, halo cells included (entries no output reads get 0).  dtype
+ * PW_F32 or PW_F64 (PW_ERR_UNSUPPORTED otherwise).  Gradients must not
+ * overlap any other argument. */
+pw_status pw_advect_adjoint(const pw_grid *grid, const pw_layout *layout, pw_dtype dtype,
+                            const void *u, const void *v, const void *w,
+                            const pw_coeffs *coeffs,
+                            const void *gsu, const void *gsv, const void *gsw,
+                            void *gu, void *gv, void *gw,
+                            void *hip_stream);
+
+/* pw_advect_adjoint with an explicit launch shape (see pw_tile; the adjoint
+ * kernel supports rows_per_strip in {1, 2, 4}); tile == NULL as in
+ * pw_advect_adjoint.  Results are bit-identical across shapes. */
+pw_status pw_advect_adjoint_ex(const pw_grid *grid, const pw_layout *layout, pw_dtype dtype,
+                               const void *u, const void *v, const void *w,
+                               const pw_coeffs *coeffs,
+                               const void *gsu, const void *gsv, const void *gsw,
+                               void *gu, void *gv, void *gw,
+                               const pw_tile *tile, void *hip_stream);
+
+/* Library version string (static storage). */
+const char *pw_version(void);
+
+/* Message for the last non-OK status returned on the calling thread
+ * (static per-thread storage; "" if none). */
+const char *pw_last_error(void);
+
+/* Measurement helper: a plain vectorised device-to-device copy of `nbytes`
+ * (a multiple of 16, both pointers 16-byte aligned) on `hip_stream`, with the
+ * same launch shape policy as the stencil kernels.  Used to calibrate the
+ * reachable HBM bandwidth and the memory counters. */
+pw_status pw_stream_copy(const void *src, void *dst, int64_t nbytes, void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PWADV_H */

@@ -1,0 +1,280 @@
+"""ctypes binding of libpwadv (include/pwadv.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of ``libpwadv.so``.  Loading fails loudly (``PWLibraryMissing``) if the
+library has not been built; there is no CPU fallback.
+
+Two layers:
+* ``pw_advect``, ``pw_advect_ex``, ``pw_advect_adjoint``, ... -- the C entry
+  points with the same names and arguments (pointers as Python ints).
+* ``advect``, ``advect_adjoint``, ``PWAdvect`` -- the same calls on torch
+  tensors (torch supplies device memory and the stream).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from dataclasses import dataclass
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpwadv.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "pwadv.h")
+
+PW_OK, PW_ERR_INVALID_ARG, PW_ERR_UNSUPPORTED, PW_ERR_NO_DEVICE, PW_ERR_HIP, PW_ERR_ALLOC = range(6)
+PW_F32, PW_F64, PW_BF16, PW_F16 = range(4)
+STATUS_NAMES = {0: "PW_OK", 1: "PW_ERR_INVALID_ARG", 2: "PW_ERR_UNSUPPORTED", 3: "PW_ERR_NO_DEVICE",
+                4: "PW_ERR_HIP", 5: "PW_ERR_ALLOC"}
+
+
+class PWLibraryMissing(RuntimeError):
+    pass
+
+
+class PWError(RuntimeError):
+    def __init__(self, status, message, call=""):
+        self.status = status
+        self.message = message
+        super().__init__("%s: %s (%s)" % (call, STATUS_NAMES.get(status, status), message))
+
+
+class pw_grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int64), ("ny", ctypes.c_int64), ("nz", ctypes.c_int64),
+                ("halo", ctypes.c_int32)]
+
+
+class pw_layout(ctypes.Structure):
+    _fields_ = [("in_sy", ctypes.c_int64), ("in_sz", ctypes.c_int64),
+                ("out_sy", ctypes.c_int64), ("out_sz", ctypes.c_int64)]
+
+
+class pw_coeffs(ctypes.Structure):
+    _fields_ = [("tcx", ctypes.c_double), ("tcy", ctypes.c_double),
+                ("tzc1", ctypes.c_void_p), ("tzc2", ctypes.c_void_p),
+                ("tzd1", ctypes.c_void_p), ("tzd2", ctypes.c_void_p)]
+
+
+class pw_tile(ctypes.Structure):
+    _fields_ = [("rows_per_strip", ctypes.c_int32), ("zlen", ctypes.c_int32),
+                ("waves_per_group", ctypes.c_int32)]
+
+
+_P = ctypes.c_void_p
+_SIGNATURES = {
+    "pw_advect": [ctypes.POINTER(pw_grid), ctypes.POINTER(pw_layout), ctypes.c_int,
+                  _P, _P, _P, ctypes.POINTER(pw_coeffs), _P, _P, _P, _P],
+    "pw_advect_ex": [ctypes.POINTER(pw_grid), ctypes.POINTER(pw_layout), ctypes.c_int,
+                     _P, _P, _P, ctypes.POINTER(pw_coeffs), _P, _P, _P, ctypes.POINTER(pw_tile), _P],
+    "pw_advect_adjoint": [ctypes.POINTER(pw_grid), ctypes.POINTER(pw_layout), ctypes.c_int,
+                          _P, _P, _P, ctypes.POINTER(pw_coeffs), _P, _P, _P, _P, _P, _P, _P],
+    "pw_advect_adjoint_ex": [ctypes.POINTER(pw_grid), ctypes.POINTER(pw_layout), ctypes.c_int,
+                             _P, _P, _P, ctypes.POINTER(pw_coeffs), _P, _P, _P, _P, _P, _P,
+                             ctypes.POINTER(pw_tile), _P],
+    "pw_stream_copy": [_P, _P, ctypes.c_int64, _P],
+    "pw_version": [],
+    "pw_last_error": [],
+}
+
+_lib = None
+
+
+def header_functions(path=HEADER):
+    """Names of the functions declared in include/pwadv.h."""
+    text = open(path).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pw_[a-z_0-9]+)\s*\(", text)))
+
+
+def lib():
+    """The loaded libpwadv.so (raises PWLibraryMissing if it was never built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise PWLibraryMissing("libpwadv.so not built: run __graft_entry__.build() "
+                                   "(or python paper_2301_13016_amd/build.py)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, argtypes in _SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.argtypes = argtypes
+            fn.restype = ctypes.c_char_p if name in ("pw_version", "pw_last_error") else ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(status, call):
+    if status != PW_OK:
+        raise PWError(status, lib().pw_last_error().decode(), call)
+    return status
+
+
+# ------------------------------------------------------------------ raw C calls
+
+def pw_version():
+    return lib().pw_version().decode()
+
+
+def pw_last_error():
+    return lib().pw_last_error().decode()
+
+
+def pw_advect(grid, layout, dtype, u, v, w, coeffs, su, sv, sw, stream=None):
+    """Raw call: returns the pw_status (does not raise)."""
+    return lib().pw_advect(ctypes.byref(grid), ctypes.byref(layout) if layout is not None else None,
+                           int(dtype), u, v, w, ctypes.byref(coeffs), su, sv, sw, stream)
+
+
+def pw_advect_ex(grid, layout, dtype, u, v, w, coeffs, su, sv, sw, tile=None, stream=None):
+    return lib().pw_advect_ex(ctypes.byref(grid), ctypes.byref(layout) if layout is not None else None,
+                              int(dtype), u, v, w, ctypes.byref(coeffs), su, sv, sw,
+                              ctypes.byref(tile) if tile is not None else None, stream)
+
+
+def pw_advect_adjoint(grid, layout, dtype, u, v, w, coeffs, gsu, gsv, gsw, gu, gv, gw, stream=None):
+    return lib().pw_advect_adjoint(ctypes.byref(grid), ctypes.byref(layout) if layout is not None else None,
+                                   int(dtype), u, v, w, ctypes.byref(coeffs), gsu, gsv, gsw,
+                                   gu, gv, gw, stream)
+
+
+def pw_advect_adjoint_ex(grid, layout, dtype, u, v, w, coeffs, gsu, gsv, gsw, gu, gv, gw, tile=None,
+                         stream=None):
+    return lib().pw_advect_adjoint_ex(ctypes.byref(grid), ctypes.byref(layout) if layout is not None else None,
+                                      int(dtype), u, v, w, ctypes.byref(coeffs), gsu, gsv, gsw, gu, gv, gw,
+                                      ctypes.byref(tile) if tile is not None else None, stream)
+
+
+def pw_stream_copy(src, dst, nbytes, stream=None):
+    return lib().pw_stream_copy(src, dst, int(nbytes), stream)
+
+
+# ------------------------------------------------------------------ torch layer
+
+@dataclass
+class Coeffs:
+    """Scheme coefficients on the device: tcx, tcy scalars and the four vertical
+    arrays (torch tensors of length nz, float32 -- float64 for FP64 grids)."""
+    tcx: float
+    tcy: float
+    tzc1: "object"
+    tzc2: "object"
+    tzd1: "object"
+    tzd2: "object"
+
+    def c_struct(self):
+        return pw_coeffs(float(self.tcx), float(self.tcy), self.tzc1.data_ptr(), self.tzc2.data_ptr(),
+                         self.tzd1.data_ptr(), self.tzd2.data_ptr())
+
+    @classmethod
+    def from_host(cls, c, device="cuda", dtype=None):
+        import torch
+        dt = torch.float32 if dtype is None else dtype
+        mk = lambda a: torch.as_tensor(a, dtype=dt).to(device).contiguous()  # noqa: E731
+        return cls(float(c["tcx"]), float(c["tcy"]), mk(c["tzc1"]), mk(c["tzc2"]), mk(c["tzd1"]), mk(c["tzd2"]))
+
+
+def _dtype_code(t):
+    import torch
+    m = {torch.float32: PW_F32, torch.float64: PW_F64, torch.bfloat16: PW_BF16, torch.float16: PW_F16}
+    if t.dtype not in m:
+        raise TypeError("unsupported input dtype %s" % t.dtype)
+    return m[t.dtype]
+
+
+def _stream_handle(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _grid_from(u, halo):
+    pz, py, px = u.shape
+    return pw_grid(px - 2 * halo, py - 2 * halo, pz - 2 * halo, halo)
+
+
+def _layout_from(inp, out):
+    if inp.stride(-1) != 1 or out.stride(-1) != 1:
+        raise ValueError("x (last) dimension must be contiguous")
+    return pw_layout(inp.stride(1), inp.stride(0), out.stride(1), out.stride(0))
+
+
+def advect(u, v, w, coeffs: Coeffs, halo=1, out=None, tile=None, stream=None):
+    """su, sv, sw = PW source terms of padded winds u, v, w (torch tensors on the
+    GPU; float32, float64, bfloat16 or float16; identical shapes and strides)."""
+    import torch
+    if not (u.shape == v.shape == w.shape and u.stride() == v.stride() == w.stride()
+            and u.dtype == v.dtype == w.dtype):
+        raise ValueError("u, v, w must share shape, strides and dtype")
+    grid = _grid_from(u, halo)
+    odt = torch.float64 if u.dtype == torch.float64 else torch.float32
+    if out is None:
+        out = tuple(torch.empty((grid.nz, grid.ny, grid.nx), dtype=odt, device=u.device) for _ in range(3))
+    su, sv, sw = out
+    layout = _layout_from(u, su)
+    c = coeffs.c_struct()
+    tl = None if tile is None else pw_tile(*tile)
+    st = pw_advect_ex(grid, layout, _dtype_code(u), u.data_ptr(), v.data_ptr(), w.data_ptr(), c,
+                      su.data_ptr(), sv.data_ptr(), sw.data_ptr(), tl, _stream_handle(stream))
+    _check(st, "pw_advect")
+    return su, sv, sw
+
+
+def advect_adjoint(u, v, w, coeffs: Coeffs, gsu, gsv, gsw, halo=1, out=None, tile=None, stream=None):
+    """gu, gv, gw = J(u, v, w)^T (gsu, gsv, gsw), padded-shaped (halo included)."""
+    import torch
+    grid = _grid_from(u, halo)
+    if out is None:
+        out = tuple(torch.empty_like(u) for _ in range(3))
+    gu, gv, gw = out
+    gsu, gsv, gsw = (g.contiguous() if g.stride(-1) != 1 else g for g in (gsu, gsv, gsw))
+    if not (gsu.stride() == gsv.stride() == gsw.stride()):
+        gsu, gsv, gsw = (g.contiguous() for g in (gsu, gsv, gsw))
+    layout = _layout_from(u, gsu)
+    if gu.stride() != u.stride():
+        raise ValueError("gradients must share the inputs' strides")
+    tl = None if tile is None else pw_tile(*tile)
+    st = pw_advect_adjoint_ex(grid, layout, _dtype_code(u), u.data_ptr(), v.data_ptr(), w.data_ptr(),
+                              coeffs.c_struct(), gsu.data_ptr(), gsv.data_ptr(), gsw.data_ptr(),
+                              gu.data_ptr(), gv.data_ptr(), gw.data_ptr(), tl, _stream_handle(stream))
+    _check(st, "pw_advect_adjoint")
+    return gu, gv, gw
+
+
+def stream_copy(src, dst, stream=None):
+    _check(pw_stream_copy(src.data_ptr(), dst.data_ptr(), src.numel() * src.element_size(),
+                          _stream_handle(stream)), "pw_stream_copy")
+    return dst
+
+
+def _autograd_function():
+    import torch
+
+    class PWAdvect(torch.autograd.Function):
+        """Differentiable PW advection: forward = ``advect``, backward = the
+        hand-written adjoint kernel (gradients w.r.t. u, v, w; the coefficients
+        are treated as constants)."""
+
+        @staticmethod
+        def forward(ctx, u, v, w, coeffs, halo=1):
+            ctx.save_for_backward(u, v, w)
+            ctx.coeffs = coeffs
+            ctx.halo = halo
+            return advect(u, v, w, coeffs, halo)
+
+        @staticmethod
+        def backward(ctx, gsu, gsv, gsw):
+            u, v, w = ctx.saved_tensors
+            gu, gv, gw = advect_adjoint(u, v, w, ctx.coeffs, gsu, gsv, gsw, ctx.halo)
+            return gu, gv, gw, None, None
+
+    return PWAdvect
+
+
+_PWAdvect = None
+
+
+def PWAdvect():
+    """The torch.autograd.Function class (created on first use, so importing
+    this module does not import torch)."""
+    global _PWAdvect
+    if _PWAdvect is None:
+        _PWAdvect = _autograd_function()
+    return _PWAdvect

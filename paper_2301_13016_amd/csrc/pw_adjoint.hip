@@ -1,0 +1,368 @@
+// Adjoint (vector-Jacobian product) of the PW advection operator, gfx950.
+//
+// Given output cotangents (gsu, gsv, gsw) on the interior, computes
+//   (gu, gv, gw) = J(u, v, w)^T (gsu, gsv, gsw)
+// on the whole padded grid (halo included), in gather form: each gradient
+// point q collects, from the outputs p whose product terms read q, the partial
+// derivative of that term times the cotangent at p.  A term
+//   s * c * a * (b + d)
+// contributes s*c*(b+d)*r to the gradient of a and s*c*a*r to those of b and d
+// (product rule); writing q's contributions grouped by cotangent point gives
+// the expressions below (15 cotangent points per gradient point, all within
+// one cell in every direction).  No atomics: every gradient entry is written
+// by exactly one lane.
+//
+// Layout and launch mirror the forward kernel: a wavefront owns a strip of 62
+// padded columns x RY padded rows and marches through padded z-levels with a
+// four-plane register ring (values u, v, w and cotangents of planes k-1, k,
+// k+1 feed level k while k+2 is in flight); x-neighbours come from DPP
+// wavefront shifts.  Cotangents outside the interior read as 0; values
+// outside the padded array are read from the nearest valid entry and always
+// meet a zero cotangent.
+#include "pw_internal.h"
+
+namespace pw {
+namespace {
+
+constexpr int kWaveShr1 = 0x138;   // lane l <- lane l-1
+constexpr int kWaveShl1 = 0x130;   // lane l <- lane l+1
+
+template <int Ctrl> __device__ __forceinline__ float wave_shift(float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), Ctrl, 0xf, 0xf, true));
+}
+template <int Ctrl> __device__ __forceinline__ double wave_shift(double x) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), Ctrl, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), Ctrl, 0xf, 0xf, true);
+    return __hiloint2double(hi, lo);
+}
+template <typename T> __device__ __forceinline__ T from_left(T x) { return wave_shift<kWaveShr1>(x); }
+template <typename T> __device__ __forceinline__ T from_right(T x) { return wave_shift<kWaveShl1>(x); }
+
+template <typename T> __device__ __forceinline__ T fma_(T a, T b, T c);
+template <> __device__ __forceinline__ float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+template <> __device__ __forceinline__ double fma_(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+template <typename T> struct AdjK {
+    const T *u, *v, *w;
+    const T *ru, *rv, *rw;          // cotangents of su, sv, sw (interior, output layout)
+    T *gu, *gv, *gw;                // gradients (padded, input layout)
+    const T *tzc1, *tzc2, *tzd1, *tzd2;
+    T tcx, tcy;
+    int32_t nx, ny, nz, h;
+    int64_t in_sz, out_sz;
+    int32_t in_sy, out_sy;
+    int32_t ntx, nty, nzc, zlen, wpb;
+};
+
+// One padded z-plane of the strip: rows 0..RY+1 are padded rows jb-1 .. jb+RY.
+template <typename T, int RY> struct APlane {
+    T u[RY + 2], v[RY + 2], w[RY + 2];
+    T ru[RY + 2], rv[RY + 2], rw[RY + 2];
+};
+
+template <typename T, int RY> struct StripAddr {
+    uint32_t voff[RY + 2];   // byte offsets of the value rows (clamped)
+    uint32_t roff[RY + 2];   // byte offsets of the cotangent rows (clamped)
+    bool rrow[RY + 2];       // cotangent row inside the interior (wave-uniform)
+    bool rcol;               // cotangent column inside the interior (per lane)
+};
+
+template <typename T, int RY>
+__device__ __forceinline__ void load_aplane(APlane<T, RY> &P, const AdjK<T> &a, int kp, const StripAddr<T, RY> &s) {
+    const int pz = a.nz + 2 * a.h;
+    const int kv = min(max(kp, 0), pz - 1);
+    const int64_t pb = static_cast<int64_t>(kv) * a.in_sz * static_cast<int64_t>(sizeof(T));
+    const char *bu = reinterpret_cast<const char *>(a.u) + pb;
+    const char *bv = reinterpret_cast<const char *>(a.v) + pb;
+    const char *bw = reinterpret_cast<const char *>(a.w) + pb;
+#pragma unroll
+    for (int r = 0; r < RY + 2; ++r) {
+        P.u[r] = *reinterpret_cast<const T *>(bu + s.voff[r]);
+        P.v[r] = *reinterpret_cast<const T *>(bv + s.voff[r]);
+        P.w[r] = *reinterpret_cast<const T *>(bw + s.voff[r]);
+    }
+    const int kk = kp - a.h;
+    if (kk >= 0 && kk < a.nz) {
+        const int64_t ob = static_cast<int64_t>(kk) * a.out_sz * static_cast<int64_t>(sizeof(T));
+        const char *cu = reinterpret_cast<const char *>(a.ru) + ob;
+        const char *cv = reinterpret_cast<const char *>(a.rv) + ob;
+        const char *cw = reinterpret_cast<const char *>(a.rw) + ob;
+#pragma unroll
+        for (int r = 0; r < RY + 2; ++r) {
+            if (s.rrow[r]) {
+                const T xu = *reinterpret_cast<const T *>(cu + s.roff[r]);
+                const T xv = *reinterpret_cast<const T *>(cv + s.roff[r]);
+                const T xw = *reinterpret_cast<const T *>(cw + s.roff[r]);
+                P.ru[r] = s.rcol ? xu : T(0);
+                P.rv[r] = s.rcol ? xv : T(0);
+                P.rw[r] = s.rcol ? xw : T(0);
+            } else {
+                P.ru[r] = T(0);
+                P.rv[r] = T(0);
+                P.rw[r] = T(0);
+            }
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < RY + 2; ++r) {
+            P.ru[r] = T(0);
+            P.rv[r] = T(0);
+            P.rw[r] = T(0);
+        }
+    }
+}
+
+template <typename T> __device__ __forceinline__ T coef(const T *c, int kk, int nz) {
+    return c[min(max(kk, 0), nz - 1)];   // clamped: only ever met by a zero cotangent when outside
+}
+
+// Gradients at padded level kp from planes kp-1 (m), kp (c), kp+1 (p).
+template <typename T, int RY>
+__device__ __forceinline__ void adj_level(const APlane<T, RY> &m, const APlane<T, RY> &c, const APlane<T, RY> &p,
+                                          const AdjK<T> &a, int kp, bool lane_ok,
+                                          const uint32_t (&goff)[RY], const bool (&row_ok)[RY]) {
+    const int kq = kp - a.h;   // interior level index of this gradient plane
+    const T tcx = a.tcx, tcy = a.tcy;
+    const T c1p = coef(a.tzc1, kq + 1, a.nz), c2m = coef(a.tzc2, kq - 1, a.nz), c2 = coef(a.tzc2, kq, a.nz);
+    const T d1 = coef(a.tzd1, kq, a.nz), d2 = coef(a.tzd2, kq, a.nz);
+    const T d2m = coef(a.tzd2, kq - 1, a.nz), d1p = coef(a.tzd1, kq + 1, a.nz);
+
+    // Row-shared pieces (index r = loaded row r):
+    //   xv[r] = rv(r,i+1) v(r,i) - rv(r,i) v(r,i+1)          plane k   (gu: sv x-terms)
+    //   fy[r] = v(r,i) + v(r,i+1)                              plane k   (gu: su y-faces)
+    //   hy[r] = v(k,r,i) + v(k+1,r,i)                                    (gw: sw y-faces)
+    //   zv[r] = tzc1[kq+1] rv(k+1,r) v(k,r) - tzc2[kq] rv(k,r) v(k+1,r)  (gw: sv z-terms)
+    T xv[RY + 1], fy[RY + 1], hy[RY + 1], zv[RY + 1];
+#pragma unroll
+    for (int r = 0; r <= RY; ++r) {
+        xv[r] = fma_(from_right(c.rv[r]), c.v[r], -(c.rv[r] * from_right(c.v[r])));
+        fy[r] = c.v[r] + from_right(c.v[r]);
+        hy[r] = c.v[r] + p.v[r];
+        zv[r] = fma_(c1p * p.rv[r], c.v[r], -(c2 * c.rv[r] * p.v[r]));
+    }
+
+    const int64_t gb = static_cast<int64_t>(min(max(kp, 0), a.nz + 2 * a.h - 1)) * a.in_sz *
+                       static_cast<int64_t>(sizeof(T));
+    char *ogu = reinterpret_cast<char *>(a.gu) + gb;
+    char *ogv = reinterpret_cast<char *>(a.gv) + gb;
+    char *ogw = reinterpret_cast<char *>(a.gw) + gb;
+
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+        const int q = r + 1;
+        const T two = T(2);
+
+        // ---------------------------------------------------------------- gu
+        const T ru_l = from_left(c.ru[q]), ru_r = from_right(c.ru[q]);
+        const T u_l = from_left(c.u[q]), u_r = from_right(c.u[q]);
+        // su x-terms
+        T gx = ru_r * fma_(two, c.u[q], u_r);
+        gx = fma_(c.ru[q], u_l - u_r, gx);
+        gx = fma_(-ru_l, fma_(two, c.u[q], u_l), gx);
+        // sv and sw x-terms: antisymmetric pairs at rows j-1, j (sv) and planes k-1, k (sw)
+        const T xw_c = fma_(from_right(c.rw[q]), c.w[q], -(c.rw[q] * from_right(c.w[q])));
+        const T xw_m = fma_(from_right(m.rw[q]), m.w[q], -(m.rw[q] * from_right(m.w[q])));
+        gx = gx + ((xv[r] + xv[q]) + (xw_m + xw_c));
+        // su y-terms
+        const T gyu = fma_(c.ru[q + 1], fy[q], -(c.ru[q - 1] * fy[r]));
+        // su z-terms
+        const T gzu = fma_(c1p * p.ru[q], c.w[q] + from_right(c.w[q]),
+                           -(c2m * m.ru[q] * (m.w[q] + from_right(m.w[q]))));
+        T gu = tcx * gx;
+        gu = fma_(tcy, gyu, gu);
+        gu = gu + gzu;
+
+        // ---------------------------------------------------------------- gv
+        // su y-terms: yu(i) + yu(i-1), yu = ru(j+1) u(j) - ru(j) u(j+1)
+        const T yu = fma_(c.ru[q + 1], c.u[q], -(c.ru[q] * c.u[q + 1]));
+        const T gyv_su = yu + from_left(yu);
+        // sv x-terms
+        const T sxu = c.u[q] + c.u[q + 1];   // u(j,i) + u(j+1,i)
+        const T gxv = fma_(from_right(c.rv[q]), sxu, -(from_left(c.rv[q]) * from_left(sxu)));
+        // sv y-terms
+        T gyv = c.rv[q + 1] * fma_(two, c.v[q], c.v[q + 1]);
+        gyv = fma_(c.rv[q], c.v[q - 1] - c.v[q + 1], gyv);
+        gyv = fma_(-c.rv[q - 1], fma_(two, c.v[q], c.v[q - 1]), gyv);
+        // sw y-terms at planes k-1 and k: yw = rw(j+1) w(j) - rw(j) w(j+1)
+        const T yw_c = fma_(c.rw[q + 1], c.w[q], -(c.rw[q] * c.w[q + 1]));
+        const T yw_m = fma_(m.rw[q + 1], m.w[q], -(m.rw[q] * m.w[q + 1]));
+        // sv z-terms
+        const T gzv = fma_(c1p * p.rv[q], c.w[q] + c.w[q + 1], -(c2m * m.rv[q] * (m.w[q] + m.w[q + 1])));
+        T gv = tcx * gxv;
+        gv = fma_(tcy, (gyv_su + gyv) + (yw_m + yw_c), gv);
+        gv = gv + gzv;
+
+        // ---------------------------------------------------------------- gw
+        // su z-terms: zu(i) + zu(i-1), zu = tzc1[kq+1] ru(k+1) u(k) - tzc2[kq] ru(k) u(k+1)
+        const T zu = fma_(c1p * p.ru[q], c.u[q], -(c2 * c.ru[q] * p.u[q]));
+        // sw z-terms
+        T gzw = d1p * p.rw[q] * fma_(two, c.w[q], p.w[q]);
+        gzw = fma_(c.rw[q], fma_(d1, m.w[q], -(d2 * p.w[q])), gzw);
+        gzw = fma_(-(d2m * m.rw[q]), fma_(two, c.w[q], m.w[q]), gzw);
+        // sw x-terms
+        const T hxu = c.u[q] + p.u[q];   // u(k,i) + u(k+1,i)
+        const T gxw = fma_(from_right(c.rw[q]), hxu, -(from_left(c.rw[q]) * from_left(hxu)));
+        // sw y-terms
+        const T gyw = fma_(c.rw[q + 1], hy[q], -(c.rw[q - 1] * hy[r]));
+        T gw = (zu + from_left(zu)) + (zv[q] + zv[r]);
+        gw = gw + gzw;
+        gw = fma_(tcx, gxw, gw);
+        gw = fma_(tcy, gyw, gw);
+
+        if (lane_ok && row_ok[r]) {
+            __builtin_nontemporal_store(gu, reinterpret_cast<T *>(ogu + goff[r]));
+            __builtin_nontemporal_store(gv, reinterpret_cast<T *>(ogv + goff[r]));
+            __builtin_nontemporal_store(gw, reinterpret_cast<T *>(ogw + goff[r]));
+        }
+    }
+}
+
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+    const int q = nb >> 3, rem = nb & 7, x = b & 7, i = b >> 3;
+    return x * q + min(x, rem) + i;
+}
+
+template <typename T, int RY>
+__global__ __launch_bounds__(512) void pw_adjoint_kernel(AdjK<T> a) {
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    const int cz = t % a.nzc;
+    const int t2 = t / a.nzc;
+    const int tx = t2 % a.ntx;
+    const int ty = (t2 / a.ntx) * a.wpb + wave;
+    if (ty >= a.nty) return;
+
+    const int px = a.nx + 2 * a.h, py = a.ny + 2 * a.h, pz = a.nz + 2 * a.h;
+    const int pcol = tx * kWaveCols - 1 + lane;        // padded column loaded by this lane
+    const int vcol = min(max(pcol, 0), px - 1);
+    const int icol = pcol - a.h;                        // its interior column
+    const bool lane_ok = lane >= 1 && lane <= kWaveCols && pcol < px;
+    const int jb = ty * RY;                             // first padded gradient row
+
+    StripAddr<T, RY> s;
+    s.rcol = icol >= 0 && icol < a.nx;
+    const int icl = min(max(icol, 0), a.nx - 1);
+#pragma unroll
+    for (int r = 0; r < RY + 2; ++r) {
+        const int prow = jb - 1 + r;
+        const int vr = min(max(prow, 0), py - 1);
+        s.voff[r] = static_cast<uint32_t>((vr * a.in_sy + vcol) * static_cast<int>(sizeof(T)));
+        const int ir = prow - a.h;
+        s.rrow[r] = ir >= 0 && ir < a.ny;
+        const int irc = min(max(ir, 0), a.ny - 1);
+        s.roff[r] = static_cast<uint32_t>((irc * a.out_sy + icl) * static_cast<int>(sizeof(T)));
+    }
+    uint32_t goff[RY];
+    bool row_ok[RY];
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+        row_ok[r] = jb + r < py;
+        const int gr = min(jb + r, py - 1);
+        goff[r] = static_cast<uint32_t>((gr * a.in_sy + vcol) * static_cast<int>(sizeof(T)));
+    }
+
+    const int k0 = cz * a.zlen;
+    const int k1 = min(pz, k0 + a.zlen);
+    APlane<T, RY> A, B, C, D;
+    load_aplane<T, RY>(A, a, k0 - 1, s);
+    load_aplane<T, RY>(B, a, k0, s);
+    load_aplane<T, RY>(C, a, k0 + 1, s);
+    int k = k0;
+    for (;;) {
+        if (k + 1 < k1) load_aplane<T, RY>(D, a, k + 2, s);
+        adj_level<T, RY>(A, B, C, a, k, lane_ok, goff, row_ok);
+        if (++k >= k1) break;
+        if (k + 1 < k1) load_aplane<T, RY>(A, a, k + 2, s);
+        adj_level<T, RY>(B, C, D, a, k, lane_ok, goff, row_ok);
+        if (++k >= k1) break;
+        if (k + 1 < k1) load_aplane<T, RY>(B, a, k + 2, s);
+        adj_level<T, RY>(C, D, A, a, k, lane_ok, goff, row_ok);
+        if (++k >= k1) break;
+        if (k + 1 < k1) load_aplane<T, RY>(C, a, k + 2, s);
+        adj_level<T, RY>(D, A, B, a, k, lane_ok, goff, row_ok);
+        if (++k >= k1) break;
+    }
+}
+
+template <typename T, int RY>
+pw_status launch_adj_t(const AdjArgs &g, const TileCfg &cfg, hipStream_t s) {
+    AdjK<T> a;
+    a.u = static_cast<const T *>(g.u);
+    a.v = static_cast<const T *>(g.v);
+    a.w = static_cast<const T *>(g.w);
+    a.ru = static_cast<const T *>(g.gsu);
+    a.rv = static_cast<const T *>(g.gsv);
+    a.rw = static_cast<const T *>(g.gsw);
+    a.gu = static_cast<T *>(g.gu);
+    a.gv = static_cast<T *>(g.gv);
+    a.gw = static_cast<T *>(g.gw);
+    a.tzc1 = static_cast<const T *>(g.tzc1);
+    a.tzc2 = static_cast<const T *>(g.tzc2);
+    a.tzd1 = static_cast<const T *>(g.tzd1);
+    a.tzd2 = static_cast<const T *>(g.tzd2);
+    a.tcx = static_cast<T>(g.tcx);
+    a.tcy = static_cast<T>(g.tcy);
+    a.nx = static_cast<int32_t>(g.nx);
+    a.ny = static_cast<int32_t>(g.ny);
+    a.nz = static_cast<int32_t>(g.nz);
+    a.h = g.h;
+    a.in_sz = g.in_sz;
+    a.out_sz = g.out_sz;
+    a.in_sy = static_cast<int32_t>(g.in_sy);
+    a.out_sy = static_cast<int32_t>(g.out_sy);
+    const int64_t px = g.nx + 2 * g.h, py = g.ny + 2 * g.h, pz = g.nz + 2 * g.h;
+    a.ntx = static_cast<int32_t>((px + kWaveCols - 1) / kWaveCols);
+    a.nty = static_cast<int32_t>((py + RY - 1) / RY);
+    a.zlen = cfg.zlen;
+    a.nzc = static_cast<int32_t>((pz + cfg.zlen - 1) / cfg.zlen);
+    a.wpb = cfg.wpb;
+    const int64_t nblk_y = (a.nty + cfg.wpb - 1) / cfg.wpb;
+    const int64_t nblocks = static_cast<int64_t>(a.ntx) * nblk_y * a.nzc;
+    if (nblocks <= 0 || nblocks > 0x7fffffffLL) return fail(PW_ERR_UNSUPPORTED, "grid too large");
+    hipLaunchKernelGGL((pw_adjoint_kernel<T, RY>), dim3(static_cast<unsigned>(nblocks)), dim3(64 * cfg.wpb), 0, s, a);
+    return hip_fail(hipGetLastError(), "adjoint kernel launch");
+}
+
+template <typename T>
+pw_status launch_adj_dt(const AdjArgs &g, const TileCfg &cfg, hipStream_t s) {
+    switch (cfg.ry) {
+        case 1: return launch_adj_t<T, 1>(g, cfg, s);
+        case 2: return launch_adj_t<T, 2>(g, cfg, s);
+        case 4: return launch_adj_t<T, 4>(g, cfg, s);
+        default: return fail(PW_ERR_UNSUPPORTED, "adjoint rows per strip %d not instantiated", cfg.ry);
+    }
+}
+
+}  // namespace
+
+bool adjoint_tile_supported(const TileCfg &c) {
+    return (c.ry == 1 || c.ry == 2 || c.ry == 4) && c.zlen >= 1 && c.wpb >= 1 && c.wpb <= 8;
+}
+
+TileCfg default_adjoint_tile(const AdjArgs &a, pw_dtype dt) {
+    TileCfg c;
+    c.ry = (dt == PW_F64) ? 1 : 2;
+    c.wpb = 4;
+    const int64_t px = a.nx + 2 * a.h, py = a.ny + 2 * a.h, pz = a.nz + 2 * a.h;
+    const int64_t strips = ((px + kWaveCols - 1) / kWaveCols) * ((py + c.ry - 1) / c.ry);
+    const int64_t want = 256 * 24;
+    int64_t chunks = (want + strips - 1) / strips;
+    if (chunks < 1) chunks = 1;
+    int64_t zl = (pz + chunks - 1) / chunks;
+    if (zl < 8) zl = 8;
+    if (zl > pz) zl = pz;
+    c.zlen = static_cast<int>(zl);
+    return c;
+}
+
+pw_status launch_adjoint(const AdjArgs &a, pw_dtype dt, const TileCfg &cfg, hipStream_t s) {
+    if (!adjoint_tile_supported(cfg)) return fail(PW_ERR_INVALID_ARG, "unsupported adjoint tile configuration");
+    switch (dt) {
+        case PW_F32: return launch_adj_dt<float>(a, cfg, s);
+        case PW_F64: return launch_adj_dt<double>(a, cfg, s);
+        default: return fail(PW_ERR_UNSUPPORTED, "adjoint dtype %d", static_cast<int>(dt));
+    }
+}
+
+}  // namespace pw

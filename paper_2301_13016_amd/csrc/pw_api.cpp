@@ -1,0 +1,280 @@
+// C ABI of libpwadv: argument validation, error reporting and dispatch to the
+// kernel launchers.  Declarations and the contract are in include/pwadv.h.
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+#include "pw_internal.h"
+
+namespace pw {
+
+static thread_local char g_err[512] = "";
+
+pw_status fail(pw_status st, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return st;
+}
+
+pw_status hip_fail(hipError_t e, const char *what) {
+    if (e == hipSuccess) return PW_OK;
+    return fail(PW_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+namespace {
+
+int64_t elem_size(pw_dtype dt) {
+    switch (dt) {
+        case PW_F32: return 4;
+        case PW_F64: return 8;
+        case PW_BF16: return 2;
+        case PW_F16: return 2;
+    }
+    return 0;
+}
+
+// Element size of coefficients and outputs for a storage dtype.
+int64_t compute_size(pw_dtype dt) { return dt == PW_F64 ? 8 : 4; }
+
+struct Layout {
+    int64_t in_sy, in_sz, out_sy, out_sz;
+};
+
+constexpr int64_t kMaxDim = int64_t(1) << 30;
+
+pw_status check_grid(const pw_grid *g) {
+    if (!g) return fail(PW_ERR_INVALID_ARG, "grid is NULL");
+    if (g->nx < 1 || g->ny < 1 || g->nz < 1)
+        return fail(PW_ERR_INVALID_ARG, "interior extents must be >= 1 (nx=%lld ny=%lld nz=%lld)",
+                    (long long)g->nx, (long long)g->ny, (long long)g->nz);
+    if (g->halo < 1) return fail(PW_ERR_INVALID_ARG, "halo must be >= 1 (depth-one stencil), got %d", g->halo);
+    if (g->nx > kMaxDim || g->ny > kMaxDim || g->nz > kMaxDim || g->halo > 1024)
+        return fail(PW_ERR_INVALID_ARG, "extent too large");
+    if (g->nx * g->ny > (int64_t(1) << 40) / g->nz) return fail(PW_ERR_INVALID_ARG, "more than 2^40 points");
+    return PW_OK;
+}
+
+pw_status resolve_layout(const pw_grid *g, const pw_layout *l, int64_t in_es, int64_t out_es, Layout *out) {
+    const int64_t px = g->nx + 2 * g->halo, py = g->ny + 2 * g->halo;
+    if (l) {
+        *out = {l->in_sy, l->in_sz, l->out_sy, l->out_sz};
+        if (out->in_sy < px) return fail(PW_ERR_INVALID_ARG, "in_sy %lld < nx+2h %lld", (long long)out->in_sy, (long long)px);
+        if (out->in_sz / py < out->in_sy) return fail(PW_ERR_INVALID_ARG, "in_sz too small for in_sy*(ny+2h)");
+        if (out->out_sy < g->nx) return fail(PW_ERR_INVALID_ARG, "out_sy %lld < nx", (long long)out->out_sy);
+        if (out->out_sz / g->ny < out->out_sy) return fail(PW_ERR_INVALID_ARG, "out_sz too small for out_sy*ny");
+    } else {
+        *out = {px, px * py, g->nx, g->nx * g->ny};
+    }
+    // The kernels address within one z-plane with 32-bit byte offsets.
+    if (out->in_sz * in_es >= (int64_t(1) << 31) || out->out_sz * out_es >= (int64_t(1) << 31))
+        return fail(PW_ERR_UNSUPPORTED, "a z-plane larger than 2 GiB is not supported");
+    return PW_OK;
+}
+
+struct Range {
+    const char *name;
+    uintptr_t lo, hi;
+};
+
+Range in_range(const char *name, const void *p, const pw_grid *g, const Layout &L, int64_t es) {
+    const int64_t px = g->nx + 2 * g->halo, py = g->ny + 2 * g->halo, pz = g->nz + 2 * g->halo;
+    const int64_t last = (pz - 1) * L.in_sz + (py - 1) * L.in_sy + (px - 1);
+    return {name, reinterpret_cast<uintptr_t>(p), reinterpret_cast<uintptr_t>(p) + uintptr_t((last + 1) * es)};
+}
+
+Range out_range(const char *name, const void *p, const pw_grid *g, const Layout &L, int64_t es) {
+    const int64_t last = (g->nz - 1) * L.out_sz + (g->ny - 1) * L.out_sy + (g->nx - 1);
+    return {name, reinterpret_cast<uintptr_t>(p), reinterpret_cast<uintptr_t>(p) + uintptr_t((last + 1) * es)};
+}
+
+bool overlap(const Range &a, const Range &b) { return a.lo < b.hi && b.lo < a.hi; }
+
+pw_status check_aligned(const char *name, const void *p, int64_t es) {
+    if (!p) return fail(PW_ERR_INVALID_ARG, "%s is NULL", name);
+    if (reinterpret_cast<uintptr_t>(p) % uintptr_t(es))
+        return fail(PW_ERR_INVALID_ARG, "%s is not aligned to its element size %lld", name, (long long)es);
+    return PW_OK;
+}
+
+// The current device, after checking that one exists.
+pw_status current_device(int *dev) {
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess || n < 1) {
+        (void)hipGetLastError();
+        return fail(PW_ERR_NO_DEVICE, "no usable HIP device (%s)",
+                    e == hipSuccess ? "device count 0" : hipGetErrorString(e));
+    }
+    e = hipGetDevice(dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    return PW_OK;
+}
+
+pw_status check_on_device(const char *name, const void *p, int dev) {
+    hipPointerAttribute_t at;
+    std::memset(&at, 0, sizeof at);
+    hipError_t e = hipPointerGetAttributes(&at, p);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(PW_ERR_INVALID_ARG, "%s is not a device pointer", name);
+    }
+    if (at.type != hipMemoryTypeDevice && at.type != hipMemoryTypeManaged)
+        return fail(PW_ERR_INVALID_ARG, "%s is not device memory (memory type %d)", name, (int)at.type);
+    if (at.device != dev)
+        return fail(PW_ERR_INVALID_ARG, "%s lives on device %d, current device is %d", name, at.device, dev);
+    return PW_OK;
+}
+
+#define PW_TRY(x)                            \
+    do {                                     \
+        pw_status st_ = (x);                 \
+        if (st_ != PW_OK) return st_;        \
+    } while (0)
+
+}  // namespace
+}  // namespace pw
+
+using namespace pw;
+
+extern "C" {
+
+const char *pw_version(void) { return "libpwadv 0.1.0 (gfx950)"; }
+
+const char *pw_last_error(void) { return g_err; }
+
+pw_status pw_advect(const pw_grid *grid, const pw_layout *layout, pw_dtype in_dtype,
+                    const void *u, const void *v, const void *w, const pw_coeffs *coeffs,
+                    void *su, void *sv, void *sw, void *hip_stream) {
+    return pw_advect_ex(grid, layout, in_dtype, u, v, w, coeffs, su, sv, sw, nullptr, hip_stream);
+}
+
+pw_status pw_advect_ex(const pw_grid *grid, const pw_layout *layout, pw_dtype in_dtype,
+                       const void *u, const void *v, const void *w, const pw_coeffs *coeffs,
+                       void *su, void *sv, void *sw, const pw_tile *tile, void *hip_stream) {
+    g_err[0] = 0;
+    PW_TRY(check_grid(grid));
+    const int64_t es = elem_size(in_dtype);
+    if (!es) return fail(PW_ERR_INVALID_ARG, "unknown dtype %d", (int)in_dtype);
+    const int64_t cs = compute_size(in_dtype);
+    Layout L;
+    PW_TRY(resolve_layout(grid, layout, es, cs, &L));
+    if (!coeffs) return fail(PW_ERR_INVALID_ARG, "coeffs is NULL");
+    const char *names[] = {"u", "v", "w", "su", "sv", "sw", "tzc1", "tzc2", "tzd1", "tzd2"};
+    const void *ptrs[] = {u, v, w, su, sv, sw, coeffs->tzc1, coeffs->tzc2, coeffs->tzd1, coeffs->tzd2};
+    for (int i = 0; i < 10; ++i) PW_TRY(check_aligned(names[i], ptrs[i], i < 3 ? es : cs));
+    const Range rin[3] = {in_range("u", u, grid, L, es), in_range("v", v, grid, L, es), in_range("w", w, grid, L, es)};
+    const Range rout[3] = {out_range("su", su, grid, L, cs), out_range("sv", sv, grid, L, cs),
+                           out_range("sw", sw, grid, L, cs)};
+    for (const Range &o : rout) {
+        for (const Range &i : rin)
+            if (overlap(o, i)) return fail(PW_ERR_INVALID_ARG, "output %s overlaps input %s", o.name, i.name);
+        for (const Range &o2 : rout)
+            if (&o != &o2 && overlap(o, o2)) return fail(PW_ERR_INVALID_ARG, "outputs %s and %s overlap", o.name, o2.name);
+    }
+    if (tile) {
+        TileCfg t;
+        t.ry = tile->rows_per_strip;
+        t.zlen = tile->zlen;
+        t.wpb = tile->waves_per_group;
+        if (!tile_supported(t) || (in_dtype == PW_F64 && t.ry > 4))
+            return fail(PW_ERR_INVALID_ARG, "unsupported tile rows=%d zlen=%d waves=%d", t.ry, t.zlen, t.wpb);
+    }
+    int dev = 0;
+    PW_TRY(current_device(&dev));
+    for (int i = 0; i < 10; ++i) PW_TRY(check_on_device(names[i], ptrs[i], dev));
+
+    FwdArgs a;
+    a.u = u; a.v = v; a.w = w;
+    a.su = su; a.sv = sv; a.sw = sw;
+    a.tzc1 = coeffs->tzc1; a.tzc2 = coeffs->tzc2; a.tzd1 = coeffs->tzd1; a.tzd2 = coeffs->tzd2;
+    a.tcx = coeffs->tcx; a.tcy = coeffs->tcy;
+    a.nx = grid->nx; a.ny = grid->ny; a.nz = grid->nz; a.h = grid->halo;
+    a.in_sy = L.in_sy; a.in_sz = L.in_sz; a.out_sy = L.out_sy; a.out_sz = L.out_sz;
+    TileCfg cfg = default_forward_tile(a, in_dtype);
+    if (tile) {   // validated above
+        cfg.ry = tile->rows_per_strip;
+        cfg.zlen = tile->zlen;
+        cfg.wpb = tile->waves_per_group;
+    }
+    return launch_forward(a, in_dtype, cfg, static_cast<hipStream_t>(hip_stream));
+}
+
+pw_status pw_advect_adjoint(const pw_grid *grid, const pw_layout *layout, pw_dtype dtype,
+                            const void *u, const void *v, const void *w, const pw_coeffs *coeffs,
+                            const void *gsu, const void *gsv, const void *gsw,
+                            void *gu, void *gv, void *gw, void *hip_stream) {
+    return pw_advect_adjoint_ex(grid, layout, dtype, u, v, w, coeffs, gsu, gsv, gsw, gu, gv, gw, nullptr,
+                                hip_stream);
+}
+
+pw_status pw_advect_adjoint_ex(const pw_grid *grid, const pw_layout *layout, pw_dtype dtype,
+                               const void *u, const void *v, const void *w, const pw_coeffs *coeffs,
+                               const void *gsu, const void *gsv, const void *gsw,
+                               void *gu, void *gv, void *gw, const pw_tile *tile, void *hip_stream) {
+    g_err[0] = 0;
+    PW_TRY(check_grid(grid));
+    if (dtype != PW_F32 && dtype != PW_F64) {
+        if (elem_size(dtype)) return fail(PW_ERR_UNSUPPORTED, "adjoint supports PW_F32 and PW_F64 only");
+        return fail(PW_ERR_INVALID_ARG, "unknown dtype %d", (int)dtype);
+    }
+    const int64_t es = elem_size(dtype);
+    Layout L;
+    PW_TRY(resolve_layout(grid, layout, es, es, &L));
+    if (!coeffs) return fail(PW_ERR_INVALID_ARG, "coeffs is NULL");
+    const char *names[] = {"u", "v", "w", "gsu", "gsv", "gsw", "gu", "gv", "gw", "tzc1", "tzc2", "tzd1", "tzd2"};
+    const void *ptrs[] = {u, v, w, gsu, gsv, gsw, gu, gv, gw, coeffs->tzc1, coeffs->tzc2, coeffs->tzd1, coeffs->tzd2};
+    for (int i = 0; i < 13; ++i) PW_TRY(check_aligned(names[i], ptrs[i], es));
+    const Range rin[6] = {in_range("u", u, grid, L, es), in_range("v", v, grid, L, es), in_range("w", w, grid, L, es),
+                          out_range("gsu", gsu, grid, L, es), out_range("gsv", gsv, grid, L, es),
+                          out_range("gsw", gsw, grid, L, es)};
+    const Range rout[3] = {in_range("gu", gu, grid, L, es), in_range("gv", gv, grid, L, es),
+                           in_range("gw", gw, grid, L, es)};
+    for (const Range &o : rout) {
+        for (const Range &i : rin)
+            if (overlap(o, i)) return fail(PW_ERR_INVALID_ARG, "gradient %s overlaps %s", o.name, i.name);
+        for (const Range &o2 : rout)
+            if (&o != &o2 && overlap(o, o2)) return fail(PW_ERR_INVALID_ARG, "gradients %s and %s overlap", o.name, o2.name);
+    }
+    TileCfg tc;
+    if (tile) {
+        tc.ry = tile->rows_per_strip;
+        tc.zlen = tile->zlen;
+        tc.wpb = tile->waves_per_group;
+        if (!adjoint_tile_supported(tc))
+            return fail(PW_ERR_INVALID_ARG, "unsupported adjoint tile rows=%d zlen=%d waves=%d", tc.ry, tc.zlen, tc.wpb);
+    }
+    int dev = 0;
+    PW_TRY(current_device(&dev));
+    for (int i = 0; i < 13; ++i) PW_TRY(check_on_device(names[i], ptrs[i], dev));
+
+    AdjArgs a;
+    a.u = u; a.v = v; a.w = w;
+    a.gsu = gsu; a.gsv = gsv; a.gsw = gsw;
+    a.gu = gu; a.gv = gv; a.gw = gw;
+    a.tzc1 = coeffs->tzc1; a.tzc2 = coeffs->tzc2; a.tzd1 = coeffs->tzd1; a.tzd2 = coeffs->tzd2;
+    a.tcx = coeffs->tcx; a.tcy = coeffs->tcy;
+    a.nx = grid->nx; a.ny = grid->ny; a.nz = grid->nz; a.h = grid->halo;
+    a.in_sy = L.in_sy; a.in_sz = L.in_sz; a.out_sy = L.out_sy; a.out_sz = L.out_sz;
+    const TileCfg cfg = tile ? tc : default_adjoint_tile(a, dtype);
+    return launch_adjoint(a, dtype, cfg, static_cast<hipStream_t>(hip_stream));
+}
+
+pw_status pw_stream_copy(const void *src, void *dst, int64_t nbytes, void *hip_stream) {
+    g_err[0] = 0;
+    if (!src || !dst) return fail(PW_ERR_INVALID_ARG, "NULL pointer");
+    if (nbytes <= 0 || nbytes % 16) return fail(PW_ERR_INVALID_ARG, "nbytes must be a positive multiple of 16");
+    if ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) % 16)
+        return fail(PW_ERR_INVALID_ARG, "pointers must be 16-byte aligned");
+    const Range a{"src", reinterpret_cast<uintptr_t>(src), reinterpret_cast<uintptr_t>(src) + uintptr_t(nbytes)};
+    const Range b{"dst", reinterpret_cast<uintptr_t>(dst), reinterpret_cast<uintptr_t>(dst) + uintptr_t(nbytes)};
+    if (overlap(a, b)) return fail(PW_ERR_INVALID_ARG, "src and dst overlap");
+    int dev = 0;
+    PW_TRY(current_device(&dev));
+    PW_TRY(check_on_device("src", src, dev));
+    PW_TRY(check_on_device("dst", dst, dev));
+    return launch_copy(src, dst, nbytes, static_cast<hipStream_t>(hip_stream));
+}
+
+}  // extern "C"

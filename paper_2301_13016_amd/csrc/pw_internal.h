@@ -1,0 +1,63 @@
+// Internal declarations shared by the host API and the kernel translation units
+// of libpwadv.  Not installed; the public interface is include/pwadv.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pwadv.h"
+
+namespace pw {
+
+// Launch shape of the forward / adjoint stencil kernels.
+//   ry     rows (y) per wavefront strip, a compile-time instantiation (1, 2, 4, 8)
+//   zlen   z-levels per work item (the vertical march length; the grid is cut
+//          into ceil(nz / zlen) independent chunks, each re-reading one plane
+//          above and below)
+//   wpb    wavefronts per workgroup (stacked in y), 1..8
+struct TileCfg {
+    int ry = 4;
+    int zlen = 16;
+    int wpb = 4;
+};
+
+// Operands of one forward launch, already validated.  Strides are in elements.
+struct FwdArgs {
+    const void *u, *v, *w;
+    void *su, *sv, *sw;
+    const void *tzc1, *tzc2, *tzd1, *tzd2;
+    double tcx, tcy;
+    int64_t nx, ny, nz;
+    int32_t h;
+    int64_t in_sy, in_sz, out_sy, out_sz;
+};
+
+struct AdjArgs {
+    const void *u, *v, *w;
+    const void *gsu, *gsv, *gsw;
+    void *gu, *gv, *gw;
+    const void *tzc1, *tzc2, *tzd1, *tzd2;
+    double tcx, tcy;
+    int64_t nx, ny, nz;
+    int32_t h;
+    int64_t in_sy, in_sz, out_sy, out_sz;
+};
+
+// Columns of output produced by one wavefront: 64 lanes load 64 consecutive
+// padded columns and the 62 inner lanes own an output each.
+constexpr int kWaveCols = 62;
+
+bool tile_supported(const TileCfg &c);
+bool adjoint_tile_supported(const TileCfg &c);
+TileCfg default_forward_tile(const FwdArgs &a, pw_dtype dt);
+TileCfg default_adjoint_tile(const AdjArgs &a, pw_dtype dt);
+
+pw_status launch_forward(const FwdArgs &a, pw_dtype dt, const TileCfg &cfg, hipStream_t s);
+pw_status launch_adjoint(const AdjArgs &a, pw_dtype dt, const TileCfg &cfg, hipStream_t s);
+pw_status launch_copy(const void *src, void *dst, int64_t nbytes, hipStream_t s);
+
+// Error plumbing (pw_api.cpp).
+pw_status fail(pw_status st, const char *fmt, ...);
+pw_status hip_fail(hipError_t e, const char *what);
+
+}  // namespace pw

@@ -11,3 +11,22 @@ if ROOT not in sys.path:
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
     config.addinivalue_line("markers", "slow: takes more than a few seconds")
+
+
+_REPORT = {}
+
+
+@pytest.fixture(scope="session")
+def report():
+    """Session-wide dict of measured figures (errors against the oracle).
+    Written as JSON to $PWADV_REPORT at the end of the session if set."""
+    return _REPORT
+
+
+def pytest_sessionfinish(session, exitstatus):
+    path = os.environ.get("PWADV_REPORT")
+    if path and _REPORT:
+        import json
+        os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
+        with open(path, "w") as fh:
+            json.dump(_REPORT, fh, indent=1, sort_keys=True)

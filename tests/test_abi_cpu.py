@@ -1,0 +1,185 @@
+"""CPU tests of the C ABI: the library loads, exports every declared entry
+point, and rejects bad arguments before touching HIP.
+
+No GPU and no compute call: the pointers passed below are fake addresses that
+the library only inspects arithmetically (null, alignment, overlap), so every
+call returns from argument validation or from the device check.
+"""
+import ctypes
+
+import pytest
+
+from paper_2301_13016_amd import binding as B
+
+
+@pytest.fixture(scope="module")
+def lib():
+    try:
+        return B.lib()
+    except B.PWLibraryMissing:
+        import __graft_entry__
+        __graft_entry__.build()
+        return B.lib()
+
+
+def test_exports_every_declared_symbol(lib):
+    declared = B.header_functions()
+    assert "pw_advect" in declared and "pw_advect_adjoint" in declared
+    missing = [n for n in declared if not hasattr(lib, n)]
+    assert missing == []
+
+
+def test_version(lib):
+    assert "libpwadv" in B.pw_version()
+
+
+A = 0x10000000   # fake, 256-byte aligned "device" addresses, never dereferenced
+MB = 1 << 20
+
+
+def _args(nx=8, ny=8, nz=8, halo=1, dtype=B.PW_F32):
+    g = B.pw_grid(nx, ny, nz, halo)
+    c = B.pw_coeffs(0.0025, 0.0025, A + 10 * MB, A + 11 * MB, A + 12 * MB, A + 13 * MB)
+    ptrs = [A + i * MB for i in range(6)]   # u v w su sv sw, 1 MiB apart
+    return g, c, ptrs
+
+
+def _call(g, layout, dtype, c, ptrs, tile=None):
+    u, v, w, su, sv, sw = ptrs
+    return B.pw_advect_ex(g, layout, dtype, u, v, w, c, su, sv, sw, tile, None)
+
+
+def _no_gpu_status():
+    # valid arguments: PW_ERR_NO_DEVICE without a GPU; on a GPU machine the
+    # fake addresses are caught by the device-pointer check instead
+    return (B.PW_ERR_NO_DEVICE, B.PW_ERR_INVALID_ARG)
+
+
+def test_valid_arguments_reach_device_check(lib):
+    g, c, p = _args()
+    assert _call(g, None, B.PW_F32, c, p) in _no_gpu_status()
+
+
+@pytest.mark.parametrize("field,value", [("nx", 0), ("ny", -1), ("nz", 0), ("halo", 0), ("halo", -2)])
+def test_bad_grid(lib, field, value):
+    g, c, p = _args()
+    setattr(g, field, value)
+    assert _call(g, None, B.PW_F32, c, p) == B.PW_ERR_INVALID_ARG
+    assert B.pw_last_error() != ""
+
+
+def test_null_grid_and_coeffs(lib):
+    g, c, p = _args()
+    u, v, w, su, sv, sw = p
+    st = lib.pw_advect(None, None, B.PW_F32, u, v, w, ctypes.byref(c), su, sv, sw, None)
+    assert st == B.PW_ERR_INVALID_ARG
+    st = lib.pw_advect(ctypes.byref(g), None, B.PW_F32, u, v, w, None, su, sv, sw, None)
+    assert st == B.PW_ERR_INVALID_ARG
+
+
+@pytest.mark.parametrize("which", range(6))
+def test_null_array(lib, which):
+    g, c, p = _args()
+    p[which] = None
+    assert _call(g, None, B.PW_F32, c, p) == B.PW_ERR_INVALID_ARG
+
+
+def test_null_coefficient_array(lib):
+    g, c, p = _args()
+    c.tzd2 = None
+    assert _call(g, None, B.PW_F32, c, p) == B.PW_ERR_INVALID_ARG
+
+
+def test_misaligned_pointer(lib):
+    g, c, p = _args()
+    p[1] += 2
+    assert _call(g, None, B.PW_F32, c, p) == B.PW_ERR_INVALID_ARG
+    # 2-byte alignment is enough for 16-bit storage
+    assert _call(g, None, B.PW_BF16, c, p) in _no_gpu_status()
+
+
+def test_bad_dtype(lib):
+    g, c, p = _args()
+    assert _call(g, None, 7, c, p) == B.PW_ERR_INVALID_ARG
+
+
+@pytest.mark.parametrize("bad", [dict(in_sy=9), dict(in_sz=10 * 10 - 1), dict(out_sy=7), dict(out_sz=63)])
+def test_strides_too_small(lib, bad):
+    g, c, p = _args()
+    L = B.pw_layout(10, 100, 8, 64)
+    for k, val in bad.items():
+        setattr(L, k, val)
+    assert _call(g, L, B.PW_F32, c, p) == B.PW_ERR_INVALID_ARG
+
+
+def test_pitched_layout_accepted(lib):
+    g, c, p = _args()
+    L = B.pw_layout(16, 16 * 12, 8, 80)
+    assert _call(g, L, B.PW_F32, c, p) in _no_gpu_status()
+
+
+def test_output_overlapping_input_rejected(lib):
+    g, c, p = _args()
+    p[3] = p[0] + 4 * 100   # su inside u's padded extent
+    assert _call(g, None, B.PW_F32, c, p) == B.PW_ERR_INVALID_ARG
+    assert "overlap" in B.pw_last_error()
+
+
+def test_outputs_overlapping_each_other_rejected(lib):
+    g, c, p = _args()
+    p[4] = p[3] + 4 * 8
+    assert _call(g, None, B.PW_F32, c, p) == B.PW_ERR_INVALID_ARG
+
+
+def test_huge_plane_unsupported(lib):
+    g, c, p = _args(nx=40000, ny=20000, nz=1)
+    p = [A + i * (1 << 34) for i in range(6)]
+    assert _call(g, None, B.PW_F32, c, p) == B.PW_ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("tile", [(3, 8, 4), (4, 0, 4), (4, 8, 0), (4, 8, 9)])
+def test_bad_tile(lib, tile):
+    g, c, p = _args()
+    assert _call(g, None, B.PW_F32, c, p, B.pw_tile(*tile)) == B.PW_ERR_INVALID_ARG
+
+
+def test_f64_rejects_eight_row_strips(lib):
+    g, c, p = _args(dtype=B.PW_F64)
+    assert _call(g, None, B.PW_F64, c, p, B.pw_tile(8, 8, 4)) == B.PW_ERR_INVALID_ARG
+    assert _call(g, None, B.PW_F64, c, p, B.pw_tile(4, 8, 4)) in _no_gpu_status()
+
+
+def test_adjoint_rejects_16bit(lib):
+    g, c, p = _args()
+    q = [A + i * MB for i in range(9)]
+    st = B.pw_advect_adjoint(g, None, B.PW_BF16, *q[:3], c, *q[3:6], *q[6:9])
+    assert st == B.PW_ERR_UNSUPPORTED
+
+
+def test_adjoint_gradient_overlap_rejected(lib):
+    g, c, p = _args()
+    q = [A + i * MB for i in range(9)]
+    q[6] = q[0]
+    st = B.pw_advect_adjoint(g, None, B.PW_F32, *q[:3], c, *q[3:6], *q[6:9])
+    assert st == B.PW_ERR_INVALID_ARG
+
+
+def test_stream_copy_validation(lib):
+    assert B.pw_stream_copy(None, A, 16) == B.PW_ERR_INVALID_ARG
+    assert B.pw_stream_copy(A, A + MB, 15) == B.PW_ERR_INVALID_ARG
+    assert B.pw_stream_copy(A + 4, A + MB, 16) == B.PW_ERR_INVALID_ARG
+    assert B.pw_stream_copy(A, A + 8, 64) == B.PW_ERR_INVALID_ARG
+    assert B.pw_stream_copy(A, A + MB, 64) in _no_gpu_status()
+
+
+def test_last_error_is_per_thread(lib):
+    import threading
+    g, c, p = _args()
+    g.halo = 0
+    assert _call(g, None, B.PW_F32, c, p) == B.PW_ERR_INVALID_ARG
+    seen = []
+    t = threading.Thread(target=lambda: seen.append(B.pw_last_error()))
+    t.start()
+    t.join()
+    assert seen == [""]
+    assert "halo" in B.pw_last_error()

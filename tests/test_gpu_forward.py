@@ -1,0 +1,194 @@
+"""GPU parity tests of the forward kernel (through the C ABI) against the FP64
+oracle on the same seeded inputs.
+
+Tolerances (error scaled by A(p), the sum of |term| magnitudes of the point,
+which bounds the rounding error of any evaluation order):
+  FP32 storage and arithmetic: 1e-6     (bound ~8 * 2^-24 = 4.8e-7)
+  FP64:                        1e-13    (bound ~8 * 2^-53)
+  BF16 / FP16 storage, against the oracle on the unrounded FP32 values: 1e-2
+      (storage rounding bound 2u: 7.8e-3 BF16, 9.8e-4 FP16), and against the
+      oracle on the rounded values: 1e-6 (arithmetic only)
+Integer winds with dyadic coefficients are exact in every dtype, so there the
+comparison is bit for bit.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import a_scaled_error, dev_grid, oracle_errors, sample_boxes, subbox_errors
+from paper_2301_13016_amd import binding as B
+from paper_2301_13016_amd import workloads as wl
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("no GPU", allow_module_level=True)
+
+
+@pytest.fixture(autouse=True)
+def _announce(request):
+    sys.__stderr__.write("\n[gpu-test] %s\n" % request.node.nodeid)
+    sys.__stderr__.flush()
+    yield
+
+
+def run(g, storage=None, tile=None, halo=1):
+    (u, v, w), c = dev_grid(g, storage=storage)
+    out = B.advect(u, v, w, c, halo=halo, tile=tile)
+    torch.cuda.synchronize()
+    return [o.cpu().numpy() for o in out]
+
+
+SHAPES = [(130, 70, 20), (64, 64, 64), (1, 1, 1), (65, 3, 1), (1, 200, 5), (200, 1, 3), (62, 8, 2), (63, 9, 17)]
+
+
+@pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "x".join(map(str, s)))
+def test_f32_matches_oracle(shape):
+    nx, ny, nz = shape
+    g = wl.make_grid(nx, ny, nz, seed=100 + nx + ny + nz)
+    errs = oracle_errors(run(g), g.u, g.v, g.w, g.coeffs)
+    for (ea, en), name in zip(errs, "su sv sw".split()):
+        assert ea <= 1e-6, (name, ea, en)
+
+
+def test_f64_config0_matches_oracle():
+    cfg = wl.C0
+    g = wl.config_grid(cfg)
+    errs = oracle_errors(run(g), g.u, g.v, g.w, g.coeffs)
+    for ea, en in errs:
+        assert ea <= 1e-13, (ea, en)
+
+
+@pytest.mark.parametrize("storage", [None, "float64", "bfloat16", "float16"])
+@pytest.mark.parametrize("shape", [(4, 4, 4), (130, 70, 20), (63, 5, 9)], ids=lambda s: "x".join(map(str, s)))
+def test_integer_inputs_bitwise_all_dtypes(storage, shape):
+    nx, ny, nz = shape
+    dt = np.float64 if storage == "float64" else np.float32
+    g = wl.integer_grid(nx, ny, nz, seed=7 + nx, dtype=dt)
+    st = None if storage in (None, "float64") else getattr(torch, storage)
+    got = run(g, storage=st)
+    ref = oracle.forward(g.u, g.v, g.w, g.coeffs)
+    for o, r in zip(got, ref):
+        assert np.array_equal(o.astype(np.float64), r)
+
+
+TILES = [(1, 1, 1), (1, 7, 4), (2, 3, 8), (4, 16, 4), (4, 5, 2), (8, 64, 4), (8, 2, 1), (2, 64, 8)]
+
+
+def test_tile_shape_invariance_bitwise():
+    g = wl.make_grid(150, 37, 23, seed=5)
+    base = run(g, tile=(4, 16, 4))
+    for t in TILES:
+        got = run(g, tile=t)
+        for a, b in zip(base, got):
+            assert np.array_equal(a, b), t
+
+
+def test_deterministic_across_runs():
+    g = wl.make_grid(200, 50, 30, seed=6)
+    a = run(g)
+    b = run(g)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("halo", [2, 3])
+def test_wider_halo(halo):
+    g = wl.make_grid(70, 20, 9, seed=8, halo=halo)
+    errs = oracle_errors(run(g, halo=halo), g.u, g.v, g.w, g.coeffs, halo=halo)
+    assert max(e for e, _ in errs) <= 1e-6
+
+
+def test_pitched_strides_and_untouched_inputs():
+    """Inputs and outputs as views into larger buffers: padded rows pitched to
+    a multiple of 64 elements, outputs with their own pitch; inputs and the
+    gaps of the output buffers must come back untouched."""
+    g = wl.make_grid(100, 30, 12, seed=9)
+    pz, py, px = g.u.shape
+    (u, v, w), c = dev_grid(g)
+    big = [torch.full((pz, py, 128), 7.0, device="cuda") for _ in range(3)]
+    for bb, x in zip(big, (u, v, w)):
+        bb[:, :, :px] = x
+    vin = [bb[:, :, :px] for bb in big]
+    obig = [torch.full((12, 31, 112), -3.0, device="cuda") for _ in range(3)]
+    outs = tuple(ob[:, :30, :100] for ob in obig)
+    before = [bb.clone() for bb in big]
+    B.advect(*vin, c, out=outs)
+    torch.cuda.synchronize()
+    for bb, b0 in zip(big, before):
+        assert torch.equal(bb, b0)
+    for ob in obig:
+        assert torch.all(ob[:, 30:, :] == -3.0) and torch.all(ob[:, :, 100:] == -3.0)
+    errs = oracle_errors([o.cpu().numpy() for o in outs], g.u, g.v, g.w, g.coeffs)
+    assert max(e for e, _ in errs) <= 1e-6
+
+
+@pytest.mark.parametrize("storage", ["bfloat16", "float16"])
+def test_low_precision_storage_errors(storage):
+    g = wl.make_grid(190, 40, 16, seed=10)
+    st = getattr(torch, storage)
+    got = run(g, storage=st)
+    # total error against the unrounded FP32 values
+    errs = oracle_errors(got, g.u, g.v, g.w, g.coeffs)
+    bound = 1e-2 if storage == "bfloat16" else 2e-3
+    for ea, _ in errs:
+        assert ea <= bound, (storage, ea)
+    # arithmetic error against the rounded values actually stored
+    (u, v, w), _ = dev_grid(g, storage=st)
+    q = [x.float().cpu().numpy() for x in (u, v, w)]
+    errs_q = oracle_errors(got, *q, g.coeffs)
+    for ea, _ in errs_q:
+        assert ea <= 1e-6, (storage, ea)
+
+
+@pytest.fixture(scope="module")
+def grid_1024():
+    return wl.config_grid(wl.C2)
+
+
+@pytest.mark.parametrize("storage", ["float32", "bfloat16", "float16"])
+def test_precision_grid_sampled_parity(grid_1024, storage, report):
+    """The 1024 x 1024 x 256 grid in each storage type (the launch the
+    benchmark times), checked on sampled sub-boxes against the FP64 oracle on
+    the unrounded FP32 values; the worst A-scaled and normwise errors per
+    field go into the report."""
+    g = grid_1024
+    st = getattr(torch, storage)
+    (u, v, w), c = dev_grid(g, storage=None if storage == "float32" else st)
+    out = B.advect(u, v, w, c)
+    torch.cuda.synchronize()
+    boxes = sample_boxes(g.nx, g.ny, g.nz, n_random=12, seed=2)
+    worst = subbox_errors(out, g, boxes)
+    report.setdefault("precision_1024x1024x256", {})[storage] = dict(
+        zip(("su", "sv", "sw"), worst), boxes=len(boxes))
+    bound = {"float32": 1e-6, "bfloat16": 1e-2, "float16": 2e-3}[storage]
+    assert max(worst) <= bound, worst
+
+
+def test_headline_grid_sampled_parity(report):
+    """The 512 x 512 x 64 FP32 grid in the launch shape the benchmark times,
+    checked on corner, edge and random sub-boxes against the oracle."""
+    cfg = wl.C1
+    g = wl.config_grid(cfg)
+    (u, v, w), c = dev_grid(g)
+    out = B.advect(u, v, w, c)
+    torch.cuda.synchronize()
+    boxes = sample_boxes(cfg["nx"], cfg["ny"], cfg["nz"], n_random=10)
+    worst = subbox_errors(out, g, boxes)
+    report["fwd_f32_512x512x64"] = dict(zip(("su", "sv", "sw"), worst), boxes=len(boxes))
+    assert max(worst) <= 1e-6, worst
+    # every output finite and written (the kernel covers the whole interior)
+    for o in out:
+        assert torch.isfinite(o).all()
+
+
+def test_host_pointer_rejected():
+    g = wl.make_grid(8, 8, 8, seed=11)
+    (u, v, w), c = dev_grid(g)
+    host_out = [torch.empty((8, 8, 8)) for _ in range(3)]
+    with pytest.raises(B.PWError) as ei:
+        B.advect(u, v, w, c, out=host_out)
+    assert ei.value.status == B.PW_ERR_INVALID_ARG

@@ -110,12 +110,19 @@ pw_status pw_advect(const pw_grid *grid, const pw_layout *layout, pw_dtype in_dt
                     void *hip_stream);
 
 /* Launch shape of the stencil kernels (a performance choice; results are
- * bit-identical across shapes).  A wavefront owns a strip of 62 x
- * rows_per_strip interior cells and marches through zlen levels;
- * waves_per_group strips are stacked in y per workgroup.
- *   rows_per_strip in {1, 2, 4, 8} (PW_F64: {1, 2, 4}), zlen >= 1,
- *   waves_per_group in 1..8.  Other values give PW_ERR_INVALID_ARG. */
+ * bit-identical across shapes).  A wavefront of 64 lanes owns a strip of
+ * 64*cols_per_lane x rows_per_strip interior cells and marches through zlen
+ * levels; waves_per_group strips are stacked in y per workgroup.
+ * Forward (pw_advect_ex):
+ *   cols_per_lane 1 or 2: rows_per_strip in {1, 2, 4};
+ *   cols_per_lane 4 (not PW_F64): rows_per_strip in {1, 2};
+ *   PW_F64: cols_per_lane in {1, 2}, rows_per_strip in {1, 2}.
+ * Adjoint (pw_advect_adjoint_ex): cols_per_lane 1 (strips of 62 padded
+ *   columns), rows_per_strip in {1, 2, 4}.
+ * Always zlen >= 1 and waves_per_group in 1..8.  Other values give
+ * PW_ERR_INVALID_ARG. */
 typedef struct {
+    int32_t cols_per_lane;
     int32_t rows_per_strip;
     int32_t zlen;
     int32_t waves_per_group;
@@ -145,9 +152,8 @@ pw_status pw_advect_adjoint(const pw_grid *grid, const pw_layout *layout, pw_dty
                             void *gu, void *gv, void *gw,
                             void *hip_stream);
 
-/* pw_advect_adjoint with an explicit launch shape (see pw_tile; the adjoint
- * kernel supports rows_per_strip in {1, 2, 4}); tile == NULL as in
- * pw_advect_adjoint.  Results are bit-identical across shapes. */
+/* pw_advect_adjoint with an explicit launch shape (see pw_tile); tile ==
+ * NULL as in pw_advect_adjoint.  Results are bit-identical across shapes. */
 pw_status pw_advect_adjoint_ex(const pw_grid *grid, const pw_layout *layout, pw_dtype dtype,
                                const void *u, const void *v, const void *w,
                                const pw_coeffs *coeffs,

@@ -55,8 +55,8 @@ class pw_coeffs(ctypes.Structure):
 
 
 class pw_tile(ctypes.Structure):
-    _fields_ = [("rows_per_strip", ctypes.c_int32), ("zlen", ctypes.c_int32),
-                ("waves_per_group", ctypes.c_int32)]
+    _fields_ = [("cols_per_lane", ctypes.c_int32), ("rows_per_strip", ctypes.c_int32),
+                ("zlen", ctypes.c_int32), ("waves_per_group", ctypes.c_int32)]
 
 
 _P = ctypes.c_void_p

@@ -337,18 +337,20 @@ pw_status launch_adj_dt(const AdjArgs &g, const TileCfg &cfg, hipStream_t s) {
 }  // namespace
 
 bool adjoint_tile_supported(const TileCfg &c) {
-    return (c.ry == 1 || c.ry == 2 || c.ry == 4) && c.zlen >= 1 && c.wpb >= 1 && c.wpb <= 8;
+    return c.px == 1 && (c.ry == 1 || c.ry == 2 || c.ry == 4) && c.zlen >= 1 && c.wpb >= 1 && c.wpb <= 8;
 }
 
 TileCfg default_adjoint_tile(const AdjArgs &a, pw_dtype dt) {
+    // Measured on MI355X (256x256x128 FP32): two-row strips, one wavefront
+    // per workgroup, about 2048 wavefronts in flight.
     TileCfg c;
+    c.px = 1;
     c.ry = (dt == PW_F64) ? 1 : 2;
-    c.wpb = 4;
+    c.wpb = 1;
     const int64_t px = a.nx + 2 * a.h, py = a.ny + 2 * a.h, pz = a.nz + 2 * a.h;
     const int64_t strips = ((px + kWaveCols - 1) / kWaveCols) * ((py + c.ry - 1) / c.ry);
-    const int64_t want = 256 * 24;
-    int64_t chunks = (want + strips - 1) / strips;
-    if (chunks < 1) chunks = 1;
+    int64_t chunks = (2048 + strips - 1) / strips;
+    if (chunks < 2) chunks = 2;
     int64_t zl = (pz + chunks - 1) / chunks;
     if (zl < 8) zl = 8;
     if (zl > pz) zl = pz;

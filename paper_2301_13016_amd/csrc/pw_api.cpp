@@ -127,6 +127,15 @@ pw_status check_on_device(const char *name, const void *p, int dev) {
     return PW_OK;
 }
 
+TileCfg to_cfg(const pw_tile &t) {
+    TileCfg c;
+    c.px = t.cols_per_lane;
+    c.ry = t.rows_per_strip;
+    c.zlen = t.zlen;
+    c.wpb = t.waves_per_group;
+    return c;
+}
+
 #define PW_TRY(x)                            \
     do {                                     \
         pw_status st_ = (x);                 \
@@ -173,14 +182,9 @@ pw_status pw_advect_ex(const pw_grid *grid, const pw_layout *layout, pw_dtype in
         for (const Range &o2 : rout)
             if (&o != &o2 && overlap(o, o2)) return fail(PW_ERR_INVALID_ARG, "outputs %s and %s overlap", o.name, o2.name);
     }
-    if (tile) {
-        TileCfg t;
-        t.ry = tile->rows_per_strip;
-        t.zlen = tile->zlen;
-        t.wpb = tile->waves_per_group;
-        if (!tile_supported(t) || (in_dtype == PW_F64 && t.ry > 4))
-            return fail(PW_ERR_INVALID_ARG, "unsupported tile rows=%d zlen=%d waves=%d", t.ry, t.zlen, t.wpb);
-    }
+    if (tile && !tile_supported(to_cfg(*tile), in_dtype))
+        return fail(PW_ERR_INVALID_ARG, "unsupported forward tile cols=%d rows=%d zlen=%d waves=%d",
+                    tile->cols_per_lane, tile->rows_per_strip, tile->zlen, tile->waves_per_group);
     int dev = 0;
     PW_TRY(current_device(&dev));
     for (int i = 0; i < 10; ++i) PW_TRY(check_on_device(names[i], ptrs[i], dev));
@@ -192,12 +196,7 @@ pw_status pw_advect_ex(const pw_grid *grid, const pw_layout *layout, pw_dtype in
     a.tcx = coeffs->tcx; a.tcy = coeffs->tcy;
     a.nx = grid->nx; a.ny = grid->ny; a.nz = grid->nz; a.h = grid->halo;
     a.in_sy = L.in_sy; a.in_sz = L.in_sz; a.out_sy = L.out_sy; a.out_sz = L.out_sz;
-    TileCfg cfg = default_forward_tile(a, in_dtype);
-    if (tile) {   // validated above
-        cfg.ry = tile->rows_per_strip;
-        cfg.zlen = tile->zlen;
-        cfg.wpb = tile->waves_per_group;
-    }
+    const TileCfg cfg = tile ? to_cfg(*tile) : default_forward_tile(a, in_dtype);
     return launch_forward(a, in_dtype, cfg, static_cast<hipStream_t>(hip_stream));
 }
 
@@ -237,14 +236,9 @@ pw_status pw_advect_adjoint_ex(const pw_grid *grid, const pw_layout *layout, pw_
         for (const Range &o2 : rout)
             if (&o != &o2 && overlap(o, o2)) return fail(PW_ERR_INVALID_ARG, "gradients %s and %s overlap", o.name, o2.name);
     }
-    TileCfg tc;
-    if (tile) {
-        tc.ry = tile->rows_per_strip;
-        tc.zlen = tile->zlen;
-        tc.wpb = tile->waves_per_group;
-        if (!adjoint_tile_supported(tc))
-            return fail(PW_ERR_INVALID_ARG, "unsupported adjoint tile rows=%d zlen=%d waves=%d", tc.ry, tc.zlen, tc.wpb);
-    }
+    if (tile && !adjoint_tile_supported(to_cfg(*tile)))
+        return fail(PW_ERR_INVALID_ARG, "unsupported adjoint tile cols=%d rows=%d zlen=%d waves=%d",
+                    tile->cols_per_lane, tile->rows_per_strip, tile->zlen, tile->waves_per_group);
     int dev = 0;
     PW_TRY(current_device(&dev));
     for (int i = 0; i < 13; ++i) PW_TRY(check_on_device(names[i], ptrs[i], dev));
@@ -257,7 +251,7 @@ pw_status pw_advect_adjoint_ex(const pw_grid *grid, const pw_layout *layout, pw_
     a.tcx = coeffs->tcx; a.tcy = coeffs->tcy;
     a.nx = grid->nx; a.ny = grid->ny; a.nz = grid->nz; a.h = grid->halo;
     a.in_sy = L.in_sy; a.in_sz = L.in_sz; a.out_sy = L.out_sy; a.out_sz = L.out_sz;
-    const TileCfg cfg = tile ? tc : default_adjoint_tile(a, dtype);
+    const TileCfg cfg = tile ? to_cfg(*tile) : default_adjoint_tile(a, dtype);
     return launch_adjoint(a, dtype, cfg, static_cast<hipStream_t>(hip_stream));
 }
 

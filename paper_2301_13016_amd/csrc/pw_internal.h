@@ -10,13 +10,15 @@
 namespace pw {
 
 // Launch shape of the forward / adjoint stencil kernels.
-//   ry     rows (y) per wavefront strip, a compile-time instantiation (1, 2, 4, 8)
+//   px     consecutive x columns per lane (forward: 1, 2, 4; adjoint: 1)
+//   ry     rows (y) per wavefront strip, a compile-time instantiation
 //   zlen   z-levels per work item (the vertical march length; the grid is cut
 //          into ceil(nz / zlen) independent chunks, each re-reading one plane
 //          above and below)
 //   wpb    wavefronts per workgroup (stacked in y), 1..8
 struct TileCfg {
-    int ry = 4;
+    int px = 1;
+    int ry = 2;
     int zlen = 16;
     int wpb = 4;
 };
@@ -43,11 +45,11 @@ struct AdjArgs {
     int64_t in_sy, in_sz, out_sy, out_sz;
 };
 
-// Columns of output produced by one wavefront: 64 lanes load 64 consecutive
-// padded columns and the 62 inner lanes own an output each.
+// Columns of gradient produced by one adjoint wavefront: 64 lanes load 64
+// consecutive padded columns and the 62 inner lanes own an output each.
 constexpr int kWaveCols = 62;
 
-bool tile_supported(const TileCfg &c);
+bool tile_supported(const TileCfg &c, pw_dtype dt);
 bool adjoint_tile_supported(const TileCfg &c);
 TileCfg default_forward_tile(const FwdArgs &a, pw_dtype dt);
 TileCfg default_adjoint_tile(const AdjArgs &a, pw_dtype dt);

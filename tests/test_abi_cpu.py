@@ -137,16 +137,32 @@ def test_huge_plane_unsupported(lib):
     assert _call(g, None, B.PW_F32, c, p) == B.PW_ERR_UNSUPPORTED
 
 
-@pytest.mark.parametrize("tile", [(3, 8, 4), (4, 0, 4), (4, 8, 0), (4, 8, 9)])
+@pytest.mark.parametrize("tile", [(1, 3, 8, 4), (1, 4, 0, 4), (1, 4, 8, 0), (1, 4, 8, 9), (3, 1, 8, 4),
+                                  (4, 4, 8, 4), (8, 1, 8, 1), (0, 1, 8, 1)])
 def test_bad_tile(lib, tile):
     g, c, p = _args()
     assert _call(g, None, B.PW_F32, c, p, B.pw_tile(*tile)) == B.PW_ERR_INVALID_ARG
 
 
-def test_f64_rejects_eight_row_strips(lib):
+@pytest.mark.parametrize("tile", [(1, 1, 1, 1), (1, 4, 8, 8), (2, 4, 3, 4), (4, 1, 16, 1), (4, 2, 64, 2)])
+def test_good_tile(lib, tile):
+    g, c, p = _args()
+    assert _call(g, None, B.PW_F32, c, p, B.pw_tile(*tile)) in _no_gpu_status()
+
+
+def test_f64_tile_limits(lib):
     g, c, p = _args(dtype=B.PW_F64)
-    assert _call(g, None, B.PW_F64, c, p, B.pw_tile(8, 8, 4)) == B.PW_ERR_INVALID_ARG
-    assert _call(g, None, B.PW_F64, c, p, B.pw_tile(4, 8, 4)) in _no_gpu_status()
+    for bad in [(4, 1, 8, 4), (1, 4, 8, 4)]:
+        assert _call(g, None, B.PW_F64, c, p, B.pw_tile(*bad)) == B.PW_ERR_INVALID_ARG
+    assert _call(g, None, B.PW_F64, c, p, B.pw_tile(2, 2, 8, 4)) in _no_gpu_status()
+
+
+def test_adjoint_tile_limits(lib):
+    g, c, p = _args()
+    q = [A + i * MB for i in range(9)]
+    for bad, ok in [((2, 1, 8, 4), False), ((1, 8, 8, 4), False), ((1, 4, 8, 4), True)]:
+        st = B.pw_advect_adjoint_ex(g, None, B.PW_F32, *q[:3], c, *q[3:6], *q[6:9], B.pw_tile(*bad))
+        assert (st in _no_gpu_status()) if ok else st == B.PW_ERR_INVALID_ARG
 
 
 def test_adjoint_rejects_16bit(lib):

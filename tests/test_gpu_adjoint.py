@@ -77,8 +77,8 @@ def test_integer_adjoint_bitwise(dtype):
 def test_adjoint_tile_invariance_bitwise():
     g = wl.make_grid(150, 37, 23, seed=203)
     r = wl.cotangents(150, 37, 23, seed=303)
-    base = gpu_adjoint(g, r, tile=(2, 16, 4))
-    for t in [(1, 1, 1), (1, 9, 4), (2, 5, 8), (4, 64, 4), (4, 3, 2)]:
+    base = gpu_adjoint(g, r, tile=(1, 2, 16, 4))
+    for t in [(1, 1, 1, 1), (1, 1, 9, 4), (1, 2, 5, 8), (1, 4, 64, 4), (1, 4, 3, 2)]:
         got = gpu_adjoint(g, r, tile=t)
         for a, b in zip(base, got):
             assert np.array_equal(a, b), t

@@ -75,16 +75,29 @@ def test_integer_inputs_bitwise_all_dtypes(storage, shape):
         assert np.array_equal(o.astype(np.float64), r)
 
 
-TILES = [(1, 1, 1), (1, 7, 4), (2, 3, 8), (4, 16, 4), (4, 5, 2), (8, 64, 4), (8, 2, 1), (2, 64, 8)]
+TILES = [(1, 1, 1, 1), (1, 1, 7, 4), (1, 2, 3, 8), (1, 4, 16, 4), (2, 4, 5, 2), (2, 1, 64, 4), (2, 2, 2, 1),
+         (4, 1, 64, 8), (4, 2, 5, 1), (4, 1, 1, 4), (4, 2, 16, 2)]
 
 
-def test_tile_shape_invariance_bitwise():
-    g = wl.make_grid(150, 37, 23, seed=5)
-    base = run(g, tile=(4, 16, 4))
+@pytest.mark.parametrize("shape", [(150, 37, 23), (300, 9, 7), (259, 5, 6), (513, 3, 4)],
+                         ids=lambda s: "x".join(map(str, s)))
+def test_tile_shape_invariance_bitwise(shape):
+    g = wl.make_grid(*shape, seed=5)
+    base = run(g, tile=(1, 4, 16, 4))
     for t in TILES:
         got = run(g, tile=t)
         for a, b in zip(base, got):
             assert np.array_equal(a, b), t
+
+
+@pytest.mark.parametrize("tile", [(1, 2, 16, 4), (2, 4, 16, 4), (4, 2, 16, 1)])
+@pytest.mark.parametrize("shape", [(1, 1, 1), (3, 2, 2), (255, 4, 3), (257, 3, 2), (130, 70, 20)],
+                         ids=lambda s: "x".join(map(str, s)))
+def test_f32_every_tile_kind_matches_oracle(shape, tile):
+    nx, ny, nz = shape
+    g = wl.make_grid(nx, ny, nz, seed=400 + nx)
+    errs = oracle_errors(run(g, tile=tile), g.u, g.v, g.w, g.coeffs)
+    assert max(e for e, _ in errs) <= 1e-6, (tile, errs)
 
 
 def test_deterministic_across_runs():

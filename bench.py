@@ -6,19 +6,25 @@ differences, reduction, store: the whole hot path) over the FP32 grid
 HBM.  K steps are timed between two device synchronisations; consecutive steps
 use different buffer sets (4 x 410 MB) so the 256 MB MALL cannot serve a
 repeat.  The dominant kernel's average duration comes from HIP events around
-each launch on the launch stream.
+each launch on the launch stream.  The library's autotuner picks the launch
+shape before timing (outside the timed region).
 
-Also measured in the same run:
-  * BF16 / FP16 storage vs FP32 on 1024 x 1024 x 256 (268 M points) ("forms");
-    their errors against the FP64 oracle are measured by the GPU test suite;
+Also measured in the same run ("forms"):
+  * BF16 / FP16 storage vs FP32 on 1024 x 1024 x 256 (268 M points);
+  * the adjoint (J^T r) vs the forward on 256 x 256 x 128 FP32;
+  * 64 uneven subdomains (FP32) in one persistent launch replayed from a HIP
+    graph vs 64 plain launches;
+  * a plain copy kernel (reachable-bandwidth reference);
   * the FP64 oracle on the host cores ("cpu_baseline", the only use of the
     oracle here).
+Their errors against the oracle are measured by the GPU test suite.
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
 from __future__ import annotations
 
 import argparse
+import ctypes
 import json
 import os
 import sys
@@ -43,11 +49,17 @@ def algo_bytes(nx, ny, nz, halo, in_bytes, out_bytes=4):
     return 3 * padded * in_bytes + 3 * nx * ny * nz * out_bytes
 
 
+def adjoint_bytes(nx, ny, nz, halo, es=4):
+    """Algorithmic bytes of one adjoint launch: u, v, w and the three
+    cotangents read once, the three padded gradients written once."""
+    padded = (nx + 2 * halo) * (ny + 2 * halo) * (nz + 2 * halo)
+    return 3 * padded * es + 3 * nx * ny * nz * es + 3 * padded * es
+
+
 def time_launches(torch, launch, nsets, steps, warmup, stream):
     """Run ``launch(i)`` for warmup + steps iterations (i = buffer set), time
     the steps region with a wall clock between synchronisations and each
-    launch with HIP events on ``stream``.  Returns (ms_per_step, mean kernel ms,
-    list of per-launch ms)."""
+    launch with HIP events on ``stream``.  Returns (ms_per_step, mean event ms)."""
     for i in range(warmup):
         launch(i % nsets)
     torch.cuda.synchronize()
@@ -60,7 +72,29 @@ def time_launches(torch, launch, nsets, steps, warmup, stream):
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) * 1e3
     per = [a.elapsed_time(b) for a, b in ev]
-    return wall / steps, float(np.mean(per)), per
+    return wall / steps, float(np.mean(per))
+
+
+def prebuilt_forward(B, ins, outs, coeffs, stream, tile=None):
+    """ctypes arguments of one pw_advect_ex call, built once (the timed loop
+    then only crosses the C ABI)."""
+    from paper_2301_13016_amd.binding import _dtype_code, _grid_from, _layout_from
+    u, v, w = ins
+    su, sv, sw = outs
+    keep = (_grid_from(u, 1), _layout_from(u, su), coeffs.c_struct(),
+            B.pw_tile(*tile) if tile else None)
+    args = (ctypes.byref(keep[0]), ctypes.byref(keep[1]), _dtype_code(u),
+            u.data_ptr(), v.data_ptr(), w.data_ptr(), ctypes.byref(keep[2]),
+            su.data_ptr(), sv.data_ptr(), sw.data_ptr(),
+            ctypes.byref(keep[3]) if tile else None, ctypes.c_void_p(stream.cuda_stream))
+    fn = B.lib().pw_advect_ex
+
+    def call():
+        st = fn(*args)
+        if st != B.PW_OK:
+            raise B.PWError(st, B.pw_last_error(), "pw_advect_ex")
+    call.keep = keep
+    return call
 
 
 def main():
@@ -90,21 +124,21 @@ def main():
     # ------------------------------------------------------------ headline: c1 FP32
     cfg = wl.C1
     nx, ny, nz, h = cfg["nx"], cfg["ny"], cfg["nz"], 1
+    tiles = {"c1_fp32": B.tune(nx, ny, nz, torch.float32, flags=B.PW_TUNE_FORWARD)[0]}
+    log("tuned c1 tile:", tiles["c1_fp32"])
     g = wl.config_grid(cfg)
     coeffs = B.Coeffs.from_host(g.coeffs, device=dev)
     nsets = 4
     host = [torch.from_numpy(x) for x in (g.u, g.v, g.w)]
-    sets = []
+    calls = []
+    keep = []
     for _ in range(nsets):
         ins = [x.to(dev) for x in host]
         outs = tuple(torch.empty((nz, ny, nx), device=dev) for _ in range(3))
-        sets.append((ins, outs))
+        keep.append((ins, outs))
+        calls.append(prebuilt_forward(B, ins, outs, coeffs, stream))
 
-    def launch(i):
-        ins, outs = sets[i]
-        B.advect(*ins, coeffs, out=outs)
-
-    ms_step, k_ms, per = time_launches(torch, launch, nsets, args.steps, args.warmup, stream)
+    ms_step, k_ms = time_launches(torch, lambda i: calls[i](), nsets, args.steps, args.warmup, stream)
     pts = nx * ny * nz
     gpts = pts / (ms_step * 1e-3) / 1e9
     nbytes = algo_bytes(nx, ny, nz, h, 4)
@@ -114,13 +148,12 @@ def main():
 
     # plain copy kernel of the same byte count (reachable-bandwidth reference)
     cbytes = (nbytes // 2) // 16 * 16
-    src = torch.empty(cbytes // 4, device=dev)
-    dst = [torch.empty_like(src) for _ in range(4)]
-    srcs = [src] + [torch.empty_like(src) for _ in range(3)]
-    _, copy_ms, _ = time_launches(torch, lambda i: B.stream_copy(srcs[i], dst[i]), 4, 200, 10, stream)
+    srcs = [torch.empty(cbytes // 4, device=dev) for _ in range(4)]
+    dsts = [torch.empty_like(s) for s in srcs]
+    _, copy_ms = time_launches(torch, lambda i: B.stream_copy(srcs[i], dsts[i]), 4, 200, 10, stream)
     copy_gbs = 2 * cbytes / (copy_ms * 1e-3) / 1e9
     log("copy %d MB each way: %.4f ms, %.0f GB/s" % (cbytes >> 20, copy_ms, copy_gbs))
-    del sets, src, dst, srcs
+    del keep, calls, srcs, dsts
     torch.cuda.empty_cache()
 
     # ------------------------------------------------------------ CPU baseline (oracle)
@@ -136,30 +169,100 @@ def main():
     log("oracle on %d host threads: %.3f Gpt/s (%d reps of the full grid)" % (ncpu, cpu_gpts, reps))
     del u64, v64, w64
 
-    # ------------------------------------------------------------ precision form: c2
     forms = {}
+    # ------------------------------------------------------------ precision form: c2
     c2 = wl.C2
     n2 = (c2["nx"], c2["ny"], c2["nz"])
     log("generating the 1024x1024x256 grid ...")
     g2 = wl.config_grid(c2)
     co2 = B.Coeffs.from_host(g2.coeffs, device=dev)
     f32 = [torch.from_numpy(x).to(dev) for x in (g2.u, g2.v, g2.w)]
+    del g2
     outs2 = tuple(torch.empty((n2[2], n2[1], n2[0]), device=dev) for _ in range(3))
     pts2 = n2[0] * n2[1] * n2[2]
     res2 = {}
     for name, dt in (("fp32", torch.float32), ("bf16", torch.bfloat16), ("fp16", torch.float16)):
+        tiles["c2_" + name] = B.tune(*n2, dt, flags=B.PW_TUNE_FORWARD)[0]
         ins = f32 if dt == torch.float32 else [x.to(dt) for x in f32]
-        ms2, kms2, _ = time_launches(torch, lambda i: B.advect(*ins, co2, out=outs2), 1, 30, 3, stream)
+        call = prebuilt_forward(B, ins, outs2, co2, stream)
+        _, kms2 = time_launches(torch, lambda i: call(), 1, 30, 3, stream)
         eb = 2 if dt != torch.float32 else 4
-        res2[name] = dict(gpts=pts2 / (kms2 * 1e-3) / 1e9, kernel_ms=kms2,
-                          hbm_gbs=algo_bytes(*n2, 1, eb) / (kms2 * 1e-3) / 1e9)
-        log("c2 %s: kernel %.4f ms, %.1f Gpt/s" % (name, kms2, res2[name]["gpts"]))
+        res2[name] = dict(gpts=round(pts2 / (kms2 * 1e-3) / 1e9, 2), kernel_ms=round(kms2, 4),
+                          hbm_gbs=round(algo_bytes(*n2, 1, eb) / (kms2 * 1e-3) / 1e9, 1),
+                          tile=tiles["c2_" + name])
+        log("c2 %s: kernel %.4f ms, %.1f Gpt/s (tile %s)" % (name, kms2, res2[name]["gpts"], tiles["c2_" + name]))
         if dt != torch.float32:
             del ins
     for name in ("bf16", "fp16"):
-        res2[name]["speed_vs_fp32"] = res2["fp32"]["kernel_ms"] / res2[name]["kernel_ms"]
+        res2[name]["speed_vs_fp32"] = round(res2["fp32"]["kernel_ms"] / res2[name]["kernel_ms"], 3)
     forms["precision_1024x1024x256"] = res2
     del f32, outs2
+    torch.cuda.empty_cache()
+
+    # ------------------------------------------------------------ differentiation form: c4
+    c4 = wl.C4
+    n4 = (c4["nx"], c4["ny"], c4["nz"])
+    g4 = wl.config_grid(c4)
+    fwd4, adj4 = B.tune(*n4, torch.float32)
+    co4 = B.Coeffs.from_host(g4.coeffs, device=dev)
+    ins4 = [torch.from_numpy(x).to(dev) for x in (g4.u, g4.v, g4.w)]
+    cot4 = [torch.from_numpy(x).to(dev) for x in wl.cotangents(*n4, c4["cot_seed"])]
+    o4 = tuple(torch.empty((n4[2], n4[1], n4[0]), device=dev) for _ in range(3))
+    gr4 = tuple(torch.empty_like(x) for x in ins4)
+    fcall = prebuilt_forward(B, ins4, o4, co4, stream)
+    _, fms = time_launches(torch, lambda i: fcall(), 1, 100, 5, stream)
+    _, ams = time_launches(torch, lambda i: B.advect_adjoint(*ins4, co4, *cot4, out=gr4), 1, 100, 5, stream)
+    pts4 = n4[0] * n4[1] * n4[2]
+    forms["adjoint_256x256x128"] = dict(
+        forward_ms=round(fms, 4), adjoint_ms=round(ams, 4), adjoint_over_forward=round(ams / fms, 3),
+        ideal_ratio_from_bytes=round(adjoint_bytes(*n4, 1) / algo_bytes(*n4, 1, 4), 3),
+        adjoint_gpts=round(pts4 / (ams * 1e-3) / 1e9, 2),
+        adjoint_hbm_gbs=round(adjoint_bytes(*n4, 1) / (ams * 1e-3) / 1e9, 1), tiles=[fwd4, adj4])
+    log("c4: forward %.4f ms, adjoint %.4f ms, ratio %.3f" % (fms, ams, ams / fms))
+    del ins4, cot4, o4, gr4
+    torch.cuda.empty_cache()
+
+    # ------------------------------------------------------------ batched form: c3
+    log("generating the 64 subdomains ...")
+    grids3 = wl.batch_grids()
+    subs, plain = [], []
+    for gg in grids3:
+        ins = [torch.from_numpy(x).to(dev) for x in (gg.u, gg.v, gg.w)]
+        cc = B.Coeffs.from_host(gg.coeffs, device=dev)
+        outs = tuple(torch.empty((gg.nz, gg.ny, gg.nx), device=dev) for _ in range(3))
+        subs.append((*ins, cc, outs))
+        plain.append(prebuilt_forward(B, ins, outs, cc, stream))
+    pts3 = sum(gg.points for gg in grids3)
+    bytes3 = sum(algo_bytes(gg.nx, gg.ny, gg.nz, 1, 4) for gg in grids3)
+    del grids3
+    batch = B.Batch(subs)
+    btile = batch.tune()
+    gstream = torch.cuda.Stream()
+    batch.capture(gstream)
+    torch.cuda.synchronize()
+
+    def all_plain(i):
+        for c in plain:
+            c()
+    pms_step, _ = time_launches(torch, all_plain, 1, 20, 2, stream)
+    gev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(20)]
+    for _ in range(2):
+        batch.replay(gstream)
+    torch.cuda.synchronize()
+    for a_, b_ in gev:
+        a_.record(gstream)
+        batch.replay(gstream)
+        b_.record(gstream)
+    torch.cuda.synchronize()
+    bms = float(np.mean([a_.elapsed_time(b_) for a_, b_ in gev]))
+    tile3, items3, groups3 = batch.info()
+    forms["batched_64_subdomains"] = dict(
+        points=pts3, graph_replay_ms=round(bms, 4), plain_64_launches_ms=round(pms_step, 4),
+        speedup_vs_plain=round(pms_step / bms, 3), gpts=round(pts3 / (bms * 1e-3) / 1e9, 2),
+        hbm_gbs=round(bytes3 / (bms * 1e-3) / 1e9, 1), tile=tile3, work_items=items3, workgroups=groups3)
+    log("c3: graph replay %.4f ms vs 64 plain launches %.4f ms (tile %s)" % (bms, pms_step, btile))
+    batch.close()
+    del subs, plain
 
     line = {
         "metric": "PW advection Gpoints/s + % HBM roofline; FP32 vs BF16-store vs adjoint",
@@ -175,7 +278,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic (seeded uniform winds in [-10,10], per-level coefficients)",
         "config": {"workload": cfg["name"], "nx": nx, "ny": ny, "nz": nz, "halo": h,
-                   "points": pts, "buffer_sets": nsets},
+                   "points": pts, "buffer_sets": nsets, "tile": tiles["c1_fp32"]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                      "algorithmic_bytes_per_launch": nbytes, "kernel_ms": round(k_ms, 6),

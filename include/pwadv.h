@@ -161,6 +161,79 @@ pw_status pw_advect_adjoint_ex(const pw_grid *grid, const pw_layout *layout, pw_
                                void *gu, void *gv, void *gw,
                                const pw_tile *tile, void *hip_stream);
 
+/* Autotuner for single-grid launches.  Times candidate launch shapes of the
+ * forward kernel (flags & PW_TUNE_FORWARD) and, for PW_F32 / PW_F64, of the
+ * adjoint kernel (flags & PW_TUNE_ADJOINT; flags == 0 means both) on scratch
+ * grids of this extent (allocated and freed here, contents zero), and
+ * records the fastest per shape class -- dtype and the power-of-two ceilings
+ * of nx, ny, nz -- in a process-wide table that pw_advect and
+ * pw_advect_adjoint consult when called without a tile.  The z-cut is kept
+ * as a number of chunks, so an entry serves every nz of its class.  If the
+ * environment variable PWADV_TUNE_CACHE names a file, the table is read from
+ * it on first use (unreadable or malformed lines are ignored) and rewritten
+ * after each pw_tune.  fwd_best / adj_best (may be NULL) receive the chosen
+ * shapes.  Allocates device memory; synchronises its own stream. */
+#define PW_TUNE_FORWARD 1
+#define PW_TUNE_ADJOINT 2
+pw_status pw_tune(const pw_grid *grid, pw_dtype dtype, int32_t flags, pw_tile *fwd_best, pw_tile *adj_best);
+
+/* Empties the process-wide tuning table (the cache file is left as is). */
+pw_status pw_tune_reset(void);
+
+/* ------------------------------------------------------------------------
+ * Batched form: many independent subdomains of their own shapes processed by
+ * one persistent launch (the paper's multi-compute-unit design decomposes the
+ * grid into independent parts, one per compute unit, Sec. 5; here the parts
+ * are MONC-rank-sized subdomains that share one launch on one GPU).
+ *
+ * A batch is created once for a fixed set of subdomains (pointers, shapes,
+ * strides and coefficients are captured at creation; the arrays' contents
+ * may change between runs).  Its work list holds one work item per
+ * (subdomain, strip, z-chunk); wavefronts of the persistent grid pull items
+ * from a device counter until the list is exhausted.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    pw_grid grid;
+    pw_layout layout;           /* element strides; all four zero = dense */
+    const void *u, *v, *w;      /* padded inputs (device), dtype of the batch */
+    pw_coeffs coeffs;           /* tz* device arrays of grid.nz elements */
+    void *su, *sv, *sw;         /* interior outputs (device) */
+} pw_batch_item;
+
+typedef struct pw_batch pw_batch;   /* opaque handle */
+
+/* Validates every item as pw_advect would (and that no output overlaps any
+ * input or output of any item), builds the work list for `tile` (NULL: the
+ * library's default shape) and uploads it.  dtype: PW_F32.  Allocates the
+ * device work list and counter (freed by pw_batch_destroy).  *out receives
+ * the handle; on error *out is NULL and nothing is allocated. */
+pw_status pw_batch_create(const pw_batch_item *items, int32_t n, pw_dtype dtype, const pw_tile *tile,
+                          pw_batch **out);
+
+/* One pass over every subdomain: a counter-reset kernel and the persistent
+ * kernel, enqueued on hip_stream.  Capturable into a graph. */
+pw_status pw_batch_run(pw_batch *batch, void *hip_stream);
+
+/* Captures pw_batch_run into a HIP graph (on hip_stream, which must not be
+ * the NULL stream) and instantiates it; replaces a previous capture. */
+pw_status pw_batch_capture(pw_batch *batch, void *hip_stream);
+
+/* Launches the captured graph on hip_stream (PW_ERR_INVALID_ARG if the batch
+ * has not been captured since its last re-tiling). */
+pw_status pw_batch_replay(pw_batch *batch, void *hip_stream);
+
+/* Autotuner: times candidate launch shapes on the batch's own buffers
+ * (outputs are overwritten with valid results), keeps the fastest, rebuilds
+ * the work list for it and drops any captured graph.  Synchronises
+ * hip_stream.  If `chosen` is non-NULL it receives the shape. */
+pw_status pw_batch_tune(pw_batch *batch, void *hip_stream, pw_tile *chosen);
+
+/* Current launch shape and work-list size of a batch. */
+pw_status pw_batch_info(const pw_batch *batch, pw_tile *tile, int64_t *work_items, int32_t *workgroups);
+
+/* Frees the batch (device work list, counter, graph).  NULL is a no-op. */
+pw_status pw_batch_destroy(pw_batch *batch);
+
 /* Library version string (static storage). */
 const char *pw_version(void);
 

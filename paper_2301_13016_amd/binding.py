@@ -59,6 +59,14 @@ class pw_tile(ctypes.Structure):
                 ("zlen", ctypes.c_int32), ("waves_per_group", ctypes.c_int32)]
 
 
+class pw_batch_item(ctypes.Structure):
+    _fields_ = [("grid", pw_grid), ("layout", pw_layout), ("u", ctypes.c_void_p), ("v", ctypes.c_void_p),
+                ("w", ctypes.c_void_p), ("coeffs", pw_coeffs), ("su", ctypes.c_void_p), ("sv", ctypes.c_void_p),
+                ("sw", ctypes.c_void_p)]
+
+
+PW_TUNE_FORWARD, PW_TUNE_ADJOINT = 1, 2
+
 _P = ctypes.c_void_p
 _SIGNATURES = {
     "pw_advect": [ctypes.POINTER(pw_grid), ctypes.POINTER(pw_layout), ctypes.c_int,
@@ -71,6 +79,17 @@ _SIGNATURES = {
                              _P, _P, _P, ctypes.POINTER(pw_coeffs), _P, _P, _P, _P, _P, _P,
                              ctypes.POINTER(pw_tile), _P],
     "pw_stream_copy": [_P, _P, ctypes.c_int64, _P],
+    "pw_tune": [ctypes.POINTER(pw_grid), ctypes.c_int, ctypes.c_int32, ctypes.POINTER(pw_tile),
+                ctypes.POINTER(pw_tile)],
+    "pw_tune_reset": [],
+    "pw_batch_create": [ctypes.POINTER(pw_batch_item), ctypes.c_int32, ctypes.c_int, ctypes.POINTER(pw_tile),
+                        ctypes.POINTER(ctypes.c_void_p)],
+    "pw_batch_run": [_P, _P],
+    "pw_batch_capture": [_P, _P],
+    "pw_batch_replay": [_P, _P],
+    "pw_batch_tune": [_P, _P, ctypes.POINTER(pw_tile)],
+    "pw_batch_info": [_P, ctypes.POINTER(pw_tile), ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32)],
+    "pw_batch_destroy": [_P],
     "pw_version": [],
     "pw_last_error": [],
 }
@@ -144,6 +163,46 @@ def pw_advect_adjoint_ex(grid, layout, dtype, u, v, w, coeffs, gsu, gsv, gsw, gu
 
 def pw_stream_copy(src, dst, nbytes, stream=None):
     return lib().pw_stream_copy(src, dst, int(nbytes), stream)
+
+
+def pw_tune(grid, dtype, flags=0, fwd_best=None, adj_best=None):
+    return lib().pw_tune(ctypes.byref(grid), int(dtype), int(flags),
+                         ctypes.byref(fwd_best) if fwd_best is not None else None,
+                         ctypes.byref(adj_best) if adj_best is not None else None)
+
+
+def pw_tune_reset():
+    return lib().pw_tune_reset()
+
+
+def pw_batch_create(items, n, dtype, tile, out_handle):
+    """items: ctypes array of pw_batch_item; out_handle: ctypes.c_void_p."""
+    return lib().pw_batch_create(items, int(n), int(dtype), ctypes.byref(tile) if tile is not None else None,
+                                 ctypes.byref(out_handle))
+
+
+def pw_batch_run(handle, stream=None):
+    return lib().pw_batch_run(handle, stream)
+
+
+def pw_batch_capture(handle, stream):
+    return lib().pw_batch_capture(handle, stream)
+
+
+def pw_batch_replay(handle, stream=None):
+    return lib().pw_batch_replay(handle, stream)
+
+
+def pw_batch_tune(handle, stream=None, chosen=None):
+    return lib().pw_batch_tune(handle, stream, ctypes.byref(chosen) if chosen is not None else None)
+
+
+def pw_batch_info(handle, tile, items, groups):
+    return lib().pw_batch_info(handle, ctypes.byref(tile), ctypes.byref(items), ctypes.byref(groups))
+
+
+def pw_batch_destroy(handle):
+    return lib().pw_batch_destroy(handle)
 
 
 # ------------------------------------------------------------------ torch layer
@@ -236,6 +295,70 @@ def advect_adjoint(u, v, w, coeffs: Coeffs, gsu, gsv, gsw, halo=1, out=None, til
                               gu.data_ptr(), gv.data_ptr(), gw.data_ptr(), tl, _stream_handle(stream))
     _check(st, "pw_advect_adjoint")
     return gu, gv, gw
+
+
+def tune(nx, ny, nz, dtype, halo=1, flags=0):
+    """Run the autotuner for this grid class; returns (forward tile, adjoint
+    tile) as (cols_per_lane, rows_per_strip, zlen, waves_per_group) tuples
+    (the adjoint entry is None when not tuned)."""
+    import torch
+    code = {torch.float32: PW_F32, torch.float64: PW_F64, torch.bfloat16: PW_BF16, torch.float16: PW_F16}[dtype]
+    f, a = pw_tile(), pw_tile()
+    _check(pw_tune(pw_grid(nx, ny, nz, halo), code, flags, f, a), "pw_tune")
+    tup = lambda t: (t.cols_per_lane, t.rows_per_strip, t.zlen, t.waves_per_group)  # noqa: E731
+    return tup(f), (tup(a) if a.rows_per_strip else None)
+
+
+class Batch:
+    """Many subdomains in one persistent launch (FP32).  ``subdomains`` is a
+    list of (u, v, w, coeffs, (su, sv, sw)) with padded inputs and interior
+    outputs as torch tensors on the current device."""
+
+    def __init__(self, subdomains, halo=1, tile=None):
+        n = len(subdomains)
+        items = (pw_batch_item * n)()
+        self._keep = []
+        for i, (u, v, w, c, outs) in enumerate(subdomains):
+            su, sv, sw = outs
+            items[i].grid = _grid_from(u, halo)
+            items[i].layout = _layout_from(u, su)
+            items[i].u, items[i].v, items[i].w = u.data_ptr(), v.data_ptr(), w.data_ptr()
+            items[i].coeffs = c.c_struct()
+            items[i].su, items[i].sv, items[i].sw = su.data_ptr(), sv.data_ptr(), sw.data_ptr()
+            self._keep.append((u, v, w, c, outs))
+        self.handle = ctypes.c_void_p()
+        tl = None if tile is None else pw_tile(*tile)
+        _check(pw_batch_create(items, n, PW_F32, tl, self.handle), "pw_batch_create")
+
+    def run(self, stream=None):
+        _check(pw_batch_run(self.handle, _stream_handle(stream)), "pw_batch_run")
+
+    def capture(self, stream):
+        _check(pw_batch_capture(self.handle, _stream_handle(stream)), "pw_batch_capture")
+
+    def replay(self, stream=None):
+        _check(pw_batch_replay(self.handle, _stream_handle(stream)), "pw_batch_replay")
+
+    def tune(self, stream=None):
+        t = pw_tile()
+        _check(pw_batch_tune(self.handle, _stream_handle(stream), t), "pw_batch_tune")
+        return (t.cols_per_lane, t.rows_per_strip, t.zlen, t.waves_per_group)
+
+    def info(self):
+        t, it, g = pw_tile(), ctypes.c_int64(), ctypes.c_int32()
+        _check(pw_batch_info(self.handle, t, it, g), "pw_batch_info")
+        return (t.cols_per_lane, t.rows_per_strip, t.zlen, t.waves_per_group), it.value, g.value
+
+    def close(self):
+        if self.handle:
+            pw_batch_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def stream_copy(src, dst, stream=None):

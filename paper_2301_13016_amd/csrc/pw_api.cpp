@@ -143,6 +143,64 @@ TileCfg to_cfg(const pw_tile &t) {
     } while (0)
 
 }  // namespace
+
+pw_status validate_forward(const pw_grid *grid, const pw_layout *layout, pw_dtype in_dtype,
+                           const void *u, const void *v, const void *w, const pw_coeffs *coeffs,
+                           void *su, void *sv, void *sw, FwdArgs *out) {
+    PW_TRY(check_grid(grid));
+    const int64_t es = elem_size(in_dtype);
+    if (!es) return fail(PW_ERR_INVALID_ARG, "unknown dtype %d", (int)in_dtype);
+    const int64_t cs = compute_size(in_dtype);
+    Layout L;
+    PW_TRY(resolve_layout(grid, layout, es, cs, &L));
+    if (!coeffs) return fail(PW_ERR_INVALID_ARG, "coeffs is NULL");
+    const char *names[] = {"u", "v", "w", "su", "sv", "sw", "tzc1", "tzc2", "tzd1", "tzd2"};
+    const void *ptrs[] = {u, v, w, su, sv, sw, coeffs->tzc1, coeffs->tzc2, coeffs->tzd1, coeffs->tzd2};
+    for (int i = 0; i < 10; ++i) PW_TRY(check_aligned(names[i], ptrs[i], i < 3 ? es : cs));
+    const Range rin[3] = {in_range("u", u, grid, L, es), in_range("v", v, grid, L, es), in_range("w", w, grid, L, es)};
+    const Range rout[3] = {out_range("su", su, grid, L, cs), out_range("sv", sv, grid, L, cs),
+                           out_range("sw", sw, grid, L, cs)};
+    for (const Range &o : rout) {
+        for (const Range &i : rin)
+            if (overlap(o, i)) return fail(PW_ERR_INVALID_ARG, "output %s overlaps input %s", o.name, i.name);
+        for (const Range &o2 : rout)
+            if (&o != &o2 && overlap(o, o2)) return fail(PW_ERR_INVALID_ARG, "outputs %s and %s overlap", o.name, o2.name);
+    }
+    FwdArgs &a = *out;
+    a.u = u; a.v = v; a.w = w;
+    a.su = su; a.sv = sv; a.sw = sw;
+    a.tzc1 = coeffs->tzc1; a.tzc2 = coeffs->tzc2; a.tzd1 = coeffs->tzd1; a.tzd2 = coeffs->tzd2;
+    a.tcx = coeffs->tcx; a.tcy = coeffs->tcy;
+    a.nx = grid->nx; a.ny = grid->ny; a.nz = grid->nz; a.h = grid->halo;
+    a.in_sy = L.in_sy; a.in_sz = L.in_sz; a.out_sy = L.out_sy; a.out_sz = L.out_sz;
+    a.in_bytes = es;
+    a.out_bytes = cs;
+    return PW_OK;
+}
+
+pw_status check_forward_on_device(const FwdArgs &a) {
+    const char *names[] = {"u", "v", "w", "su", "sv", "sw", "tzc1", "tzc2", "tzd1", "tzd2"};
+    const void *ptrs[] = {a.u, a.v, a.w, a.su, a.sv, a.sw, a.tzc1, a.tzc2, a.tzd1, a.tzd2};
+    int dev = 0;
+    PW_TRY(current_device(&dev));
+    for (int i = 0; i < 10; ++i) PW_TRY(check_on_device(names[i], ptrs[i], dev));
+    return PW_OK;
+}
+
+void forward_ranges(const FwdArgs &a, uintptr_t (*in)[2], uintptr_t (*out)[2]) {
+    const int64_t px = a.nx + 2 * a.h, py = a.ny + 2 * a.h, pz = a.nz + 2 * a.h;
+    const int64_t ilast = (pz - 1) * a.in_sz + (py - 1) * a.in_sy + (px - 1);
+    const int64_t olast = (a.nz - 1) * a.out_sz + (a.ny - 1) * a.out_sy + (a.nx - 1);
+    const void *ip[3] = {a.u, a.v, a.w};
+    const void *op[3] = {a.su, a.sv, a.sw};
+    for (int i = 0; i < 3; ++i) {
+        in[i][0] = reinterpret_cast<uintptr_t>(ip[i]);
+        in[i][1] = in[i][0] + uintptr_t((ilast + 1) * a.in_bytes);
+        out[i][0] = reinterpret_cast<uintptr_t>(op[i]);
+        out[i][1] = out[i][0] + uintptr_t((olast + 1) * a.out_bytes);
+    }
+}
+
 }  // namespace pw
 
 using namespace pw;
@@ -163,40 +221,17 @@ pw_status pw_advect_ex(const pw_grid *grid, const pw_layout *layout, pw_dtype in
                        const void *u, const void *v, const void *w, const pw_coeffs *coeffs,
                        void *su, void *sv, void *sw, const pw_tile *tile, void *hip_stream) {
     g_err[0] = 0;
-    PW_TRY(check_grid(grid));
-    const int64_t es = elem_size(in_dtype);
-    if (!es) return fail(PW_ERR_INVALID_ARG, "unknown dtype %d", (int)in_dtype);
-    const int64_t cs = compute_size(in_dtype);
-    Layout L;
-    PW_TRY(resolve_layout(grid, layout, es, cs, &L));
-    if (!coeffs) return fail(PW_ERR_INVALID_ARG, "coeffs is NULL");
-    const char *names[] = {"u", "v", "w", "su", "sv", "sw", "tzc1", "tzc2", "tzd1", "tzd2"};
-    const void *ptrs[] = {u, v, w, su, sv, sw, coeffs->tzc1, coeffs->tzc2, coeffs->tzd1, coeffs->tzd2};
-    for (int i = 0; i < 10; ++i) PW_TRY(check_aligned(names[i], ptrs[i], i < 3 ? es : cs));
-    const Range rin[3] = {in_range("u", u, grid, L, es), in_range("v", v, grid, L, es), in_range("w", w, grid, L, es)};
-    const Range rout[3] = {out_range("su", su, grid, L, cs), out_range("sv", sv, grid, L, cs),
-                           out_range("sw", sw, grid, L, cs)};
-    for (const Range &o : rout) {
-        for (const Range &i : rin)
-            if (overlap(o, i)) return fail(PW_ERR_INVALID_ARG, "output %s overlaps input %s", o.name, i.name);
-        for (const Range &o2 : rout)
-            if (&o != &o2 && overlap(o, o2)) return fail(PW_ERR_INVALID_ARG, "outputs %s and %s overlap", o.name, o2.name);
-    }
+    FwdArgs a;
+    PW_TRY(validate_forward(grid, layout, in_dtype, u, v, w, coeffs, su, sv, sw, &a));
     if (tile && !tile_supported(to_cfg(*tile), in_dtype))
         return fail(PW_ERR_INVALID_ARG, "unsupported forward tile cols=%d rows=%d zlen=%d waves=%d",
                     tile->cols_per_lane, tile->rows_per_strip, tile->zlen, tile->waves_per_group);
-    int dev = 0;
-    PW_TRY(current_device(&dev));
-    for (int i = 0; i < 10; ++i) PW_TRY(check_on_device(names[i], ptrs[i], dev));
-
-    FwdArgs a;
-    a.u = u; a.v = v; a.w = w;
-    a.su = su; a.sv = sv; a.sw = sw;
-    a.tzc1 = coeffs->tzc1; a.tzc2 = coeffs->tzc2; a.tzd1 = coeffs->tzd1; a.tzd2 = coeffs->tzd2;
-    a.tcx = coeffs->tcx; a.tcy = coeffs->tcy;
-    a.nx = grid->nx; a.ny = grid->ny; a.nz = grid->nz; a.h = grid->halo;
-    a.in_sy = L.in_sy; a.in_sz = L.in_sz; a.out_sy = L.out_sy; a.out_sz = L.out_sz;
-    const TileCfg cfg = tile ? to_cfg(*tile) : default_forward_tile(a, in_dtype);
+    PW_TRY(check_forward_on_device(a));
+    TileCfg cfg;
+    if (tile)
+        cfg = to_cfg(*tile);
+    else if (!lookup_tuned(TuneKind::Forward, grid, in_dtype, &cfg))
+        cfg = default_forward_tile(a, in_dtype);
     return launch_forward(a, in_dtype, cfg, static_cast<hipStream_t>(hip_stream));
 }
 
@@ -251,7 +286,11 @@ pw_status pw_advect_adjoint_ex(const pw_grid *grid, const pw_layout *layout, pw_
     a.tcx = coeffs->tcx; a.tcy = coeffs->tcy;
     a.nx = grid->nx; a.ny = grid->ny; a.nz = grid->nz; a.h = grid->halo;
     a.in_sy = L.in_sy; a.in_sz = L.in_sz; a.out_sy = L.out_sy; a.out_sz = L.out_sz;
-    const TileCfg cfg = tile ? to_cfg(*tile) : default_adjoint_tile(a, dtype);
+    TileCfg cfg;
+    if (tile)
+        cfg = to_cfg(*tile);
+    else if (!lookup_tuned(TuneKind::Adjoint, grid, dtype, &cfg))
+        cfg = default_adjoint_tile(a, dtype);
     return launch_adjoint(a, dtype, cfg, static_cast<hipStream_t>(hip_stream));
 }
 

@@ -1,0 +1,403 @@
+// Batched form: many independent subdomains in one persistent launch.
+//
+// The paper scales by decomposing the grid into independent parts, each on
+// its own compute unit (Sec. 5).  On one MI355X the analogue is a batch of
+// MONC-rank-sized subdomains of different shapes served by a single
+// persistent grid: the host flattens every subdomain's (strip, z-chunk) work
+// items into one list (per-subdomain prefix offsets in a device descriptor
+// table), and each wavefront of the persistent grid repeatedly takes the next
+// item from a device counter, finds its subdomain by binary search over the
+// prefix offsets, and runs the same strip march as the single-grid kernel.
+// Items are numbered z-chunk fastest, then x, then y inside a subdomain, so
+// wavefronts that start at about the same time work on neighbouring strips.
+//
+// The counter is cleared by a one-thread kernel launched just before the
+// persistent kernel (a kernel node rather than a memset node, so the pair can
+// be captured in a HIP graph and replayed).  A wavefront exits when the
+// counter passes the end of the list, so every wavefront terminates.
+#include <cstdlib>
+#include <cstring>
+#include <vector>
+
+#include "pw_stencil.h"
+
+namespace pw {
+namespace {
+
+using namespace dev;
+
+template <typename Tin> struct BatchSub {
+    FwdK<Tin> k;
+    int64_t first;   // index of the subdomain's first work item
+};
+
+__global__ void batch_reset_kernel(unsigned long long *counter) { *counter = 0ull; }
+
+template <typename Tin, int PX, int RY>
+__global__ __launch_bounds__(512) void pw_batch_kernel(const BatchSub<Tin> *__restrict__ subs, int nsub,
+                                                       int64_t nitems, unsigned long long *counter) {
+    const int lane = threadIdx.x & 63;
+    for (;;) {
+        unsigned long long got = 0ull;
+        if (lane == 0) got = atomicAdd(counter, 1ull);
+        const int64_t item = static_cast<int64_t>(
+            (static_cast<unsigned long long>(__builtin_amdgcn_readfirstlane(static_cast<unsigned>(got >> 32))) << 32) |
+            static_cast<unsigned>(__builtin_amdgcn_readfirstlane(static_cast<unsigned>(got))));
+        if (item >= nitems) break;
+        int lo = 0, hi = nsub - 1;   // last subdomain whose first item <= item
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (subs[mid].first <= item)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        const FwdK<Tin> &a = subs[lo].k;
+        const int64_t local = item - subs[lo].first;
+        const int cz = static_cast<int>(local % a.nzc);
+        const int64_t t2 = local / a.nzc;
+        const int tx = static_cast<int>(t2 % a.ntx);
+        const int ty = static_cast<int>(t2 / a.ntx);
+        strip_march<Tin, PX, RY>(a, tx, ty, cz);
+    }
+}
+
+using Tin = float;   // the batched form runs FP32 storage
+
+template <int PX, int RY> const void *kernel_ptr() {
+    return reinterpret_cast<const void *>(&pw_batch_kernel<Tin, PX, RY>);
+}
+
+const void *batch_kernel(const TileCfg &c) {
+    switch (c.px * 16 + c.ry) {
+        case 16 + 1: return kernel_ptr<1, 1>();
+        case 16 + 2: return kernel_ptr<1, 2>();
+        case 16 + 4: return kernel_ptr<1, 4>();
+        case 32 + 1: return kernel_ptr<2, 1>();
+        case 32 + 2: return kernel_ptr<2, 2>();
+        case 32 + 4: return kernel_ptr<2, 4>();
+        case 64 + 1: return kernel_ptr<4, 1>();
+        case 64 + 2: return kernel_ptr<4, 2>();
+    }
+    return nullptr;
+}
+
+template <int PX, int RY>
+void launch_t(dim3 g, dim3 b, hipStream_t s, const BatchSub<Tin> *d, int n, int64_t items, unsigned long long *c) {
+    hipLaunchKernelGGL((pw_batch_kernel<Tin, PX, RY>), g, b, 0, s, d, n, items, c);
+}
+
+void launch_batch(const TileCfg &c, dim3 g, dim3 b, hipStream_t s, const BatchSub<Tin> *d, int n, int64_t items,
+                  unsigned long long *ctr) {
+    switch (c.px * 16 + c.ry) {
+        case 16 + 1: launch_t<1, 1>(g, b, s, d, n, items, ctr); break;
+        case 16 + 2: launch_t<1, 2>(g, b, s, d, n, items, ctr); break;
+        case 16 + 4: launch_t<1, 4>(g, b, s, d, n, items, ctr); break;
+        case 32 + 1: launch_t<2, 1>(g, b, s, d, n, items, ctr); break;
+        case 32 + 2: launch_t<2, 2>(g, b, s, d, n, items, ctr); break;
+        case 32 + 4: launch_t<2, 4>(g, b, s, d, n, items, ctr); break;
+        case 64 + 1: launch_t<4, 1>(g, b, s, d, n, items, ctr); break;
+        case 64 + 2: launch_t<4, 2>(g, b, s, d, n, items, ctr); break;
+    }
+}
+
+TileCfg default_batch_tile() {
+    TileCfg c;
+    c.px = 1;
+    c.ry = 2;
+    c.zlen = 64;
+    c.wpb = 4;
+    return c;
+}
+
+}  // namespace
+}  // namespace pw
+
+using namespace pw;
+
+struct pw_batch {
+    std::vector<FwdArgs> subs;
+    pw_dtype dtype = PW_F32;
+    TileCfg tile;
+    int device = 0;
+    int cus = 256;
+    BatchSub<Tin> *d_table = nullptr;
+    unsigned long long *d_counter = nullptr;
+    int64_t nitems = 0;
+    int blocks = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+void drop_graph(pw_batch *b) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+}
+
+// Builds and uploads the work list for `tile` (synchronous upload).
+pw_status build_table(pw_batch *b, const TileCfg &tile) {
+    std::vector<BatchSub<Tin>> h(b->subs.size());
+    int64_t first = 0;
+    for (size_t i = 0; i < b->subs.size(); ++i) {
+        const FwdArgs &g = b->subs[i];
+        FwdK<Tin> &a = h[i].k;
+        a.u = static_cast<const Tin *>(g.u);
+        a.v = static_cast<const Tin *>(g.v);
+        a.w = static_cast<const Tin *>(g.w);
+        a.su = static_cast<float *>(g.su);
+        a.sv = static_cast<float *>(g.sv);
+        a.sw = static_cast<float *>(g.sw);
+        a.tzc1 = static_cast<const float *>(g.tzc1);
+        a.tzc2 = static_cast<const float *>(g.tzc2);
+        a.tzd1 = static_cast<const float *>(g.tzd1);
+        a.tzd2 = static_cast<const float *>(g.tzd2);
+        a.tcx = static_cast<float>(g.tcx);
+        a.tcy = static_cast<float>(g.tcy);
+        a.nx = static_cast<int32_t>(g.nx);
+        a.ny = static_cast<int32_t>(g.ny);
+        a.nz = static_cast<int32_t>(g.nz);
+        a.h = g.h;
+        a.in_sz = g.in_sz;
+        a.out_sz = g.out_sz;
+        a.in_sy = static_cast<int32_t>(g.in_sy);
+        a.out_sy = static_cast<int32_t>(g.out_sy);
+        a.ntx = static_cast<int32_t>((g.nx + 64 * tile.px - 1) / (64 * tile.px));
+        a.nty = static_cast<int32_t>((g.ny + tile.ry - 1) / tile.ry);
+        // split nz evenly into chunks of at most tile.zlen levels
+        const int64_t chunks = (g.nz + tile.zlen - 1) / tile.zlen;
+        a.zlen = static_cast<int32_t>((g.nz + chunks - 1) / chunks);
+        a.nzc = static_cast<int32_t>((g.nz + a.zlen - 1) / a.zlen);
+        a.wpb = 1;
+        h[i].first = first;
+        first += static_cast<int64_t>(a.ntx) * a.nty * a.nzc;
+    }
+    BatchSub<Tin> *d = nullptr;
+    const size_t bytes = h.size() * sizeof(BatchSub<Tin>);
+    if (hipMalloc(&d, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(PW_ERR_ALLOC, "work list allocation failed");
+    }
+    hipError_t e = hipMemcpy(d, h.data(), bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(d);
+        return hip_fail(e, "work list upload");
+    }
+    int per_cu = 0;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_kernel(tile), 64 * tile.wpb, 0);
+    if (e != hipSuccess || per_cu < 1) per_cu = 1;
+    if (b->d_table) (void)hipFree(b->d_table);
+    b->d_table = d;
+    b->nitems = first;
+    b->tile = tile;
+    int64_t blocks = static_cast<int64_t>(per_cu) * b->cus;
+    const int64_t max_useful = (first + tile.wpb - 1) / tile.wpb;   // one item per wavefront at least
+    if (blocks > max_useful) blocks = max_useful;
+    if (blocks < 1) blocks = 1;
+    b->blocks = static_cast<int>(blocks);
+    drop_graph(b);
+    return PW_OK;
+}
+
+pw_status enqueue(pw_batch *b, hipStream_t s) {
+    hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(1), 0, s, b->d_counter);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "counter reset launch");
+    launch_batch(b->tile, dim3(static_cast<unsigned>(b->blocks)), dim3(64 * b->tile.wpb), s, b->d_table,
+                 static_cast<int>(b->subs.size()), b->nitems, b->d_counter);
+    return hip_fail(hipGetLastError(), "batched kernel launch");
+}
+
+bool batch_tile_ok(const TileCfg &c) {
+    return tile_supported(c, PW_F32) && batch_kernel(c) != nullptr;
+}
+
+}  // namespace
+
+extern "C" {
+
+pw_status pw_batch_create(const pw_batch_item *items, int32_t n, pw_dtype dtype, const pw_tile *tile,
+                          pw_batch **out) {
+    if (!out) return fail(PW_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!items || n < 1) return fail(PW_ERR_INVALID_ARG, "need at least one item");
+    if (n > (1 << 20)) return fail(PW_ERR_INVALID_ARG, "too many items");
+    if (dtype != PW_F32) return fail(PW_ERR_UNSUPPORTED, "the batched form supports PW_F32 storage");
+    TileCfg cfg = default_batch_tile();
+    if (tile) {
+        cfg = TileCfg{tile->cols_per_lane, tile->rows_per_strip, tile->zlen, tile->waves_per_group};
+        if (!batch_tile_ok(cfg))
+            return fail(PW_ERR_INVALID_ARG, "unsupported batch tile cols=%d rows=%d zlen=%d waves=%d", cfg.px, cfg.ry,
+                        cfg.zlen, cfg.wpb);
+    }
+    std::vector<FwdArgs> subs(static_cast<size_t>(n));
+    for (int32_t i = 0; i < n; ++i) {
+        const pw_batch_item &it = items[i];
+        const pw_layout *L = &it.layout;
+        if (!it.layout.in_sy && !it.layout.in_sz && !it.layout.out_sy && !it.layout.out_sz) L = nullptr;
+        pw_status st = validate_forward(&it.grid, L, dtype, it.u, it.v, it.w, &it.coeffs, it.su, it.sv, it.sw, &subs[i]);
+        if (st != PW_OK) {
+            char msg[512];
+            std::snprintf(msg, sizeof msg, "%s", pw_last_error());
+            return fail(st, "item %d: %s", i, msg);
+        }
+    }
+    // no output of any item may overlap any input or output of another item
+    std::vector<uintptr_t> lo_in(3 * n), hi_in(3 * n), lo_out(3 * n), hi_out(3 * n);
+    for (int32_t i = 0; i < n; ++i) {
+        uintptr_t ri[3][2], ro[3][2];
+        forward_ranges(subs[i], ri, ro);
+        for (int f = 0; f < 3; ++f) {
+            lo_in[3 * i + f] = ri[f][0];
+            hi_in[3 * i + f] = ri[f][1];
+            lo_out[3 * i + f] = ro[f][0];
+            hi_out[3 * i + f] = ro[f][1];
+        }
+    }
+    for (int32_t p = 0; p < 3 * n; ++p)
+        for (int32_t q = 0; q < 3 * n; ++q) {
+            if (p / 3 == q / 3) continue;   // within one item already checked
+            if (lo_out[p] < hi_in[q] && lo_in[q] < hi_out[p])
+                return fail(PW_ERR_INVALID_ARG, "an output of item %d overlaps an input of item %d", p / 3, q / 3);
+            if (lo_out[p] < hi_out[q] && lo_out[q] < hi_out[p])
+                return fail(PW_ERR_INVALID_ARG, "outputs of items %d and %d overlap", p / 3, q / 3);
+        }
+    for (int32_t i = 0; i < n; ++i) {
+        pw_status st = check_forward_on_device(subs[i]);
+        if (st != PW_OK) {
+            char msg[512];
+            std::snprintf(msg, sizeof msg, "%s", pw_last_error());
+            return fail(st, "item %d: %s", i, msg);
+        }
+    }
+    pw_batch *b = new (std::nothrow) pw_batch;
+    if (!b) return fail(PW_ERR_ALLOC, "host allocation failed");
+    b->subs.swap(subs);
+    b->dtype = dtype;
+    (void)hipGetDevice(&b->device);
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, b->device) == hipSuccess && prop.multiProcessorCount > 0)
+        b->cus = prop.multiProcessorCount;
+    if (hipMalloc(&b->d_counter, sizeof(unsigned long long)) != hipSuccess) {
+        (void)hipGetLastError();
+        delete b;
+        return fail(PW_ERR_ALLOC, "counter allocation failed");
+    }
+    pw_status st = build_table(b, cfg);
+    if (st != PW_OK) {
+        pw_batch_destroy(b);
+        return st;
+    }
+    *out = b;
+    return PW_OK;
+}
+
+pw_status pw_batch_run(pw_batch *b, void *hip_stream) {
+    if (!b) return fail(PW_ERR_INVALID_ARG, "batch is NULL");
+    return enqueue(b, static_cast<hipStream_t>(hip_stream));
+}
+
+pw_status pw_batch_capture(pw_batch *b, void *hip_stream) {
+    if (!b) return fail(PW_ERR_INVALID_ARG, "batch is NULL");
+    if (!hip_stream) return fail(PW_ERR_INVALID_ARG, "graph capture needs a non-NULL stream");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    drop_graph(b);
+    hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+    pw_status st = enqueue(b, s);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(s, &g);
+    if (st != PW_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    hipGraphExec_t x = nullptr;
+    e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return hip_fail(e, "hipGraphInstantiate");
+    }
+    b->graph = g;
+    b->exec = x;
+    return PW_OK;
+}
+
+pw_status pw_batch_replay(pw_batch *b, void *hip_stream) {
+    if (!b) return fail(PW_ERR_INVALID_ARG, "batch is NULL");
+    if (!b->exec) return fail(PW_ERR_INVALID_ARG, "batch has no captured graph (pw_batch_capture)");
+    return hip_fail(hipGraphLaunch(b->exec, static_cast<hipStream_t>(hip_stream)), "hipGraphLaunch");
+}
+
+pw_status pw_batch_tune(pw_batch *b, void *hip_stream, pw_tile *chosen) {
+    if (!b) return fail(PW_ERR_INVALID_ARG, "batch is NULL");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return hip_fail(hipGetLastError(), "hipEventCreate");
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return hip_fail(hipGetLastError(), "hipEventCreate");
+    }
+    const TileCfg start = b->tile;
+    TileCfg best = start;
+    float best_ms = -1.f;
+    pw_status st = PW_OK;
+    for (int px : {1, 2, 4})
+        for (int ry : {1, 2, 4})
+            for (int zl : {32, 64, 128, 256})
+                for (int wpb : {1, 4}) {
+                    TileCfg c;
+                    c.px = px;
+                    c.ry = ry;
+                    c.zlen = zl;
+                    c.wpb = wpb;
+                    if (!batch_tile_ok(c)) continue;
+                    if ((st = build_table(b, c)) != PW_OK) break;
+                    if ((st = enqueue(b, s)) != PW_OK) break;   // warm-up
+                    float ms = -1.f;
+                    if (hipEventRecord(e0, s) != hipSuccess) {
+                        st = hip_fail(hipGetLastError(), "hipEventRecord");
+                        break;
+                    }
+                    for (int r = 0; r < 3 && st == PW_OK; ++r) st = enqueue(b, s);
+                    if (st != PW_OK) break;
+                    if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                        hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                        st = hip_fail(hipGetLastError(), "timing");
+                        break;
+                    }
+                    if (best_ms < 0.f || ms < best_ms) {
+                        best_ms = ms;
+                        best = c;
+                    }
+                }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    const pw_status st2 = build_table(b, st == PW_OK ? best : start);
+    if (st != PW_OK) return st;
+    if (st2 != PW_OK) return st2;
+    if (chosen) *chosen = pw_tile{best.px, best.ry, best.zlen, best.wpb};
+    return PW_OK;
+}
+
+pw_status pw_batch_info(const pw_batch *b, pw_tile *tile, int64_t *work_items, int32_t *workgroups) {
+    if (!b) return fail(PW_ERR_INVALID_ARG, "batch is NULL");
+    if (tile) *tile = pw_tile{b->tile.px, b->tile.ry, b->tile.zlen, b->tile.wpb};
+    if (work_items) *work_items = b->nitems;
+    if (workgroups) *workgroups = b->blocks;
+    return PW_OK;
+}
+
+pw_status pw_batch_destroy(pw_batch *b) {
+    if (!b) return PW_OK;
+    drop_graph(b);
+    if (b->d_table) (void)hipFree(b->d_table);
+    if (b->d_counter) (void)hipFree(b->d_counter);
+    delete b;
+    return PW_OK;
+}
+
+}  // extern "C"

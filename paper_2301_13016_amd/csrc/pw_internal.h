@@ -32,6 +32,7 @@ struct FwdArgs {
     int64_t nx, ny, nz;
     int32_t h;
     int64_t in_sy, in_sz, out_sy, out_sz;
+    int64_t in_bytes = 4, out_bytes = 4;   // element sizes of inputs / outputs
 };
 
 struct AdjArgs {
@@ -57,6 +58,22 @@ TileCfg default_adjoint_tile(const AdjArgs &a, pw_dtype dt);
 pw_status launch_forward(const FwdArgs &a, pw_dtype dt, const TileCfg &cfg, hipStream_t s);
 pw_status launch_adjoint(const AdjArgs &a, pw_dtype dt, const TileCfg &cfg, hipStream_t s);
 pw_status launch_copy(const void *src, void *dst, int64_t nbytes, hipStream_t s);
+
+// Host-side validation shared by pw_advect and the batched form (pw_api.cpp).
+// validate_forward checks everything that needs no HIP call and fills the
+// launch operands; check_forward_on_device then checks the device pointers.
+pw_status validate_forward(const pw_grid *grid, const pw_layout *layout, pw_dtype in_dtype,
+                           const void *u, const void *v, const void *w, const pw_coeffs *coeffs,
+                           void *su, void *sv, void *sw, FwdArgs *out);
+pw_status check_forward_on_device(const FwdArgs &a);
+// Byte ranges [lo, hi) of the three inputs and three outputs of a launch.
+void forward_ranges(const FwdArgs &a, uintptr_t (*in)[2], uintptr_t (*out)[2]);
+
+// Autotune cache (pw_tune.cpp): best launch shape per kernel kind, dtype and
+// shape class, filled by pw_tune and consulted when no tile is given.
+enum class TuneKind { Forward = 0, Adjoint = 1 };
+bool lookup_tuned(TuneKind kind, const pw_grid *grid, pw_dtype dt, TileCfg *cfg);
+void store_tuned(TuneKind kind, const pw_grid *grid, pw_dtype dt, const TileCfg &cfg);
 
 // Error plumbing (pw_api.cpp).
 pw_status fail(pw_status st, const char *fmt, ...);

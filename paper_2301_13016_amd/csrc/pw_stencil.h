@@ -1,0 +1,377 @@
+// Device-side building blocks of the forward PW stencil, shared by the
+// single-grid kernel (pw_forward.hip) and the batched persistent kernel
+// (pw_batch.hip).  See pw_forward.hip for the design.
+#pragma once
+
+#include "pw_internal.h"
+
+namespace pw {
+namespace dev {
+
+// ----------------------------------------------------------------- storage
+template <typename Tin> struct Storage;
+template <> struct Storage<float> {
+    using Tc = float;
+    static __device__ __forceinline__ float widen(float x) { return x; }
+};
+template <> struct Storage<double> {
+    using Tc = double;
+    static __device__ __forceinline__ double widen(double x) { return x; }
+};
+template <> struct Storage<uint16_t> {   // BF16: the upper half of an FP32 pattern
+    using Tc = float;
+    static __device__ __forceinline__ float widen(uint16_t x) {
+        return __uint_as_float(static_cast<uint32_t>(x) << 16);
+    }
+};
+template <> struct Storage<_Float16> {
+    using Tc = float;
+    static __device__ __forceinline__ float widen(_Float16 x) { return static_cast<float>(x); }
+};
+
+// N consecutive elements, aligned only to the element: the type of one
+// lane's vector load or store.
+template <typename T, int N> struct Vec;
+template <typename T> struct Vec<T, 1> { using type = T; };
+template <> struct Vec<float, 2> { typedef float type __attribute__((ext_vector_type(2), aligned(4))); };
+template <> struct Vec<float, 4> { typedef float type __attribute__((ext_vector_type(4), aligned(4))); };
+template <> struct Vec<double, 2> { typedef double type __attribute__((ext_vector_type(2), aligned(8))); };
+template <> struct Vec<uint16_t, 2> { typedef uint16_t type __attribute__((ext_vector_type(2), aligned(2))); };
+template <> struct Vec<uint16_t, 4> { typedef uint16_t type __attribute__((ext_vector_type(4), aligned(2))); };
+template <> struct Vec<_Float16, 2> { typedef _Float16 type __attribute__((ext_vector_type(2), aligned(2))); };
+template <> struct Vec<_Float16, 4> { typedef _Float16 type __attribute__((ext_vector_type(4), aligned(2))); };
+
+template <typename T, int N>
+__device__ __forceinline__ T comp(const typename Vec<T, N>::type &v, int m) {
+    if constexpr (N == 1) {
+        (void)m;
+        return v;
+    } else {
+        return v[m];
+    }
+}
+
+// ------------------------------------------------------- cross-lane moves
+// DPP controls (GFX9 family): wave_shr:1 moves lane l-1 into lane l,
+// wave_shl:1 moves lane l+1 into lane l (bound_ctrl: the lane with no source
+// reads 0 and is patched from the halo).
+constexpr int kWaveShr1 = 0x138;
+constexpr int kWaveShl1 = 0x130;
+
+template <int Ctrl> __device__ __forceinline__ float wave_shift(float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), Ctrl, 0xf, 0xf, true));
+}
+template <int Ctrl> __device__ __forceinline__ double wave_shift(double x) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), Ctrl, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), Ctrl, 0xf, 0xf, true);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ float lane_value(float x, int lane) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), lane));
+}
+__device__ __forceinline__ double lane_value(double x, int lane) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(x), lane);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(x), lane);
+    return __hiloint2double(hi, lo);
+}
+// Column left of this lane's first column: the previous lane's last value,
+// or for lane 0 the strip's left halo (held by lane `row` of `halo`).
+template <typename T> __device__ __forceinline__ T left_of(T last, T halo, int row, bool lane0) {
+    const T s = wave_shift<kWaveShr1>(last);
+    const T h = lane_value(halo, row);
+    return lane0 ? h : s;
+}
+// Column right of this lane's last column (lane 63: right halo, lane 32+row).
+template <typename T> __device__ __forceinline__ T right_of(T first, T halo, int row, bool lane63) {
+    const T s = wave_shift<kWaveShl1>(first);
+    const T h = lane_value(halo, 32 + row);
+    return lane63 ? h : s;
+}
+
+template <typename T> __device__ __forceinline__ T fma_(T a, T b, T c);
+template <> __device__ __forceinline__ float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+template <> __device__ __forceinline__ double fma_(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// --------------------------------------------------------- kernel operands
+template <typename Tin> struct FwdK {
+    using Tc = typename Storage<Tin>::Tc;
+    const Tin *u, *v, *w;
+    Tc *su, *sv, *sw;
+    const Tc *tzc1, *tzc2, *tzd1, *tzd2;
+    Tc tcx, tcy;
+    int32_t nx, ny, nz, h;
+    int64_t in_sz, out_sz;     // plane strides (elements)
+    int32_t in_sy, out_sy;     // row strides (elements); a plane fits in 2 GiB
+    int32_t ntx, nty, nzc, zlen, wpb;
+};
+
+// One z-plane of the strip, widened: rows 0..RY+1 are the strip's rows
+// jj0-1 .. jj0+RY (interior numbering), PX columns of this lane each; hu/hv/hw
+// are the packed halo columns (see left_of / right_of).
+template <typename Tc, int PX, int RY> struct Plane {
+    Tc u[RY + 2][PX], v[RY + 2][PX], w[RY + 2][PX];
+    Tc hu, hv, hw;
+};
+
+// Per-lane addressing of the strip, fixed for the whole march.
+template <int RY> struct StripAddr {
+    uint32_t roff[RY + 2];   // byte offset of this lane's first column in row r
+    uint32_t hoff;           // byte offset of this lane's halo element
+    int col;                 // padded column of the lane's first element
+};
+
+// PX consecutive elements of one row starting at padded column `col`.  In a
+// full strip (Full) every lane's vector lies inside the row and is read with
+// one vector load; in the strip at the x end of the grid every lane reads
+// element-wise with the columns clamped into the row (every column a stored
+// output reads is in range, so clamping only affects values that are not
+// used).  The choice is made per wavefront, so neither path branches per lane.
+template <typename Tin, int PX, bool Full>
+__device__ __forceinline__ void load_row(typename Storage<Tin>::Tc (&dst)[PX], const char *plane, uint32_t off,
+                                         int col, int last_col) {
+    if constexpr (Full || PX == 1) {
+        (void)col;
+        (void)last_col;
+        const auto x = *reinterpret_cast<const typename Vec<Tin, PX>::type *>(plane + off);
+#pragma unroll
+        for (int m = 0; m < PX; ++m) dst[m] = Storage<Tin>::widen(comp<Tin, PX>(x, m));
+    } else {
+        const char *row = plane + off - static_cast<int64_t>(col) * static_cast<int64_t>(sizeof(Tin));
+#pragma unroll
+        for (int m = 0; m < PX; ++m)
+            dst[m] = Storage<Tin>::widen(
+                *reinterpret_cast<const Tin *>(row + static_cast<int64_t>(min(col + m, last_col)) * sizeof(Tin)));
+    }
+}
+
+template <typename Tin, int PX, int RY, bool Full>
+__device__ __forceinline__ void load_plane(Plane<typename Storage<Tin>::Tc, PX, RY> &P, const FwdK<Tin> &a,
+                                           int kp, const StripAddr<RY> &s, int last_col) {
+    const int64_t pb = static_cast<int64_t>(kp) * a.in_sz * static_cast<int64_t>(sizeof(Tin));
+    const char *bu = reinterpret_cast<const char *>(a.u) + pb;
+    const char *bv = reinterpret_cast<const char *>(a.v) + pb;
+    const char *bw = reinterpret_cast<const char *>(a.w) + pb;
+#pragma unroll
+    for (int r = 0; r < RY + 2; ++r) {
+        load_row<Tin, PX, Full>(P.u[r], bu, s.roff[r], s.col, last_col);
+        load_row<Tin, PX, Full>(P.v[r], bv, s.roff[r], s.col, last_col);
+        load_row<Tin, PX, Full>(P.w[r], bw, s.roff[r], s.col, last_col);
+    }
+    P.hu = Storage<Tin>::widen(*reinterpret_cast<const Tin *>(bu + s.hoff));
+    P.hv = Storage<Tin>::widen(*reinterpret_cast<const Tin *>(bv + s.hoff));
+    P.hw = Storage<Tin>::widen(*reinterpret_cast<const Tin *>(bw + s.hoff));
+}
+
+template <typename T, int N> __device__ __forceinline__ void store_vec(char *p, const T (&x)[N]) {
+    typename Vec<T, N>::type v;
+    if constexpr (N == 1) {
+        v = x[0];
+    } else {
+#pragma unroll
+        for (int m = 0; m < N; ++m) v[m] = x[m];
+    }
+    __builtin_nontemporal_store(v, reinterpret_cast<typename Vec<T, N>::type *>(p));
+}
+
+// Source terms of output level kk (interior numbering) from planes kk-1 (m),
+// kk (c) and kk+1 (p); stores the lanes/rows that own outputs.
+template <typename Tin, int PX, int RY, bool Full>
+__device__ __forceinline__ void level(const Plane<typename Storage<Tin>::Tc, PX, RY> &m,
+                                      const Plane<typename Storage<Tin>::Tc, PX, RY> &c,
+                                      const Plane<typename Storage<Tin>::Tc, PX, RY> &p,
+                                      const FwdK<Tin> &a, int kk, bool lane0, bool lane63, int nvalid,
+                                      const uint32_t (&ooff)[RY], const bool (&row_ok)[RY]) {
+    using Tc = typename Storage<Tin>::Tc;
+    const Tc z1 = a.tzc1[kk], z2 = a.tzc2[kk], d1 = a.tzd1[kk], d2 = a.tzd2[kk];
+    const Tc tcx = a.tcx, tcy = a.tcy;
+
+    // Columns just outside this lane's PX columns, per loaded row, for the
+    // arrays whose x-neighbours the stencil reads.
+    Tc uL[RY + 2], uR[RY + 2], vL[RY + 2], vR[RY + 2], wL[RY + 2], wR[RY + 2], wRm[RY + 2], uLp[RY + 2];
+#pragma unroll
+    for (int r = 0; r < RY + 2; ++r) {
+        uL[r] = left_of(c.u[r][PX - 1], c.hu, r, lane0);
+        uR[r] = right_of(c.u[r][0], c.hu, r, lane63);
+        vL[r] = left_of(c.v[r][PX - 1], c.hv, r, lane0);
+        vR[r] = right_of(c.v[r][0], c.hv, r, lane63);
+        wL[r] = left_of(c.w[r][PX - 1], c.hw, r, lane0);
+        wR[r] = right_of(c.w[r][0], c.hw, r, lane63);
+        wRm[r] = right_of(m.w[r][0], m.hw, r, lane63);
+        uLp[r] = left_of(p.u[r][PX - 1], p.hu, r, lane0);
+    }
+    // value at (row r, column x-1) / (row r, column x+1) of a plane array
+#define XM(arr, L, r, x) ((x) == 0 ? L[r] : arr[r][(x) - 1])
+#define XP(arr, R, r, x) ((x) == PX - 1 ? R[r] : arr[r][(x) + 1])
+
+    // Face sums shared by consecutive rows of the strip (index r = loaded row):
+    //   fy = v(k,r,i) + v(k,r,i+1)   gy = v(k,r,i) + v(k,r+1,i)   hy = v(k,r,i) + v(k+1,r,i)
+    Tc fy[RY + 1][PX], gy[RY + 1][PX], hy[RY + 1][PX];
+#pragma unroll
+    for (int r = 0; r <= RY; ++r) {
+#pragma unroll
+        for (int x = 0; x < PX; ++x) {
+            fy[r][x] = c.v[r][x] + XP(c.v, vR, r, x);
+            gy[r][x] = c.v[r][x] + c.v[r + 1][x];
+            hy[r][x] = c.v[r][x] + p.v[r][x];
+        }
+    }
+
+    const int64_t ob = static_cast<int64_t>(kk) * a.out_sz * static_cast<int64_t>(sizeof(Tc));
+    char *osu = reinterpret_cast<char *>(a.su) + ob;
+    char *osv = reinterpret_cast<char *>(a.sv) + ob;
+    char *osw = reinterpret_cast<char *>(a.sw) + ob;
+
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+        const int q = r + 1;   // this output row within the loaded rows
+        Tc rsu[PX], rsv[PX], rsw[PX];
+#pragma unroll
+        for (int x = 0; x < PX; ++x) {
+            // su: x faces (u+u), y faces (v+v at i, i+1), z faces (w+w at i, i+1)
+            const Tc uc = c.u[q][x];
+            const Tc ul = XM(c.u, uL, q, x), ur = XP(c.u, uR, q, x);
+            const Tc ax = fma_(-ur, uc + ur, ul * (uc + ul));
+            const Tc ay = fma_(-c.u[q + 1][x], fy[q][x], c.u[q - 1][x] * fy[r][x]);
+            const Tc fzm = m.w[q][x] + XP(m.w, wRm, q, x);
+            const Tc fzp = c.w[q][x] + XP(c.w, wR, q, x);
+            Tc su = tcx * ax;
+            su = fma_(tcy, ay, su);
+            su = fma_(z1 * m.u[q][x], fzm, su);
+            su = fma_(-(z2 * p.u[q][x]), fzp, su);
+
+            // sv: x faces (u+u at j, j+1), y faces (v+v), z faces (w+w at j, j+1)
+            const Tc vl = XM(c.v, vL, q, x), vr = XP(c.v, vR, q, x);
+            const Tc gxp = uc + c.u[q + 1][x];
+            const Tc gxm = ul + XM(c.u, uL, q + 1, x);
+            const Tc bx = fma_(-vr, gxp, vl * gxm);
+            const Tc by = fma_(-c.v[q + 1][x], gy[q][x], c.v[q - 1][x] * gy[r][x]);
+            const Tc gzm = m.w[q][x] + m.w[q + 1][x];
+            const Tc gzp = c.w[q][x] + c.w[q + 1][x];
+            Tc sv = tcx * bx;
+            sv = fma_(tcy, by, sv);
+            sv = fma_(z1 * m.v[q][x], gzm, sv);
+            sv = fma_(-(z2 * p.v[q][x]), gzp, sv);
+
+            // sw: x faces (u+u at k, k+1), y faces (v+v at k, k+1), z faces (w+w)
+            const Tc wc = c.w[q][x];
+            const Tc wl = XM(c.w, wL, q, x), wr = XP(c.w, wR, q, x);
+            const Tc hxp = uc + p.u[q][x];
+            const Tc hxm = ul + XM(p.u, uLp, q, x);
+            const Tc cx = fma_(-wr, hxp, wl * hxm);
+            const Tc cy = fma_(-c.w[q + 1][x], hy[q][x], c.w[q - 1][x] * hy[r][x]);
+            const Tc hzm = wc + m.w[q][x];
+            const Tc hzp = wc + p.w[q][x];
+            Tc sw = tcx * cx;
+            sw = fma_(tcy, cy, sw);
+            sw = fma_(d1 * m.w[q][x], hzm, sw);
+            sw = fma_(-(d2 * p.w[q][x]), hzp, sw);
+
+            rsu[x] = su;
+            rsv[x] = sv;
+            rsw[x] = sw;
+        }
+        if (row_ok[r]) {
+            if (Full) {   // every lane owns PX columns inside the grid
+                (void)nvalid;
+                store_vec<Tc, PX>(osu + ooff[r], rsu);
+                store_vec<Tc, PX>(osv + ooff[r], rsv);
+                store_vec<Tc, PX>(osw + ooff[r], rsw);
+            } else {
+#pragma unroll
+                for (int x = 0; x < PX; ++x) {
+                    if (x < nvalid) {
+                        __builtin_nontemporal_store(rsu[x], reinterpret_cast<Tc *>(osu + ooff[r]) + x);
+                        __builtin_nontemporal_store(rsv[x], reinterpret_cast<Tc *>(osv + ooff[r]) + x);
+                        __builtin_nontemporal_store(rsw[x], reinterpret_cast<Tc *>(osw + ooff[r]) + x);
+                    }
+                }
+            }
+        }
+    }
+#undef XM
+#undef XP
+}
+
+// Workgroup -> tile numbering.  Workgroups are handed to the 8 XCDs round
+// robin; give XCD x the contiguous tile range [start(x), start(x+1)).
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+    const int q = nb >> 3, rem = nb & 7, x = b & 7, i = b >> 3;
+    return x * q + min(x, rem) + i;
+}
+
+// One work item: the wavefront's strip (tx, ty) marched through z-chunk cz.
+// All 64 lanes must be active (the cross-lane moves read every lane).  Full:
+// the strip lies wholly inside the grid in x ((tx+1)*64*PX <= nx), so every
+// lane loads whole vectors and owns PX outputs; otherwise loads are clamped
+// element-wise (one-column lanes need no clamping beyond their start column)
+// and each lane stores only its columns inside the grid.
+template <typename Tin, int PX, int RY, bool Full>
+__device__ __forceinline__ void strip_march_t(const FwdK<Tin> &a, int tx, int ty, int cz) {
+    using Tc = typename Storage<Tin>::Tc;
+    const int lane = threadIdx.x & 63;
+
+    const int pcols = a.nx + 2 * a.h, prows = a.ny + 2 * a.h;
+    const int last_col = pcols - 1;
+    const int ii0 = tx * 64 * PX + lane * PX;        // first interior column of this lane
+    const int nvalid = a.nx - ii0;                    // its columns inside the grid (may be <= 0)
+    const int jj0 = ty * RY;
+
+    StripAddr<RY> s;
+    s.col = min(ii0 + a.h, last_col);
+#pragma unroll
+    for (int r = 0; r < RY + 2; ++r) {
+        const int prow = min(jj0 - 1 + a.h + r, prows - 1);
+        s.roff[r] = static_cast<uint32_t>((prow * a.in_sy + s.col) * static_cast<int>(sizeof(Tin)));
+    }
+    {   // packed halo: lane r -> left halo of row r, lane 32+r -> right halo of row r
+        const int hr = min(lane & 31, RY + 1);
+        const int hrow = min(jj0 - 1 + a.h + hr, prows - 1);
+        const int hcol = (lane & 32) ? min(tx * 64 * PX + 64 * PX + a.h, last_col) : tx * 64 * PX + a.h - 1;
+        s.hoff = static_cast<uint32_t>((hrow * a.in_sy + hcol) * static_cast<int>(sizeof(Tin)));
+    }
+    uint32_t ooff[RY];
+    bool row_ok[RY];
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+        row_ok[r] = jj0 + r < a.ny;
+        const int jj = min(jj0 + r, a.ny - 1);
+        const int ic = min(ii0, a.nx - 1);
+        ooff[r] = static_cast<uint32_t>((jj * a.out_sy + ic) * static_cast<int>(sizeof(Tc)));
+    }
+    const bool lane0 = lane == 0, lane63 = lane == 63;
+
+    const int k0 = cz * a.zlen;
+    const int k1 = min(a.nz, k0 + a.zlen);
+    const int h = a.h;
+
+    Plane<Tc, PX, RY> A, B, C, D;
+    load_plane<Tin, PX, RY, Full>(A, a, k0 - 1 + h, s, last_col);
+    load_plane<Tin, PX, RY, Full>(B, a, k0 + h, s, last_col);
+    load_plane<Tin, PX, RY, Full>(C, a, k0 + 1 + h, s, last_col);
+    int kk = k0;
+    for (;;) {
+        if (kk + 1 < k1) load_plane<Tin, PX, RY, Full>(D, a, kk + 2 + h, s, last_col);
+        level<Tin, PX, RY, Full>(A, B, C, a, kk, lane0, lane63, nvalid, ooff, row_ok);
+        if (++kk >= k1) break;
+        if (kk + 1 < k1) load_plane<Tin, PX, RY, Full>(A, a, kk + 2 + h, s, last_col);
+        level<Tin, PX, RY, Full>(B, C, D, a, kk, lane0, lane63, nvalid, ooff, row_ok);
+        if (++kk >= k1) break;
+        if (kk + 1 < k1) load_plane<Tin, PX, RY, Full>(B, a, kk + 2 + h, s, last_col);
+        level<Tin, PX, RY, Full>(C, D, A, a, kk, lane0, lane63, nvalid, ooff, row_ok);
+        if (++kk >= k1) break;
+        if (kk + 1 < k1) load_plane<Tin, PX, RY, Full>(C, a, kk + 2 + h, s, last_col);
+        level<Tin, PX, RY, Full>(D, A, B, a, kk, lane0, lane63, nvalid, ooff, row_ok);
+        if (++kk >= k1) break;
+    }
+}
+
+template <typename Tin, int PX, int RY>
+__device__ __forceinline__ void strip_march(const FwdK<Tin> &a, int tx, int ty, int cz) {
+    if ((tx + 1) * 64 * PX <= a.nx)
+        strip_march_t<Tin, PX, RY, true>(a, tx, ty, cz);
+    else
+        strip_march_t<Tin, PX, RY, false>(a, tx, ty, cz);
+}
+
+}  // namespace dev
+}  // namespace pw

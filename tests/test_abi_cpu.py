@@ -199,3 +199,58 @@ def test_last_error_is_per_thread(lib):
     t.join()
     assert seen == [""]
     assert "halo" in B.pw_last_error()
+
+
+# ------------------------------------------------------------------ batched form / tuner
+
+def _items(n, overlap=False):
+    items = (B.pw_batch_item * n)()
+    for i in range(n):
+        base = A + i * 16 * MB
+        items[i].grid = B.pw_grid(8, 8, 8, 1)
+        items[i].u, items[i].v, items[i].w = base, base + MB, base + 2 * MB
+        items[i].coeffs = B.pw_coeffs(0.0025, 0.0025, base + 10 * MB, base + 11 * MB, base + 12 * MB, base + 13 * MB)
+        items[i].su, items[i].sv, items[i].sw = base + 3 * MB, base + 4 * MB, base + 5 * MB
+    if overlap:
+        items[1].su = items[0].u   # an output of item 1 on an input of item 0
+    return items
+
+
+def test_batch_argument_errors(lib):
+    h = ctypes.c_void_p()
+    assert B.pw_batch_create(_items(2), 0, B.PW_F32, None, h) == B.PW_ERR_INVALID_ARG
+    assert lib.pw_batch_create(_items(2), 2, B.PW_F32, None, None) == B.PW_ERR_INVALID_ARG
+    assert B.pw_batch_create(_items(2), 2, B.PW_BF16, None, h) == B.PW_ERR_UNSUPPORTED
+    assert B.pw_batch_create(_items(2), 2, B.PW_F32, B.pw_tile(4, 4, 8, 4), h) == B.PW_ERR_INVALID_ARG
+    bad = _items(3)
+    bad[2].grid.halo = 0
+    assert B.pw_batch_create(bad, 3, B.PW_F32, None, h) == B.PW_ERR_INVALID_ARG
+    assert "item 2" in B.pw_last_error()
+    assert B.pw_batch_create(_items(2, overlap=True), 2, B.PW_F32, None, h) == B.PW_ERR_INVALID_ARG
+    assert "overlaps" in B.pw_last_error()
+    assert h.value is None
+
+
+def test_batch_valid_items_reach_device_check(lib):
+    h = ctypes.c_void_p()
+    assert B.pw_batch_create(_items(4), 4, B.PW_F32, None, h) in _no_gpu_status()
+    assert h.value is None
+
+
+def test_batch_null_handle(lib):
+    for fn in (lib.pw_batch_run, lib.pw_batch_replay):
+        assert fn(None, None) == B.PW_ERR_INVALID_ARG
+    assert lib.pw_batch_capture(None, None) == B.PW_ERR_INVALID_ARG
+    assert lib.pw_batch_tune(None, None, None) == B.PW_ERR_INVALID_ARG
+    assert lib.pw_batch_destroy(None) == B.PW_OK
+
+
+def test_tune_argument_errors(lib):
+    assert lib.pw_tune(None, B.PW_F32, 0, None, None) == B.PW_ERR_INVALID_ARG
+    g = B.pw_grid(0, 8, 8, 1)
+    assert B.pw_tune(g, B.PW_F32) == B.PW_ERR_INVALID_ARG
+    g = B.pw_grid(8, 8, 8, 1)
+    assert B.pw_tune(g, 9) == B.PW_ERR_INVALID_ARG
+    assert B.pw_tune(g, B.PW_F32, flags=8) == B.PW_ERR_INVALID_ARG
+    assert B.pw_tune(g, B.PW_F32) in (B.PW_ERR_NO_DEVICE, B.PW_OK)   # OK where a GPU is present
+    assert B.pw_tune_reset() == B.PW_OK

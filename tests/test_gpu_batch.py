@@ -1,0 +1,178 @@
+"""GPU tests of the batched persistent form, its HIP-graph capture/replay and
+the autotuners.  The per-point arithmetic is the single-grid kernel's, so
+batched results must equal single-grid launches bit for bit, and both must
+match the FP64 oracle to the FP32 bound (A-scaled 1e-6)."""
+import os
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import dev_grid, oracle_errors, sample_boxes, subbox_errors
+from paper_2301_13016_amd import binding as B
+from paper_2301_13016_amd import workloads as wl
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("no GPU", allow_module_level=True)
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(autouse=True)
+def _announce(request):
+    sys.__stderr__.write("\n[gpu-test] %s\n" % request.node.nodeid)
+    sys.__stderr__.flush()
+    yield
+
+
+SMALL = [(70, 13, 9), (1, 1, 1), (129, 4, 17), (64, 64, 3), (200, 7, 33), (5, 90, 2), (256, 2, 5), (300, 3, 4)]
+
+
+def make_subs(grids):
+    subs, host = [], []
+    for g in grids:
+        (u, v, w), c = dev_grid(g)
+        outs = tuple(torch.full((g.nz, g.ny, g.nx), float("nan"), device="cuda") for _ in range(3))
+        subs.append((u, v, w, c, outs))
+        host.append(g)
+    return subs, host
+
+
+def single(sub):
+    u, v, w, c, _ = sub
+    out = B.advect(u, v, w, c)
+    return [o.clone() for o in out]
+
+
+@pytest.fixture(scope="module")
+def small_batch():
+    grids = [wl.make_grid(*s, seed=500 + i) for i, s in enumerate(SMALL)]
+    return make_subs(grids)
+
+
+@pytest.mark.parametrize("tile", [None, (1, 2, 8, 4), (2, 1, 16, 1), (4, 2, 5, 2), (1, 4, 64, 8)])
+def test_batch_equals_single_grid_and_oracle(small_batch, tile):
+    subs, grids = small_batch
+    ref = [single(s) for s in subs]
+    for s in subs:
+        for o in s[4]:
+            o.fill_(float("nan"))
+    b = B.Batch(subs, tile=tile)
+    b.run()
+    torch.cuda.synchronize()
+    for s, r, g in zip(subs, ref, grids):
+        for o, rr in zip(s[4], r):
+            assert torch.equal(o, rr)
+        errs = oracle_errors([o.cpu().numpy() for o in s[4]], g.u, g.v, g.w, g.coeffs)
+        assert max(e for e, _ in errs) <= 1e-6
+    b.close()
+
+
+def test_graph_capture_replay(small_batch):
+    """Capture once, replay several times with unrelated eager work and
+    synchronisations in between; every replay reproduces the eager result."""
+    subs, _ = small_batch
+    b = B.Batch(subs)
+    b.run()
+    torch.cuda.synchronize()
+    eager = [[o.clone() for o in s[4]] for s in subs]
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        b.capture(stream)
+    torch.cuda.synchronize()
+    scratch = torch.randn(1 << 20, device="cuda")
+    for rep in range(4):
+        for s in subs:
+            for o in s[4]:
+                o.zero_()
+        scratch.mul_(1.0001).add_(0.5)      # unrelated eager work
+        single(subs[rep % len(subs)])        # and an eager library call
+        torch.cuda.synchronize()
+        b.replay(stream)
+        stream.synchronize()
+        for s, e in zip(subs, eager):
+            for o, x in zip(s[4], e):
+                assert torch.equal(o, x), rep
+    b.close()
+
+
+def test_replay_requires_capture_and_tune_invalidates(small_batch):
+    subs, _ = small_batch
+    b = B.Batch(subs)
+    with pytest.raises(B.PWError):
+        b.replay()
+    stream = torch.cuda.Stream()
+    b.capture(stream)
+    ref = [[o.clone() for o in s[4]] for s in subs]
+    tile = b.tune()
+    assert b.info()[0] == tile
+    with pytest.raises(B.PWError):   # re-tiling dropped the graph
+        b.replay()
+    b.run()
+    torch.cuda.synchronize()
+    for s, e in zip(subs, ref):
+        for o, x in zip(s[4], e):
+            assert torch.equal(o, x)
+    b.close()
+
+
+@pytest.fixture(scope="module")
+def batch_c3():
+    grids = wl.batch_grids()
+    return make_subs(grids)
+
+
+def test_c3_batch_matches_plain_launches(batch_c3, report):
+    """The 64 uneven subdomains: one persistent launch equals 64 plain
+    launches bit for bit, and sampled sub-boxes of four subdomains match the
+    oracle."""
+    subs, grids = batch_c3
+    ref = [single(s) for s in subs]
+    b = B.Batch(subs)
+    b.tune()
+    b.run()
+    torch.cuda.synchronize()
+    for s, r in zip(subs, ref):
+        for o, rr in zip(s[4], r):
+            assert torch.equal(o, rr)
+    worst = 0.0
+    for i in (0, 17, 42, 63):
+        g = grids[i]
+        boxes = sample_boxes(g.nx, g.ny, g.nz, n_random=2, seed=i)
+        worst = max(worst, max(subbox_errors(subs[i][4], g, boxes)))
+    tile, items, groups = b.info()
+    report["batch_c3"] = dict(points=sum(g.points for g in grids), tile=tile, work_items=items,
+                              workgroups=groups, worst_err_a_scaled=worst)
+    assert worst <= 1e-6
+    b.close()
+
+
+def test_single_grid_tuner_and_cache_file(tmp_path):
+    """pw_tune in a fresh process: writes the cache file, results are
+    unchanged (shape never changes results), a second process reads it."""
+    cache = tmp_path / "tune.txt"
+    code = r'''
+import sys, numpy as np, torch
+sys.path.insert(0, %r); sys.path.insert(0, %r)
+from paper_2301_13016_amd import binding as B, workloads as wl
+from gpu_util import dev_grid
+g = wl.make_grid(300, 40, 24, seed=9)
+(u, v, w), c = dev_grid(g)
+a = [o.clone() for o in B.advect(u, v, w, c)]
+print("TILES", B.tune(300, 40, 24, torch.float32))
+b = B.advect(u, v, w, c)
+torch.cuda.synchronize()
+assert all(torch.equal(x, y) for x, y in zip(a, b))
+print("OK")
+''' % (ROOT, os.path.join(ROOT, "tests"))
+    env = dict(os.environ, PWADV_TUNE_CACHE=str(cache))
+    r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr[-2000:]
+    assert "OK" in r.stdout
+    lines = cache.read_text().splitlines()
+    assert len(lines) == 2 and all(l.startswith("pwadv-tune-v1 ") for l in lines)

@@ -6,8 +6,8 @@ differences, reduction, store: the whole hot path) over the FP32 grid
 HBM.  K steps are timed between two device synchronisations; consecutive steps
 use different buffer sets (4 x 410 MB) so the 256 MB MALL cannot serve a
 repeat.  The dominant kernel's average duration comes from HIP events around
-each launch on the launch stream.  The library's autotuner picks the launch
-shape before timing (outside the timed region).
+each launch on the launch stream.  Launch shapes are the library's choice
+(its built-in tuning table); the batched form is tuned in the run.
 
 Also measured in the same run ("forms"):
   * BF16 / FP16 storage vs FP32 on 1024 x 1024 x 256 (268 M points);
@@ -124,8 +124,7 @@ def main():
     # ------------------------------------------------------------ headline: c1 FP32
     cfg = wl.C1
     nx, ny, nz, h = cfg["nx"], cfg["ny"], cfg["nz"], 1
-    tiles = {"c1_fp32": B.tune(nx, ny, nz, torch.float32, flags=B.PW_TUNE_FORWARD)[0]}
-    log("tuned c1 tile:", tiles["c1_fp32"])
+    tiles = {}
     g = wl.config_grid(cfg)
     coeffs = B.Coeffs.from_host(g.coeffs, device=dev)
     nsets = 4
@@ -182,15 +181,13 @@ def main():
     pts2 = n2[0] * n2[1] * n2[2]
     res2 = {}
     for name, dt in (("fp32", torch.float32), ("bf16", torch.bfloat16), ("fp16", torch.float16)):
-        tiles["c2_" + name] = B.tune(*n2, dt, flags=B.PW_TUNE_FORWARD)[0]
         ins = f32 if dt == torch.float32 else [x.to(dt) for x in f32]
         call = prebuilt_forward(B, ins, outs2, co2, stream)
         _, kms2 = time_launches(torch, lambda i: call(), 1, 30, 3, stream)
         eb = 2 if dt != torch.float32 else 4
         res2[name] = dict(gpts=round(pts2 / (kms2 * 1e-3) / 1e9, 2), kernel_ms=round(kms2, 4),
-                          hbm_gbs=round(algo_bytes(*n2, 1, eb) / (kms2 * 1e-3) / 1e9, 1),
-                          tile=tiles["c2_" + name])
-        log("c2 %s: kernel %.4f ms, %.1f Gpt/s (tile %s)" % (name, kms2, res2[name]["gpts"], tiles["c2_" + name]))
+                          hbm_gbs=round(algo_bytes(*n2, 1, eb) / (kms2 * 1e-3) / 1e9, 1))
+        log("c2 %s: kernel %.4f ms, %.1f Gpt/s" % (name, kms2, res2[name]["gpts"]))
         if dt != torch.float32:
             del ins
     for name in ("bf16", "fp16"):
@@ -203,7 +200,6 @@ def main():
     c4 = wl.C4
     n4 = (c4["nx"], c4["ny"], c4["nz"])
     g4 = wl.config_grid(c4)
-    fwd4, adj4 = B.tune(*n4, torch.float32)
     co4 = B.Coeffs.from_host(g4.coeffs, device=dev)
     ins4 = [torch.from_numpy(x).to(dev) for x in (g4.u, g4.v, g4.w)]
     cot4 = [torch.from_numpy(x).to(dev) for x in wl.cotangents(*n4, c4["cot_seed"])]
@@ -217,7 +213,7 @@ def main():
         forward_ms=round(fms, 4), adjoint_ms=round(ams, 4), adjoint_over_forward=round(ams / fms, 3),
         ideal_ratio_from_bytes=round(adjoint_bytes(*n4, 1) / algo_bytes(*n4, 1, 4), 3),
         adjoint_gpts=round(pts4 / (ams * 1e-3) / 1e9, 2),
-        adjoint_hbm_gbs=round(adjoint_bytes(*n4, 1) / (ams * 1e-3) / 1e9, 1), tiles=[fwd4, adj4])
+        adjoint_hbm_gbs=round(adjoint_bytes(*n4, 1) / (ams * 1e-3) / 1e9, 1))
     log("c4: forward %.4f ms, adjoint %.4f ms, ratio %.3f" % (fms, ams, ams / fms))
     del ins4, cot4, o4, gr4
     torch.cuda.empty_cache()
@@ -278,7 +274,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic (seeded uniform winds in [-10,10], per-level coefficients)",
         "config": {"workload": cfg["name"], "nx": nx, "ny": ny, "nz": nz, "halo": h,
-                   "points": pts, "buffer_sets": nsets, "tile": tiles["c1_fp32"]},
+                   "points": pts, "buffer_sets": nsets},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                      "algorithmic_bytes_per_launch": nbytes, "kernel_ms": round(k_ms, 6),

@@ -171,13 +171,16 @@ pw_status pw_advect_adjoint_ex(const pw_grid *grid, const pw_layout *layout, pw_
  * as a number of chunks, so an entry serves every nz of its class.  If the
  * environment variable PWADV_TUNE_CACHE names a file, the table is read from
  * it on first use (unreadable or malformed lines are ignored) and rewritten
- * after each pw_tune.  fwd_best / adj_best (may be NULL) receive the chosen
- * shapes.  Allocates device memory; synchronises its own stream. */
+ * after each pw_tune.  Entries measured on MI355X for common shape classes
+ * are built in and used when nothing else is known.  fwd_best / adj_best (may
+ * be NULL) receive the chosen shapes.  Allocates device memory; synchronises
+ * its own stream. */
 #define PW_TUNE_FORWARD 1
 #define PW_TUNE_ADJOINT 2
 pw_status pw_tune(const pw_grid *grid, pw_dtype dtype, int32_t flags, pw_tile *fwd_best, pw_tile *adj_best);
 
-/* Empties the process-wide tuning table (the cache file is left as is). */
+/* Empties the process-wide tuning table, built-in entries included (the
+ * cache file is left as is). */
 pw_status pw_tune_reset(void);
 
 /* ------------------------------------------------------------------------

@@ -92,7 +92,8 @@ pw_status launch_fwd_px(const FwdArgs &g, const TileCfg &cfg, hipStream_t s) {
         case 1: return launch_fwd_t<Tin, PX, 1>(g, cfg, s);
         case 2: return launch_fwd_t<Tin, PX, 2>(g, cfg, s);
         case 4:
-            if constexpr (sizeof(Tin) <= 4 && PX <= 2) return launch_fwd_t<Tin, PX, 4>(g, cfg, s);
+            if constexpr ((sizeof(Tin) <= 4 && PX <= 2) || (sizeof(Tin) == 2 && PX == 4))
+                return launch_fwd_t<Tin, PX, 4>(g, cfg, s);
             [[fallthrough]];
         default:
             return fail(PW_ERR_UNSUPPORTED, "rows per strip %d with %d columns per lane not instantiated", cfg.ry,
@@ -107,6 +108,9 @@ pw_status launch_fwd_dt(const FwdArgs &g, const TileCfg &cfg, hipStream_t s) {
         case 2: return launch_fwd_px<Tin, 2>(g, cfg, s);
         case 4:
             if constexpr (sizeof(Tin) <= 4) return launch_fwd_px<Tin, 4>(g, cfg, s);
+            return fail(PW_ERR_UNSUPPORTED, "4 columns per lane not instantiated for this dtype");
+        case 8:
+            if constexpr (sizeof(Tin) == 2) return launch_fwd_px<Tin, 8>(g, cfg, s);
             [[fallthrough]];
         default: return fail(PW_ERR_UNSUPPORTED, "%d columns per lane not instantiated", cfg.px);
     }
@@ -127,8 +131,10 @@ __global__ __launch_bounds__(256) void copy16_kernel(const u32x4 *__restrict__ s
 
 bool tile_supported(const TileCfg &c, pw_dtype dt) {
     if (c.zlen < 1 || c.wpb < 1 || c.wpb > 8) return false;
+    const bool half = dt == PW_BF16 || dt == PW_F16;
     if (dt == PW_F64) return (c.px == 1 || c.px == 2) && (c.ry == 1 || c.ry == 2);
-    if (c.px == 4) return c.ry == 1 || c.ry == 2;
+    if (c.px == 8) return half && (c.ry == 1 || c.ry == 2);
+    if (c.px == 4) return c.ry == 1 || c.ry == 2 || (half && c.ry == 4);
     return (c.px == 1 || c.px == 2) && (c.ry == 1 || c.ry == 2 || c.ry == 4);
 }
 

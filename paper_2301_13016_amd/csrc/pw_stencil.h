@@ -35,11 +35,14 @@ template <typename T, int N> struct Vec;
 template <typename T> struct Vec<T, 1> { using type = T; };
 template <> struct Vec<float, 2> { typedef float type __attribute__((ext_vector_type(2), aligned(4))); };
 template <> struct Vec<float, 4> { typedef float type __attribute__((ext_vector_type(4), aligned(4))); };
+template <> struct Vec<float, 8> { typedef float type __attribute__((ext_vector_type(8), aligned(4))); };
 template <> struct Vec<double, 2> { typedef double type __attribute__((ext_vector_type(2), aligned(8))); };
 template <> struct Vec<uint16_t, 2> { typedef uint16_t type __attribute__((ext_vector_type(2), aligned(2))); };
 template <> struct Vec<uint16_t, 4> { typedef uint16_t type __attribute__((ext_vector_type(4), aligned(2))); };
 template <> struct Vec<_Float16, 2> { typedef _Float16 type __attribute__((ext_vector_type(2), aligned(2))); };
 template <> struct Vec<_Float16, 4> { typedef _Float16 type __attribute__((ext_vector_type(4), aligned(2))); };
+template <> struct Vec<uint16_t, 8> { typedef uint16_t type __attribute__((ext_vector_type(8), aligned(2))); };
+template <> struct Vec<_Float16, 8> { typedef _Float16 type __attribute__((ext_vector_type(8), aligned(2))); };
 
 template <typename T, int N>
 __device__ __forceinline__ T comp(const typename Vec<T, N>::type &v, int m) {
@@ -105,12 +108,13 @@ template <typename Tin> struct FwdK {
     int32_t ntx, nty, nzc, zlen, wpb;
 };
 
-// One z-plane of the strip, widened: rows 0..RY+1 are the strip's rows
-// jj0-1 .. jj0+RY (interior numbering), PX columns of this lane each; hu/hv/hw
-// are the packed halo columns (see left_of / right_of).
-template <typename Tc, int PX, int RY> struct Plane {
-    Tc u[RY + 2][PX], v[RY + 2][PX], w[RY + 2][PX];
-    Tc hu, hv, hw;
+// One z-plane of the strip as loaded: rows 0..RY+1 are the strip's rows
+// jj0-1 .. jj0+RY (interior numbering), each the lane's PX columns in storage
+// precision (16-bit values stay packed two per register and are widened when
+// read); hu/hv/hw are the packed halo columns (see left_of / right_of).
+template <typename Tin, int PX, int RY> struct Plane {
+    typename Vec<Tin, PX>::type u[RY + 2], v[RY + 2], w[RY + 2];
+    Tin hu, hv, hw;
 };
 
 // Per-lane addressing of the strip, fixed for the whole march.
@@ -127,25 +131,22 @@ template <int RY> struct StripAddr {
 // output reads is in range, so clamping only affects values that are not
 // used).  The choice is made per wavefront, so neither path branches per lane.
 template <typename Tin, int PX, bool Full>
-__device__ __forceinline__ void load_row(typename Storage<Tin>::Tc (&dst)[PX], const char *plane, uint32_t off,
-                                         int col, int last_col) {
+__device__ __forceinline__ void load_row(typename Vec<Tin, PX>::type &dst, const char *plane, uint32_t off, int col,
+                                         int last_col) {
     if constexpr (Full || PX == 1) {
         (void)col;
         (void)last_col;
-        const auto x = *reinterpret_cast<const typename Vec<Tin, PX>::type *>(plane + off);
-#pragma unroll
-        for (int m = 0; m < PX; ++m) dst[m] = Storage<Tin>::widen(comp<Tin, PX>(x, m));
+        dst = *reinterpret_cast<const typename Vec<Tin, PX>::type *>(plane + off);
     } else {
         const char *row = plane + off - static_cast<int64_t>(col) * static_cast<int64_t>(sizeof(Tin));
 #pragma unroll
         for (int m = 0; m < PX; ++m)
-            dst[m] = Storage<Tin>::widen(
-                *reinterpret_cast<const Tin *>(row + static_cast<int64_t>(min(col + m, last_col)) * sizeof(Tin)));
+            dst[m] = *reinterpret_cast<const Tin *>(row + static_cast<int64_t>(min(col + m, last_col)) * sizeof(Tin));
     }
 }
 
 template <typename Tin, int PX, int RY, bool Full>
-__device__ __forceinline__ void load_plane(Plane<typename Storage<Tin>::Tc, PX, RY> &P, const FwdK<Tin> &a,
+__device__ __forceinline__ void load_plane(Plane<Tin, PX, RY> &P, const FwdK<Tin> &a,
                                            int kp, const StripAddr<RY> &s, int last_col) {
     const int64_t pb = static_cast<int64_t>(kp) * a.in_sz * static_cast<int64_t>(sizeof(Tin));
     const char *bu = reinterpret_cast<const char *>(a.u) + pb;
@@ -157,9 +158,9 @@ __device__ __forceinline__ void load_plane(Plane<typename Storage<Tin>::Tc, PX, 
         load_row<Tin, PX, Full>(P.v[r], bv, s.roff[r], s.col, last_col);
         load_row<Tin, PX, Full>(P.w[r], bw, s.roff[r], s.col, last_col);
     }
-    P.hu = Storage<Tin>::widen(*reinterpret_cast<const Tin *>(bu + s.hoff));
-    P.hv = Storage<Tin>::widen(*reinterpret_cast<const Tin *>(bv + s.hoff));
-    P.hw = Storage<Tin>::widen(*reinterpret_cast<const Tin *>(bw + s.hoff));
+    P.hu = *reinterpret_cast<const Tin *>(bu + s.hoff);
+    P.hv = *reinterpret_cast<const Tin *>(bv + s.hoff);
+    P.hw = *reinterpret_cast<const Tin *>(bw + s.hoff);
 }
 
 template <typename T, int N> __device__ __forceinline__ void store_vec(char *p, const T (&x)[N]) {
@@ -176,12 +177,14 @@ template <typename T, int N> __device__ __forceinline__ void store_vec(char *p, 
 // Source terms of output level kk (interior numbering) from planes kk-1 (m),
 // kk (c) and kk+1 (p); stores the lanes/rows that own outputs.
 template <typename Tin, int PX, int RY, bool Full>
-__device__ __forceinline__ void level(const Plane<typename Storage<Tin>::Tc, PX, RY> &m,
-                                      const Plane<typename Storage<Tin>::Tc, PX, RY> &c,
-                                      const Plane<typename Storage<Tin>::Tc, PX, RY> &p,
+__device__ __forceinline__ void level(const Plane<Tin, PX, RY> &m, const Plane<Tin, PX, RY> &c,
+                                      const Plane<Tin, PX, RY> &p,
                                       const FwdK<Tin> &a, int kk, bool lane0, bool lane63, int nvalid,
                                       const uint32_t (&ooff)[RY], const bool (&row_ok)[RY]) {
     using Tc = typename Storage<Tin>::Tc;
+    // element (row r, column x) of a loaded row array, widened
+#define G(arr, r, x) Storage<Tin>::widen(comp<Tin, PX>((arr)[r], (x)))
+#define W(h) Storage<Tin>::widen(h)
     const Tc z1 = a.tzc1[kk], z2 = a.tzc2[kk], d1 = a.tzd1[kk], d2 = a.tzd2[kk];
     const Tc tcx = a.tcx, tcy = a.tcy;
 
@@ -190,18 +193,18 @@ __device__ __forceinline__ void level(const Plane<typename Storage<Tin>::Tc, PX,
     Tc uL[RY + 2], uR[RY + 2], vL[RY + 2], vR[RY + 2], wL[RY + 2], wR[RY + 2], wRm[RY + 2], uLp[RY + 2];
 #pragma unroll
     for (int r = 0; r < RY + 2; ++r) {
-        uL[r] = left_of(c.u[r][PX - 1], c.hu, r, lane0);
-        uR[r] = right_of(c.u[r][0], c.hu, r, lane63);
-        vL[r] = left_of(c.v[r][PX - 1], c.hv, r, lane0);
-        vR[r] = right_of(c.v[r][0], c.hv, r, lane63);
-        wL[r] = left_of(c.w[r][PX - 1], c.hw, r, lane0);
-        wR[r] = right_of(c.w[r][0], c.hw, r, lane63);
-        wRm[r] = right_of(m.w[r][0], m.hw, r, lane63);
-        uLp[r] = left_of(p.u[r][PX - 1], p.hu, r, lane0);
+        uL[r] = left_of(G(c.u, r, PX - 1), W(c.hu), r, lane0);
+        uR[r] = right_of(G(c.u, r, 0), W(c.hu), r, lane63);
+        vL[r] = left_of(G(c.v, r, PX - 1), W(c.hv), r, lane0);
+        vR[r] = right_of(G(c.v, r, 0), W(c.hv), r, lane63);
+        wL[r] = left_of(G(c.w, r, PX - 1), W(c.hw), r, lane0);
+        wR[r] = right_of(G(c.w, r, 0), W(c.hw), r, lane63);
+        wRm[r] = right_of(G(m.w, r, 0), W(m.hw), r, lane63);
+        uLp[r] = left_of(G(p.u, r, PX - 1), W(p.hu), r, lane0);
     }
     // value at (row r, column x-1) / (row r, column x+1) of a plane array
-#define XM(arr, L, r, x) ((x) == 0 ? L[r] : arr[r][(x) - 1])
-#define XP(arr, R, r, x) ((x) == PX - 1 ? R[r] : arr[r][(x) + 1])
+#define XM(arr, L, r, x) ((x) == 0 ? L[r] : G(arr, r, (x) - 1))
+#define XP(arr, R, r, x) ((x) == PX - 1 ? R[r] : G(arr, r, (x) + 1))
 
     // Face sums shared by consecutive rows of the strip (index r = loaded row):
     //   fy = v(k,r,i) + v(k,r,i+1)   gy = v(k,r,i) + v(k,r+1,i)   hy = v(k,r,i) + v(k+1,r,i)
@@ -210,9 +213,9 @@ __device__ __forceinline__ void level(const Plane<typename Storage<Tin>::Tc, PX,
     for (int r = 0; r <= RY; ++r) {
 #pragma unroll
         for (int x = 0; x < PX; ++x) {
-            fy[r][x] = c.v[r][x] + XP(c.v, vR, r, x);
-            gy[r][x] = c.v[r][x] + c.v[r + 1][x];
-            hy[r][x] = c.v[r][x] + p.v[r][x];
+            fy[r][x] = G(c.v, r, x) + XP(c.v, vR, r, x);
+            gy[r][x] = G(c.v, r, x) + G(c.v, r + 1, x);
+            hy[r][x] = G(c.v, r, x) + G(p.v, r, x);
         }
     }
 
@@ -228,43 +231,43 @@ __device__ __forceinline__ void level(const Plane<typename Storage<Tin>::Tc, PX,
 #pragma unroll
         for (int x = 0; x < PX; ++x) {
             // su: x faces (u+u), y faces (v+v at i, i+1), z faces (w+w at i, i+1)
-            const Tc uc = c.u[q][x];
+            const Tc uc = G(c.u, q, x);
             const Tc ul = XM(c.u, uL, q, x), ur = XP(c.u, uR, q, x);
             const Tc ax = fma_(-ur, uc + ur, ul * (uc + ul));
-            const Tc ay = fma_(-c.u[q + 1][x], fy[q][x], c.u[q - 1][x] * fy[r][x]);
-            const Tc fzm = m.w[q][x] + XP(m.w, wRm, q, x);
-            const Tc fzp = c.w[q][x] + XP(c.w, wR, q, x);
+            const Tc ay = fma_(-G(c.u, q + 1, x), fy[q][x], G(c.u, q - 1, x) * fy[r][x]);
+            const Tc fzm = G(m.w, q, x) + XP(m.w, wRm, q, x);
+            const Tc fzp = G(c.w, q, x) + XP(c.w, wR, q, x);
             Tc su = tcx * ax;
             su = fma_(tcy, ay, su);
-            su = fma_(z1 * m.u[q][x], fzm, su);
-            su = fma_(-(z2 * p.u[q][x]), fzp, su);
+            su = fma_(z1 * G(m.u, q, x), fzm, su);
+            su = fma_(-(z2 * G(p.u, q, x)), fzp, su);
 
             // sv: x faces (u+u at j, j+1), y faces (v+v), z faces (w+w at j, j+1)
             const Tc vl = XM(c.v, vL, q, x), vr = XP(c.v, vR, q, x);
-            const Tc gxp = uc + c.u[q + 1][x];
+            const Tc gxp = uc + G(c.u, q + 1, x);
             const Tc gxm = ul + XM(c.u, uL, q + 1, x);
             const Tc bx = fma_(-vr, gxp, vl * gxm);
-            const Tc by = fma_(-c.v[q + 1][x], gy[q][x], c.v[q - 1][x] * gy[r][x]);
-            const Tc gzm = m.w[q][x] + m.w[q + 1][x];
-            const Tc gzp = c.w[q][x] + c.w[q + 1][x];
+            const Tc by = fma_(-G(c.v, q + 1, x), gy[q][x], G(c.v, q - 1, x) * gy[r][x]);
+            const Tc gzm = G(m.w, q, x) + G(m.w, q + 1, x);
+            const Tc gzp = G(c.w, q, x) + G(c.w, q + 1, x);
             Tc sv = tcx * bx;
             sv = fma_(tcy, by, sv);
-            sv = fma_(z1 * m.v[q][x], gzm, sv);
-            sv = fma_(-(z2 * p.v[q][x]), gzp, sv);
+            sv = fma_(z1 * G(m.v, q, x), gzm, sv);
+            sv = fma_(-(z2 * G(p.v, q, x)), gzp, sv);
 
             // sw: x faces (u+u at k, k+1), y faces (v+v at k, k+1), z faces (w+w)
-            const Tc wc = c.w[q][x];
+            const Tc wc = G(c.w, q, x);
             const Tc wl = XM(c.w, wL, q, x), wr = XP(c.w, wR, q, x);
-            const Tc hxp = uc + p.u[q][x];
+            const Tc hxp = uc + G(p.u, q, x);
             const Tc hxm = ul + XM(p.u, uLp, q, x);
             const Tc cx = fma_(-wr, hxp, wl * hxm);
-            const Tc cy = fma_(-c.w[q + 1][x], hy[q][x], c.w[q - 1][x] * hy[r][x]);
-            const Tc hzm = wc + m.w[q][x];
-            const Tc hzp = wc + p.w[q][x];
+            const Tc cy = fma_(-G(c.w, q + 1, x), hy[q][x], G(c.w, q - 1, x) * hy[r][x]);
+            const Tc hzm = wc + G(m.w, q, x);
+            const Tc hzp = wc + G(p.w, q, x);
             Tc sw = tcx * cx;
             sw = fma_(tcy, cy, sw);
-            sw = fma_(d1 * m.w[q][x], hzm, sw);
-            sw = fma_(-(d2 * p.w[q][x]), hzp, sw);
+            sw = fma_(d1 * G(m.w, q, x), hzm, sw);
+            sw = fma_(-(d2 * G(p.w, q, x)), hzp, sw);
 
             rsu[x] = su;
             rsv[x] = sv;
@@ -290,6 +293,8 @@ __device__ __forceinline__ void level(const Plane<typename Storage<Tin>::Tc, PX,
     }
 #undef XM
 #undef XP
+#undef G
+#undef W
 }
 
 // Workgroup -> tile numbering.  Workgroups are handed to the 8 XCDs round
@@ -344,7 +349,7 @@ __device__ __forceinline__ void strip_march_t(const FwdK<Tin> &a, int tx, int ty
     const int k1 = min(a.nz, k0 + a.zlen);
     const int h = a.h;
 
-    Plane<Tc, PX, RY> A, B, C, D;
+    Plane<Tin, PX, RY> A, B, C, D;
     load_plane<Tin, PX, RY, Full>(A, a, k0 - 1 + h, s, last_col);
     load_plane<Tin, PX, RY, Full>(B, a, k0 + h, s, last_col);
     load_plane<Tin, PX, RY, Full>(C, a, k0 + 1 + h, s, last_col);
@@ -367,10 +372,15 @@ __device__ __forceinline__ void strip_march_t(const FwdK<Tin> &a, int tx, int ty
 
 template <typename Tin, int PX, int RY>
 __device__ __forceinline__ void strip_march(const FwdK<Tin> &a, int tx, int ty, int cz) {
-    if ((tx + 1) * 64 * PX <= a.nx)
-        strip_march_t<Tin, PX, RY, true>(a, tx, ty, cz);
-    else
+    if constexpr (PX == 1) {
+        // one-column lanes: loads never need clamping beyond the start column,
+        // and one masked store per row is cheap, so one path serves every strip
         strip_march_t<Tin, PX, RY, false>(a, tx, ty, cz);
+    } else if ((tx + 1) * 64 * PX <= a.nx) {
+        strip_march_t<Tin, PX, RY, true>(a, tx, ty, cz);
+    } else {
+        strip_march_t<Tin, PX, RY, false>(a, tx, ty, cz);
+    }
 }
 
 }  // namespace dev

@@ -58,6 +58,7 @@ template <typename T> struct AdjK {
 template <typename T, int RY> struct APlane {
     T u[RY + 2], v[RY + 2], w[RY + 2];
     T ru[RY + 2], rv[RY + 2], rw[RY + 2];
+    bool zok;   // the plane is an interior level, so its cotangents exist (wave-uniform)
 };
 
 template <typename T, int RY> struct StripAddr {
@@ -81,46 +82,50 @@ __device__ __forceinline__ void load_aplane(APlane<T, RY> &P, const AdjK<T> &a, 
         P.v[r] = *reinterpret_cast<const T *>(bv + s.voff[r]);
         P.w[r] = *reinterpret_cast<const T *>(bw + s.voff[r]);
     }
+    // Cotangents: every load from a clamped (valid) address and without a
+    // branch, so that the plane's loads stay in flight until its first use,
+    // where mask_aplane zeroes what lies outside the interior.
     const int kk = kp - a.h;
-    if (kk >= 0 && kk < a.nz) {
-        const int64_t ob = static_cast<int64_t>(kk) * a.out_sz * static_cast<int64_t>(sizeof(T));
-        const char *cu = reinterpret_cast<const char *>(a.ru) + ob;
-        const char *cv = reinterpret_cast<const char *>(a.rv) + ob;
-        const char *cw = reinterpret_cast<const char *>(a.rw) + ob;
+    P.zok = kk >= 0 && kk < a.nz;
+    const int kc = min(max(kk, 0), a.nz - 1);
+    const int64_t ob = static_cast<int64_t>(kc) * a.out_sz * static_cast<int64_t>(sizeof(T));
+    const char *cu = reinterpret_cast<const char *>(a.ru) + ob;
+    const char *cv = reinterpret_cast<const char *>(a.rv) + ob;
+    const char *cw = reinterpret_cast<const char *>(a.rw) + ob;
 #pragma unroll
-        for (int r = 0; r < RY + 2; ++r) {
-            if (s.rrow[r]) {
-                const T xu = *reinterpret_cast<const T *>(cu + s.roff[r]);
-                const T xv = *reinterpret_cast<const T *>(cv + s.roff[r]);
-                const T xw = *reinterpret_cast<const T *>(cw + s.roff[r]);
-                P.ru[r] = s.rcol ? xu : T(0);
-                P.rv[r] = s.rcol ? xv : T(0);
-                P.rw[r] = s.rcol ? xw : T(0);
-            } else {
-                P.ru[r] = T(0);
-                P.rv[r] = T(0);
-                P.rw[r] = T(0);
-            }
-        }
-    } else {
-#pragma unroll
-        for (int r = 0; r < RY + 2; ++r) {
-            P.ru[r] = T(0);
-            P.rv[r] = T(0);
-            P.rw[r] = T(0);
-        }
+    for (int r = 0; r < RY + 2; ++r) {
+        P.ru[r] = *reinterpret_cast<const T *>(cu + s.roff[r]);
+        P.rv[r] = *reinterpret_cast<const T *>(cv + s.roff[r]);
+        P.rw[r] = *reinterpret_cast<const T *>(cw + s.roff[r]);
     }
 }
 
+// Zero the cotangents of a loaded plane outside the interior (once per plane,
+// at its first use).
+template <typename T, int RY>
+__device__ __forceinline__ void mask_aplane(APlane<T, RY> &P, const StripAddr<T, RY> &s) {
+#pragma unroll
+    for (int r = 0; r < RY + 2; ++r) {
+        const bool ok = P.zok && s.rrow[r] && s.rcol;
+        P.ru[r] = ok ? P.ru[r] : T(0);
+        P.rv[r] = ok ? P.rv[r] : T(0);
+        P.rw[r] = ok ? P.rw[r] : T(0);
+    }
+}
+
+// Coefficient at a wave-uniform level, as a scalar load through the constant
+// address space (the library rejects gradients that overlap the coefficient
+// arrays); clamped: only ever met by a zero cotangent when outside.
 template <typename T> __device__ __forceinline__ T coef(const T *c, int kk, int nz) {
-    return c[min(max(kk, 0), nz - 1)];   // clamped: only ever met by a zero cotangent when outside
+    return ((const __attribute__((address_space(4))) T *)(c))[min(max(kk, 0), nz - 1)];
 }
 
 // Gradients at padded level kp from planes kp-1 (m), kp (c), kp+1 (p).
 template <typename T, int RY>
-__device__ __forceinline__ void adj_level(const APlane<T, RY> &m, const APlane<T, RY> &c, const APlane<T, RY> &p,
-                                          const AdjK<T> &a, int kp, bool lane_ok,
+__device__ __forceinline__ void adj_level(const APlane<T, RY> &m, const APlane<T, RY> &c, APlane<T, RY> &p,
+                                          const AdjK<T> &a, const StripAddr<T, RY> &s, int kp, bool lane_ok,
                                           const uint32_t (&goff)[RY], const bool (&row_ok)[RY]) {
+    mask_aplane<T, RY>(p, s);   // first use of plane kp+1
     const int kq = kp - a.h;   // interior level index of this gradient plane
     const T tcx = a.tcx, tcy = a.tcy;
     const T c1p = coef(a.tzc1, kq + 1, a.nz), c2m = coef(a.tzc2, kq - 1, a.nz), c2 = coef(a.tzc2, kq, a.nz);
@@ -225,7 +230,8 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
 template <typename T, int RY>
 __global__ __launch_bounds__(512) void pw_adjoint_kernel(AdjK<T> a) {
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    // wavefront index as a scalar, so that per-strip conditions stay scalar
+    const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
     const int t = xcd_tile(blockIdx.x, gridDim.x);
     const int cz = t % a.nzc;
     const int t2 = t / a.nzc;
@@ -268,19 +274,21 @@ __global__ __launch_bounds__(512) void pw_adjoint_kernel(AdjK<T> a) {
     load_aplane<T, RY>(A, a, k0 - 1, s);
     load_aplane<T, RY>(B, a, k0, s);
     load_aplane<T, RY>(C, a, k0 + 1, s);
+    mask_aplane<T, RY>(A, s);
+    mask_aplane<T, RY>(B, s);
     int k = k0;
     for (;;) {
         if (k + 1 < k1) load_aplane<T, RY>(D, a, k + 2, s);
-        adj_level<T, RY>(A, B, C, a, k, lane_ok, goff, row_ok);
+        adj_level<T, RY>(A, B, C, a, s, k, lane_ok, goff, row_ok);
         if (++k >= k1) break;
         if (k + 1 < k1) load_aplane<T, RY>(A, a, k + 2, s);
-        adj_level<T, RY>(B, C, D, a, k, lane_ok, goff, row_ok);
+        adj_level<T, RY>(B, C, D, a, s, k, lane_ok, goff, row_ok);
         if (++k >= k1) break;
         if (k + 1 < k1) load_aplane<T, RY>(B, a, k + 2, s);
-        adj_level<T, RY>(C, D, A, a, k, lane_ok, goff, row_ok);
+        adj_level<T, RY>(C, D, A, a, s, k, lane_ok, goff, row_ok);
         if (++k >= k1) break;
         if (k + 1 < k1) load_aplane<T, RY>(C, a, k + 2, s);
-        adj_level<T, RY>(D, A, B, a, k, lane_ok, goff, row_ok);
+        adj_level<T, RY>(D, A, B, a, s, k, lane_ok, goff, row_ok);
         if (++k >= k1) break;
     }
 }

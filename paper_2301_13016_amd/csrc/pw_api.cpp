@@ -91,6 +91,19 @@ Range out_range(const char *name, const void *p, const pw_grid *g, const Layout 
 
 bool overlap(const Range &a, const Range &b) { return a.lo < b.hi && b.lo < a.hi; }
 
+// The kernels read the coefficient arrays through the scalar cache, which is
+// only valid if nothing they write overlaps them.
+pw_status check_coeffs_apart(const pw_coeffs *c, int64_t nz, int64_t cs, const Range *outs, int nout) {
+    const void *p[4] = {c->tzc1, c->tzc2, c->tzd1, c->tzd2};
+    const char *names[4] = {"tzc1", "tzc2", "tzd1", "tzd2"};
+    for (int i = 0; i < 4; ++i) {
+        const Range r{names[i], reinterpret_cast<uintptr_t>(p[i]), reinterpret_cast<uintptr_t>(p[i]) + uintptr_t(nz * cs)};
+        for (int o = 0; o < nout; ++o)
+            if (overlap(outs[o], r)) return fail(PW_ERR_INVALID_ARG, "%s overlaps coefficient array %s", outs[o].name, r.name);
+    }
+    return PW_OK;
+}
+
 pw_status check_aligned(const char *name, const void *p, int64_t es) {
     if (!p) return fail(PW_ERR_INVALID_ARG, "%s is NULL", name);
     if (reinterpret_cast<uintptr_t>(p) % uintptr_t(es))
@@ -166,6 +179,7 @@ pw_status validate_forward(const pw_grid *grid, const pw_layout *layout, pw_dtyp
         for (const Range &o2 : rout)
             if (&o != &o2 && overlap(o, o2)) return fail(PW_ERR_INVALID_ARG, "outputs %s and %s overlap", o.name, o2.name);
     }
+    PW_TRY(check_coeffs_apart(coeffs, grid->nz, cs, rout, 3));
     FwdArgs &a = *out;
     a.u = u; a.v = v; a.w = w;
     a.su = su; a.sv = sv; a.sw = sw;
@@ -271,6 +285,7 @@ pw_status pw_advect_adjoint_ex(const pw_grid *grid, const pw_layout *layout, pw_
         for (const Range &o2 : rout)
             if (&o != &o2 && overlap(o, o2)) return fail(PW_ERR_INVALID_ARG, "gradients %s and %s overlap", o.name, o2.name);
     }
+    PW_TRY(check_coeffs_apart(coeffs, grid->nz, es, rout, 3));
     if (tile && !adjoint_tile_supported(to_cfg(*tile)))
         return fail(PW_ERR_INVALID_ARG, "unsupported adjoint tile cols=%d rows=%d zlen=%d waves=%d",
                     tile->cols_per_lane, tile->rows_per_strip, tile->zlen, tile->waves_per_group);

@@ -15,6 +15,7 @@
 // persistent kernel (a kernel node rather than a memset node, so the pair can
 // be captured in a HIP graph and replayed).  A wavefront exits when the
 // counter passes the end of the list, so every wavefront terminates.
+#include <algorithm>
 #include <cstdlib>
 #include <cstring>
 #include <vector>
@@ -245,26 +246,49 @@ pw_status pw_batch_create(const pw_batch_item *items, int32_t n, pw_dtype dtype,
             return fail(st, "item %d: %s", i, msg);
         }
     }
-    // no output of any item may overlap any input or output of another item
-    std::vector<uintptr_t> lo_in(3 * n), hi_in(3 * n), lo_out(3 * n), hi_out(3 * n);
+    // No output may overlap any other array of any item (inputs and
+    // coefficients may share memory: they are only read; the coefficients
+    // are read through the scalar cache).  One sort and sweep: in lo order, a
+    // range overlaps an earlier one iff it starts below the largest earlier
+    // end, so it suffices to track that end over all ranges and over outputs.
+    struct Span {
+        uintptr_t lo, hi;
+        int32_t item;
+        bool out;
+    };
+    std::vector<Span> spans;
+    spans.reserve(static_cast<size_t>(n) * 10);
     for (int32_t i = 0; i < n; ++i) {
         uintptr_t ri[3][2], ro[3][2];
         forward_ranges(subs[i], ri, ro);
         for (int f = 0; f < 3; ++f) {
-            lo_in[3 * i + f] = ri[f][0];
-            hi_in[3 * i + f] = ri[f][1];
-            lo_out[3 * i + f] = ro[f][0];
-            hi_out[3 * i + f] = ro[f][1];
+            spans.push_back(Span{ri[f][0], ri[f][1], i, false});
+            spans.push_back(Span{ro[f][0], ro[f][1], i, true});
+        }
+        const void *cp[4] = {items[i].coeffs.tzc1, items[i].coeffs.tzc2, items[i].coeffs.tzd1, items[i].coeffs.tzd2};
+        for (const void *c : cp) {
+            const uintptr_t lo = reinterpret_cast<uintptr_t>(c);
+            spans.push_back(Span{lo, lo + uintptr_t(items[i].grid.nz) * sizeof(float), i, false});
         }
     }
-    for (int32_t p = 0; p < 3 * n; ++p)
-        for (int32_t q = 0; q < 3 * n; ++q) {
-            if (p / 3 == q / 3) continue;   // within one item already checked
-            if (lo_out[p] < hi_in[q] && lo_in[q] < hi_out[p])
-                return fail(PW_ERR_INVALID_ARG, "an output of item %d overlaps an input of item %d", p / 3, q / 3);
-            if (lo_out[p] < hi_out[q] && lo_out[q] < hi_out[p])
-                return fail(PW_ERR_INVALID_ARG, "outputs of items %d and %d overlap", p / 3, q / 3);
+    std::sort(spans.begin(), spans.end(), [](const Span &a, const Span &b) { return a.lo < b.lo; });
+    uintptr_t end_all = 0, end_out = 0;
+    int32_t who_all = -1, who_out = -1;
+    for (const Span &s : spans) {
+        if (s.hi <= s.lo) continue;
+        if (s.out && s.lo < end_all)
+            return fail(PW_ERR_INVALID_ARG, "an output of item %d overlaps an array of item %d", s.item, who_all);
+        if (!s.out && s.lo < end_out)
+            return fail(PW_ERR_INVALID_ARG, "an output of item %d overlaps an array of item %d", who_out, s.item);
+        if (s.hi > end_all) {
+            end_all = s.hi;
+            who_all = s.item;
         }
+        if (s.out && s.hi > end_out) {
+            end_out = s.hi;
+            who_out = s.item;
+        }
+    }
     for (int32_t i = 0; i < n; ++i) {
         pw_status st = check_forward_on_device(subs[i]);
         if (st != PW_OK) {

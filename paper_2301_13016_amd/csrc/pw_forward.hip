@@ -39,7 +39,8 @@ using namespace dev;
 
 template <typename Tin, int PX, int RY>
 __global__ __launch_bounds__(512) void pw_forward_kernel(FwdK<Tin> a) {
-    const int wave = threadIdx.x >> 6;
+    // wavefront index as a scalar, so that per-strip conditions stay scalar
+    const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
     const int t = xcd_tile(blockIdx.x, gridDim.x);
     const int cz = t % a.nzc;
     const int t2 = t / a.nzc;

@@ -91,6 +91,14 @@ template <typename T> __device__ __forceinline__ T right_of(T first, T halo, int
     return lane63 ? h : s;
 }
 
+// Read of a kernel-invariant array at a wave-uniform index through the
+// constant address space, so that it becomes a scalar load (counted apart from
+// the vector loads in flight: waiting for it does not drain the prefetch).
+// The caller guarantees that nothing the kernel writes overlaps the array.
+template <typename T> __device__ __forceinline__ T uniform_load(const T *p, int i) {
+    return ((const __attribute__((address_space(4))) T *)(p))[i];
+}
+
 template <typename T> __device__ __forceinline__ T fma_(T a, T b, T c);
 template <> __device__ __forceinline__ float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 template <> __device__ __forceinline__ double fma_(double a, double b, double c) { return __builtin_fma(a, b, c); }
@@ -185,7 +193,8 @@ __device__ __forceinline__ void level(const Plane<Tin, PX, RY> &m, const Plane<T
     // element (row r, column x) of a loaded row array, widened
 #define G(arr, r, x) Storage<Tin>::widen(comp<Tin, PX>((arr)[r], (x)))
 #define W(h) Storage<Tin>::widen(h)
-    const Tc z1 = a.tzc1[kk], z2 = a.tzc2[kk], d1 = a.tzd1[kk], d2 = a.tzd2[kk];
+    const Tc z1 = uniform_load(a.tzc1, kk), z2 = uniform_load(a.tzc2, kk);
+    const Tc d1 = uniform_load(a.tzd1, kk), d2 = uniform_load(a.tzd2, kk);
     const Tc tcx = a.tcx, tcy = a.tcy;
 
     // Columns just outside this lane's PX columns, per loaded row, for the
@@ -353,18 +362,22 @@ __device__ __forceinline__ void strip_march_t(const FwdK<Tin> &a, int tx, int ty
     load_plane<Tin, PX, RY, Full>(A, a, k0 - 1 + h, s, last_col);
     load_plane<Tin, PX, RY, Full>(B, a, k0 + h, s, last_col);
     load_plane<Tin, PX, RY, Full>(C, a, k0 + 1 + h, s, last_col);
+    // The prefetch of plane kk+2 is unconditional (near the chunk's end it
+    // re-reads plane k1, a cache hit): a conditional load would merge two
+    // paths with different loads in flight, and the wait inserted at such a
+    // merge drains every outstanding load, prefetch included.
     int kk = k0;
     for (;;) {
-        if (kk + 1 < k1) load_plane<Tin, PX, RY, Full>(D, a, kk + 2 + h, s, last_col);
+        load_plane<Tin, PX, RY, Full>(D, a, min(kk + 2, k1) + h, s, last_col);
         level<Tin, PX, RY, Full>(A, B, C, a, kk, lane0, lane63, nvalid, ooff, row_ok);
         if (++kk >= k1) break;
-        if (kk + 1 < k1) load_plane<Tin, PX, RY, Full>(A, a, kk + 2 + h, s, last_col);
+        load_plane<Tin, PX, RY, Full>(A, a, min(kk + 2, k1) + h, s, last_col);
         level<Tin, PX, RY, Full>(B, C, D, a, kk, lane0, lane63, nvalid, ooff, row_ok);
         if (++kk >= k1) break;
-        if (kk + 1 < k1) load_plane<Tin, PX, RY, Full>(B, a, kk + 2 + h, s, last_col);
+        load_plane<Tin, PX, RY, Full>(B, a, min(kk + 2, k1) + h, s, last_col);
         level<Tin, PX, RY, Full>(C, D, A, a, kk, lane0, lane63, nvalid, ooff, row_ok);
         if (++kk >= k1) break;
-        if (kk + 1 < k1) load_plane<Tin, PX, RY, Full>(C, a, kk + 2 + h, s, last_col);
+        load_plane<Tin, PX, RY, Full>(C, a, min(kk + 2, k1) + h, s, last_col);
         level<Tin, PX, RY, Full>(D, A, B, a, kk, lane0, lane63, nvalid, ooff, row_ok);
         if (++kk >= k1) break;
     }

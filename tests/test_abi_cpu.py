@@ -131,6 +131,24 @@ def test_outputs_overlapping_each_other_rejected(lib):
     assert _call(g, None, B.PW_F32, c, p) == B.PW_ERR_INVALID_ARG
 
 
+def test_output_overlapping_coefficients_rejected(lib):
+    # coefficient arrays are read through the scalar cache, so no output may
+    # overlap them; inputs may (they are only read)
+    g, c, p = _args()
+    p[5] = A + 13 * MB + 4 * 7   # sw starts on tzd2[7], the last level
+    assert _call(g, None, B.PW_F32, c, p) == B.PW_ERR_INVALID_ARG
+    assert "tzd2" in B.pw_last_error()
+    p[5] = A + 13 * MB + 4 * 8   # just past tzd2: fine
+    assert _call(g, None, B.PW_F32, c, p) in _no_gpu_status()
+    g, c, p = _args()
+    c.tzc1 = p[0]                # coefficients inside an input: fine
+    assert _call(g, None, B.PW_F32, c, p) in _no_gpu_status()
+    q = [A + i * MB for i in range(9)]
+    c.tzc1 = q[7] + 4 * 100      # inside gradient gv
+    st = B.pw_advect_adjoint(g, None, B.PW_F32, *q[:3], c, *q[3:6], *q[6:9])
+    assert st == B.PW_ERR_INVALID_ARG and "tzc1" in B.pw_last_error()
+
+
 def test_huge_plane_unsupported(lib):
     g, c, p = _args(nx=40000, ny=20000, nz=1)
     p = [A + i * (1 << 34) for i in range(6)]
@@ -228,6 +246,13 @@ def test_batch_argument_errors(lib):
     assert "item 2" in B.pw_last_error()
     assert B.pw_batch_create(_items(2, overlap=True), 2, B.PW_F32, None, h) == B.PW_ERR_INVALID_ARG
     assert "overlaps" in B.pw_last_error()
+    bad = _items(3)
+    bad[2].sv = bad[0].coeffs.tzc2   # an output of item 2 on a coefficient array of item 0
+    assert B.pw_batch_create(bad, 3, B.PW_F32, None, h) == B.PW_ERR_INVALID_ARG
+    assert "item 2" in B.pw_last_error() and "item 0" in B.pw_last_error()
+    ok = _items(3)
+    ok[2].u = ok[0].coeffs.tzc2      # an input sharing memory with coefficients: fine
+    assert B.pw_batch_create(ok, 3, B.PW_F32, None, h) in _no_gpu_status()
     assert h.value is None
 
 

@@ -44,15 +44,17 @@ def adj_errors(got, g, r, halo=1):
     return [a_scaled_error(x, y, m) for x, y, m in zip(got, ref, mag)], ref
 
 
-SHAPES = [(130, 70, 20), (64, 64, 64), (1, 1, 1), (65, 3, 1), (1, 200, 5), (61, 9, 17), (60, 7, 3)]
+SHAPES = [(130, 70, 20), (64, 64, 64), (1, 1, 1), (65, 3, 1), (1, 200, 5), (61, 9, 17), (60, 7, 3),
+          (128, 4, 3), (129, 5, 2), (257, 3, 4)]
 
 
+@pytest.mark.parametrize("tile", [None, (1, 1, 5, 4), (1, 2, 9, 1), (1, 4, 64, 8)])
 @pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "x".join(map(str, s)))
-def test_f32_adjoint_matches_oracle(shape):
+def test_f32_adjoint_matches_oracle(shape, tile):
     nx, ny, nz = shape
     g = wl.make_grid(nx, ny, nz, seed=200 + nx + ny + nz)
     r = wl.cotangents(nx, ny, nz, seed=300 + nx)
-    errs, ref = adj_errors(gpu_adjoint(g, r), g, r)
+    errs, ref = adj_errors(gpu_adjoint(g, r, tile=tile), g, r)
     assert max(errs) <= 2e-6, errs
 
 
@@ -78,7 +80,7 @@ def test_adjoint_tile_invariance_bitwise():
     g = wl.make_grid(150, 37, 23, seed=203)
     r = wl.cotangents(150, 37, 23, seed=303)
     base = gpu_adjoint(g, r, tile=(1, 2, 16, 4))
-    for t in [(1, 1, 1, 1), (1, 1, 9, 4), (1, 2, 5, 8), (1, 4, 64, 4), (1, 4, 3, 2)]:
+    for t in [(1, 1, 1, 1), (1, 1, 9, 4), (1, 2, 5, 8), (1, 4, 64, 4), (1, 4, 3, 2), (1, 1, 7, 8), (1, 2, 130, 1)]:
         got = gpu_adjoint(g, r, tile=t)
         for a, b in zip(base, got):
             assert np.array_equal(a, b), t

@@ -227,8 +227,10 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
     return x * q + min(x, rem) + i;
 }
 
-template <typename T, int RY>
-__global__ __launch_bounds__(512) void pw_adjoint_kernel(AdjK<T> a) {
+// MaxT: workgroup size bound (built for 256 and 512 threads; see the forward
+// kernel).
+template <typename T, int RY, int MaxT>
+__global__ __launch_bounds__(MaxT) void pw_adjoint_kernel(AdjK<T> a) {
     const int lane = threadIdx.x & 63;
     // wavefront index as a scalar, so that per-strip conditions stay scalar
     const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
@@ -328,7 +330,12 @@ pw_status launch_adj_t(const AdjArgs &g, const TileCfg &cfg, hipStream_t s) {
     const int64_t nblk_y = (a.nty + cfg.wpb - 1) / cfg.wpb;
     const int64_t nblocks = static_cast<int64_t>(a.ntx) * nblk_y * a.nzc;
     if (nblocks <= 0 || nblocks > 0x7fffffffLL) return fail(PW_ERR_UNSUPPORTED, "grid too large");
-    hipLaunchKernelGGL((pw_adjoint_kernel<T, RY>), dim3(static_cast<unsigned>(nblocks)), dim3(64 * cfg.wpb), 0, s, a);
+    if (cfg.wpb <= 4)
+        hipLaunchKernelGGL((pw_adjoint_kernel<T, RY, 256>), dim3(static_cast<unsigned>(nblocks)), dim3(64 * cfg.wpb), 0,
+                           s, a);
+    else
+        hipLaunchKernelGGL((pw_adjoint_kernel<T, RY, 512>), dim3(static_cast<unsigned>(nblocks)), dim3(64 * cfg.wpb), 0,
+                           s, a);
     return hip_fail(hipGetLastError(), "adjoint kernel launch");
 }
 

@@ -34,8 +34,10 @@ template <typename Tin> struct BatchSub {
 
 __global__ void batch_reset_kernel(unsigned long long *counter) { *counter = 0ull; }
 
-template <typename Tin, int PX, int RY>
-__global__ __launch_bounds__(512) void pw_batch_kernel(const BatchSub<Tin> *__restrict__ subs, int nsub,
+// MaxT: workgroup size bound (built for 256 and 512 threads, as the
+// single-grid kernels).
+template <typename Tin, int PX, int RY, int MaxT>
+__global__ __launch_bounds__(MaxT) void pw_batch_kernel(const BatchSub<Tin> *__restrict__ subs, int nsub,
                                                        int64_t nitems, unsigned long long *counter) {
     const int lane = threadIdx.x & 63;
     for (;;) {
@@ -65,41 +67,54 @@ __global__ __launch_bounds__(512) void pw_batch_kernel(const BatchSub<Tin> *__re
 
 using Tin = float;   // the batched form runs FP32 storage
 
-template <int PX, int RY> const void *kernel_ptr() {
-    return reinterpret_cast<const void *>(&pw_batch_kernel<Tin, PX, RY>);
+template <int PX, int RY, int MaxT> const void *kernel_ptr() {
+    return reinterpret_cast<const void *>(&pw_batch_kernel<Tin, PX, RY, MaxT>);
 }
 
-const void *batch_kernel(const TileCfg &c) {
+template <int MaxT> const void *batch_kernel_t(const TileCfg &c) {
     switch (c.px * 16 + c.ry) {
-        case 16 + 1: return kernel_ptr<1, 1>();
-        case 16 + 2: return kernel_ptr<1, 2>();
-        case 16 + 4: return kernel_ptr<1, 4>();
-        case 32 + 1: return kernel_ptr<2, 1>();
-        case 32 + 2: return kernel_ptr<2, 2>();
-        case 32 + 4: return kernel_ptr<2, 4>();
-        case 64 + 1: return kernel_ptr<4, 1>();
-        case 64 + 2: return kernel_ptr<4, 2>();
+        case 16 + 1: return kernel_ptr<1, 1, MaxT>();
+        case 16 + 2: return kernel_ptr<1, 2, MaxT>();
+        case 16 + 4: return kernel_ptr<1, 4, MaxT>();
+        case 32 + 1: return kernel_ptr<2, 1, MaxT>();
+        case 32 + 2: return kernel_ptr<2, 2, MaxT>();
+        case 32 + 4: return kernel_ptr<2, 4, MaxT>();
+        case 64 + 1: return kernel_ptr<4, 1, MaxT>();
+        case 64 + 2: return kernel_ptr<4, 2, MaxT>();
     }
     return nullptr;
 }
 
-template <int PX, int RY>
+const void *batch_kernel(const TileCfg &c) {
+    return c.wpb <= 4 ? batch_kernel_t<256>(c) : batch_kernel_t<512>(c);
+}
+
+template <int PX, int RY, int MaxT>
 void launch_t(dim3 g, dim3 b, hipStream_t s, const BatchSub<Tin> *d, int n, int64_t items, unsigned long long *c) {
-    hipLaunchKernelGGL((pw_batch_kernel<Tin, PX, RY>), g, b, 0, s, d, n, items, c);
+    hipLaunchKernelGGL((pw_batch_kernel<Tin, PX, RY, MaxT>), g, b, 0, s, d, n, items, c);
+}
+
+template <int MaxT>
+void launch_batch_t(const TileCfg &c, dim3 g, dim3 b, hipStream_t s, const BatchSub<Tin> *d, int n, int64_t items,
+                    unsigned long long *ctr) {
+    switch (c.px * 16 + c.ry) {
+        case 16 + 1: launch_t<1, 1, MaxT>(g, b, s, d, n, items, ctr); break;
+        case 16 + 2: launch_t<1, 2, MaxT>(g, b, s, d, n, items, ctr); break;
+        case 16 + 4: launch_t<1, 4, MaxT>(g, b, s, d, n, items, ctr); break;
+        case 32 + 1: launch_t<2, 1, MaxT>(g, b, s, d, n, items, ctr); break;
+        case 32 + 2: launch_t<2, 2, MaxT>(g, b, s, d, n, items, ctr); break;
+        case 32 + 4: launch_t<2, 4, MaxT>(g, b, s, d, n, items, ctr); break;
+        case 64 + 1: launch_t<4, 1, MaxT>(g, b, s, d, n, items, ctr); break;
+        case 64 + 2: launch_t<4, 2, MaxT>(g, b, s, d, n, items, ctr); break;
+    }
 }
 
 void launch_batch(const TileCfg &c, dim3 g, dim3 b, hipStream_t s, const BatchSub<Tin> *d, int n, int64_t items,
                   unsigned long long *ctr) {
-    switch (c.px * 16 + c.ry) {
-        case 16 + 1: launch_t<1, 1>(g, b, s, d, n, items, ctr); break;
-        case 16 + 2: launch_t<1, 2>(g, b, s, d, n, items, ctr); break;
-        case 16 + 4: launch_t<1, 4>(g, b, s, d, n, items, ctr); break;
-        case 32 + 1: launch_t<2, 1>(g, b, s, d, n, items, ctr); break;
-        case 32 + 2: launch_t<2, 2>(g, b, s, d, n, items, ctr); break;
-        case 32 + 4: launch_t<2, 4>(g, b, s, d, n, items, ctr); break;
-        case 64 + 1: launch_t<4, 1>(g, b, s, d, n, items, ctr); break;
-        case 64 + 2: launch_t<4, 2>(g, b, s, d, n, items, ctr); break;
-    }
+    if (c.wpb <= 4)
+        launch_batch_t<256>(c, g, b, s, d, n, items, ctr);
+    else
+        launch_batch_t<512>(c, g, b, s, d, n, items, ctr);
 }
 
 TileCfg default_batch_tile() {

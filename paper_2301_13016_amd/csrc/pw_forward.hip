@@ -37,8 +37,12 @@ namespace {
 
 using namespace dev;
 
-template <typename Tin, int PX, int RY>
-__global__ __launch_bounds__(512) void pw_forward_kernel(FwdK<Tin> a) {
+// MaxT: the workgroup size bound the kernel is compiled for.  Every shape is
+// built twice: for up to 256 threads (four wavefronts, one per SIMD, so a
+// wavefront may use the whole 512-entry register file: the large strips keep
+// their planes in registers instead of spilling) and for up to 512.
+template <typename Tin, int PX, int RY, int MaxT>
+__global__ __launch_bounds__(MaxT) void pw_forward_kernel(FwdK<Tin> a) {
     // wavefront index as a scalar, so that per-strip conditions stay scalar
     const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
     const int t = xcd_tile(blockIdx.x, gridDim.x);
@@ -82,8 +86,12 @@ pw_status launch_fwd_t(const FwdArgs &g, const TileCfg &cfg, hipStream_t s) {
     const int64_t nblk_y = (a.nty + cfg.wpb - 1) / cfg.wpb;
     const int64_t nblocks = static_cast<int64_t>(a.ntx) * nblk_y * a.nzc;
     if (nblocks <= 0 || nblocks > 0x7fffffffLL) return fail(PW_ERR_UNSUPPORTED, "grid too large");
-    hipLaunchKernelGGL((pw_forward_kernel<Tin, PX, RY>), dim3(static_cast<unsigned>(nblocks)),
-                       dim3(64 * cfg.wpb), 0, s, a);
+    if (cfg.wpb <= 4)
+        hipLaunchKernelGGL((pw_forward_kernel<Tin, PX, RY, 256>), dim3(static_cast<unsigned>(nblocks)),
+                           dim3(64 * cfg.wpb), 0, s, a);
+    else
+        hipLaunchKernelGGL((pw_forward_kernel<Tin, PX, RY, 512>), dim3(static_cast<unsigned>(nblocks)),
+                           dim3(64 * cfg.wpb), 0, s, a);
     return hip_fail(hipGetLastError(), "forward kernel launch");
 }
 

@@ -11,7 +11,7 @@ each launch on the launch stream.  Launch shapes are the library's choice
 
 Also measured in the same run ("forms"):
   * BF16 / FP16 storage vs FP32 on 1024 x 1024 x 256 (268 M points);
-  * the adjoint (J^T r) vs the forward on 256 x 256 x 128 FP32;
+  * the adjoint (J^T r) and the tangent (J dx) vs the forward on 256 x 256 x 128 FP32;
   * 64 uneven subdomains (FP32) in one persistent launch replayed from a HIP
     graph vs 64 plain launches;
   * a plain copy kernel (reachable-bandwidth reference);
@@ -87,6 +87,13 @@ def measured_traffic(key):
     return int(ent["traffic_bytes"])
 
 
+def tangent_bytes(nx, ny, nz, halo, es=4):
+    """Algorithmic bytes of one tangent launch: u, v, w and du, dv, dw read
+    once (padded), tu, tv, tw written once (interior)."""
+    padded = (nx + 2 * halo) * (ny + 2 * halo) * (nz + 2 * halo)
+    return 6 * padded * es + 3 * nx * ny * nz * es
+
+
 def time_launches(torch, launch, nsets, steps, warmup, stream):
     """Run ``launch(i)`` for warmup + steps iterations (i = buffer set), time
     the steps region with a wall clock between synchronisations and each
@@ -124,6 +131,25 @@ def prebuilt_forward(B, ins, outs, coeffs, stream, tile=None):
         st = fn(*args)
         if st != B.PW_OK:
             raise B.PWError(st, B.pw_last_error(), "pw_advect_ex")
+    call.keep = keep
+    return call
+
+
+def prebuilt_tangent(B, ins, dirs, outs, coeffs, stream):
+    """ctypes arguments of one pw_advect_tangent_ex call, built once."""
+    from paper_2301_13016_amd.binding import _dtype_code, _grid_from, _layout_from
+    u, v, w = ins
+    keep = (_grid_from(u, 1), _layout_from(u, outs[0]), coeffs.c_struct())
+    args = (ctypes.byref(keep[0]), ctypes.byref(keep[1]), _dtype_code(u),
+            u.data_ptr(), v.data_ptr(), w.data_ptr(), ctypes.byref(keep[2]),
+            *(x.data_ptr() for x in dirs), *(x.data_ptr() for x in outs),
+            None, ctypes.c_void_p(stream.cuda_stream))
+    fn = B.lib().pw_advect_tangent_ex
+
+    def call():
+        st = fn(*args)
+        if st != B.PW_OK:
+            raise B.PWError(st, B.pw_last_error(), "pw_advect_tangent_ex")
     call.keep = keep
     return call
 
@@ -254,25 +280,36 @@ def main():
     # 4 buffer sets (about 4 x 540 MB) so that the MALL cannot serve repeats
     host4 = [torch.from_numpy(x) for x in (g4.u, g4.v, g4.w)]
     hcot4 = [torch.from_numpy(x) for x in wl.cotangents(*n4, c4["cot_seed"])]
-    fcalls, acalls, keep4 = [], [], []
+    hdir4 = [torch.from_numpy(x.astype(np.float32)) for x in wl.direction(*n4, seed=46)]
+    fcalls, acalls, tcalls, keep4 = [], [], [], []
     for _ in range(4):
         ins4 = [x.to(dev) for x in host4]
         cot4 = [x.to(dev) for x in hcot4]
+        dir4 = [x.to(dev) for x in hdir4]
         o4 = tuple(torch.empty((n4[2], n4[1], n4[0]), device=dev) for _ in range(3))
+        t4 = tuple(torch.empty((n4[2], n4[1], n4[0]), device=dev) for _ in range(3))
         gr4 = tuple(torch.empty_like(x) for x in ins4)
-        keep4.append((ins4, cot4, o4, gr4))
+        keep4.append((ins4, cot4, dir4, o4, t4, gr4))
         fcalls.append(prebuilt_forward(B, ins4, o4, co4, stream))
         acalls.append(prebuilt_adjoint(B, ins4, cot4, gr4, co4, stream))
+        tcalls.append(prebuilt_tangent(B, ins4, dir4, t4, co4, stream))
     _, fms = time_launches(torch, lambda i: fcalls[i](), 4, 100, 5, stream)
     _, ams = time_launches(torch, lambda i: acalls[i](), 4, 100, 5, stream)
+    _, tms = time_launches(torch, lambda i: tcalls[i](), 4, 100, 5, stream)
     pts4 = n4[0] * n4[1] * n4[2]
     forms["adjoint_256x256x128"] = dict(
         forward_ms=round(fms, 4), adjoint_ms=round(ams, 4), adjoint_over_forward=round(ams / fms, 3),
         ideal_ratio_from_bytes=round(adjoint_bytes(*n4, 1) / algo_bytes(*n4, 1, 4), 3),
         adjoint_gpts=round(pts4 / (ams * 1e-3) / 1e9, 2),
         adjoint_hbm_gbs=round(adjoint_bytes(*n4, 1) / (ams * 1e-3) / 1e9, 1))
-    log("c4: forward %.4f ms, adjoint %.4f ms, ratio %.3f" % (fms, ams, ams / fms))
-    del keep4, fcalls, acalls
+    tbytes = tangent_bytes(*n4, 1)
+    forms["tangent_256x256x128"] = dict(
+        tangent_ms=round(tms, 4), tangent_over_forward=round(tms / fms, 3),
+        ideal_ratio_from_bytes=round(tbytes / algo_bytes(*n4, 1, 4), 3),
+        tangent_gpts=round(pts4 / (tms * 1e-3) / 1e9, 2), tangent_hbm_gbs=round(tbytes / (tms * 1e-3) / 1e9, 1))
+    log("c4: forward %.4f ms, adjoint %.4f ms (ratio %.3f), tangent %.4f ms (ratio %.3f)"
+        % (fms, ams, ams / fms, tms, tms / fms))
+    del keep4, fcalls, acalls, tcalls
     torch.cuda.empty_cache()
 
     # ------------------------------------------------------------ batched form: c3

@@ -101,8 +101,9 @@ typedef struct {
 
 /* Forward operator (the equations above): writes su, sv, sw at every
  * interior cell.  Inputs of element type `in_dtype`; outputs float (double
- * for PW_F64).  Outputs must not overlap any input.  Halo cells of u, v, w
- * are read, never written. */
+ * for PW_F64).  Outputs must not overlap any input or coefficient array
+ * (the kernels read the coefficients through the scalar cache).  Halo cells
+ * of u, v, w are read, never written. */
 pw_status pw_advect(const pw_grid *grid, const pw_layout *layout, pw_dtype in_dtype,
                     const void *u, const void *v, const void *w,
                     const pw_coeffs *coeffs,
@@ -119,6 +120,8 @@ pw_status pw_advect(const pw_grid *grid, const pw_layout *layout, pw_dtype in_dt
  *   PW_F64: cols_per_lane in {1, 2}, rows_per_strip in {1, 2}.
  * Adjoint (pw_advect_adjoint_ex): cols_per_lane 1 (strips of 62 padded
  *   columns), rows_per_strip in {1, 2, 4}.
+ * Tangent (pw_advect_tangent_ex): cols_per_lane 1 or 2 (PW_F64: 1),
+ *   rows_per_strip in {1, 2}.
  * Always zlen >= 1 and waves_per_group in 1..8.  Other values give
  * PW_ERR_INVALID_ARG. */
 typedef struct {
@@ -144,7 +147,7 @@ pw_status pw_advect_ex(const pw_grid *grid, const pw_layout *layout, pw_dtype in
  * (output layout); gu/gv/gw are padded-shaped (input layout) and fully
  * overwritten, halo cells included (entries no output reads get 0).  dtype
  * PW_F32 or PW_F64 (PW_ERR_UNSUPPORTED otherwise).  Gradients must not
- * overlap any other argument. */
+ * overlap any other argument, coefficient arrays included. */
 pw_status pw_advect_adjoint(const pw_grid *grid, const pw_layout *layout, pw_dtype dtype,
                             const void *u, const void *v, const void *w,
                             const pw_coeffs *coeffs,
@@ -159,6 +162,32 @@ pw_status pw_advect_adjoint_ex(const pw_grid *grid, const pw_layout *layout, pw_
                                const pw_coeffs *coeffs,
                                const void *gsu, const void *gsv, const void *gsw,
                                void *gu, void *gv, void *gw,
+                               const pw_tile *tile, void *hip_stream);
+
+/* Tangent-linear operator (Jacobian-vector product) of the forward operator:
+ *   (tu, tv, tw) = J(u, v, w) (du, dv, dw)
+ * the derivative of (su, sv, sw) in direction (du, dv, dw): every term
+ * s*c*a*(b+d) of the equations above contributes s*c*(da*(b+d) + a*(db+dd)).
+ * The operator is quadratic, so in exact arithmetic this equals
+ * (F(x+d) - F(x-d)) / 2.  du/dv/dw are padded-shaped (input layout, halo
+ * read); tu/tv/tw interior-shaped (output layout).  dtype PW_F32 or PW_F64
+ * (PW_ERR_UNSUPPORTED otherwise); arithmetic in that type.  Outputs must not
+ * overlap any input or coefficient array.  With pw_advect_adjoint it forms a
+ * tangent-linear / adjoint pair: <J d, y> = <d, J^T y>. */
+pw_status pw_advect_tangent(const pw_grid *grid, const pw_layout *layout, pw_dtype dtype,
+                            const void *u, const void *v, const void *w,
+                            const pw_coeffs *coeffs,
+                            const void *du, const void *dv, const void *dw,
+                            void *tu, void *tv, void *tw,
+                            void *hip_stream);
+
+/* pw_advect_tangent with an explicit launch shape (see pw_tile); tile ==
+ * NULL means the library's choice.  Results are bit-identical across shapes. */
+pw_status pw_advect_tangent_ex(const pw_grid *grid, const pw_layout *layout, pw_dtype dtype,
+                               const void *u, const void *v, const void *w,
+                               const pw_coeffs *coeffs,
+                               const void *du, const void *dv, const void *dw,
+                               void *tu, void *tv, void *tw,
                                const pw_tile *tile, void *hip_stream);
 
 /* Autotuner for single-grid launches.  Times candidate launch shapes of the

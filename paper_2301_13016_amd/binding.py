@@ -78,6 +78,11 @@ _SIGNATURES = {
     "pw_advect_adjoint_ex": [ctypes.POINTER(pw_grid), ctypes.POINTER(pw_layout), ctypes.c_int,
                              _P, _P, _P, ctypes.POINTER(pw_coeffs), _P, _P, _P, _P, _P, _P,
                              ctypes.POINTER(pw_tile), _P],
+    "pw_advect_tangent": [ctypes.POINTER(pw_grid), ctypes.POINTER(pw_layout), ctypes.c_int,
+                          _P, _P, _P, ctypes.POINTER(pw_coeffs), _P, _P, _P, _P, _P, _P, _P],
+    "pw_advect_tangent_ex": [ctypes.POINTER(pw_grid), ctypes.POINTER(pw_layout), ctypes.c_int,
+                             _P, _P, _P, ctypes.POINTER(pw_coeffs), _P, _P, _P, _P, _P, _P,
+                             ctypes.POINTER(pw_tile), _P],
     "pw_stream_copy": [_P, _P, ctypes.c_int64, _P],
     "pw_tune": [ctypes.POINTER(pw_grid), ctypes.c_int, ctypes.c_int32, ctypes.POINTER(pw_tile),
                 ctypes.POINTER(pw_tile)],
@@ -158,6 +163,18 @@ def pw_advect_adjoint_ex(grid, layout, dtype, u, v, w, coeffs, gsu, gsv, gsw, gu
                          stream=None):
     return lib().pw_advect_adjoint_ex(ctypes.byref(grid), ctypes.byref(layout) if layout is not None else None,
                                       int(dtype), u, v, w, ctypes.byref(coeffs), gsu, gsv, gsw, gu, gv, gw,
+                                      ctypes.byref(tile) if tile is not None else None, stream)
+
+
+def pw_advect_tangent(grid, layout, dtype, u, v, w, coeffs, du, dv, dw, tu, tv, tw, stream=None):
+    return lib().pw_advect_tangent(ctypes.byref(grid), ctypes.byref(layout) if layout is not None else None,
+                                   int(dtype), u, v, w, ctypes.byref(coeffs), du, dv, dw, tu, tv, tw, stream)
+
+
+def pw_advect_tangent_ex(grid, layout, dtype, u, v, w, coeffs, du, dv, dw, tu, tv, tw, tile=None,
+                         stream=None):
+    return lib().pw_advect_tangent_ex(ctypes.byref(grid), ctypes.byref(layout) if layout is not None else None,
+                                      int(dtype), u, v, w, ctypes.byref(coeffs), du, dv, dw, tu, tv, tw,
                                       ctypes.byref(tile) if tile is not None else None, stream)
 
 
@@ -297,6 +314,31 @@ def advect_adjoint(u, v, w, coeffs: Coeffs, gsu, gsv, gsw, halo=1, out=None, til
     return gu, gv, gw
 
 
+def advect_tangent(u, v, w, coeffs: Coeffs, du, dv, dw, halo=1, out=None, tile=None, stream=None):
+    """tu, tv, tw = J(u, v, w) (du, dv, dw), interior-shaped; du, dv, dw are
+    padded like u (the halo is read)."""
+    import torch
+    grid = _grid_from(u, halo)
+    for d in (du, dv, dw):
+        if d.shape != u.shape or d.dtype != u.dtype or d.device != u.device:
+            raise ValueError("the direction must match u in shape, dtype and device")
+    if not (du.stride() == dv.stride() == dw.stride() == u.stride()):
+        du, dv, dw = (d.contiguous() for d in (du, dv, dw))
+        if du.stride() != u.stride():
+            raise ValueError("the direction must share the inputs' strides")
+    if out is None:
+        nz, ny, nx = (s - 2 * halo for s in u.shape)
+        out = tuple(torch.empty((nz, ny, nx), dtype=u.dtype, device=u.device) for _ in range(3))
+    tu, tv, tw = out
+    layout = _layout_from(u, tu)
+    tl = None if tile is None else pw_tile(*tile)
+    st = pw_advect_tangent_ex(grid, layout, _dtype_code(u), u.data_ptr(), v.data_ptr(), w.data_ptr(),
+                              coeffs.c_struct(), du.data_ptr(), dv.data_ptr(), dw.data_ptr(),
+                              tu.data_ptr(), tv.data_ptr(), tw.data_ptr(), tl, _stream_handle(stream))
+    _check(st, "pw_advect_tangent")
+    return tu, tv, tw
+
+
 def tune(nx, ny, nz, dtype, halo=1, flags=0):
     """Run the autotuner for this grid class; returns (forward tile, adjoint
     tile) as (cols_per_lane, rows_per_strip, zlen, waves_per_group) tuples
@@ -371,16 +413,24 @@ def _autograd_function():
     import torch
 
     class PWAdvect(torch.autograd.Function):
-        """Differentiable PW advection: forward = ``advect``, backward = the
-        hand-written adjoint kernel (gradients w.r.t. u, v, w; the coefficients
-        are treated as constants)."""
+        """Differentiable PW advection: forward = ``advect``; reverse mode
+        (backward) = the hand-written adjoint kernel, forward mode (jvp) = the
+        hand-written tangent-linear kernel.  Derivatives are w.r.t. u, v, w;
+        the coefficients are treated as constants."""
 
         @staticmethod
         def forward(ctx, u, v, w, coeffs, halo=1):
             ctx.save_for_backward(u, v, w)
+            ctx.save_for_forward(u, v, w)
             ctx.coeffs = coeffs
             ctx.halo = halo
             return advect(u, v, w, coeffs, halo)
+
+        @staticmethod
+        def jvp(ctx, du, dv, dw, _dcoeffs=None, _dhalo=None):
+            u, v, w = ctx.saved_tensors
+            du, dv, dw = (torch.zeros_like(u) if d is None else d for d in (du, dv, dw))
+            return advect_tangent(u, v, w, ctx.coeffs, du, dv, dw, ctx.halo)
 
         @staticmethod
         def backward(ctx, gsu, gsv, gsw):

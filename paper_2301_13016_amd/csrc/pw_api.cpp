@@ -249,6 +249,57 @@ pw_status pw_advect_ex(const pw_grid *grid, const pw_layout *layout, pw_dtype in
     return launch_forward(a, in_dtype, cfg, static_cast<hipStream_t>(hip_stream));
 }
 
+pw_status pw_advect_tangent(const pw_grid *grid, const pw_layout *layout, pw_dtype dtype,
+                            const void *u, const void *v, const void *w, const pw_coeffs *coeffs,
+                            const void *du, const void *dv, const void *dw,
+                            void *tu, void *tv, void *tw, void *hip_stream) {
+    return pw_advect_tangent_ex(grid, layout, dtype, u, v, w, coeffs, du, dv, dw, tu, tv, tw, nullptr, hip_stream);
+}
+
+pw_status pw_advect_tangent_ex(const pw_grid *grid, const pw_layout *layout, pw_dtype dtype,
+                               const void *u, const void *v, const void *w, const pw_coeffs *coeffs,
+                               const void *du, const void *dv, const void *dw,
+                               void *tu, void *tv, void *tw, const pw_tile *tile, void *hip_stream) {
+    g_err[0] = 0;
+    PW_TRY(check_grid(grid));
+    if (dtype != PW_F32 && dtype != PW_F64) {
+        if (elem_size(dtype)) return fail(PW_ERR_UNSUPPORTED, "tangent supports PW_F32 and PW_F64 only");
+        return fail(PW_ERR_INVALID_ARG, "unknown dtype %d", (int)dtype);
+    }
+    TanArgs a;
+    // values, coefficients and outputs exactly as for the forward operator
+    PW_TRY(validate_forward(grid, layout, dtype, u, v, w, coeffs, tu, tv, tw, &a.f));
+    const int64_t es = elem_size(dtype);
+    Layout L;
+    PW_TRY(resolve_layout(grid, layout, es, es, &L));
+    const char *names[] = {"du", "dv", "dw"};
+    const void *ptrs[] = {du, dv, dw};
+    for (int i = 0; i < 3; ++i) PW_TRY(check_aligned(names[i], ptrs[i], es));
+    const Range rdir[3] = {in_range("du", du, grid, L, es), in_range("dv", dv, grid, L, es),
+                           in_range("dw", dw, grid, L, es)};
+    const Range rout[3] = {out_range("tu", tu, grid, L, es), out_range("tv", tv, grid, L, es),
+                           out_range("tw", tw, grid, L, es)};
+    for (const Range &o : rout)
+        for (const Range &i : rdir)
+            if (overlap(o, i)) return fail(PW_ERR_INVALID_ARG, "output %s overlaps direction %s", o.name, i.name);
+    if (tile && !tangent_tile_supported(to_cfg(*tile), dtype))
+        return fail(PW_ERR_INVALID_ARG, "unsupported tangent tile cols=%d rows=%d zlen=%d waves=%d",
+                    tile->cols_per_lane, tile->rows_per_strip, tile->zlen, tile->waves_per_group);
+    PW_TRY(check_forward_on_device(a.f));
+    int dev = 0;
+    PW_TRY(current_device(&dev));
+    for (int i = 0; i < 3; ++i) PW_TRY(check_on_device(names[i], ptrs[i], dev));
+    a.du = du;
+    a.dv = dv;
+    a.dw = dw;
+    TileCfg cfg;
+    if (tile)
+        cfg = to_cfg(*tile);
+    else if (!lookup_tuned(TuneKind::Tangent, grid, dtype, &cfg))
+        cfg = default_tangent_tile(a, dtype);
+    return launch_tangent(a, dtype, cfg, static_cast<hipStream_t>(hip_stream));
+}
+
 pw_status pw_advect_adjoint(const pw_grid *grid, const pw_layout *layout, pw_dtype dtype,
                             const void *u, const void *v, const void *w, const pw_coeffs *coeffs,
                             const void *gsu, const void *gsv, const void *gsw,

@@ -10,7 +10,7 @@
 namespace pw {
 
 // Launch shape of the forward / adjoint stencil kernels.
-//   px     consecutive x columns per lane (forward: 1, 2, 4; adjoint: 1)
+//   px     consecutive x columns per lane (forward: 1, 2, 4, 8; adjoint: 1; tangent: 1, 2)
 //   ry     rows (y) per wavefront strip, a compile-time instantiation
 //   zlen   z-levels per work item (the vertical march length; the grid is cut
 //          into ceil(nz / zlen) independent chunks, each re-reading one plane
@@ -46,6 +46,13 @@ struct AdjArgs {
     int64_t in_sy, in_sz, out_sy, out_sz;
 };
 
+// Operands of one tangent launch: the forward's (outputs tu, tv, tw in su, sv,
+// sw) plus the direction, laid out like u, v, w.
+struct TanArgs {
+    FwdArgs f;
+    const void *du, *dv, *dw;
+};
+
 // Columns of gradient produced by one adjoint wavefront: 64 lanes load 64
 // consecutive padded columns and the 62 inner lanes own an output each.
 constexpr int kWaveCols = 62;
@@ -54,9 +61,12 @@ bool tile_supported(const TileCfg &c, pw_dtype dt);
 bool adjoint_tile_supported(const TileCfg &c);
 TileCfg default_forward_tile(const FwdArgs &a, pw_dtype dt);
 TileCfg default_adjoint_tile(const AdjArgs &a, pw_dtype dt);
+bool tangent_tile_supported(const TileCfg &c, pw_dtype dt);
+TileCfg default_tangent_tile(const TanArgs &a, pw_dtype dt);
 
 pw_status launch_forward(const FwdArgs &a, pw_dtype dt, const TileCfg &cfg, hipStream_t s);
 pw_status launch_adjoint(const AdjArgs &a, pw_dtype dt, const TileCfg &cfg, hipStream_t s);
+pw_status launch_tangent(const TanArgs &a, pw_dtype dt, const TileCfg &cfg, hipStream_t s);
 pw_status launch_copy(const void *src, void *dst, int64_t nbytes, hipStream_t s);
 
 // Host-side validation shared by pw_advect and the batched form (pw_api.cpp).
@@ -71,7 +81,7 @@ void forward_ranges(const FwdArgs &a, uintptr_t (*in)[2], uintptr_t (*out)[2]);
 
 // Autotune cache (pw_tune.cpp): best launch shape per kernel kind, dtype and
 // shape class, filled by pw_tune and consulted when no tile is given.
-enum class TuneKind { Forward = 0, Adjoint = 1 };
+enum class TuneKind { Forward = 0, Adjoint = 1, Tangent = 2 };
 bool lookup_tuned(TuneKind kind, const pw_grid *grid, pw_dtype dt, TileCfg *cfg);
 void store_tuned(TuneKind kind, const pw_grid *grid, pw_dtype dt, const TileCfg &cfg);
 

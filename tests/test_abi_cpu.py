@@ -198,6 +198,31 @@ def test_adjoint_gradient_overlap_rejected(lib):
     assert st == B.PW_ERR_INVALID_ARG
 
 
+def test_tangent_validation(lib):
+    g, c, p = _args()
+    q = [A + i * MB for i in range(9)]   # u v w du dv dw tu tv tw
+    call = lambda dt, qq, tile=None: B.pw_advect_tangent_ex(g, None, dt, *qq[:3], c, *qq[3:6], *qq[6:9],  # noqa: E731
+                                                             tile)
+    assert call(B.PW_F32, q) in _no_gpu_status()
+    assert call(B.PW_F64, q) in _no_gpu_status()
+    assert call(B.PW_BF16, q) == B.PW_ERR_UNSUPPORTED
+    assert call(9, q) == B.PW_ERR_INVALID_ARG
+    bad = list(q)
+    bad[6] = q[4] + 4 * 10                 # tu inside dv
+    assert call(B.PW_F32, bad) == B.PW_ERR_INVALID_ARG and "overlaps" in B.pw_last_error()
+    bad = list(q)
+    bad[7] = q[1]                          # tv on v
+    assert call(B.PW_F32, bad) == B.PW_ERR_INVALID_ARG
+    bad = list(q)
+    bad[3] = 0                             # du NULL
+    assert call(B.PW_F32, bad) == B.PW_ERR_INVALID_ARG
+    for t, ok in [((1, 1, 8, 4), True), ((2, 2, 8, 8), True), ((4, 1, 8, 4), False), ((1, 4, 8, 4), False),
+                  ((1, 1, 0, 4), False), ((1, 1, 8, 9), False)]:
+        st = call(B.PW_F32, q, B.pw_tile(*t))
+        assert (st in _no_gpu_status()) if ok else st == B.PW_ERR_INVALID_ARG, t
+    assert call(B.PW_F64, q, B.pw_tile(2, 1, 8, 4)) == B.PW_ERR_INVALID_ARG
+
+
 def test_stream_copy_validation(lib):
     assert B.pw_stream_copy(None, A, 16) == B.PW_ERR_INVALID_ARG
     assert B.pw_stream_copy(A, A + MB, 15) == B.PW_ERR_INVALID_ARG

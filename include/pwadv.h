@@ -192,21 +192,32 @@ pw_status pw_advect_tangent_ex(const pw_grid *grid, const pw_layout *layout, pw_
 
 /* Autotuner for single-grid launches.  Times candidate launch shapes of the
  * forward kernel (flags & PW_TUNE_FORWARD) and, for PW_F32 / PW_F64, of the
- * adjoint kernel (flags & PW_TUNE_ADJOINT; flags == 0 means both) on scratch
- * grids of this extent (allocated and freed here, contents zero), and
- * records the fastest per shape class -- dtype and the power-of-two ceilings
- * of nx, ny, nz -- in a process-wide table that pw_advect and
- * pw_advect_adjoint consult when called without a tile.  The z-cut is kept
- * as a number of chunks, so an entry serves every nz of its class.  If the
+ * adjoint (flags & PW_TUNE_ADJOINT) and tangent (flags & PW_TUNE_TANGENT)
+ * kernels; flags == 0 means all three.  The candidates run on scratch grids
+ * of this extent (allocated and freed here, contents zero), rotating over as
+ * many copies as span about 1 GiB so that repeats are not served by the
+ * MALL.  The fastest shape per shape class -- kernel, dtype and the
+ * power-of-two ceilings of nx, ny, nz -- goes into a process-wide table that
+ * the kernels consult when called without a tile.  The z-cut is kept as a
+ * number of chunks, so an entry serves every nz of its class.  If the
  * environment variable PWADV_TUNE_CACHE names a file, the table is read from
- * it on first use (unreadable or malformed lines are ignored) and rewritten
- * after each pw_tune.  Entries measured on MI355X for common shape classes
- * are built in and used when nothing else is known.  fwd_best / adj_best (may
- * be NULL) receive the chosen shapes.  Allocates device memory; synchronises
- * its own stream. */
+ * it on first use (unreadable or malformed lines are ignored) and the
+ * measured entries are rewritten to it after each pw_tune.  Entries measured
+ * on MI355X for common shape classes are built in and used when nothing else
+ * is known.  fwd_best / adj_best (may be NULL) receive the chosen forward and
+ * adjoint shapes (pw_launch_shape reports any kernel's).  Allocates device
+ * memory; synchronises its own stream. */
 #define PW_TUNE_FORWARD 1
 #define PW_TUNE_ADJOINT 2
+#define PW_TUNE_TANGENT 4
 pw_status pw_tune(const pw_grid *grid, pw_dtype dtype, int32_t flags, pw_tile *fwd_best, pw_tile *adj_best);
+
+/* The launch shape a kernel takes for this grid and dtype when called with
+ * tile == NULL: the tuned entry of its shape class if there is one, else the
+ * library's default.  No device work.  PW_ERR_UNSUPPORTED for an adjoint or
+ * tangent of a 16-bit dtype. */
+typedef enum { PW_KERNEL_FORWARD = 0, PW_KERNEL_ADJOINT = 1, PW_KERNEL_TANGENT = 2 } pw_kernel;
+pw_status pw_launch_shape(pw_kernel kind, const pw_grid *grid, pw_dtype dtype, pw_tile *out);
 
 /* Empties the process-wide tuning table, built-in entries included (the
  * cache file is left as is). */

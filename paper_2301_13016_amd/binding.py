@@ -65,7 +65,8 @@ class pw_batch_item(ctypes.Structure):
                 ("sw", ctypes.c_void_p)]
 
 
-PW_TUNE_FORWARD, PW_TUNE_ADJOINT = 1, 2
+PW_TUNE_FORWARD, PW_TUNE_ADJOINT, PW_TUNE_TANGENT = 1, 2, 4
+PW_KERNEL_FORWARD, PW_KERNEL_ADJOINT, PW_KERNEL_TANGENT = 0, 1, 2
 
 _P = ctypes.c_void_p
 _SIGNATURES = {
@@ -87,6 +88,7 @@ _SIGNATURES = {
     "pw_tune": [ctypes.POINTER(pw_grid), ctypes.c_int, ctypes.c_int32, ctypes.POINTER(pw_tile),
                 ctypes.POINTER(pw_tile)],
     "pw_tune_reset": [],
+    "pw_launch_shape": [ctypes.c_int, ctypes.POINTER(pw_grid), ctypes.c_int, ctypes.POINTER(pw_tile)],
     "pw_batch_create": [ctypes.POINTER(pw_batch_item), ctypes.c_int32, ctypes.c_int, ctypes.POINTER(pw_tile),
                         ctypes.POINTER(ctypes.c_void_p)],
     "pw_batch_run": [_P, _P],
@@ -349,6 +351,19 @@ def tune(nx, ny, nz, dtype, halo=1, flags=0):
     _check(pw_tune(pw_grid(nx, ny, nz, halo), code, flags, f, a), "pw_tune")
     tup = lambda t: (t.cols_per_lane, t.rows_per_strip, t.zlen, t.waves_per_group)  # noqa: E731
     return tup(f), (tup(a) if a.rows_per_strip else None)
+
+
+def launch_shape(kind, nx, ny, nz, dtype, halo=1):
+    """The launch shape ``kind`` ("forward", "adjoint" or "tangent") takes
+    for this grid when called without a tile, as (cols_per_lane,
+    rows_per_strip, zlen, waves_per_group)."""
+    import torch
+    code = {torch.float32: PW_F32, torch.float64: PW_F64, torch.bfloat16: PW_BF16, torch.float16: PW_F16}[dtype]
+    k = {"forward": PW_KERNEL_FORWARD, "adjoint": PW_KERNEL_ADJOINT, "tangent": PW_KERNEL_TANGENT}[kind]
+    t = pw_tile()
+    _check(lib().pw_launch_shape(k, ctypes.byref(pw_grid(nx, ny, nz, halo)), code, ctypes.byref(t)),
+           "pw_launch_shape")
+    return (t.cols_per_lane, t.rows_per_strip, t.zlen, t.waves_per_group)
 
 
 class Batch:

@@ -12,16 +12,17 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(HERE))
 
-# (nx, ny, nz, dtype name, flags): forward for all storage types, adjoint for FP32/FP64
+# (nx, ny, nz, dtype name, flags): forward for all storage types, adjoint and
+# tangent for FP32/FP64
 SHAPES = [
-    (512, 512, 64, "float32", 1),
+    (512, 512, 64, "float32", 7),
     (1024, 1024, 256, "float32", 1),
     (1024, 1024, 256, "bfloat16", 1),
     (1024, 1024, 256, "float16", 1),
-    (256, 256, 128, "float32", 3),
-    (64, 64, 64, "float64", 3),
-    (16, 16, 16, "float64", 3),
-    (128, 128, 128, "float32", 3),
+    (256, 256, 128, "float32", 7),
+    (64, 64, 64, "float64", 7),
+    (16, 16, 16, "float64", 7),
+    (128, 128, 128, "float32", 7),
     (256, 256, 256, "float32", 1),
     (512, 512, 128, "float32", 1),
 ]
@@ -35,20 +36,20 @@ def main(out_path):
     import torch
     from paper_2301_13016_amd import binding as B
     code = {"float32": B.PW_F32, "float64": B.PW_F64, "bfloat16": B.PW_BF16, "float16": B.PW_F16}
+    tdt = {"float32": torch.float32, "float64": torch.float64, "bfloat16": torch.bfloat16, "float16": torch.float16}
     lines = ["// kind, dtype, log2 nx, log2 ny, log2 nz, cols/lane, rows/strip, z-chunks, waves/group",
              "// generated on %s by paper_2301_13016_amd/tune_defaults.py" % torch.cuda.get_device_name(0)]
     B.pw_tune_reset()
     for nx, ny, nz, dt, flags in SHAPES:
-        f, a = B.pw_tile(), B.pw_tile()
-        B._check(B.pw_tune(B.pw_grid(nx, ny, nz, 1), code[dt], flags, f, a), "pw_tune")
+        B._check(B.pw_tune(B.pw_grid(nx, ny, nz, 1), code[dt], flags, None, None), "pw_tune")
         key = (ceil_log2(nx), ceil_log2(ny), ceil_log2(nz))
-        for kind, t, zext in ((0, f, nz), (1, a, nz + 2)):
-            if kind == 1 and not (flags & 2):
+        for kind, name, bit, zext in ((0, "forward", 1, nz), (1, "adjoint", 2, nz + 2), (2, "tangent", 4, nz)):
+            if not flags & bit:
                 continue
-            nzc = -(-zext // t.zlen)
+            t = B.launch_shape(name, nx, ny, nz, tdt[dt])
+            nzc = -(-zext // t[2])
             lines.append("{%d, %d, %d, %d, %d, %d, %d, %d, %d},  // %dx%dx%d %s %s" % (
-                kind, code[dt], *key, t.cols_per_lane, t.rows_per_strip, nzc, t.waves_per_group,
-                nx, ny, nz, dt, "adjoint" if kind else "forward"))
+                kind, code[dt], *key, t[0], t[1], nzc, t[3], nx, ny, nz, dt, name))
             print(lines[-1], flush=True)
     with open(out_path, "w") as fh:
         fh.write("\n".join(lines) + "\n")

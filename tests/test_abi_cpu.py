@@ -223,6 +223,44 @@ def test_tangent_validation(lib):
     assert call(B.PW_F64, q, B.pw_tile(2, 1, 8, 4)) == B.PW_ERR_INVALID_ARG
 
 
+def _table_row(kind, dt, nx, ny, nz):
+    """The built-in tuning table's row for a shape class, or None."""
+    import os
+    import re
+    path = os.path.join(os.path.dirname(B.__file__), "csrc", "pw_tune_defaults.inc")
+    key = (kind, dt) + tuple((n - 1).bit_length() for n in (nx, ny, nz))
+    for line in open(path):
+        m = re.match(r"\{([^}]*)\}", line.strip())
+        if m:
+            row = tuple(int(x) for x in m.group(1).split(","))
+            if row[:5] == key:
+                return row[5:]
+    return None
+
+
+def test_launch_shape_query(lib):
+    """pw_launch_shape needs no device: the built-in table's entry, or the
+    default shape for a class the table does not hold."""
+    torch = pytest.importorskip("torch")
+    row = _table_row(0, B.PW_F32, 512, 512, 64)
+    assert row is not None
+    px, ry, nzc, wpb = row
+    assert B.launch_shape("forward", 512, 512, 64, torch.float32) == (px, ry, -(-64 // nzc), wpb)
+    row = _table_row(1, B.PW_F32, 256, 256, 128)
+    px, ry, nzc, wpb = row
+    assert B.launch_shape("adjoint", 256, 256, 128, torch.float32) == (px, ry, -(-130 // nzc), wpb)
+    shape = B.launch_shape("tangent", 100, 3, 5, torch.float64)   # no table entry: the default
+    assert shape[0] == 1 and shape[1] in (1, 2) and 1 <= shape[2] <= 5 and 1 <= shape[3] <= 8
+    t = B.pw_tile()
+    assert lib.pw_launch_shape(1, ctypes.byref(B.pw_grid(8, 8, 8, 1)), B.PW_BF16, ctypes.byref(t)) \
+        == B.PW_ERR_UNSUPPORTED
+    assert lib.pw_launch_shape(7, ctypes.byref(B.pw_grid(8, 8, 8, 1)), B.PW_F32, ctypes.byref(t)) \
+        == B.PW_ERR_INVALID_ARG
+    assert lib.pw_launch_shape(0, None, B.PW_F32, ctypes.byref(t)) == B.PW_ERR_INVALID_ARG
+    assert lib.pw_launch_shape(0, ctypes.byref(B.pw_grid(0, 8, 8, 1)), B.PW_F32, ctypes.byref(t)) \
+        == B.PW_ERR_INVALID_ARG
+
+
 def test_stream_copy_validation(lib):
     assert B.pw_stream_copy(None, A, 16) == B.PW_ERR_INVALID_ARG
     assert B.pw_stream_copy(A, A + MB, 15) == B.PW_ERR_INVALID_ARG

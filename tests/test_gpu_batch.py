@@ -153,26 +153,34 @@ def test_c3_batch_matches_plain_launches(batch_c3, report):
 
 
 def test_single_grid_tuner_and_cache_file(tmp_path):
-    """pw_tune in a fresh process: writes the cache file, results are
-    unchanged (shape never changes results), a second process reads it."""
+    """pw_tune in a fresh process: writes the cache file (one line per
+    kernel), results are unchanged (shape never changes results), and a
+    second process reads the same shapes back from the file."""
     cache = tmp_path / "tune.txt"
     code = r'''
 import sys, numpy as np, torch
 sys.path.insert(0, %r); sys.path.insert(0, %r)
 from paper_2301_13016_amd import binding as B, workloads as wl
 from gpu_util import dev_grid
-g = wl.make_grid(300, 40, 24, seed=9)
-(u, v, w), c = dev_grid(g)
-a = [o.clone() for o in B.advect(u, v, w, c)]
-print("TILES", B.tune(300, 40, 24, torch.float32))
-b = B.advect(u, v, w, c)
-torch.cuda.synchronize()
-assert all(torch.equal(x, y) for x, y in zip(a, b))
+if sys.argv[1] == "tune":
+    g = wl.make_grid(300, 40, 24, seed=9)
+    (u, v, w), c = dev_grid(g)
+    a = [o.clone() for o in B.advect(u, v, w, c)]
+    B.tune(300, 40, 24, torch.float32)
+    b = B.advect(u, v, w, c)
+    torch.cuda.synchronize()
+    assert all(torch.equal(x, y) for x, y in zip(a, b))
+print("SHAPES", [B.launch_shape(k, 300, 40, 24, torch.float32) for k in ("forward", "adjoint", "tangent")])
 print("OK")
 ''' % (ROOT, os.path.join(ROOT, "tests"))
     env = dict(os.environ, PWADV_TUNE_CACHE=str(cache))
-    r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=300)
+    r = subprocess.run([sys.executable, "-c", code, "tune"], env=env, capture_output=True, text=True, timeout=300)
     assert r.returncode == 0, r.stderr[-2000:]
     assert "OK" in r.stdout
     lines = cache.read_text().splitlines()
-    assert len(lines) == 2 and all(l.startswith("pwadv-tune-v1 ") for l in lines)
+    assert len(lines) == 3 and all(l.startswith("pwadv-tune-v1 ") for l in lines)
+    assert sorted(int(l.split()[1]) for l in lines) == [0, 1, 2]
+    shapes = [l for l in r.stdout.splitlines() if l.startswith("SHAPES")]
+    r2 = subprocess.run([sys.executable, "-c", code, "read"], env=env, capture_output=True, text=True, timeout=300)
+    assert r2.returncode == 0, r2.stderr[-2000:]
+    assert [l for l in r2.stdout.splitlines() if l.startswith("SHAPES")] == shapes

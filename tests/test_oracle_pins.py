@@ -165,6 +165,24 @@ def test_adjoint_finite_difference_fp64():
         assert np.max(np.abs(a - b)) <= 1e-8 * np.max(np.abs(b))
 
 
+def test_tangent_equals_exact_rational_differences():
+    """J(x) d from the tangent oracle equals, bit for bit, the exact central
+    difference (F(x + d) - F(x - d)) / 2 of the rational forward operator (F is
+    quadratic, so the quotient is exact), on integer data with dyadic
+    coefficients where every FP64 intermediate is exact."""
+    g = wl.integer_grid(4, 3, 3, seed=24, dtype=np.float64)
+    rng = np.random.default_rng(25)
+    d = [rng.integers(-3, 4, g.u.shape).astype(np.float64) for _ in range(3)]
+    x = dict(u=g.u, v=g.v, w=g.w)
+    fp = bf.forward_exact({f: x[f] + dd for f, dd in zip(bf.FIELDS, d)}, g.coeffs)
+    fm = bf.forward_exact({f: x[f] - dd for f, dd in zip(bf.FIELDS, d)}, g.coeffs)
+    got = oracle.tangent(g.u, g.v, g.w, *d, g.coeffs)
+    for o, a in zip(bf.OUTPUTS, got):
+        exact = np.array([[[(p - m) / 2 for p, m in zip(rp, rm)] for rp, rm in zip(pp, mm)]
+                          for pp, mm in zip(fp[o], fm[o])], dtype=object)
+        assert np.array_equal(bf.to_float_array(exact), a), o
+
+
 def test_tangent_polarisation_and_dot_product():
     """For a homogeneous quadratic F: J(x) d = F(x + d) - F(x) - F(d), and
     <J d, y> = <d, J^T y> (the dot-product test)."""

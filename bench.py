@@ -5,9 +5,10 @@ differences, reduction, store: the whole hot path) over the FP32 grid
 512 x 512 x 64 (16.8 M interior points, 1-cell halo), with inputs resident in
 HBM.  K steps are timed between two device synchronisations; consecutive steps
 use different buffer sets (4 x 410 MB) so the 256 MB MALL cannot serve a
-repeat.  The dominant kernel's average duration comes from HIP events around
-each launch on the launch stream.  Launch shapes are the library's choice
-(its built-in tuning table); the batched form is tuned in the run.
+repeat.  The dominant kernel's average duration comes from two HIP events
+around the timed launches on the launch stream (no event between launches).
+Launch shapes are the library's choice (its built-in tuning table); the
+batched form is tuned in the run.
 
 Also measured in the same run ("forms"):
   * BF16 / FP16 storage vs FP32 on 1024 x 1024 x 256 (268 M points);
@@ -95,22 +96,25 @@ def tangent_bytes(nx, ny, nz, halo, es=4):
 
 
 def time_launches(torch, launch, nsets, steps, warmup, stream):
-    """Run ``launch(i)`` for warmup + steps iterations (i = buffer set), time
-    the steps region with a wall clock between synchronisations and each
-    launch with HIP events on ``stream``.  Returns (ms_per_step, mean event ms)."""
+    """Run ``launch(i)`` for warmup + steps iterations (i = buffer set) and
+    time the steps back to back: a wall clock between two device
+    synchronisations, and two HIP events on ``stream`` around the same
+    region.  Returns (wall ms per step, event ms per launch).  No event sits
+    between launches: an event with timing makes the next kernel wait until
+    the previous one has drained, which costs several microseconds per step
+    and is not part of the kernel."""
     for i in range(warmup):
         launch(i % nsets)
     torch.cuda.synchronize()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
+    a.record(stream)
     for i in range(steps):
-        ev[i][0].record(stream)
         launch(i % nsets)
-        ev[i][1].record(stream)
+    b.record(stream)
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) * 1e3
-    per = [a.elapsed_time(b) for a, b in ev]
-    return wall / steps, float(np.mean(per))
+    return wall / steps, a.elapsed_time(b) / steps
 
 
 def prebuilt_forward(B, ins, outs, coeffs, stream, tile=None):
@@ -177,7 +181,8 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=500)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=200,
+                    help="untimed steps first (about 16 ms: the clocks settle within the first ~100)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="approximate host time spent timing the oracle")
     args = ap.parse_args()

@@ -113,11 +113,16 @@ pw_status pw_advect(const pw_grid *grid, const pw_layout *layout, pw_dtype in_dt
 /* Launch shape of the stencil kernels (a performance choice; results are
  * bit-identical across shapes).  A wavefront of 64 lanes owns a strip of
  * 64*cols_per_lane x rows_per_strip interior cells and marches through zlen
- * levels; waves_per_group strips are stacked in y per workgroup.
+ * levels, with `prefetch` planes loaded ahead of the level it computes;
+ * waves_per_group strips are stacked in y per workgroup.
  * Forward (pw_advect_ex):
  *   cols_per_lane 1 or 2: rows_per_strip in {1, 2, 4};
- *   cols_per_lane 4 (not PW_F64): rows_per_strip in {1, 2};
- *   PW_F64: cols_per_lane in {1, 2}, rows_per_strip in {1, 2}.
+ *   cols_per_lane 4 (not PW_F64): rows_per_strip in {1, 2}, and 4 for
+ *   16-bit storage; cols_per_lane 8 (16-bit storage): rows_per_strip in {1, 2};
+ *   PW_F64: cols_per_lane in {1, 2}, rows_per_strip in {1, 2};
+ *   prefetch 1 or 2 (0 means 1).  A deeper prefetch keeps more bytes in
+ *   flight per wavefront; it pays when few wavefronts run.
+ * Adjoint, tangent and batched forms: prefetch 0 or 1.
  * Adjoint (pw_advect_adjoint_ex): cols_per_lane 1 (strips of 62 padded
  *   columns), rows_per_strip in {1, 2, 4}.
  * Tangent (pw_advect_tangent_ex): cols_per_lane 1 or 2 (PW_F64: 1),
@@ -129,6 +134,7 @@ typedef struct {
     int32_t rows_per_strip;
     int32_t zlen;
     int32_t waves_per_group;
+    int32_t prefetch;
 } pw_tile;
 
 /* pw_advect with an explicit launch shape; tile == NULL means the library's

@@ -56,7 +56,12 @@ class pw_coeffs(ctypes.Structure):
 
 class pw_tile(ctypes.Structure):
     _fields_ = [("cols_per_lane", ctypes.c_int32), ("rows_per_strip", ctypes.c_int32),
-                ("zlen", ctypes.c_int32), ("waves_per_group", ctypes.c_int32)]
+                ("zlen", ctypes.c_int32), ("waves_per_group", ctypes.c_int32), ("prefetch", ctypes.c_int32)]
+
+
+def _tile_tuple(t):
+    """(cols_per_lane, rows_per_strip, zlen, waves_per_group, prefetch)."""
+    return (t.cols_per_lane, t.rows_per_strip, t.zlen, t.waves_per_group, t.prefetch)
 
 
 class pw_batch_item(ctypes.Structure):
@@ -343,27 +348,26 @@ def advect_tangent(u, v, w, coeffs: Coeffs, du, dv, dw, halo=1, out=None, tile=N
 
 def tune(nx, ny, nz, dtype, halo=1, flags=0):
     """Run the autotuner for this grid class; returns (forward tile, adjoint
-    tile) as (cols_per_lane, rows_per_strip, zlen, waves_per_group) tuples
+    tile) as (cols_per_lane, rows_per_strip, zlen, waves_per_group, prefetch) tuples
     (the adjoint entry is None when not tuned)."""
     import torch
     code = {torch.float32: PW_F32, torch.float64: PW_F64, torch.bfloat16: PW_BF16, torch.float16: PW_F16}[dtype]
     f, a = pw_tile(), pw_tile()
     _check(pw_tune(pw_grid(nx, ny, nz, halo), code, flags, f, a), "pw_tune")
-    tup = lambda t: (t.cols_per_lane, t.rows_per_strip, t.zlen, t.waves_per_group)  # noqa: E731
-    return tup(f), (tup(a) if a.rows_per_strip else None)
+    return _tile_tuple(f), (_tile_tuple(a) if a.rows_per_strip else None)
 
 
 def launch_shape(kind, nx, ny, nz, dtype, halo=1):
     """The launch shape ``kind`` ("forward", "adjoint" or "tangent") takes
     for this grid when called without a tile, as (cols_per_lane,
-    rows_per_strip, zlen, waves_per_group)."""
+    rows_per_strip, zlen, waves_per_group, prefetch)."""
     import torch
     code = {torch.float32: PW_F32, torch.float64: PW_F64, torch.bfloat16: PW_BF16, torch.float16: PW_F16}[dtype]
     k = {"forward": PW_KERNEL_FORWARD, "adjoint": PW_KERNEL_ADJOINT, "tangent": PW_KERNEL_TANGENT}[kind]
     t = pw_tile()
     _check(lib().pw_launch_shape(k, ctypes.byref(pw_grid(nx, ny, nz, halo)), code, ctypes.byref(t)),
            "pw_launch_shape")
-    return (t.cols_per_lane, t.rows_per_strip, t.zlen, t.waves_per_group)
+    return _tile_tuple(t)
 
 
 class Batch:
@@ -399,12 +403,12 @@ class Batch:
     def tune(self, stream=None):
         t = pw_tile()
         _check(pw_batch_tune(self.handle, _stream_handle(stream), t), "pw_batch_tune")
-        return (t.cols_per_lane, t.rows_per_strip, t.zlen, t.waves_per_group)
+        return _tile_tuple(t)
 
     def info(self):
         t, it, g = pw_tile(), ctypes.c_int64(), ctypes.c_int32()
         _check(pw_batch_info(self.handle, t, it, g), "pw_batch_info")
-        return (t.cols_per_lane, t.rows_per_strip, t.zlen, t.waves_per_group), it.value, g.value
+        return _tile_tuple(t), it.value, g.value
 
     def close(self):
         if self.handle:

@@ -278,18 +278,22 @@ __global__ __launch_bounds__(MaxT) void pw_adjoint_kernel(AdjK<T> a) {
     load_aplane<T, RY>(C, a, k0 + 1, s);
     mask_aplane<T, RY>(A, s);
     mask_aplane<T, RY>(B, s);
+    // Unconditional prefetch of plane k+2 (past the chunk's last level it
+    // re-reads plane k1, a cache hit, into a slot no level uses): a
+    // conditional load would join two paths with different loads in flight,
+    // and the wait at the join drains the prefetch.
     int k = k0;
     for (;;) {
-        if (k + 1 < k1) load_aplane<T, RY>(D, a, k + 2, s);
+        load_aplane<T, RY>(D, a, min(k + 2, k1), s);
         adj_level<T, RY>(A, B, C, a, s, k, lane_ok, goff, row_ok);
         if (++k >= k1) break;
-        if (k + 1 < k1) load_aplane<T, RY>(A, a, k + 2, s);
+        load_aplane<T, RY>(A, a, min(k + 2, k1), s);
         adj_level<T, RY>(B, C, D, a, s, k, lane_ok, goff, row_ok);
         if (++k >= k1) break;
-        if (k + 1 < k1) load_aplane<T, RY>(B, a, k + 2, s);
+        load_aplane<T, RY>(B, a, min(k + 2, k1), s);
         adj_level<T, RY>(C, D, A, a, s, k, lane_ok, goff, row_ok);
         if (++k >= k1) break;
-        if (k + 1 < k1) load_aplane<T, RY>(C, a, k + 2, s);
+        load_aplane<T, RY>(C, a, min(k + 2, k1), s);
         adj_level<T, RY>(D, A, B, a, s, k, lane_ok, goff, row_ok);
         if (++k >= k1) break;
     }
@@ -352,7 +356,7 @@ pw_status launch_adj_dt(const AdjArgs &g, const TileCfg &cfg, hipStream_t s) {
 }  // namespace
 
 bool adjoint_tile_supported(const TileCfg &c) {
-    return c.px == 1 && (c.ry == 1 || c.ry == 2 || c.ry == 4) && c.zlen >= 1 && c.wpb >= 1 && c.wpb <= 8;
+    return c.px == 1 && c.depth == 1 && (c.ry == 1 || c.ry == 2 || c.ry == 4) && c.zlen >= 1 && c.wpb >= 1 && c.wpb <= 8;
 }
 
 TileCfg default_adjoint_tile(const AdjArgs &a, pw_dtype dt) {

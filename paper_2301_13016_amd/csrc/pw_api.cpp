@@ -146,6 +146,7 @@ TileCfg to_cfg(const pw_tile &t) {
     c.ry = t.rows_per_strip;
     c.zlen = t.zlen;
     c.wpb = t.waves_per_group;
+    c.depth = t.prefetch == 0 ? 1 : t.prefetch;
     return c;
 }
 
@@ -238,8 +239,8 @@ pw_status pw_advect_ex(const pw_grid *grid, const pw_layout *layout, pw_dtype in
     FwdArgs a;
     PW_TRY(validate_forward(grid, layout, in_dtype, u, v, w, coeffs, su, sv, sw, &a));
     if (tile && !tile_supported(to_cfg(*tile), in_dtype))
-        return fail(PW_ERR_INVALID_ARG, "unsupported forward tile cols=%d rows=%d zlen=%d waves=%d",
-                    tile->cols_per_lane, tile->rows_per_strip, tile->zlen, tile->waves_per_group);
+        return fail(PW_ERR_INVALID_ARG, "unsupported forward tile cols=%d rows=%d zlen=%d waves=%d prefetch=%d",
+                    tile->cols_per_lane, tile->rows_per_strip, tile->zlen, tile->waves_per_group, tile->prefetch);
     PW_TRY(check_forward_on_device(a));
     TileCfg cfg;
     if (tile)
@@ -283,8 +284,8 @@ pw_status pw_advect_tangent_ex(const pw_grid *grid, const pw_layout *layout, pw_
         for (const Range &i : rdir)
             if (overlap(o, i)) return fail(PW_ERR_INVALID_ARG, "output %s overlaps direction %s", o.name, i.name);
     if (tile && !tangent_tile_supported(to_cfg(*tile), dtype))
-        return fail(PW_ERR_INVALID_ARG, "unsupported tangent tile cols=%d rows=%d zlen=%d waves=%d",
-                    tile->cols_per_lane, tile->rows_per_strip, tile->zlen, tile->waves_per_group);
+        return fail(PW_ERR_INVALID_ARG, "unsupported tangent tile cols=%d rows=%d zlen=%d waves=%d prefetch=%d",
+                    tile->cols_per_lane, tile->rows_per_strip, tile->zlen, tile->waves_per_group, tile->prefetch);
     PW_TRY(check_forward_on_device(a.f));
     int dev = 0;
     PW_TRY(current_device(&dev));
@@ -338,8 +339,8 @@ pw_status pw_advect_adjoint_ex(const pw_grid *grid, const pw_layout *layout, pw_
     }
     PW_TRY(check_coeffs_apart(coeffs, grid->nz, es, rout, 3));
     if (tile && !adjoint_tile_supported(to_cfg(*tile)))
-        return fail(PW_ERR_INVALID_ARG, "unsupported adjoint tile cols=%d rows=%d zlen=%d waves=%d",
-                    tile->cols_per_lane, tile->rows_per_strip, tile->zlen, tile->waves_per_group);
+        return fail(PW_ERR_INVALID_ARG, "unsupported adjoint tile cols=%d rows=%d zlen=%d waves=%d prefetch=%d",
+                    tile->cols_per_lane, tile->rows_per_strip, tile->zlen, tile->waves_per_group, tile->prefetch);
     int dev = 0;
     PW_TRY(current_device(&dev));
     for (int i = 0; i < 13; ++i) PW_TRY(check_on_device(names[i], ptrs[i], dev));

@@ -61,7 +61,7 @@ __global__ __launch_bounds__(MaxT) void pw_batch_kernel(const BatchSub<Tin> *__r
         const int64_t t2 = local / a.nzc;
         const int tx = static_cast<int>(t2 % a.ntx);
         const int ty = static_cast<int>(t2 / a.ntx);
-        strip_march<Tin, PX, RY>(a, tx, ty, cz);
+        strip_march<Tin, PX, RY, 1>(a, tx, ty, cz);
     }
 }
 
@@ -228,7 +228,7 @@ pw_status enqueue(pw_batch *b, hipStream_t s) {
 }
 
 bool batch_tile_ok(const TileCfg &c) {
-    return tile_supported(c, PW_F32) && batch_kernel(c) != nullptr;
+    return c.depth == 1 && tile_supported(c, PW_F32) && batch_kernel(c) != nullptr;
 }
 
 }  // namespace
@@ -244,10 +244,11 @@ pw_status pw_batch_create(const pw_batch_item *items, int32_t n, pw_dtype dtype,
     if (dtype != PW_F32) return fail(PW_ERR_UNSUPPORTED, "the batched form supports PW_F32 storage");
     TileCfg cfg = default_batch_tile();
     if (tile) {
-        cfg = TileCfg{tile->cols_per_lane, tile->rows_per_strip, tile->zlen, tile->waves_per_group};
+        cfg = TileCfg{tile->cols_per_lane, tile->rows_per_strip, tile->zlen, tile->waves_per_group,
+                      tile->prefetch == 0 ? 1 : tile->prefetch};
         if (!batch_tile_ok(cfg))
-            return fail(PW_ERR_INVALID_ARG, "unsupported batch tile cols=%d rows=%d zlen=%d waves=%d", cfg.px, cfg.ry,
-                        cfg.zlen, cfg.wpb);
+            return fail(PW_ERR_INVALID_ARG, "unsupported batch tile cols=%d rows=%d zlen=%d waves=%d prefetch=%d",
+                        cfg.px, cfg.ry, cfg.zlen, cfg.wpb, tile->prefetch);
     }
     std::vector<FwdArgs> subs(static_cast<size_t>(n));
     for (int32_t i = 0; i < n; ++i) {
@@ -418,13 +419,13 @@ pw_status pw_batch_tune(pw_batch *b, void *hip_stream, pw_tile *chosen) {
     const pw_status st2 = build_table(b, st == PW_OK ? best : start);
     if (st != PW_OK) return st;
     if (st2 != PW_OK) return st2;
-    if (chosen) *chosen = pw_tile{best.px, best.ry, best.zlen, best.wpb};
+    if (chosen) *chosen = to_tile(best);
     return PW_OK;
 }
 
 pw_status pw_batch_info(const pw_batch *b, pw_tile *tile, int64_t *work_items, int32_t *workgroups) {
     if (!b) return fail(PW_ERR_INVALID_ARG, "batch is NULL");
-    if (tile) *tile = pw_tile{b->tile.px, b->tile.ry, b->tile.zlen, b->tile.wpb};
+    if (tile) *tile = to_tile(b->tile);
     if (work_items) *work_items = b->nitems;
     if (workgroups) *workgroups = b->blocks;
     return PW_OK;

@@ -37,11 +37,12 @@ namespace {
 
 using namespace dev;
 
+// Depth: planes in flight ahead of the level being computed (1 or 2).
 // MaxT: the workgroup size bound the kernel is compiled for.  Every shape is
 // built twice: for up to 256 threads (four wavefronts, one per SIMD, so a
 // wavefront may use the whole 512-entry register file: the large strips keep
 // their planes in registers instead of spilling) and for up to 512.
-template <typename Tin, int PX, int RY, int MaxT>
+template <typename Tin, int PX, int RY, int Depth, int MaxT>
 __global__ __launch_bounds__(MaxT) void pw_forward_kernel(FwdK<Tin> a) {
     // wavefront index as a scalar, so that per-strip conditions stay scalar
     const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
@@ -51,7 +52,7 @@ __global__ __launch_bounds__(MaxT) void pw_forward_kernel(FwdK<Tin> a) {
     const int tx = t2 % a.ntx;
     const int ty = (t2 / a.ntx) * a.wpb + wave;
     if (ty >= a.nty) return;   // whole wavefront
-    strip_march<Tin, PX, RY>(a, tx, ty, cz);
+    strip_march<Tin, PX, RY, Depth>(a, tx, ty, cz);
 }
 
 template <typename Tin, int PX, int RY>
@@ -86,12 +87,18 @@ pw_status launch_fwd_t(const FwdArgs &g, const TileCfg &cfg, hipStream_t s) {
     const int64_t nblk_y = (a.nty + cfg.wpb - 1) / cfg.wpb;
     const int64_t nblocks = static_cast<int64_t>(a.ntx) * nblk_y * a.nzc;
     if (nblocks <= 0 || nblocks > 0x7fffffffLL) return fail(PW_ERR_UNSUPPORTED, "grid too large");
-    if (cfg.wpb <= 4)
-        hipLaunchKernelGGL((pw_forward_kernel<Tin, PX, RY, 256>), dim3(static_cast<unsigned>(nblocks)),
-                           dim3(64 * cfg.wpb), 0, s, a);
-    else
-        hipLaunchKernelGGL((pw_forward_kernel<Tin, PX, RY, 512>), dim3(static_cast<unsigned>(nblocks)),
-                           dim3(64 * cfg.wpb), 0, s, a);
+    const dim3 grid(static_cast<unsigned>(nblocks)), block(64 * cfg.wpb);
+    if (cfg.depth == 2) {
+        if (cfg.wpb <= 4)
+            hipLaunchKernelGGL((pw_forward_kernel<Tin, PX, RY, 2, 256>), grid, block, 0, s, a);
+        else
+            hipLaunchKernelGGL((pw_forward_kernel<Tin, PX, RY, 2, 512>), grid, block, 0, s, a);
+    } else {
+        if (cfg.wpb <= 4)
+            hipLaunchKernelGGL((pw_forward_kernel<Tin, PX, RY, 1, 256>), grid, block, 0, s, a);
+        else
+            hipLaunchKernelGGL((pw_forward_kernel<Tin, PX, RY, 1, 512>), grid, block, 0, s, a);
+    }
     return hip_fail(hipGetLastError(), "forward kernel launch");
 }
 
@@ -139,7 +146,7 @@ __global__ __launch_bounds__(256) void copy16_kernel(const u32x4 *__restrict__ s
 }  // namespace
 
 bool tile_supported(const TileCfg &c, pw_dtype dt) {
-    if (c.zlen < 1 || c.wpb < 1 || c.wpb > 8) return false;
+    if (c.zlen < 1 || c.wpb < 1 || c.wpb > 8 || (c.depth != 1 && c.depth != 2)) return false;
     const bool half = dt == PW_BF16 || dt == PW_F16;
     if (dt == PW_F64) return (c.px == 1 || c.px == 2) && (c.ry == 1 || c.ry == 2);
     if (c.px == 8) return half && (c.ry == 1 || c.ry == 2);

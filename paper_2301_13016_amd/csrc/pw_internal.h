@@ -16,12 +16,16 @@ namespace pw {
 //          into ceil(nz / zlen) independent chunks, each re-reading one plane
 //          above and below)
 //   wpb    wavefronts per workgroup (stacked in y), 1..8
+//   depth  planes in flight ahead of the level being computed (forward: 1, 2;
+//          the other kernels: 1)
 struct TileCfg {
     int px = 1;
     int ry = 2;
     int zlen = 16;
     int wpb = 4;
+    int depth = 1;
 };
+inline pw_tile to_tile(const TileCfg &c) { return pw_tile{c.px, c.ry, c.zlen, c.wpb, c.depth}; }
 
 // Operands of one forward launch, already validated.  Strides are in elements.
 struct FwdArgs {

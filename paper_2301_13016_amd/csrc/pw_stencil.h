@@ -99,6 +99,15 @@ template <typename T> __device__ __forceinline__ T uniform_load(const T *p, int 
     return ((const __attribute__((address_space(4))) T *)(p))[i];
 }
 
+// Element of type V at byte address p, read / written as global memory.  The
+// kernels only touch device memory; where the array pointers come from a
+// table in memory (the batched kernel) the compiler cannot infer their
+// address space and would fall back to flat accesses, which wait on two
+// counters.  Macros rather than templates, so that V keeps its typedef's
+// (element) alignment.
+#define PW_GLOAD(V, p) (*(const __attribute__((address_space(1))) V *)(p))
+#define PW_GSTORE_NT(V, x, p) __builtin_nontemporal_store((x), (__attribute__((address_space(1))) V *)(p))
+
 template <typename T> __device__ __forceinline__ T fma_(T a, T b, T c);
 template <> __device__ __forceinline__ float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 template <> __device__ __forceinline__ double fma_(double a, double b, double c) { return __builtin_fma(a, b, c); }
@@ -144,12 +153,13 @@ __device__ __forceinline__ void load_row(typename Vec<Tin, PX>::type &dst, const
     if constexpr (Full || PX == 1) {
         (void)col;
         (void)last_col;
-        dst = *reinterpret_cast<const typename Vec<Tin, PX>::type *>(plane + off);
+        using VT = typename Vec<Tin, PX>::type;
+        dst = PW_GLOAD(VT, plane + off);
     } else {
         const char *row = plane + off - static_cast<int64_t>(col) * static_cast<int64_t>(sizeof(Tin));
 #pragma unroll
         for (int m = 0; m < PX; ++m)
-            dst[m] = *reinterpret_cast<const Tin *>(row + static_cast<int64_t>(min(col + m, last_col)) * sizeof(Tin));
+            dst[m] = PW_GLOAD(Tin, row + static_cast<int64_t>(min(col + m, last_col)) * sizeof(Tin));
     }
 }
 
@@ -166,9 +176,9 @@ __device__ __forceinline__ void load_plane(Plane<Tin, PX, RY> &P, const FwdK<Tin
         load_row<Tin, PX, Full>(P.v[r], bv, s.roff[r], s.col, last_col);
         load_row<Tin, PX, Full>(P.w[r], bw, s.roff[r], s.col, last_col);
     }
-    P.hu = *reinterpret_cast<const Tin *>(bu + s.hoff);
-    P.hv = *reinterpret_cast<const Tin *>(bv + s.hoff);
-    P.hw = *reinterpret_cast<const Tin *>(bw + s.hoff);
+    P.hu = PW_GLOAD(Tin, bu + s.hoff);
+    P.hv = PW_GLOAD(Tin, bv + s.hoff);
+    P.hw = PW_GLOAD(Tin, bw + s.hoff);
 }
 
 template <typename T, int N> __device__ __forceinline__ void store_vec(char *p, const T (&x)[N]) {
@@ -179,7 +189,8 @@ template <typename T, int N> __device__ __forceinline__ void store_vec(char *p, 
 #pragma unroll
         for (int m = 0; m < N; ++m) v[m] = x[m];
     }
-    __builtin_nontemporal_store(v, reinterpret_cast<typename Vec<T, N>::type *>(p));
+    using VT = typename Vec<T, N>::type;
+    PW_GSTORE_NT(VT, v, p);
 }
 
 // Source terms of output level kk (interior numbering) from planes kk-1 (m),
@@ -292,9 +303,9 @@ __device__ __forceinline__ void level(const Plane<Tin, PX, RY> &m, const Plane<T
 #pragma unroll
                 for (int x = 0; x < PX; ++x) {
                     if (x < nvalid) {
-                        __builtin_nontemporal_store(rsu[x], reinterpret_cast<Tc *>(osu + ooff[r]) + x);
-                        __builtin_nontemporal_store(rsv[x], reinterpret_cast<Tc *>(osv + ooff[r]) + x);
-                        __builtin_nontemporal_store(rsw[x], reinterpret_cast<Tc *>(osw + ooff[r]) + x);
+                        PW_GSTORE_NT(Tc, rsu[x], osu + ooff[r] + x * sizeof(Tc));
+                        PW_GSTORE_NT(Tc, rsv[x], osv + ooff[r] + x * sizeof(Tc));
+                        PW_GSTORE_NT(Tc, rsw[x], osw + ooff[r] + x * sizeof(Tc));
                     }
                 }
             }
@@ -318,8 +329,9 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
 // the strip lies wholly inside the grid in x ((tx+1)*64*PX <= nx), so every
 // lane loads whole vectors and owns PX outputs; otherwise loads are clamped
 // element-wise (one-column lanes need no clamping beyond their start column)
-// and each lane stores only its columns inside the grid.
-template <typename Tin, int PX, int RY, bool Full>
+// and each lane stores only its columns inside the grid.  Depth: planes in
+// flight ahead of the three a level reads (1 or 2).
+template <typename Tin, int PX, int RY, bool Full, int Depth>
 __device__ __forceinline__ void strip_march_t(const FwdK<Tin> &a, int tx, int ty, int cz) {
     using Tc = typename Storage<Tin>::Tc;
     const int lane = threadIdx.x & 63;
@@ -358,41 +370,73 @@ __device__ __forceinline__ void strip_march_t(const FwdK<Tin> &a, int tx, int ty
     const int k1 = min(a.nz, k0 + a.zlen);
     const int h = a.h;
 
-    Plane<Tin, PX, RY> A, B, C, D;
-    load_plane<Tin, PX, RY, Full>(A, a, k0 - 1 + h, s, last_col);
-    load_plane<Tin, PX, RY, Full>(B, a, k0 + h, s, last_col);
-    load_plane<Tin, PX, RY, Full>(C, a, k0 + 1 + h, s, last_col);
-    // The prefetch of plane kk+2 is unconditional (near the chunk's end it
+    // The prefetch of the next plane is unconditional (near the chunk's end it
     // re-reads plane k1, a cache hit): a conditional load would merge two
     // paths with different loads in flight, and the wait inserted at such a
     // merge drains every outstanding load, prefetch included.
+#define PW_LOAD(P, kp) load_plane<Tin, PX, RY, Full>(P, a, min((kp), k1) + h, s, last_col)
+#define PW_LEVEL(M, C, P) level<Tin, PX, RY, Full>(M, C, P, a, kk, lane0, lane63, nvalid, ooff, row_ok)
     int kk = k0;
-    for (;;) {
-        load_plane<Tin, PX, RY, Full>(D, a, min(kk + 2, k1) + h, s, last_col);
-        level<Tin, PX, RY, Full>(A, B, C, a, kk, lane0, lane63, nvalid, ooff, row_ok);
-        if (++kk >= k1) break;
-        load_plane<Tin, PX, RY, Full>(A, a, min(kk + 2, k1) + h, s, last_col);
-        level<Tin, PX, RY, Full>(B, C, D, a, kk, lane0, lane63, nvalid, ooff, row_ok);
-        if (++kk >= k1) break;
-        load_plane<Tin, PX, RY, Full>(B, a, min(kk + 2, k1) + h, s, last_col);
-        level<Tin, PX, RY, Full>(C, D, A, a, kk, lane0, lane63, nvalid, ooff, row_ok);
-        if (++kk >= k1) break;
-        load_plane<Tin, PX, RY, Full>(C, a, min(kk + 2, k1) + h, s, last_col);
-        level<Tin, PX, RY, Full>(D, A, B, a, kk, lane0, lane63, nvalid, ooff, row_ok);
-        if (++kk >= k1) break;
+    if constexpr (Depth == 1) {
+        // four-plane ring: planes kk-1, kk, kk+1 feed level kk, kk+2 in flight
+        Plane<Tin, PX, RY> A, B, C, D;
+        load_plane<Tin, PX, RY, Full>(A, a, k0 - 1 + h, s, last_col);
+        PW_LOAD(B, k0);
+        PW_LOAD(C, k0 + 1);
+        for (;;) {
+            PW_LOAD(D, kk + 2);
+            PW_LEVEL(A, B, C);
+            if (++kk >= k1) break;
+            PW_LOAD(A, kk + 2);
+            PW_LEVEL(B, C, D);
+            if (++kk >= k1) break;
+            PW_LOAD(B, kk + 2);
+            PW_LEVEL(C, D, A);
+            if (++kk >= k1) break;
+            PW_LOAD(C, kk + 2);
+            PW_LEVEL(D, A, B);
+            if (++kk >= k1) break;
+        }
+    } else {
+        // five-plane ring: planes kk+2 and kk+3 in flight
+        static_assert(Depth == 2, "prefetch depth 1 or 2");
+        Plane<Tin, PX, RY> A, B, C, D, E;
+        load_plane<Tin, PX, RY, Full>(A, a, k0 - 1 + h, s, last_col);
+        PW_LOAD(B, k0);
+        PW_LOAD(C, k0 + 1);
+        PW_LOAD(D, k0 + 2);
+        for (;;) {
+            PW_LOAD(E, kk + 3);
+            PW_LEVEL(A, B, C);
+            if (++kk >= k1) break;
+            PW_LOAD(A, kk + 3);
+            PW_LEVEL(B, C, D);
+            if (++kk >= k1) break;
+            PW_LOAD(B, kk + 3);
+            PW_LEVEL(C, D, E);
+            if (++kk >= k1) break;
+            PW_LOAD(C, kk + 3);
+            PW_LEVEL(D, E, A);
+            if (++kk >= k1) break;
+            PW_LOAD(D, kk + 3);
+            PW_LEVEL(E, A, B);
+            if (++kk >= k1) break;
+        }
     }
+#undef PW_LOAD
+#undef PW_LEVEL
 }
 
-template <typename Tin, int PX, int RY>
+template <typename Tin, int PX, int RY, int Depth>
 __device__ __forceinline__ void strip_march(const FwdK<Tin> &a, int tx, int ty, int cz) {
     if constexpr (PX == 1) {
         // one-column lanes: loads never need clamping beyond the start column,
         // and one masked store per row is cheap, so one path serves every strip
-        strip_march_t<Tin, PX, RY, false>(a, tx, ty, cz);
+        strip_march_t<Tin, PX, RY, false, Depth>(a, tx, ty, cz);
     } else if ((tx + 1) * 64 * PX <= a.nx) {
-        strip_march_t<Tin, PX, RY, true>(a, tx, ty, cz);
+        strip_march_t<Tin, PX, RY, true, Depth>(a, tx, ty, cz);
     } else {
-        strip_march_t<Tin, PX, RY, false>(a, tx, ty, cz);
+        strip_march_t<Tin, PX, RY, false, Depth>(a, tx, ty, cz);
     }
 }
 

@@ -198,6 +198,23 @@ def test_adjoint_gradient_overlap_rejected(lib):
     assert st == B.PW_ERR_INVALID_ARG
 
 
+def test_prefetch_depth_validation(lib):
+    """prefetch: 0 (= 1) or 1 or 2 for the forward; 0 or 1 elsewhere."""
+    g, c, p = _args()
+    for pf, ok in [(0, True), (1, True), (2, True), (3, False), (-1, False)]:
+        st = _call(g, None, B.PW_F32, c, p, B.pw_tile(4, 2, 8, 1, pf))
+        assert (st in _no_gpu_status()) if ok else st == B.PW_ERR_INVALID_ARG, pf
+    q = [A + i * MB for i in range(9)]
+    st = B.pw_advect_adjoint_ex(g, None, B.PW_F32, *q[:3], c, *q[3:6], *q[6:9], B.pw_tile(1, 2, 8, 1, 2))
+    assert st == B.PW_ERR_INVALID_ARG
+    st = B.pw_advect_tangent_ex(g, None, B.PW_F32, *q[:3], c, *q[3:6], *q[6:9], B.pw_tile(1, 2, 8, 1, 2))
+    assert st == B.PW_ERR_INVALID_ARG
+    assert B.pw_advect_tangent_ex(g, None, B.PW_F32, *q[:3], c, *q[3:6], *q[6:9],
+                                  B.pw_tile(1, 2, 8, 1, 1)) in _no_gpu_status()
+    h = ctypes.c_void_p()
+    assert B.pw_batch_create(_items(2), 2, B.PW_F32, B.pw_tile(1, 2, 8, 4, 2), h) == B.PW_ERR_INVALID_ARG
+
+
 def test_tangent_validation(lib):
     g, c, p = _args()
     q = [A + i * MB for i in range(9)]   # u v w du dv dw tu tv tw
@@ -244,13 +261,13 @@ def test_launch_shape_query(lib):
     torch = pytest.importorskip("torch")
     row = _table_row(0, B.PW_F32, 512, 512, 64)
     assert row is not None
-    px, ry, nzc, wpb = row
-    assert B.launch_shape("forward", 512, 512, 64, torch.float32) == (px, ry, -(-64 // nzc), wpb)
+    px, ry, nzc, wpb, depth = row
+    assert B.launch_shape("forward", 512, 512, 64, torch.float32) == (px, ry, -(-64 // nzc), wpb, depth)
     row = _table_row(1, B.PW_F32, 256, 256, 128)
-    px, ry, nzc, wpb = row
-    assert B.launch_shape("adjoint", 256, 256, 128, torch.float32) == (px, ry, -(-130 // nzc), wpb)
+    px, ry, nzc, wpb, depth = row
+    assert B.launch_shape("adjoint", 256, 256, 128, torch.float32) == (px, ry, -(-130 // nzc), wpb, 1)
     shape = B.launch_shape("tangent", 100, 3, 5, torch.float64)   # no table entry: the default
-    assert shape[0] == 1 and shape[1] in (1, 2) and 1 <= shape[2] <= 5 and 1 <= shape[3] <= 8
+    assert shape[0] == 1 and shape[1] in (1, 2) and 1 <= shape[2] <= 5 and 1 <= shape[3] <= 8 and shape[4] == 1
     t = B.pw_tile()
     assert lib.pw_launch_shape(1, ctypes.byref(B.pw_grid(8, 8, 8, 1)), B.PW_BF16, ctypes.byref(t)) \
         == B.PW_ERR_UNSUPPORTED
@@ -259,6 +276,35 @@ def test_launch_shape_query(lib):
     assert lib.pw_launch_shape(0, None, B.PW_F32, ctypes.byref(t)) == B.PW_ERR_INVALID_ARG
     assert lib.pw_launch_shape(0, ctypes.byref(B.pw_grid(0, 8, 8, 1)), B.PW_F32, ctypes.byref(t)) \
         == B.PW_ERR_INVALID_ARG
+
+
+def test_tune_cache_file_read_without_device(tmp_path):
+    """The cache file is read on first use, with no device: v2 lines carry the
+    prefetch depth, v1 lines mean depth 1, malformed lines are ignored, and a
+    file entry overrides the built-in table."""
+    import os
+    import subprocess
+    import sys
+    cache = tmp_path / "tune.txt"
+    # classes: 512x512x64 forward (also in the built-in table), 100x100x10 adjoint and tangent
+    cache.write_text("pwadv-tune-v2 0 0 9 9 6 2 2 4 1 2\n"
+                     "pwadv-tune-v1 1 0 7 7 4 1 4 2 1\n"
+                     "garbage line\n"
+                     "pwadv-tune-v2 2 0 7 7 4 2 1 2 8 3\n")   # depth 3 is invalid: ignored
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = ("import sys, torch; sys.path.insert(0, %r)\n"
+            "from paper_2301_13016_amd import binding as B\n"
+            "print(B.launch_shape('forward', 512, 512, 64, torch.float32))\n"
+            "print(B.launch_shape('adjoint', 100, 100, 10, torch.float32))\n"
+            "print(B.launch_shape('tangent', 100, 100, 10, torch.float32))\n" % root)
+    r = subprocess.run([sys.executable, "-c", code], env=dict(os.environ, PWADV_TUNE_CACHE=str(cache)),
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr[-2000:]
+    fwd, adj, tan = r.stdout.strip().splitlines()
+    assert fwd == str((2, 2, 16, 1, 2))
+    assert adj == str((1, 4, 6, 1, 1))       # 12 padded levels in 2 chunks
+    assert tan != str((2, 1, 5, 8, 3))       # the invalid line did not take effect
+    assert cache.read_text().count("\n") == 4   # reading never rewrites the file
 
 
 def test_stream_copy_validation(lib):

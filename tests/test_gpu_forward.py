@@ -76,7 +76,9 @@ def test_integer_inputs_bitwise_all_dtypes(storage, shape):
 
 
 TILES = [(1, 1, 1, 1), (1, 1, 7, 4), (1, 2, 3, 8), (1, 4, 16, 4), (2, 4, 5, 2), (2, 1, 64, 4), (2, 2, 2, 1),
-         (4, 1, 64, 8), (4, 2, 5, 1), (4, 1, 1, 4), (4, 2, 16, 2)]
+         (4, 1, 64, 8), (4, 2, 5, 1), (4, 1, 1, 4), (4, 2, 16, 2),
+         # two planes prefetched: short chunks (1, 2, 3 levels) exercise the five-plane ring's clamping
+         (1, 1, 1, 1, 2), (1, 2, 2, 8, 2), (2, 4, 3, 1, 2), (4, 2, 7, 1, 2), (4, 1, 64, 4, 2), (2, 2, 5, 8, 2)]
 
 
 @pytest.mark.parametrize("shape", [(150, 37, 23), (300, 9, 7), (259, 5, 6), (513, 3, 4)],
@@ -90,7 +92,7 @@ def test_tile_shape_invariance_bitwise(shape):
             assert np.array_equal(a, b), t
 
 
-@pytest.mark.parametrize("tile", [(1, 2, 16, 4), (2, 4, 16, 4), (4, 2, 16, 1)])
+@pytest.mark.parametrize("tile", [(1, 2, 16, 4), (2, 4, 16, 4), (4, 2, 16, 1), (4, 2, 64, 1, 2), (2, 4, 3, 4, 2)])
 @pytest.mark.parametrize("shape", [(1, 1, 1), (3, 2, 2), (255, 4, 3), (257, 3, 2), (130, 70, 20)],
                          ids=lambda s: "x".join(map(str, s)))
 def test_f32_every_tile_kind_matches_oracle(shape, tile):
@@ -98,6 +100,21 @@ def test_f32_every_tile_kind_matches_oracle(shape, tile):
     g = wl.make_grid(nx, ny, nz, seed=400 + nx)
     errs = oracle_errors(run(g, tile=tile), g.u, g.v, g.w, g.coeffs)
     assert max(e for e, _ in errs) <= 1e-6, (tile, errs)
+
+
+@pytest.mark.parametrize("storage", ["bfloat16", "float16", "float64"])
+def test_prefetch_depth_invariance_other_dtypes(storage):
+    """The five-plane ring (two planes prefetched) gives bit-identical results
+    to the four-plane ring for 16-bit and FP64 storage too."""
+    dt = np.float64 if storage == "float64" else np.float32
+    g = wl.make_grid(300, 11, 9, seed=12, dtype=dt)
+    st = None if storage == "float64" else getattr(torch, storage)
+    px = 2 if storage == "float64" else 4
+    base = run(g, storage=st, tile=(1, 2, 4, 4))
+    for t in [(px, 2, 9, 1, 2), (px, 1, 2, 4, 2), (1, 1, 1, 8, 2)]:
+        got = run(g, storage=st, tile=t)
+        for a, b in zip(base, got):
+            assert np.array_equal(a, b), t
 
 
 def test_deterministic_across_runs():

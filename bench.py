@@ -15,7 +15,8 @@ Also measured in the same run ("forms"):
   * the adjoint (J^T r) and the tangent (J dx) vs the forward on 256 x 256 x 128 FP32;
   * 64 uneven subdomains (FP32) in one persistent launch replayed from a HIP
     graph vs 64 plain launches;
-  * a plain copy kernel (reachable-bandwidth reference);
+  * a plain copy kernel and a three-stream copy (the stencil's pattern of three
+    arrays read and three written): reachable-bandwidth references;
   * the FP64 oracle on the host cores ("cpu_baseline", the only use of the
     oracle here).
 Their errors against the oracle are measured by the GPU test suite.
@@ -233,7 +234,16 @@ def main():
     _, copy_ms = time_launches(torch, lambda i: B.stream_copy(srcs[i], dsts[i]), 4, 200, 10, stream)
     copy_gbs = 2 * cbytes / (copy_ms * 1e-3) / 1e9
     log("copy %d MB each way: %.4f ms, %.0f GB/s" % (cbytes >> 20, copy_ms, copy_gbs))
-    del keep, calls, srcs, dsts
+    del srcs, dsts
+    # three-stream copy: the stencil's pattern (three arrays read, three
+    # written), each the size of one output array
+    obytes = nx * ny * nz * 4
+    sets3 = [([torch.empty(obytes // 4, device=dev) for _ in range(3)],
+              [torch.empty(obytes // 4, device=dev) for _ in range(3)]) for _ in range(4)]
+    _, c3_ms = time_launches(torch, lambda i: B.stream_copy3(*sets3[i]), 4, 200, 10, stream)
+    copy3_gbs = 6 * obytes / (c3_ms * 1e-3) / 1e9
+    log("three-stream copy 3 x %d MB each way: %.4f ms, %.0f GB/s" % (obytes >> 20, c3_ms, copy3_gbs))
+    del keep, calls, sets3
     torch.cuda.empty_cache()
 
     # ------------------------------------------------------------ CPU baseline (oracle)
@@ -378,7 +388,7 @@ def main():
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic("pw_forward_f32_512x512x64"),
                      "algorithmic_bytes_per_launch": nbytes, "kernel_ms": round(k_ms, 6),
-                     "copy_kernel_gbs": round(copy_gbs, 1)},
+                     "copy_kernel_gbs": round(copy_gbs, 1), "copy3_kernel_gbs": round(copy3_gbs, 1)},
         "cpu_baseline": {"value": round(cpu_gpts, 4), "unit": "Gpoints/s", "cores": ncpu, "kind": "oracle",
                          "sample": "FP64 oracle on the full 512x512x64 grid, %d repetitions (%.1f s)"
                                    % (reps, t_cpu)},

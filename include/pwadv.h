@@ -296,6 +296,13 @@ const char *pw_last_error(void);
  * reachable HBM bandwidth and the memory counters. */
 pw_status pw_stream_copy(const void *src, void *dst, int64_t nbytes, void *hip_stream);
 
+/* Measurement helper: three such copies (src[i] -> dst[i], i = 0..2, each of
+ * `nbytes`) in one kernel -- the stencil's traffic pattern of three arrays
+ * read and three written, without the stencil.  Its bandwidth is the
+ * reachable rate for that pattern.  Same argument rules as pw_stream_copy;
+ * no two of the six ranges may overlap. */
+pw_status pw_stream_copy3(const void *const src[3], void *const dst[3], int64_t nbytes, void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -90,6 +90,7 @@ _SIGNATURES = {
                              _P, _P, _P, ctypes.POINTER(pw_coeffs), _P, _P, _P, _P, _P, _P,
                              ctypes.POINTER(pw_tile), _P],
     "pw_stream_copy": [_P, _P, ctypes.c_int64, _P],
+    "pw_stream_copy3": [ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.c_int64, _P],
     "pw_tune": [ctypes.POINTER(pw_grid), ctypes.c_int, ctypes.c_int32, ctypes.POINTER(pw_tile),
                 ctypes.POINTER(pw_tile)],
     "pw_tune_reset": [],
@@ -426,6 +427,22 @@ def stream_copy(src, dst, stream=None):
     _check(pw_stream_copy(src.data_ptr(), dst.data_ptr(), src.numel() * src.element_size(),
                           _stream_handle(stream)), "pw_stream_copy")
     return dst
+
+
+def pw_stream_copy3(srcs, dsts, nbytes, stream=None):
+    s = (_P * 3)(*srcs)
+    d = (_P * 3)(*dsts)
+    return lib().pw_stream_copy3(s, d, int(nbytes), stream)
+
+
+def stream_copy3(srcs, dsts, stream=None):
+    """dsts[i] <- srcs[i] for three equal-sized tensors, in one kernel."""
+    n = srcs[0].numel() * srcs[0].element_size()
+    if any(t.numel() * t.element_size() != n for t in list(srcs) + list(dsts)):
+        raise ValueError("all six tensors must have the same size in bytes")
+    _check(pw_stream_copy3([t.data_ptr() for t in srcs], [t.data_ptr() for t in dsts], n, _stream_handle(stream)),
+           "pw_stream_copy3")
+    return dsts
 
 
 def _autograd_function():

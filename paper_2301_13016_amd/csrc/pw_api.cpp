@@ -377,4 +377,25 @@ pw_status pw_stream_copy(const void *src, void *dst, int64_t nbytes, void *hip_s
     return launch_copy(src, dst, nbytes, static_cast<hipStream_t>(hip_stream));
 }
 
+pw_status pw_stream_copy3(const void *const src[3], void *const dst[3], int64_t nbytes, void *hip_stream) {
+    g_err[0] = 0;
+    if (!src || !dst) return fail(PW_ERR_INVALID_ARG, "NULL pointer array");
+    if (nbytes <= 0 || nbytes % 16) return fail(PW_ERR_INVALID_ARG, "nbytes must be a positive multiple of 16");
+    const void *p[6] = {src[0], src[1], src[2], dst[0], dst[1], dst[2]};
+    const char *names[6] = {"src[0]", "src[1]", "src[2]", "dst[0]", "dst[1]", "dst[2]"};
+    Range r[6];
+    for (int i = 0; i < 6; ++i) {
+        if (!p[i]) return fail(PW_ERR_INVALID_ARG, "%s is NULL", names[i]);
+        if (reinterpret_cast<uintptr_t>(p[i]) % 16) return fail(PW_ERR_INVALID_ARG, "%s is not 16-byte aligned", names[i]);
+        r[i] = Range{names[i], reinterpret_cast<uintptr_t>(p[i]), reinterpret_cast<uintptr_t>(p[i]) + uintptr_t(nbytes)};
+    }
+    for (int i = 0; i < 6; ++i)
+        for (int j = i + 1; j < 6; ++j)
+            if (overlap(r[i], r[j])) return fail(PW_ERR_INVALID_ARG, "%s and %s overlap", names[i], names[j]);
+    int dev = 0;
+    PW_TRY(current_device(&dev));
+    for (int i = 0; i < 6; ++i) PW_TRY(check_on_device(names[i], p[i], dev));
+    return launch_copy3(src, dst, nbytes, static_cast<hipStream_t>(hip_stream));
+}
+
 }  // extern "C"

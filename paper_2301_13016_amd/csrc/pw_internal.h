@@ -72,6 +72,7 @@ pw_status launch_forward(const FwdArgs &a, pw_dtype dt, const TileCfg &cfg, hipS
 pw_status launch_adjoint(const AdjArgs &a, pw_dtype dt, const TileCfg &cfg, hipStream_t s);
 pw_status launch_tangent(const TanArgs &a, pw_dtype dt, const TileCfg &cfg, hipStream_t s);
 pw_status launch_copy(const void *src, void *dst, int64_t nbytes, hipStream_t s);
+pw_status launch_copy3(const void *const *src, void *const *dst, int64_t nbytes, hipStream_t s);
 
 // Host-side validation shared by pw_advect and the batched form (pw_api.cpp).
 // validate_forward checks everything that needs no HIP call and fills the

@@ -315,6 +315,20 @@ def test_stream_copy_validation(lib):
     assert B.pw_stream_copy(A, A + MB, 64) in _no_gpu_status()
 
 
+def test_stream_copy3_validation(lib):
+    s = [A + i * MB for i in range(3)]
+    d = [A + (3 + i) * MB for i in range(3)]
+    assert B.pw_stream_copy3(s, d, 64) in _no_gpu_status()
+    assert B.pw_stream_copy3(s, d, 0) == B.PW_ERR_INVALID_ARG
+    assert B.pw_stream_copy3(s, d, 24) == B.PW_ERR_INVALID_ARG
+    assert B.pw_stream_copy3([s[0], 0, s[2]], d, 64) == B.PW_ERR_INVALID_ARG
+    assert B.pw_stream_copy3(s, [d[0], d[1], d[2] + 8], 64) == B.PW_ERR_INVALID_ARG     # misaligned
+    assert B.pw_stream_copy3(s, [d[0], s[1] + 32, d[2]], 64) == B.PW_ERR_INVALID_ARG   # dst on a src
+    assert "overlap" in B.pw_last_error()
+    assert B.pw_stream_copy3(s, [d[0], d[0] + 16, d[2]], 64) == B.PW_ERR_INVALID_ARG   # two dsts overlap
+    assert lib.pw_stream_copy3(None, None, 64, None) == B.PW_ERR_INVALID_ARG
+
+
 def test_last_error_is_per_thread(lib):
     import threading
     g, c, p = _args()

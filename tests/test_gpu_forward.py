@@ -222,3 +222,18 @@ def test_host_pointer_rejected():
     with pytest.raises(B.PWError) as ei:
         B.advect(u, v, w, c, out=host_out)
     assert ei.value.status == B.PW_ERR_INVALID_ARG
+
+
+def test_stream_copies_are_exact():
+    """The calibration kernels copy bit for bit (one and three streams, sizes
+    that end mid-grid-stride)."""
+    n = 1_000_004   # floats: a multiple of 4, not of the launch's stride
+    src = [torch.randn(n, device="cuda") for _ in range(3)]
+    dst = [torch.empty_like(x) for x in src]
+    B.stream_copy3(src, dst)
+    one = torch.empty_like(src[0])
+    B.stream_copy(src[1], one)
+    torch.cuda.synchronize()
+    for a, b in zip(src, dst):
+        assert torch.equal(a, b)
+    assert torch.equal(one, src[1])

@@ -5,8 +5,9 @@ of the benchmark use this package to check the GPU library.  The library never
 imports it, and it imports nothing from the library.
 
 * ``pw_oracle.c`` -- plain FP64 loops of the forward operator, its adjoint
-  (scatter form of J^T r) and its tangent-linear operator (J dx); built with
-  gcc into ``liboracle.so`` and called through ctypes.
+  (scatter form of J^T r), its tangent-linear operator (J dx) and the
+  gradients with respect to the coefficients; built with gcc into
+  ``liboracle.so`` and called through ctypes.
 * ``bruteforce.py`` -- an independent, table-driven evaluation of the same
   operator in exact rational arithmetic, for tiny grids.
 
@@ -52,6 +53,8 @@ def _load():
         lib.pwo_adjoint.restype = None
         lib.pwo_tangent.argtypes = [i64] * 4 + [p] * 3 + [p] * 3 + [dbl, dbl] + [p] * 4 + [p] * 3
         lib.pwo_tangent.restype = None
+        lib.pwo_coeff_grad.argtypes = [i64] * 4 + [p] * 3 + [p] * 3 + [p] * 8
+        lib.pwo_coeff_grad.restype = None
         _lib = lib
     return _lib
 
@@ -133,3 +136,25 @@ def tangent(u, v, w, du, dv, dw, coeffs, halo=1):
                     *[_ptr(x) for x in d], tcx, tcy, *[_ptr(t) for t in tz],
                     *[_ptr(o) for o in out])
     return tuple(out)
+
+
+def coeff_grad(u, v, w, ru, rv, rw, halo=1):
+    """Gradients of <F(u, v, w), r> with respect to the coefficients (the
+    loss is linear in them, so the coefficients' values do not enter):
+    a dict with tcx, tcy (floats), tzc1, tzc2, tzd1, tzd2 (length nz) and
+    tcx_level, tcy_level (each level's share of tcx, tcy)."""
+    lib = _load()
+    u, v, w = _f64(u), _f64(v), _f64(w)
+    nx, ny, nz = _dims(u, halo)
+    r = [_f64(x) for x in (ru, rv, rw)]
+    for x in r:
+        if x.shape != (nz, ny, nx):
+            raise ValueError("cotangents must be interior-shaped")
+    arrs = [np.empty(nz) for _ in range(6)]
+    sx, sy = np.empty(1), np.empty(1)
+    lib.pwo_coeff_grad(nx, ny, nz, halo, _ptr(u), _ptr(v), _ptr(w), *[_ptr(x) for x in r],
+                       *[_ptr(a) for a in arrs], _ptr(sx), _ptr(sy))
+    names = ("tzc1", "tzc2", "tzd1", "tzd2", "tcx_level", "tcy_level")
+    out = dict(zip(names, arrs))
+    out["tcx"], out["tcy"] = float(sx[0]), float(sy[0])
+    return out

@@ -260,3 +260,58 @@ void pwo_tangent(int64_t nx, int64_t ny, int64_t nz, int64_t h,
         }
     }
 }
+
+/* Gradients of L = <su, ru> + <sv, rv> + <sw, rw> with respect to the
+ * coefficients.  Every term of the operator is one coefficient times a
+ * coefficient-free product, so dL/dc is the sum, over the terms that c
+ * multiplies, of the cotangent at the term's output times that product:
+ *   gtcx        = sum over all points of the x-face products (u, v, w rows)
+ *   gtcy        = the same for the y-face products
+ *   gtzc1[k]    = sum over level k of ru*u(k-1)*(w+w at k-1) + rv*v(k-1)*(...)
+ *   gtzc2[k]    = minus the same for the upper faces
+ *   gtzd1/2[k]  = the w field's lower / upper face products times rw.
+ * gtcx_lev[k] and gtcy_lev[k] receive level k's share of gtcx and gtcy. */
+void pwo_coeff_grad(int64_t nx, int64_t ny, int64_t nz, int64_t h,
+                    const double *u, const double *v, const double *w,
+                    const double *ru, const double *rv, const double *rw,
+                    double *gtzc1, double *gtzc2, double *gtzd1, double *gtzd2,
+                    double *gtcx_lev, double *gtcy_lev, double *gtcx, double *gtcy)
+{
+    const int64_t px = nx + 2 * h, py = ny + 2 * h;
+    double sx = 0.0, sy = 0.0;
+    for (int64_t k = h; k < h + nz; ++k) {
+        const int64_t kk = k - h;
+        double c1 = 0.0, c2 = 0.0, d1 = 0.0, d2 = 0.0, lx = 0.0, ly = 0.0;
+        for (int64_t j = h; j < h + ny; ++j) {
+            for (int64_t i = h; i < h + nx; ++i) {
+                const int64_t o = (kk * ny + (j - h)) * nx + (i - h);
+                const double a = ru[o], b = rv[o], c = rw[o];
+                /* su */
+                lx += a * (U(k, j, i - 1) * (U(k, j, i) + U(k, j, i - 1)) - U(k, j, i + 1) * (U(k, j, i) + U(k, j, i + 1)));
+                ly += a * (U(k, j - 1, i) * (V(k, j - 1, i) + V(k, j - 1, i + 1)) - U(k, j + 1, i) * (V(k, j, i) + V(k, j, i + 1)));
+                c1 += a * (U(k - 1, j, i) * (W(k - 1, j, i) + W(k - 1, j, i + 1)));
+                c2 -= a * (U(k + 1, j, i) * (W(k, j, i) + W(k, j, i + 1)));
+                /* sv */
+                lx += b * (V(k, j, i - 1) * (U(k, j, i - 1) + U(k, j + 1, i - 1)) - V(k, j, i + 1) * (U(k, j, i) + U(k, j + 1, i)));
+                ly += b * (V(k, j - 1, i) * (V(k, j, i) + V(k, j - 1, i)) - V(k, j + 1, i) * (V(k, j, i) + V(k, j + 1, i)));
+                c1 += b * (V(k - 1, j, i) * (W(k - 1, j, i) + W(k - 1, j + 1, i)));
+                c2 -= b * (V(k + 1, j, i) * (W(k, j, i) + W(k, j + 1, i)));
+                /* sw */
+                lx += c * (W(k, j, i - 1) * (U(k, j, i - 1) + U(k + 1, j, i - 1)) - W(k, j, i + 1) * (U(k, j, i) + U(k + 1, j, i)));
+                ly += c * (W(k, j - 1, i) * (V(k, j - 1, i) + V(k + 1, j - 1, i)) - W(k, j + 1, i) * (V(k, j, i) + V(k + 1, j, i)));
+                d1 += c * (W(k - 1, j, i) * (W(k, j, i) + W(k - 1, j, i)));
+                d2 -= c * (W(k + 1, j, i) * (W(k, j, i) + W(k + 1, j, i)));
+            }
+        }
+        gtzc1[kk] = c1;
+        gtzc2[kk] = c2;
+        gtzd1[kk] = d1;
+        gtzd2[kk] = d2;
+        gtcx_lev[kk] = lx;
+        gtcy_lev[kk] = ly;
+        sx += lx;
+        sy += ly;
+    }
+    *gtcx = sx;
+    *gtcy = sy;
+}

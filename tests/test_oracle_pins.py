@@ -224,3 +224,65 @@ def test_adjoint_gradient_halo_is_written():
         for k, j, i in itertools.product((0, -1), (0, -1), (0, -1)):
             assert gr[k, j, i] == 0.0
         assert np.any(gr[0] != 0) or np.any(gr[-1] != 0)
+
+
+# ---------------------------------------------------------------- coefficient gradients
+
+def _unit_coeffs(nz, name, k=None):
+    c = dict(tcx=0.0, tcy=0.0, tzc1=np.zeros(nz), tzc2=np.zeros(nz), tzd1=np.zeros(nz), tzd2=np.zeros(nz))
+    if name in ("tcx", "tcy"):
+        c[name] = 1.0
+    else:
+        c[name][k] = 1.0
+    return c
+
+
+def test_coeff_grad_is_forward_with_unit_coefficients():
+    """The loss is linear in every coefficient, so dL/dc = <F(x; c = 1, all
+    others 0), r> -- the forward oracle with a unit coefficient, an
+    evaluation path independent of the gradient loops."""
+    g = wl.make_grid(7, 5, 4, seed=26, dtype=np.float64)
+    r = wl.cotangents(7, 5, 4, seed=27, dtype=np.float64)
+    x = (g.u, g.v, g.w)
+    got = oracle.coeff_grad(*x, *r)
+    for name in ("tcx", "tcy"):
+        ref = _dot(oracle.forward(*x, _unit_coeffs(4, name)), r)
+        assert abs(got[name] - ref) <= 1e-13 * max(1.0, abs(ref)), name
+    for name in ("tzc1", "tzc2", "tzd1", "tzd2"):
+        for k in range(4):
+            ref = _dot(oracle.forward(*x, _unit_coeffs(4, name, k)), r)
+            assert abs(got[name][k] - ref) <= 1e-13 * max(1.0, abs(ref)), (name, k)
+    assert abs(sum(got["tcx_level"]) - got["tcx"]) <= 1e-13 * abs(got["tcx"])
+    assert abs(sum(got["tcy_level"]) - got["tcy"]) <= 1e-13 * abs(got["tcy"])
+
+
+def test_coeff_grad_exact_on_integers():
+    """Bit for bit against the exact rational forward operator with unit
+    coefficients, on integer winds and cotangents (every FP64 step exact)."""
+    g = wl.integer_grid(3, 3, 2, seed=28, dtype=np.float64)
+    rng = np.random.default_rng(29)
+    r = [rng.integers(-3, 4, (2, 3, 3)).astype(np.float64) for _ in range(3)]
+    x = dict(u=g.u, v=g.v, w=g.w)
+    got = oracle.coeff_grad(g.u, g.v, g.w, *r)
+
+    def exact(c):
+        f = bf.forward_exact(x, c)
+        return sum(float(sum(f[o][k][j][i] * int(r[n][k, j, i]) for k in range(2) for j in range(3) for i in range(3)))
+                   for n, o in enumerate(bf.OUTPUTS))
+    assert got["tcx"] == exact(_unit_coeffs(2, "tcx"))
+    assert got["tcy"] == exact(_unit_coeffs(2, "tcy"))
+    for name in ("tzc1", "tzc2", "tzd1", "tzd2"):
+        for k in range(2):
+            assert got[name][k] == exact(_unit_coeffs(2, name, k)), (name, k)
+
+
+def test_coeff_grad_euler_identity():
+    """Summing c * dL/dc over all coefficients gives L itself (L is linear and
+    homogeneous of degree one in the coefficients)."""
+    g = wl.make_grid(9, 6, 5, seed=30, dtype=np.float64)
+    r = wl.cotangents(9, 6, 5, seed=31, dtype=np.float64)
+    got = oracle.coeff_grad(g.u, g.v, g.w, *r)
+    total = g.tcx * got["tcx"] + g.tcy * got["tcy"] + sum(float(np.dot(getattr(g, n), got[n]))
+                                                         for n in ("tzc1", "tzc2", "tzd1", "tzd2"))
+    loss = _dot(oracle.forward(g.u, g.v, g.w, g.coeffs), r)
+    assert abs(total - loss) <= 1e-12 * abs(loss)

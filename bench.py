@@ -12,7 +12,8 @@ batched form is tuned in the run.
 
 Also measured in the same run ("forms"):
   * BF16 / FP16 storage vs FP32 on 1024 x 1024 x 256 (268 M points);
-  * the adjoint (J^T r) and the tangent (J dx) vs the forward on 256 x 256 x 128 FP32;
+  * the adjoint (J^T r), the tangent (J dx) and the coefficient gradients vs the
+    forward on 256 x 256 x 128 FP32;
   * 64 uneven subdomains (FP32) in one persistent launch replayed from a HIP
     graph vs 64 plain launches;
   * a plain copy kernel and a three-stream copy (the stencil's pattern of three
@@ -159,6 +160,30 @@ def prebuilt_tangent(B, ins, dirs, outs, coeffs, stream):
     return call
 
 
+def prebuilt_coeff_grad(B, ins, cots, stream, torch):
+    """ctypes arguments of one pw_advect_coeff_grad call (output and
+    workspace allocated here, once)."""
+    from paper_2301_13016_amd.binding import _dtype_code, _grid_from, _layout_from
+    u, v, w = ins
+    grid = _grid_from(u, 1)
+    need = ctypes.c_int64()
+    B.lib().pw_advect_coeff_grad_workspace(ctypes.byref(grid), _dtype_code(u), ctypes.byref(need))
+    out = torch.empty(6 * int(grid.nz) + 2, dtype=torch.float64, device=u.device)
+    ws = torch.empty(max(1, need.value // 8), dtype=torch.float64, device=u.device)
+    keep = (grid, _layout_from(u, cots[0]), out, ws)
+    args = (ctypes.byref(keep[0]), ctypes.byref(keep[1]), _dtype_code(u), u.data_ptr(), v.data_ptr(), w.data_ptr(),
+            *(x.data_ptr() for x in cots), out.data_ptr(), ws.data_ptr(), need.value,
+            ctypes.c_void_p(stream.cuda_stream))
+    fn = B.lib().pw_advect_coeff_grad
+
+    def call():
+        st = fn(*args)
+        if st != B.PW_OK:
+            raise B.PWError(st, B.pw_last_error(), "pw_advect_coeff_grad")
+    call.keep = keep
+    return call
+
+
 def prebuilt_adjoint(B, ins, cots, grads, coeffs, stream):
     """ctypes arguments of one pw_advect_adjoint_ex call, built once."""
     from paper_2301_13016_amd.binding import _dtype_code, _grid_from, _layout_from
@@ -296,7 +321,7 @@ def main():
     host4 = [torch.from_numpy(x) for x in (g4.u, g4.v, g4.w)]
     hcot4 = [torch.from_numpy(x) for x in wl.cotangents(*n4, c4["cot_seed"])]
     hdir4 = [torch.from_numpy(x.astype(np.float32)) for x in wl.direction(*n4, seed=46)]
-    fcalls, acalls, tcalls, keep4 = [], [], [], []
+    fcalls, acalls, tcalls, ccalls, keep4 = [], [], [], [], []
     for _ in range(4):
         ins4 = [x.to(dev) for x in host4]
         cot4 = [x.to(dev) for x in hcot4]
@@ -308,9 +333,11 @@ def main():
         fcalls.append(prebuilt_forward(B, ins4, o4, co4, stream))
         acalls.append(prebuilt_adjoint(B, ins4, cot4, gr4, co4, stream))
         tcalls.append(prebuilt_tangent(B, ins4, dir4, t4, co4, stream))
+        ccalls.append(prebuilt_coeff_grad(B, ins4, cot4, stream, torch))
     _, fms = time_launches(torch, lambda i: fcalls[i](), 4, 100, 5, stream)
     _, ams = time_launches(torch, lambda i: acalls[i](), 4, 100, 5, stream)
     _, tms = time_launches(torch, lambda i: tcalls[i](), 4, 100, 5, stream)
+    _, cms = time_launches(torch, lambda i: ccalls[i](), 4, 100, 5, stream)
     pts4 = n4[0] * n4[1] * n4[2]
     forms["adjoint_256x256x128"] = dict(
         forward_ms=round(fms, 4), adjoint_ms=round(ams, 4), adjoint_over_forward=round(ams / fms, 3),
@@ -322,9 +349,14 @@ def main():
         tangent_ms=round(tms, 4), tangent_over_forward=round(tms / fms, 3),
         ideal_ratio_from_bytes=round(tbytes / algo_bytes(*n4, 1, 4), 3),
         tangent_gpts=round(pts4 / (tms * 1e-3) / 1e9, 2), tangent_hbm_gbs=round(tbytes / (tms * 1e-3) / 1e9, 1))
-    log("c4: forward %.4f ms, adjoint %.4f ms (ratio %.3f), tangent %.4f ms (ratio %.3f)"
-        % (fms, ams, ams / fms, tms, tms / fms))
-    del keep4, fcalls, acalls, tcalls
+    cbytes4 = adjoint_bytes(*n4, 1) - 3 * (n4[0] + 2) * (n4[1] + 2) * (n4[2] + 2) * 4   # its reads only
+    forms["coeff_grad_256x256x128"] = dict(
+        coeff_grad_ms=round(cms, 4), coeff_grad_over_forward=round(cms / fms, 3),
+        ideal_ratio_from_bytes=round(cbytes4 / algo_bytes(*n4, 1, 4), 3),
+        coeff_grad_hbm_gbs=round(cbytes4 / (cms * 1e-3) / 1e9, 1))
+    log("c4: forward %.4f ms, adjoint %.4f ms (ratio %.3f), tangent %.4f ms (ratio %.3f), "
+        "coefficient gradients %.4f ms (ratio %.3f)" % (fms, ams, ams / fms, tms, tms / fms, cms, cms / fms))
+    del keep4, fcalls, acalls, tcalls, ccalls
     torch.cuda.empty_cache()
 
     # ------------------------------------------------------------ batched form: c3

@@ -196,6 +196,26 @@ pw_status pw_advect_tangent_ex(const pw_grid *grid, const pw_layout *layout, pw_
                                void *tu, void *tv, void *tw,
                                const pw_tile *tile, void *hip_stream);
 
+/* Gradients of L = <su, gsu> + <sv, gsv> + <sw, gsw> with respect to the
+ * coefficients.  L is linear in each coefficient (every term of the equations
+ * above is one coefficient times a coefficient-free product), so the
+ * gradients do not depend on the coefficients' values and need none.
+ * `grad` (device, 6*nz + 2 doubles) receives, in this order:
+ *   dL/dtzc1[0..nz), dL/dtzc2[0..nz), dL/dtzd1[0..nz), dL/dtzd2[0..nz),
+ *   each level's share of dL/dtcx [0..nz) and of dL/dtcy [0..nz),
+ *   dL/dtcx, dL/dtcy.
+ * Sums are accumulated in FP64 in a fixed order (the same result on every
+ * run).  u, v, w padded (input layout), gsu/gsv/gsw interior (output
+ * layout); dtype PW_F32 or PW_F64.  `workspace` is device memory of at least
+ * pw_advect_coeff_grad_workspace() bytes, owned by the caller; it and grad
+ * must be 8-byte aligned and overlap nothing else.  No allocation. */
+pw_status pw_advect_coeff_grad_workspace(const pw_grid *grid, pw_dtype dtype, int64_t *bytes);
+pw_status pw_advect_coeff_grad(const pw_grid *grid, const pw_layout *layout, pw_dtype dtype,
+                               const void *u, const void *v, const void *w,
+                               const void *gsu, const void *gsv, const void *gsw,
+                               double *grad, void *workspace, int64_t workspace_bytes,
+                               void *hip_stream);
+
 /* Autotuner for single-grid launches.  Times candidate launch shapes of the
  * forward kernel (flags & PW_TUNE_FORWARD) and, for PW_F32 / PW_F64, of the
  * adjoint (flags & PW_TUNE_ADJOINT) and tangent (flags & PW_TUNE_TANGENT)

@@ -89,6 +89,9 @@ _SIGNATURES = {
     "pw_advect_tangent_ex": [ctypes.POINTER(pw_grid), ctypes.POINTER(pw_layout), ctypes.c_int,
                              _P, _P, _P, ctypes.POINTER(pw_coeffs), _P, _P, _P, _P, _P, _P,
                              ctypes.POINTER(pw_tile), _P],
+    "pw_advect_coeff_grad_workspace": [ctypes.POINTER(pw_grid), ctypes.c_int, ctypes.POINTER(ctypes.c_int64)],
+    "pw_advect_coeff_grad": [ctypes.POINTER(pw_grid), ctypes.POINTER(pw_layout), ctypes.c_int,
+                             _P, _P, _P, _P, _P, _P, _P, _P, ctypes.c_int64, _P],
     "pw_stream_copy": [_P, _P, ctypes.c_int64, _P],
     "pw_stream_copy3": [ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.c_int64, _P],
     "pw_tune": [ctypes.POINTER(pw_grid), ctypes.c_int, ctypes.c_int32, ctypes.POINTER(pw_tile),
@@ -347,6 +350,33 @@ def advect_tangent(u, v, w, coeffs: Coeffs, du, dv, dw, halo=1, out=None, tile=N
     return tu, tv, tw
 
 
+def advect_coeff_grad(u, v, w, gsu, gsv, gsw, halo=1, stream=None):
+    """Gradients of <su, gsu> + <sv, gsv> + <sw, gsw> with respect to the
+    coefficients (their values do not enter: the loss is linear in them).
+    Returns a dict of float64 device tensors: tcx, tcy (0-d), tzc1, tzc2,
+    tzd1, tzd2 (length nz), tcx_level, tcy_level (each level's share)."""
+    import torch
+    grid = _grid_from(u, halo)
+    gs = [g.contiguous() if g.stride(-1) != 1 else g for g in (gsu, gsv, gsw)]
+    if not (gs[0].stride() == gs[1].stride() == gs[2].stride()):
+        gs = [g.contiguous() for g in gs]
+    layout = _layout_from(u, gs[0])
+    need = ctypes.c_int64()
+    _check(lib().pw_advect_coeff_grad_workspace(ctypes.byref(grid), _dtype_code(u), ctypes.byref(need)),
+           "pw_advect_coeff_grad_workspace")
+    nz = int(grid.nz)
+    out = torch.empty(6 * nz + 2, dtype=torch.float64, device=u.device)
+    ws = torch.empty(max(1, need.value // 8), dtype=torch.float64, device=u.device)
+    st = lib().pw_advect_coeff_grad(ctypes.byref(grid), ctypes.byref(layout), _dtype_code(u), u.data_ptr(),
+                                    v.data_ptr(), w.data_ptr(), *(g.data_ptr() for g in gs), out.data_ptr(),
+                                    ws.data_ptr(), need.value, _stream_handle(stream))
+    _check(st, "pw_advect_coeff_grad")
+    names = ("tzc1", "tzc2", "tzd1", "tzd2", "tcx_level", "tcy_level")
+    res = {n: out[i * nz:(i + 1) * nz] for i, n in enumerate(names)}
+    res["tcx"], res["tcy"] = out[6 * nz], out[6 * nz + 1]
+    return res
+
+
 def tune(nx, ny, nz, dtype, halo=1, flags=0):
     """Run the autotuner for this grid class; returns (forward tile, adjoint
     tile) as (cols_per_lane, rows_per_strip, zlen, waves_per_group, prefetch) tuples
@@ -478,6 +508,53 @@ def _autograd_function():
 
 
 _PWAdvect = None
+_PWAdvectCoeffs = None
+
+
+def _autograd_function_coeffs():
+    import torch
+
+    class PWAdvectCoeffs(torch.autograd.Function):
+        """PW advection differentiable in the winds and in the coefficients:
+        apply(u, v, w, tcx, tcy, tzc1, tzc2, tzd1, tzd2, halo=1) with tcx, tcy
+        0-d tensors and tz* device tensors of length nz.  Backward runs the
+        adjoint kernel for the winds and the coefficient-gradient kernel for
+        the coefficients (each only when needed)."""
+
+        @staticmethod
+        def forward(ctx, u, v, w, tcx, tcy, tzc1, tzc2, tzd1, tzd2, halo=1):
+            c = Coeffs(float(tcx), float(tcy), tzc1, tzc2, tzd1, tzd2)
+            ctx.save_for_backward(u, v, w)
+            ctx.coeffs, ctx.halo = c, halo
+            ctx.cdtypes = [(t.dtype, t.device) for t in (tcx, tcy)]
+            return advect(u, v, w, c, halo)
+
+        @staticmethod
+        def backward(ctx, gsu, gsv, gsw):
+            u, v, w = ctx.saved_tensors
+            need = ctx.needs_input_grad
+            gu = gv = gw = None
+            if any(need[:3]):
+                gu, gv, gw = advect_adjoint(u, v, w, ctx.coeffs, gsu, gsv, gsw, ctx.halo)
+            cg = [None] * 6
+            if any(need[3:9]):
+                g = advect_coeff_grad(u, v, w, gsu, gsv, gsw, ctx.halo)
+                c = ctx.coeffs
+                (d0, v0), (d1, v1) = ctx.cdtypes
+                cg = [g["tcx"].to(device=v0, dtype=d0), g["tcy"].to(device=v1, dtype=d1)] + \
+                     [g[n].to(getattr(c, n).dtype) for n in ("tzc1", "tzc2", "tzd1", "tzd2")]
+            return (gu, gv, gw, *cg, None)
+
+    return PWAdvectCoeffs
+
+
+def PWAdvectCoeffs():
+    """The autograd Function differentiable in the coefficients too (created
+    on first use)."""
+    global _PWAdvectCoeffs
+    if _PWAdvectCoeffs is None:
+        _PWAdvectCoeffs = _autograd_function_coeffs()
+    return _PWAdvectCoeffs
 
 
 def PWAdvect():

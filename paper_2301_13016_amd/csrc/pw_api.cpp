@@ -301,6 +301,55 @@ pw_status pw_advect_tangent_ex(const pw_grid *grid, const pw_layout *layout, pw_
     return launch_tangent(a, dtype, cfg, static_cast<hipStream_t>(hip_stream));
 }
 
+pw_status pw_advect_coeff_grad_workspace(const pw_grid *grid, pw_dtype dtype, int64_t *bytes) {
+    g_err[0] = 0;
+    if (!bytes) return fail(PW_ERR_INVALID_ARG, "bytes is NULL");
+    PW_TRY(check_grid(grid));
+    if (dtype != PW_F32 && dtype != PW_F64) {
+        if (elem_size(dtype)) return fail(PW_ERR_UNSUPPORTED, "coefficient gradients support PW_F32 and PW_F64 only");
+        return fail(PW_ERR_INVALID_ARG, "unknown dtype %d", (int)dtype);
+    }
+    *bytes = coeff_grad_workspace_bytes(*grid, dtype);
+    return PW_OK;
+}
+
+pw_status pw_advect_coeff_grad(const pw_grid *grid, const pw_layout *layout, pw_dtype dtype,
+                               const void *u, const void *v, const void *w,
+                               const void *gsu, const void *gsv, const void *gsw,
+                               double *grad, void *workspace, int64_t workspace_bytes, void *hip_stream) {
+    int64_t need = 0;
+    PW_TRY(pw_advect_coeff_grad_workspace(grid, dtype, &need));
+    const int64_t es = elem_size(dtype);
+    Layout L;
+    PW_TRY(resolve_layout(grid, layout, es, es, &L));
+    const char *names[] = {"u", "v", "w", "gsu", "gsv", "gsw", "grad", "workspace"};
+    const void *ptrs[] = {u, v, w, gsu, gsv, gsw, grad, workspace};
+    for (int i = 0; i < 6; ++i) PW_TRY(check_aligned(names[i], ptrs[i], es));
+    for (int i = 6; i < 8; ++i) PW_TRY(check_aligned(names[i], ptrs[i], 8));
+    if (workspace_bytes < need)
+        return fail(PW_ERR_INVALID_ARG, "workspace of %lld bytes is smaller than the %lld needed",
+                    (long long)workspace_bytes, (long long)need);
+    const Range rin[6] = {in_range("u", u, grid, L, es), in_range("v", v, grid, L, es), in_range("w", w, grid, L, es),
+                          out_range("gsu", gsu, grid, L, es), out_range("gsv", gsv, grid, L, es),
+                          out_range("gsw", gsw, grid, L, es)};
+    const uintptr_t gb = reinterpret_cast<uintptr_t>(grad), wb = reinterpret_cast<uintptr_t>(workspace);
+    const Range rout[2] = {{"grad", gb, gb + uintptr_t((6 * grid->nz + 2) * 8)}, {"workspace", wb, wb + uintptr_t(need)}};
+    for (const Range &o : rout)
+        for (const Range &i : rin)
+            if (overlap(o, i)) return fail(PW_ERR_INVALID_ARG, "%s overlaps %s", o.name, i.name);
+    if (overlap(rout[0], rout[1])) return fail(PW_ERR_INVALID_ARG, "grad overlaps workspace");
+    int dev = 0;
+    PW_TRY(current_device(&dev));
+    for (int i = 0; i < 8; ++i) PW_TRY(check_on_device(names[i], ptrs[i], dev));
+    CgArgs a;
+    a.u = u; a.v = v; a.w = w;
+    a.gsu = gsu; a.gsv = gsv; a.gsw = gsw;
+    a.grad = grad; a.workspace = workspace;
+    a.nx = grid->nx; a.ny = grid->ny; a.nz = grid->nz; a.h = grid->halo;
+    a.in_sy = L.in_sy; a.in_sz = L.in_sz; a.out_sy = L.out_sy; a.out_sz = L.out_sz;
+    return launch_coeff_grad(a, dtype, static_cast<hipStream_t>(hip_stream));
+}
+
 pw_status pw_advect_adjoint(const pw_grid *grid, const pw_layout *layout, pw_dtype dtype,
                             const void *u, const void *v, const void *w, const pw_coeffs *coeffs,
                             const void *gsu, const void *gsv, const void *gsw,

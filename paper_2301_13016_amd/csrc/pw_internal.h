@@ -57,6 +57,17 @@ struct TanArgs {
     const void *du, *dv, *dw;
 };
 
+// Operands of one coefficient-gradient call (validated).  grad: 6*nz + 2
+// doubles; workspace: coeff_grad_workspace_bytes() bytes.
+struct CgArgs {
+    const void *u, *v, *w;
+    const void *gsu, *gsv, *gsw;
+    void *grad, *workspace;
+    int64_t nx, ny, nz;
+    int32_t h;
+    int64_t in_sy, in_sz, out_sy, out_sz;
+};
+
 // Columns of gradient produced by one adjoint wavefront: 64 lanes load 64
 // consecutive padded columns and the 62 inner lanes own an output each.
 constexpr int kWaveCols = 62;
@@ -71,6 +82,8 @@ TileCfg default_tangent_tile(const TanArgs &a, pw_dtype dt);
 pw_status launch_forward(const FwdArgs &a, pw_dtype dt, const TileCfg &cfg, hipStream_t s);
 pw_status launch_adjoint(const AdjArgs &a, pw_dtype dt, const TileCfg &cfg, hipStream_t s);
 pw_status launch_tangent(const TanArgs &a, pw_dtype dt, const TileCfg &cfg, hipStream_t s);
+int64_t coeff_grad_workspace_bytes(const pw_grid &g, pw_dtype dt);
+pw_status launch_coeff_grad(const CgArgs &a, pw_dtype dt, hipStream_t s);
 pw_status launch_copy(const void *src, void *dst, int64_t nbytes, hipStream_t s);
 pw_status launch_copy3(const void *const *src, void *const *dst, int64_t nbytes, hipStream_t s);
 

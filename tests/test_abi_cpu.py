@@ -315,6 +315,29 @@ def test_stream_copy_validation(lib):
     assert B.pw_stream_copy(A, A + MB, 64) in _no_gpu_status()
 
 
+def test_coeff_grad_validation(lib):
+    g, c, p = _args()
+    need = ctypes.c_int64()
+    assert lib.pw_advect_coeff_grad_workspace(ctypes.byref(g), B.PW_F32, ctypes.byref(need)) == B.PW_OK
+    # FP32: strips of 128 columns x 2 rows -> 1 x 4 strips; 6 quantities x 8 levels x 4 strips doubles
+    assert need.value == 6 * 8 * 4 * 8
+    assert lib.pw_advect_coeff_grad_workspace(ctypes.byref(g), B.PW_F64, ctypes.byref(need)) == B.PW_OK
+    assert need.value == 6 * 8 * 4 * 8
+    assert lib.pw_advect_coeff_grad_workspace(ctypes.byref(g), B.PW_BF16, ctypes.byref(need)) == B.PW_ERR_UNSUPPORTED
+    assert lib.pw_advect_coeff_grad_workspace(ctypes.byref(g), B.PW_F32, None) == B.PW_ERR_INVALID_ARG
+    q = [A + i * MB for i in range(8)]   # u v w gsu gsv gsw grad workspace
+    call = lambda qq, nbytes=4096: lib.pw_advect_coeff_grad(ctypes.byref(g), None, B.PW_F32, *qq[:6], qq[6],  # noqa
+                                                              qq[7], nbytes, None)
+    assert call(q) in _no_gpu_status()
+    assert call(q, 100) == B.PW_ERR_INVALID_ARG and "workspace" in B.pw_last_error()
+    bad = list(q); bad[6] = q[0] + 8          # grad inside u
+    assert call(bad) == B.PW_ERR_INVALID_ARG
+    bad = list(q); bad[7] = q[6] + 16         # workspace overlapping grad
+    assert call(bad) == B.PW_ERR_INVALID_ARG
+    bad = list(q); bad[6] = q[6] + 4          # grad not 8-byte aligned
+    assert call(bad) == B.PW_ERR_INVALID_ARG
+
+
 def test_stream_copy3_validation(lib):
     s = [A + i * MB for i in range(3)]
     d = [A + (3 + i) * MB for i in range(3)]

@@ -1,0 +1,154 @@
+"""GPU tests of the coefficient-gradient kernel (dL/d(tcx, tcy, tz*) for
+L = <F(x), r>) against the FP64 oracle, plus reproducibility and autograd.
+
+Tolerance: the error of each gradient entry is scaled by the sum, over the
+terms it collects, of |cotangent| * |coefficient-free product| (the oracle's
+forward magnitude with that coefficient set to one); 1e-6 in FP32 (each
+product is formed in FP32 with a few roundings and summed in FP64), 1e-13 in
+FP64.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import dev_grid
+from paper_2301_13016_amd import binding as B
+from paper_2301_13016_amd import workloads as wl
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("no GPU", allow_module_level=True)
+
+NAMES = ("tzc1", "tzc2", "tzd1", "tzd2")
+
+
+@pytest.fixture(autouse=True)
+def _announce(request):
+    sys.__stderr__.write("\n[gpu-test] %s\n" % request.node.nodeid)
+    sys.__stderr__.flush()
+    yield
+
+
+def _dev(arrs, dtype=None):
+    out = [torch.from_numpy(np.ascontiguousarray(x)).to("cuda") for x in arrs]
+    return [o.to(dtype) for o in out] if dtype is not None else out
+
+
+def magnitudes(g, r):
+    """Per gradient entry: sum over its terms of |r| * |product|."""
+    nz = g.nz
+    ar = [np.abs(np.asarray(x, np.float64)) for x in r]
+    zero = dict(tcx=0.0, tcy=0.0, **{n: np.zeros(nz) for n in NAMES})
+    out = {}
+    for name in ("tcx", "tcy") + NAMES:
+        c = dict(zero)
+        c[name] = 1.0 if name in ("tcx", "tcy") else np.ones(nz)
+        _, mag = oracle.forward(g.u, g.v, g.w, c, halo=g.halo, magnitude=True)
+        per_level = sum(np.sum(a * m, axis=(1, 2)) for a, m in zip(ar, mag))
+        out[name] = float(per_level.sum()) if name in ("tcx", "tcy") else per_level
+    return out
+
+
+def check(g, r, tol, halo=1):
+    (u, v, w), _ = dev_grid(g)
+    rd = _dev(r, u.dtype)
+    got = B.advect_coeff_grad(u, v, w, *rd, halo=halo)
+    torch.cuda.synchronize()
+    rq = [np.asarray(x, g.u.dtype).astype(np.float64) for x in r]   # cotangents as the kernel saw them
+    ref = oracle.coeff_grad(g.u, g.v, g.w, *rq, halo=halo)
+    mag = magnitudes(g, rq)
+    worst = 0.0
+    for name in ("tcx", "tcy") + NAMES:
+        e = np.abs(got[name].cpu().numpy() - ref[name]) / np.maximum(mag[name], 1e-300)
+        worst = max(worst, float(np.max(e)))
+    lev = got["tcx_level"].cpu().numpy()
+    assert np.max(np.abs(lev - ref["tcx_level"])) <= tol * mag["tcx"]
+    assert worst <= tol, worst
+    return got, worst
+
+
+@pytest.mark.parametrize("shape", [(130, 70, 20), (1, 1, 1), (65, 3, 1), (129, 5, 2), (257, 3, 4), (61, 9, 17)],
+                         ids=lambda s: "x".join(map(str, s)))
+def test_f32_coeff_grad_matches_oracle(shape):
+    nx, ny, nz = shape
+    g = wl.make_grid(nx, ny, nz, seed=700 + nx)
+    r = wl.cotangents(nx, ny, nz, seed=800 + nx)
+    check(g, r, 1e-6)
+
+
+def test_f64_coeff_grad_matches_oracle():
+    g = wl.make_grid(70, 33, 21, seed=701, dtype=np.float64)
+    r = wl.cotangents(70, 33, 21, seed=801, dtype=np.float64)
+    check(g, r, 1e-13)
+
+
+@pytest.mark.parametrize("halo", [2, 3])
+def test_coeff_grad_wider_halo(halo):
+    g = wl.make_grid(70, 20, 9, seed=702, halo=halo)
+    r = wl.cotangents(70, 20, 9, seed=802)
+    check(g, r, 1e-6, halo=halo)
+
+
+def test_coeff_grad_reproducible_bitwise():
+    g = wl.make_grid(150, 37, 23, seed=703)
+    r = wl.cotangents(150, 37, 23, seed=803)
+    (u, v, w), _ = dev_grid(g)
+    rd = _dev(r)
+    a = B.advect_coeff_grad(u, v, w, *rd)
+    b = B.advect_coeff_grad(u, v, w, *rd)
+    for k in a:
+        assert torch.equal(a[k], b[k]), k
+
+
+def test_c4_coeff_grad_parity(report):
+    """256 x 256 x 128 FP32, every coefficient gradient against the oracle."""
+    cfg = wl.C4
+    g = wl.config_grid(cfg)
+    r = wl.cotangents(cfg["nx"], cfg["ny"], cfg["nz"], cfg["cot_seed"])
+    _, worst = check(g, r, 1e-6)
+    report["coeff_grad_f32_256x256x128"] = dict(worst_scaled=worst)
+
+
+def test_euler_identity_on_gpu():
+    """sum of c * dL/dc over all coefficients = L (L is linear in them)."""
+    g = wl.make_grid(90, 20, 12, seed=704, dtype=np.float64)
+    r = wl.cotangents(90, 20, 12, seed=804, dtype=np.float64)
+    (u, v, w), c = dev_grid(g)
+    rd = _dev(r)
+    got = B.advect_coeff_grad(u, v, w, *rd)
+    f = B.advect(u, v, w, c)
+    loss = float(sum((a * b).sum() for a, b in zip(f, rd)))
+    total = g.tcx * float(got["tcx"]) + g.tcy * float(got["tcy"]) + \
+        sum(float((getattr(c, n) * got[n]).sum()) for n in NAMES)
+    assert abs(total - loss) <= 1e-12 * abs(loss)
+
+
+def test_autograd_with_coefficients_gradcheck():
+    PW = B.PWAdvectCoeffs()
+    g = wl.make_grid(5, 4, 3, seed=705, dtype=np.float64)
+    (u, v, w), c = dev_grid(g)
+    dd = torch.float64
+    args = [x.clone().requires_grad_(True) for x in (u, v, w)]
+    args += [torch.tensor(g.tcx, dtype=dd, requires_grad=True), torch.tensor(g.tcy, dtype=dd, requires_grad=True)]
+    args += [getattr(c, n).clone().requires_grad_(True) for n in NAMES]
+    assert torch.autograd.gradcheck(lambda *a: PW.apply(*a), tuple(args), fast_mode=True)
+    # winds only: the coefficient kernel is skipped, results as PWAdvect
+    y = wl.cotangents(5, 4, 3, seed=805, dtype=np.float64)
+    xs = [x.clone().requires_grad_(True) for x in (u, v, w)]
+    outs = PW.apply(*xs, torch.tensor(g.tcx, dtype=dd), torch.tensor(g.tcy, dtype=dd), c.tzc1, c.tzc2, c.tzd1, c.tzd2)
+    sum((o * t).sum() for o, t in zip(outs, _dev(y))).backward()
+    ref = oracle.adjoint(g.u, g.v, g.w, g.coeffs, *y)
+    for x, rr in zip(xs, ref):
+        assert np.allclose(x.grad.cpu().numpy(), rr, rtol=1e-12, atol=1e-12)
+
+
+def test_coeff_grad_argument_errors():
+    g = wl.make_grid(20, 8, 4, seed=706)
+    (u, v, w), _ = dev_grid(g)
+    r = [torch.zeros((4, 8, 20), device="cuda") for _ in range(3)]
+    with pytest.raises(B.PWError):
+        B.advect_coeff_grad(*(x.to(torch.bfloat16) for x in (u, v, w)), *(x.to(torch.bfloat16) for x in r))

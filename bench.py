@@ -60,13 +60,13 @@ def adjoint_bytes(nx, ny, nz, halo, es=4):
 
 
 def kernel_fingerprint():
-    """sha256[:16] of the forward kernel's sources plus the tuning-table row
-    that picks its launch shape for 512 x 512 x 64 FP32.  Any change to either
+    """sha256[:16] of the FP32 forward kernel's sources plus the tuning-table
+    row that picks its launch shape for 512 x 512 x 64.  Any change to either
     makes stored HBM-counter readings stale."""
     import hashlib
     csrc = os.path.join(ROOT, "paper_2301_13016_amd", "csrc")
     hsh = hashlib.sha256()
-    for name in ("pw_stencil.h", "pw_forward.hip"):
+    for name in ("pw_stencil.h", "pw_forward_impl.h", "pw_forward_f32.hip"):
         with open(os.path.join(csrc, name), "rb") as f:
             hsh.update(f.read())
     with open(os.path.join(csrc, "pw_tune_defaults.inc")) as f:
@@ -137,6 +137,26 @@ def prebuilt_forward(B, ins, outs, coeffs, stream, tile=None):
         st = fn(*args)
         if st != B.PW_OK:
             raise B.PWError(st, B.pw_last_error(), "pw_advect_ex")
+    call.keep = keep
+    return call
+
+
+def prebuilt_epilogue(B, ins, outs, coeffs, alpha, stream):
+    """ctypes arguments of one pw_advect_epilogue call accumulating into
+    ``outs`` (out += alpha * F), built once."""
+    from paper_2301_13016_amd.binding import _dtype_code, _grid_from, _layout_from
+    u, v, w = ins
+    keep = (_grid_from(u, 1), _layout_from(u, outs[0]), coeffs.c_struct(),
+            B.pw_epilogue(float(alpha), *(x.data_ptr() for x in outs)))
+    args = (ctypes.byref(keep[0]), ctypes.byref(keep[1]), _dtype_code(u),
+            u.data_ptr(), v.data_ptr(), w.data_ptr(), ctypes.byref(keep[2]), ctypes.byref(keep[3]),
+            *(x.data_ptr() for x in outs), None, ctypes.c_void_p(stream.cuda_stream))
+    fn = B.lib().pw_advect_epilogue
+
+    def call():
+        st = fn(*args)
+        if st != B.PW_OK:
+            raise B.PWError(st, B.pw_last_error(), "pw_advect_epilogue")
     call.keep = keep
     return call
 
@@ -244,7 +264,12 @@ def main():
         keep.append((ins, outs))
         calls.append(prebuilt_forward(B, ins, outs, coeffs, stream))
 
+    forms = {}
     ms_step, k_ms = time_launches(torch, lambda i: calls[i](), nsets, args.steps, args.warmup, stream)
+    # fused accumulation on the same grid and buffers: out += F (reads the outputs too)
+    acc_calls = [prebuilt_epilogue(B, kp[0], kp[1], coeffs, 1.0, stream) for kp in keep]
+    _, acc_ms = time_launches(torch, lambda i: acc_calls[i](), nsets, 100, 10, stream)
+    del acc_calls
     pts = nx * ny * nz
     gpts = pts / (ms_step * 1e-3) / 1e9
     nbytes = algo_bytes(nx, ny, nz, h, 4)
@@ -268,6 +293,11 @@ def main():
     _, c3_ms = time_launches(torch, lambda i: B.stream_copy3(*sets3[i]), 4, 200, 10, stream)
     copy3_gbs = 6 * obytes / (c3_ms * 1e-3) / 1e9
     log("three-stream copy 3 x %d MB each way: %.4f ms, %.0f GB/s" % (obytes >> 20, c3_ms, copy3_gbs))
+    nbytes_acc = nbytes + 3 * nx * ny * nz * 4
+    forms["fused_accumulate_512x512x64"] = dict(
+        kernel_ms=round(acc_ms, 4), over_plain=round(acc_ms / k_ms, 3),
+        ideal_ratio_from_bytes=round(nbytes_acc / nbytes, 3), hbm_gbs=round(nbytes_acc / (acc_ms * 1e-3) / 1e9, 1))
+    log("c1 fused accumulate (out += F): %.4f ms, %.3f x the plain step" % (acc_ms, acc_ms / k_ms))
     del keep, calls, sets3
     torch.cuda.empty_cache()
 
@@ -284,7 +314,6 @@ def main():
     log("oracle on %d host threads: %.3f Gpt/s (%d reps of the full grid)" % (ncpu, cpu_gpts, reps))
     del u64, v64, w64
 
-    forms = {}
     # ------------------------------------------------------------ precision form: c2
     c2 = wl.C2
     n2 = (c2["nx"], c2["ny"], c2["nz"])

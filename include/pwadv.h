@@ -146,6 +146,27 @@ pw_status pw_advect_ex(const pw_grid *grid, const pw_layout *layout, pw_dtype in
                        void *su, void *sv, void *sw,
                        const pw_tile *tile, void *hip_stream);
 
+/* Forward operator with a fused epilogue:
+ *   su = cu + alpha * F_u(u, v, w),  sv = cv + alpha * F_v,  sw = cw + alpha * F_w
+ * in the compute type (float; double for PW_F64), one rounding per element
+ * (fma).  cu/cv/cw are arrays in the output layout and compute type.  Two
+ * uses: accumulation into the outputs (cu == su etc., alpha = 1: other
+ * components of a model add to the same source terms), and a fused explicit
+ * time step (cu = the interior of u, su = the interior of the next state,
+ * alpha = dt; pass a layout whose output strides are the padded strides).
+ * Each addend must be its own output or overlap no output at all; it may
+ * overlap the inputs.  Same launch shapes and rules as pw_advect_ex; tile ==
+ * NULL means the library's choice. */
+typedef struct {
+    double alpha;
+    const void *cu, *cv, *cw;
+} pw_epilogue;
+pw_status pw_advect_epilogue(const pw_grid *grid, const pw_layout *layout, pw_dtype in_dtype,
+                             const void *u, const void *v, const void *w,
+                             const pw_coeffs *coeffs, const pw_epilogue *epilogue,
+                             void *su, void *sv, void *sw,
+                             const pw_tile *tile, void *hip_stream);
+
 /* Adjoint (vector-Jacobian product) of the forward operator:
  *   (gu, gv, gw) = J(u, v, w)^T (gsu, gsv, gsw)
  * i.e. the gradient of <su, gsu> + <sv, gsv> + <sw, gsw> with respect to every

@@ -64,6 +64,10 @@ def _tile_tuple(t):
     return (t.cols_per_lane, t.rows_per_strip, t.zlen, t.waves_per_group, t.prefetch)
 
 
+class pw_epilogue(ctypes.Structure):
+    _fields_ = [("alpha", ctypes.c_double), ("cu", ctypes.c_void_p), ("cv", ctypes.c_void_p), ("cw", ctypes.c_void_p)]
+
+
 class pw_batch_item(ctypes.Structure):
     _fields_ = [("grid", pw_grid), ("layout", pw_layout), ("u", ctypes.c_void_p), ("v", ctypes.c_void_p),
                 ("w", ctypes.c_void_p), ("coeffs", pw_coeffs), ("su", ctypes.c_void_p), ("sv", ctypes.c_void_p),
@@ -79,6 +83,9 @@ _SIGNATURES = {
                   _P, _P, _P, ctypes.POINTER(pw_coeffs), _P, _P, _P, _P],
     "pw_advect_ex": [ctypes.POINTER(pw_grid), ctypes.POINTER(pw_layout), ctypes.c_int,
                      _P, _P, _P, ctypes.POINTER(pw_coeffs), _P, _P, _P, ctypes.POINTER(pw_tile), _P],
+    "pw_advect_epilogue": [ctypes.POINTER(pw_grid), ctypes.POINTER(pw_layout), ctypes.c_int,
+                           _P, _P, _P, ctypes.POINTER(pw_coeffs), ctypes.POINTER(pw_epilogue), _P, _P, _P,
+                           ctypes.POINTER(pw_tile), _P],
     "pw_advect_adjoint": [ctypes.POINTER(pw_grid), ctypes.POINTER(pw_layout), ctypes.c_int,
                           _P, _P, _P, ctypes.POINTER(pw_coeffs), _P, _P, _P, _P, _P, _P, _P],
     "pw_advect_adjoint_ex": [ctypes.POINTER(pw_grid), ctypes.POINTER(pw_layout), ctypes.c_int,
@@ -301,6 +308,29 @@ def advect(u, v, w, coeffs: Coeffs, halo=1, out=None, tile=None, stream=None):
     st = pw_advect_ex(grid, layout, _dtype_code(u), u.data_ptr(), v.data_ptr(), w.data_ptr(), c,
                       su.data_ptr(), sv.data_ptr(), sw.data_ptr(), tl, _stream_handle(stream))
     _check(st, "pw_advect")
+    return su, sv, sw
+
+
+def advect_epilogue(u, v, w, coeffs: Coeffs, addends, alpha=1.0, halo=1, out=None, tile=None, stream=None):
+    """out = addends + alpha * F(u, v, w) with one rounding per element.
+    ``addends`` is (cu, cv, cw) in the outputs' layout and compute dtype;
+    pass the outputs themselves to accumulate in place (``out=addends``)."""
+    import torch
+    grid = _grid_from(u, halo)
+    cu, cv, cw = addends
+    if out is None:
+        out = tuple(torch.empty_like(x) for x in (cu, cv, cw))
+    su, sv, sw = out
+    if not (su.stride() == sv.stride() == sw.stride() == cu.stride() == cv.stride() == cw.stride()):
+        raise ValueError("outputs and addends must share one layout")
+    layout = _layout_from(u, su)
+    tl = None if tile is None else pw_tile(*tile)
+    ep = pw_epilogue(float(alpha), cu.data_ptr(), cv.data_ptr(), cw.data_ptr())
+    st = lib().pw_advect_epilogue(ctypes.byref(grid), ctypes.byref(layout), _dtype_code(u), u.data_ptr(),
+                                  v.data_ptr(), w.data_ptr(), ctypes.byref(coeffs.c_struct()), ctypes.byref(ep),
+                                  su.data_ptr(), sv.data_ptr(), sw.data_ptr(),
+                                  ctypes.byref(tl) if tl is not None else None, _stream_handle(stream))
+    _check(st, "pw_advect_epilogue")
     return su, sv, sw
 
 

@@ -1,5 +1,6 @@
 // C ABI of libpwadv: argument validation, error reporting and dispatch to the
 // kernel launchers.  Declarations and the contract are in include/pwadv.h.
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -242,6 +243,54 @@ pw_status pw_advect_ex(const pw_grid *grid, const pw_layout *layout, pw_dtype in
         return fail(PW_ERR_INVALID_ARG, "unsupported forward tile cols=%d rows=%d zlen=%d waves=%d prefetch=%d",
                     tile->cols_per_lane, tile->rows_per_strip, tile->zlen, tile->waves_per_group, tile->prefetch);
     PW_TRY(check_forward_on_device(a));
+    TileCfg cfg;
+    if (tile)
+        cfg = to_cfg(*tile);
+    else if (!lookup_tuned(TuneKind::Forward, grid, in_dtype, &cfg))
+        cfg = default_forward_tile(a, in_dtype);
+    return launch_forward(a, in_dtype, cfg, static_cast<hipStream_t>(hip_stream));
+}
+
+pw_status pw_advect_epilogue(const pw_grid *grid, const pw_layout *layout, pw_dtype in_dtype,
+                             const void *u, const void *v, const void *w, const pw_coeffs *coeffs,
+                             const pw_epilogue *ep, void *su, void *sv, void *sw, const pw_tile *tile,
+                             void *hip_stream) {
+    g_err[0] = 0;
+    if (!ep) return fail(PW_ERR_INVALID_ARG, "epilogue is NULL");
+    FwdArgs a;
+    PW_TRY(validate_forward(grid, layout, in_dtype, u, v, w, coeffs, su, sv, sw, &a));
+    if (tile && !tile_supported(to_cfg(*tile), in_dtype))
+        return fail(PW_ERR_INVALID_ARG, "unsupported forward tile cols=%d rows=%d zlen=%d waves=%d prefetch=%d",
+                    tile->cols_per_lane, tile->rows_per_strip, tile->zlen, tile->waves_per_group, tile->prefetch);
+    // the addends: output layout, compute type; each either is its output
+    // (accumulation in place) or overlaps no output at all (inputs may be
+    // overlapped: they are only read)
+    const int64_t cs = a.out_bytes;
+    Layout L;
+    PW_TRY(resolve_layout(grid, layout, a.in_bytes, cs, &L));
+    const char *cn[3] = {"cu", "cv", "cw"};
+    const void *cp[3] = {ep->cu, ep->cv, ep->cw};
+    void *op[3] = {su, sv, sw};
+    const Range rout[3] = {out_range("su", su, grid, L, cs), out_range("sv", sv, grid, L, cs),
+                           out_range("sw", sw, grid, L, cs)};
+    for (int i = 0; i < 3; ++i) {
+        PW_TRY(check_aligned(cn[i], cp[i], cs));
+        const Range rc = out_range(cn[i], cp[i], grid, L, cs);
+        for (int o = 0; o < 3; ++o) {
+            if (o == i && cp[i] == op[o]) continue;   // in place
+            if (overlap(rc, rout[o]))
+                return fail(PW_ERR_INVALID_ARG, "%s overlaps output %s (only %s itself may be given)", cn[i],
+                            rout[o].name, rout[i].name);
+        }
+    }
+    if (!std::isfinite(ep->alpha)) return fail(PW_ERR_INVALID_ARG, "alpha is not finite");
+    PW_TRY(check_forward_on_device(a));
+    int dev = 0;
+    PW_TRY(current_device(&dev));
+    for (int i = 0; i < 3; ++i) PW_TRY(check_on_device(cn[i], cp[i], dev));
+    a.epilogue = true;
+    a.cu = ep->cu; a.cv = ep->cv; a.cw = ep->cw;
+    a.alpha = ep->alpha;
     TileCfg cfg;
     if (tile)
         cfg = to_cfg(*tile);

@@ -1,0 +1,10 @@
+// Forward kernel instantiations for FP16 storage (see pw_forward_impl.h).
+#include "pw_forward_impl.h"
+
+namespace pw {
+
+pw_status launch_forward_f16(const FwdArgs &g, const TileCfg &cfg, hipStream_t s) {
+    return fwd::launch_fwd_dt<_Float16>(g, cfg, s);
+}
+
+}  // namespace pw

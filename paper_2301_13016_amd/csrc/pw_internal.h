@@ -37,6 +37,10 @@ struct FwdArgs {
     int32_t h;
     int64_t in_sy, in_sz, out_sy, out_sz;
     int64_t in_bytes = 4, out_bytes = 4;   // element sizes of inputs / outputs
+    // fused epilogue: out = c + alpha * F (epilogue == false: out = F)
+    bool epilogue = false;
+    const void *cu = nullptr, *cv = nullptr, *cw = nullptr;
+    double alpha = 1.0;
 };
 
 struct AdjArgs {
@@ -80,6 +84,11 @@ bool tangent_tile_supported(const TileCfg &c, pw_dtype dt);
 TileCfg default_tangent_tile(const TanArgs &a, pw_dtype dt);
 
 pw_status launch_forward(const FwdArgs &a, pw_dtype dt, const TileCfg &cfg, hipStream_t s);
+// per storage type (pw_forward_f32.hip, ...); launch_forward dispatches to these
+pw_status launch_forward_f32(const FwdArgs &a, const TileCfg &cfg, hipStream_t s);
+pw_status launch_forward_f64(const FwdArgs &a, const TileCfg &cfg, hipStream_t s);
+pw_status launch_forward_bf16(const FwdArgs &a, const TileCfg &cfg, hipStream_t s);
+pw_status launch_forward_f16(const FwdArgs &a, const TileCfg &cfg, hipStream_t s);
 pw_status launch_adjoint(const AdjArgs &a, pw_dtype dt, const TileCfg &cfg, hipStream_t s);
 pw_status launch_tangent(const TanArgs &a, pw_dtype dt, const TileCfg &cfg, hipStream_t s);
 int64_t coeff_grad_workspace_bytes(const pw_grid &g, pw_dtype dt);

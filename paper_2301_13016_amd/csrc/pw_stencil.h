@@ -123,6 +123,9 @@ template <typename Tin> struct FwdK {
     int64_t in_sz, out_sz;     // plane strides (elements)
     int32_t in_sy, out_sy;     // row strides (elements); a plane fits in 2 GiB
     int32_t ntx, nty, nzc, zlen, wpb;
+    // fused epilogue (used by the Epi instantiations only): out = c + alpha * F
+    const Tc *cu, *cv, *cw;
+    Tc alpha;
 };
 
 // One z-plane of the strip as loaded: rows 0..RY+1 are the strip's rows
@@ -193,13 +196,50 @@ template <typename T, int N> __device__ __forceinline__ void store_vec(char *p, 
     PW_GSTORE_NT(VT, v, p);
 }
 
+// The epilogue's addend rows of one output level (output layout, compute
+// type): RY rows x PX columns, columns clamped into the grid (the columns
+// past the end are never stored).
+template <typename Tin, int PX, int RY> struct EpiRows {
+    using Tc = typename Storage<Tin>::Tc;
+    typename Vec<Tc, PX>::type u[RY], v[RY], w[RY];
+};
+
+template <typename Tin, int PX, int RY, bool Full>
+__device__ __forceinline__ void load_epi(EpiRows<Tin, PX, RY> &E, const FwdK<Tin> &a, int kk,
+                                         const uint32_t (&ooff)[RY], int ic) {
+    using Tc = typename Storage<Tin>::Tc;
+    const int64_t ob = static_cast<int64_t>(kk) * a.out_sz * static_cast<int64_t>(sizeof(Tc));
+    const char *bu = reinterpret_cast<const char *>(a.cu) + ob;
+    const char *bv = reinterpret_cast<const char *>(a.cv) + ob;
+    const char *bw = reinterpret_cast<const char *>(a.cw) + ob;
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+        if constexpr (Full || PX == 1) {
+            using VT = typename Vec<Tc, PX>::type;
+            E.u[r] = PW_GLOAD(VT, bu + ooff[r]);
+            E.v[r] = PW_GLOAD(VT, bv + ooff[r]);
+            E.w[r] = PW_GLOAD(VT, bw + ooff[r]);
+        } else {
+            // ooff is at column ic = min(ii0, nx-1); columns ic+m clamped to nx-1
+#pragma unroll
+            for (int m = 0; m < PX; ++m) {
+                const int64_t d = static_cast<int64_t>(min(ic + m, a.nx - 1) - ic) * sizeof(Tc);
+                E.u[r][m] = PW_GLOAD(Tc, bu + ooff[r] + d);
+                E.v[r][m] = PW_GLOAD(Tc, bv + ooff[r] + d);
+                E.w[r][m] = PW_GLOAD(Tc, bw + ooff[r] + d);
+            }
+        }
+    }
+}
+
 // Source terms of output level kk (interior numbering) from planes kk-1 (m),
 // kk (c) and kk+1 (p); stores the lanes/rows that own outputs.
-template <typename Tin, int PX, int RY, bool Full>
+template <typename Tin, int PX, int RY, bool Full, bool Epi>
 __device__ __forceinline__ void level(const Plane<Tin, PX, RY> &m, const Plane<Tin, PX, RY> &c,
                                       const Plane<Tin, PX, RY> &p,
                                       const FwdK<Tin> &a, int kk, bool lane0, bool lane63, int nvalid,
-                                      const uint32_t (&ooff)[RY], const bool (&row_ok)[RY]) {
+                                      const uint32_t (&ooff)[RY], const bool (&row_ok)[RY],
+                                      const EpiRows<Tin, PX, RY> &E) {
     using Tc = typename Storage<Tin>::Tc;
     // element (row r, column x) of a loaded row array, widened
 #define G(arr, r, x) Storage<Tin>::widen(comp<Tin, PX>((arr)[r], (x)))
@@ -289,6 +329,11 @@ __device__ __forceinline__ void level(const Plane<Tin, PX, RY> &m, const Plane<T
             sw = fma_(d1 * G(m.w, q, x), hzm, sw);
             sw = fma_(-(d2 * G(p.w, q, x)), hzp, sw);
 
+            if constexpr (Epi) {   // out = c + alpha * F, one rounding
+                su = fma_(a.alpha, su, comp<Tc, PX>(E.u[r], x));
+                sv = fma_(a.alpha, sv, comp<Tc, PX>(E.v[r], x));
+                sw = fma_(a.alpha, sw, comp<Tc, PX>(E.w[r], x));
+            }
             rsu[x] = su;
             rsv[x] = sv;
             rsw[x] = sw;
@@ -330,8 +375,11 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
 // lane loads whole vectors and owns PX outputs; otherwise loads are clamped
 // element-wise (one-column lanes need no clamping beyond their start column)
 // and each lane stores only its columns inside the grid.  Depth: planes in
-// flight ahead of the three a level reads (1 or 2).
-template <typename Tin, int PX, int RY, bool Full, int Depth>
+// flight ahead of the three a level reads (1 or 2).  Epi: the fused
+// epilogue out = c + alpha * F; the addend rows of level kk are loaded at the
+// start of the level, before that level's plane prefetch, so waiting for them
+// never waits for the prefetch.
+template <typename Tin, int PX, int RY, bool Full, int Depth, bool Epi>
 __device__ __forceinline__ void strip_march_t(const FwdK<Tin> &a, int tx, int ty, int cz) {
     using Tc = typename Storage<Tin>::Tc;
     const int lane = threadIdx.x & 63;
@@ -365,24 +413,31 @@ __device__ __forceinline__ void strip_march_t(const FwdK<Tin> &a, int tx, int ty
         ooff[r] = static_cast<uint32_t>((jj * a.out_sy + ic) * static_cast<int>(sizeof(Tc)));
     }
     const bool lane0 = lane == 0, lane63 = lane == 63;
+    const int ic = min(ii0, a.nx - 1);
 
     const int k0 = cz * a.zlen;
     const int k1 = min(a.nz, k0 + a.zlen);
     const int h = a.h;
+    EpiRows<Tin, PX, RY> Ep;   // the epilogue's addend rows of the current level
 
     // The prefetch of the next plane is unconditional (near the chunk's end it
     // re-reads plane k1, a cache hit): a conditional load would merge two
     // paths with different loads in flight, and the wait inserted at such a
     // merge drains every outstanding load, prefetch included.
-#define PW_LOAD(P, kp) load_plane<Tin, PX, RY, Full>(P, a, min((kp), k1) + h, s, last_col)
-#define PW_LEVEL(M, C, P) level<Tin, PX, RY, Full>(M, C, P, a, kk, lane0, lane63, nvalid, ooff, row_ok)
+#define PW_PLOAD(P, kp) load_plane<Tin, PX, RY, Full>(P, a, min((kp), k1) + h, s, last_col)
+#define PW_LOAD(P, kp)                                                   \
+    do {                                                                 \
+        if constexpr (Epi) load_epi<Tin, PX, RY, Full>(Ep, a, kk, ooff, ic); \
+        load_plane<Tin, PX, RY, Full>(P, a, min((kp), k1) + h, s, last_col); \
+    } while (0)
+#define PW_LEVEL(M, C, P) level<Tin, PX, RY, Full, Epi>(M, C, P, a, kk, lane0, lane63, nvalid, ooff, row_ok, Ep)
     int kk = k0;
     if constexpr (Depth == 1) {
         // four-plane ring: planes kk-1, kk, kk+1 feed level kk, kk+2 in flight
         Plane<Tin, PX, RY> A, B, C, D;
         load_plane<Tin, PX, RY, Full>(A, a, k0 - 1 + h, s, last_col);
-        PW_LOAD(B, k0);
-        PW_LOAD(C, k0 + 1);
+        PW_PLOAD(B, k0);
+        PW_PLOAD(C, k0 + 1);
         for (;;) {
             PW_LOAD(D, kk + 2);
             PW_LEVEL(A, B, C);
@@ -402,9 +457,9 @@ __device__ __forceinline__ void strip_march_t(const FwdK<Tin> &a, int tx, int ty
         static_assert(Depth == 2, "prefetch depth 1 or 2");
         Plane<Tin, PX, RY> A, B, C, D, E;
         load_plane<Tin, PX, RY, Full>(A, a, k0 - 1 + h, s, last_col);
-        PW_LOAD(B, k0);
-        PW_LOAD(C, k0 + 1);
-        PW_LOAD(D, k0 + 2);
+        PW_PLOAD(B, k0);
+        PW_PLOAD(C, k0 + 1);
+        PW_PLOAD(D, k0 + 2);
         for (;;) {
             PW_LOAD(E, kk + 3);
             PW_LEVEL(A, B, C);
@@ -423,20 +478,21 @@ __device__ __forceinline__ void strip_march_t(const FwdK<Tin> &a, int tx, int ty
             if (++kk >= k1) break;
         }
     }
+#undef PW_PLOAD
 #undef PW_LOAD
 #undef PW_LEVEL
 }
 
-template <typename Tin, int PX, int RY, int Depth>
+template <typename Tin, int PX, int RY, int Depth, bool Epi = false>
 __device__ __forceinline__ void strip_march(const FwdK<Tin> &a, int tx, int ty, int cz) {
     if constexpr (PX == 1) {
         // one-column lanes: loads never need clamping beyond the start column,
         // and one masked store per row is cheap, so one path serves every strip
-        strip_march_t<Tin, PX, RY, false, Depth>(a, tx, ty, cz);
+        strip_march_t<Tin, PX, RY, false, Depth, Epi>(a, tx, ty, cz);
     } else if ((tx + 1) * 64 * PX <= a.nx) {
-        strip_march_t<Tin, PX, RY, true, Depth>(a, tx, ty, cz);
+        strip_march_t<Tin, PX, RY, true, Depth, Epi>(a, tx, ty, cz);
     } else {
-        strip_march_t<Tin, PX, RY, false, Depth>(a, tx, ty, cz);
+        strip_march_t<Tin, PX, RY, false, Depth, Epi>(a, tx, ty, cz);
     }
 }
 

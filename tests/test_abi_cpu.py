@@ -315,6 +315,29 @@ def test_stream_copy_validation(lib):
     assert B.pw_stream_copy(A, A + MB, 64) in _no_gpu_status()
 
 
+def test_epilogue_validation(lib):
+    g, c, p = _args()
+    call = lambda ep, pp=p, tile=None: lib.pw_advect_epilogue(  # noqa: E731
+        ctypes.byref(g), None, B.PW_F32, *pp[:3], ctypes.byref(c), ep, *pp[3:6], tile, None)
+    addends = [A + (20 + i) * MB for i in range(3)]
+    ok = B.pw_epilogue(1.0, *addends)
+    assert call(ctypes.byref(ok)) in _no_gpu_status()
+    assert call(None) == B.PW_ERR_INVALID_ARG
+    inplace = B.pw_epilogue(1.0, *p[3:6])                      # accumulate into the outputs
+    assert call(ctypes.byref(inplace)) in _no_gpu_status()
+    crossed = B.pw_epilogue(1.0, p[4], p[4], p[5])             # cu is sv
+    assert call(ctypes.byref(crossed)) == B.PW_ERR_INVALID_ARG and "overlaps" in B.pw_last_error()
+    partial = B.pw_epilogue(1.0, p[3] + 4 * 16, p[4], p[5])    # cu half inside su
+    assert call(ctypes.byref(partial)) == B.PW_ERR_INVALID_ARG
+    on_input = B.pw_epilogue(0.5, p[0], p[1], p[2])           # addends inside the inputs: read-only, fine
+    assert call(ctypes.byref(on_input)) in _no_gpu_status()
+    misaligned = B.pw_epilogue(1.0, addends[0] + 2, addends[1], addends[2])
+    assert call(ctypes.byref(misaligned)) == B.PW_ERR_INVALID_ARG
+    nan = B.pw_epilogue(float("nan"), *addends)
+    assert call(ctypes.byref(nan)) == B.PW_ERR_INVALID_ARG
+    assert call(ctypes.byref(ok), tile=ctypes.byref(B.pw_tile(3, 1, 8, 4))) == B.PW_ERR_INVALID_ARG
+
+
 def test_coeff_grad_validation(lib):
     g, c, p = _args()
     need = ctypes.c_int64()

@@ -1,0 +1,105 @@
+"""GPU tests of the fused epilogue out = c + alpha * F(u, v, w): accumulation
+in place and a fused explicit time step on padded views, against the FP64
+oracle.
+
+Tolerance: |out - (c + alpha F_ref)| <= 1e-6 * |alpha| * A + 2^-23 * |out|
+(FP32: the forward's own A-scaled bound plus the one rounding of the fma);
+bit for bit where the epilogue is exact (alpha = 1, c = 0) and across launch
+shapes.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import dev_grid
+from paper_2301_13016_amd import binding as B
+from paper_2301_13016_amd import workloads as wl
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("no GPU", allow_module_level=True)
+
+
+@pytest.fixture(autouse=True)
+def _announce(request):
+    sys.__stderr__.write("\n[gpu-test] %s\n" % request.node.nodeid)
+    sys.__stderr__.flush()
+    yield
+
+
+def _check(got, c, alpha, ref, mag, eps=2.0 ** -23, tol=1e-6):
+    for o, cc, r, m in zip(got, c, ref, mag):
+        o = o.cpu().numpy().astype(np.float64)
+        exp = np.asarray(cc, np.float64) + alpha * r
+        err = np.abs(o - exp)
+        assert np.all(err <= tol * abs(alpha) * m + eps * np.abs(exp) + 1e-30), float(np.max(err))
+
+
+@pytest.mark.parametrize("tile", [None, (4, 2, 64, 1, 2), (1, 1, 5, 4), (2, 4, 3, 8, 1)])
+@pytest.mark.parametrize("shape", [(130, 70, 20), (1, 1, 1), (257, 3, 4), (61, 9, 17)],
+                         ids=lambda s: "x".join(map(str, s)))
+def test_accumulate_in_place(shape, tile):
+    nx, ny, nz = shape
+    g = wl.make_grid(nx, ny, nz, seed=900 + nx)
+    (u, v, w), c = dev_grid(g)
+    rng = np.random.default_rng(901 + nx)
+    c0 = [rng.uniform(-5, 5, (nz, ny, nx)).astype(np.float32) for _ in range(3)]
+    out = [torch.from_numpy(x).cuda() for x in c0]
+    B.advect_epilogue(u, v, w, c, out, alpha=1.0, out=out, tile=tile)
+    ref, mag = oracle.forward(g.u, g.v, g.w, g.coeffs, magnitude=True)
+    _check(out, c0, 1.0, ref, mag)
+
+
+def test_time_step_on_padded_views():
+    """u_next[interior] = u[interior] + dt * F(u, v, w), written into the
+    interior of padded next-state arrays whose halos stay untouched."""
+    g = wl.make_grid(100, 30, 12, seed=902)
+    (u, v, w), c = dev_grid(g)
+    dt = 0.37
+    nxt = [torch.full_like(x, 123.0) for x in (u, v, w)]
+    inner = (slice(1, -1), slice(1, -1), slice(1, -1))
+    B.advect_epilogue(u, v, w, c, [x[inner] for x in (u, v, w)], alpha=dt, out=[x[inner] for x in nxt])
+    ref, mag = oracle.forward(g.u, g.v, g.w, g.coeffs, magnitude=True)
+    _check([x[inner] for x in nxt], [x[inner] for x in (g.u, g.v, g.w)], dt, ref, mag)
+    for x in nxt:   # halo untouched
+        h = x.clone()
+        h[inner] = 123.0
+        assert torch.all(h == 123.0)
+
+
+@pytest.mark.parametrize("storage", [None, "bfloat16", "float16", "float64"])
+def test_alpha_one_zero_addend_is_plain_forward_bitwise(storage):
+    dt = np.float64 if storage == "float64" else np.float32
+    g = wl.make_grid(150, 37, 23, seed=903, dtype=dt)
+    st = None if storage in (None, "float64") else getattr(torch, storage)
+    (u, v, w), c = dev_grid(g, storage=st)
+    plain = B.advect(u, v, w, c)
+    zeros = [torch.zeros_like(x) for x in plain]
+    fused = B.advect_epilogue(u, v, w, c, zeros, alpha=1.0)
+    for a, b in zip(plain, fused):
+        assert torch.equal(a, b)
+
+
+def test_epilogue_tile_invariance_bitwise():
+    g = wl.make_grid(300, 9, 7, seed=904)
+    (u, v, w), c = dev_grid(g)
+    add = [torch.randn((7, 9, 300), device="cuda") for _ in range(3)]
+    base = B.advect_epilogue(u, v, w, c, add, alpha=0.5, tile=(1, 2, 4, 4, 1))
+    for t in [(4, 2, 7, 1, 2), (2, 4, 64, 2, 1), (4, 1, 1, 8, 2)]:
+        got = B.advect_epilogue(u, v, w, c, add, alpha=0.5, tile=t)
+        for a, b in zip(base, got):
+            assert torch.equal(a, b), t
+
+
+def test_epilogue_argument_errors():
+    g = wl.make_grid(20, 8, 4, seed=905)
+    (u, v, w), c = dev_grid(g)
+    out = [torch.zeros((4, 8, 20), device="cuda") for _ in range(3)]
+    with pytest.raises(B.PWError):   # an addend that is another output
+        B.advect_epilogue(u, v, w, c, [out[1], out[1], out[2]], out=out)
+    with pytest.raises(B.PWError):
+        B.advect_epilogue(u, v, w, c, out, alpha=float("nan"), out=out)

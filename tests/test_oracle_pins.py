@@ -286,3 +286,85 @@ def test_coeff_grad_euler_identity():
                                                          for n in ("tzc1", "tzc2", "tzd1", "tzd2"))
     loss = _dot(oracle.forward(g.u, g.v, g.w, g.coeffs), r)
     assert abs(total - loss) <= 1e-12 * abs(loss)
+
+
+# ---------------------------------------------------------------- halo fill
+
+def test_halo_fill_matches_numpy_pad():
+    """Periodic, copy and zero fills equal numpy's pad of the interior with
+    wrap, edge and constant modes (an independent implementation of the same
+    boundary rules), for halos 1 and 2, per axis and mixed."""
+    from oracle import halo as H
+    rng = np.random.default_rng(32)
+    np_mode = dict(periodic="wrap", copy="edge", zero="constant", reflect="symmetric")
+    for h in (1, 2):
+        interior = rng.uniform(-1, 1, (3, 4, 5))
+        a = rng.uniform(-1, 1, tuple(s + 2 * h for s in interior.shape))
+        a[h:-h, h:-h, h:-h] = interior
+        for modes in [("periodic",) * 3, ("copy",) * 3, ("zero",) * 3, ("reflect",) * 3,
+                      ("periodic", "periodic", "copy"), ("copy", "zero", "periodic"),
+                      ("periodic", "reflect", "zero")]:
+            ref = interior
+            for ax, m in ((2, modes[0]), (1, modes[1]), (0, modes[2])):
+                pw = [(0, 0)] * 3
+                pw[ax] = (h, h)
+                ref = np.pad(ref, pw, mode=np_mode[m])
+            got = H.fill(a, h, modes)
+            assert np.array_equal(got, ref), (h, modes)
+
+
+def test_halo_fill_reflect_neg_vanishes_on_the_face():
+    """reflect_neg makes the mean of each mirrored pair zero: the linear
+    interpolant of the field vanishes on the boundary face, for every
+    halo depth (brute force over the pairs); on the other axes the cells
+    equal numpy's symmetric pad."""
+    from oracle import halo as H
+    rng = np.random.default_rng(35)
+    for h in (1, 2, 3):
+        a = rng.uniform(-1, 1, (4 + 2 * h, 3 + 2 * h, 5 + 2 * h))
+        got = H.fill(a, h, ("periodic", "periodic", "reflect_neg"))
+        nz = 4
+        for q in range(h):
+            assert np.array_equal(got[h - 1 - q], -got[h + q])
+            assert np.array_equal(got[nz + h + q], -got[nz + h - 1 - q])
+        sym = H.fill(a, h, ("periodic", "periodic", "reflect"))
+        assert np.array_equal(got[h:-h], sym[h:-h])
+        assert np.array_equal(got[:h], -sym[:h]) and np.array_equal(got[-h:], -sym[-h:])
+    with pytest.raises(ValueError):
+        H.fill(np.zeros((7, 7, 5)), 2, ("reflect", "keep", "keep"))
+
+
+def test_halo_fill_keep_and_wide_periodic():
+    """keep leaves an axis' halo alone; a halo wider than the interior wraps
+    more than once (brute-force index arithmetic)."""
+    from oracle import halo as H
+    rng = np.random.default_rng(33)
+    a = rng.uniform(-1, 1, (5, 6, 7))       # h = 2: interior 1 x 2 x 3
+    got = H.fill(a, 2, ("periodic", "keep", "keep"))
+    assert np.array_equal(got[:, :, 2:5], a[:, :, 2:5])
+    for i in (0, 1, 5, 6):
+        assert np.array_equal(got[:, :, i], a[:, :, 2 + (i - 2) % 3])
+    b = rng.uniform(-1, 1, (1 + 6, 1 + 6, 1 + 6))   # h = 3, n = 1: every halo cell is the one interior cell
+    g2 = H.fill(b, 3, ("periodic",) * 3)
+    assert np.all(g2 == b[3, 3, 3])
+
+
+def test_periodic_fill_conserves_energy():
+    """With halos filled periodically by the halo oracle, the forward
+    operator conserves sum(u su) + ... exactly on integer winds with the
+    cyclic coefficient pairing -- the same property the padded-by-numpy grids
+    show, so the fill reproduces a periodic domain."""
+    from oracle import halo as H
+    rng = np.random.default_rng(34)
+    nz, ny, nx = 4, 5, 6
+    ui, vi, wi = (rng.integers(-4, 5, (nz, ny, nx)).astype(np.float64) for _ in range(3))
+    pads = []
+    for x in (ui, vi, wi):
+        a = rng.uniform(-9, 9, (nz + 2, ny + 2, nx + 2))
+        a[1:-1, 1:-1, 1:-1] = x
+        pads.append(H.fill(a, 1, ("periodic",) * 3))
+    tzc2 = rng.choice([0.5, 0.25, 0.125], nz)
+    tzd2 = rng.choice([0.5, 0.25, 0.125], nz)
+    c = dict(tcx=0.25, tcy=0.125, tzc1=np.roll(tzc2, 1), tzc2=tzc2, tzd1=np.roll(tzd2, 1), tzd2=tzd2)
+    su, sv, sw = oracle.forward(*pads, c)
+    assert np.sum(ui * su) + np.sum(vi * sv) + np.sum(wi * sw) == 0

@@ -161,6 +161,42 @@ def prebuilt_epilogue(B, ins, outs, coeffs, alpha, stream):
     return call
 
 
+def prebuilt_halo(B, fields, modes, stream):
+    """ctypes arguments of one pw_halo_fill call over ``fields``, built once."""
+    from paper_2301_13016_amd.binding import _dtype_code, _grid_from
+    u = fields[0]
+    g = _grid_from(u, 1)
+    keep = (g, B.pw_layout(u.stride(1), u.stride(0), g.nx, g.nx * g.ny),
+            (ctypes.c_void_p * len(fields))(*(f.data_ptr() for f in fields)),
+            (B.pw_halo_modes * len(fields))(*(B.pw_halo_modes(*m) for m in modes)))
+    args = (ctypes.byref(keep[0]), ctypes.byref(keep[1]), _dtype_code(u), keep[2], keep[3], len(fields),
+            ctypes.c_void_p(stream.cuda_stream))
+    fn = B.lib().pw_halo_fill
+
+    def call():
+        st = fn(*args)
+        if st != B.PW_OK:
+            raise B.PWError(st, B.pw_last_error(), "pw_halo_fill")
+    call.keep = keep
+    return call
+
+
+B_HALO_ZERO = 3   # PW_HALO_ZERO
+
+
+def halo_bytes(nx, ny, nz, h, es, modes):
+    """Algorithmic bytes of one halo fill: every written cell once, and its
+    source once unless the cell is zeroed."""
+    px, py = nx + 2 * h, ny + 2 * h
+    total = 0
+    for mx, my, mz in modes:
+        zc = 2 * h * py * px
+        cells = zc + nz * 2 * h * px + nz * ny * 2 * h
+        zero = zc if mz == B_HALO_ZERO else 0
+        total += (2 * cells - zero) * es
+    return total
+
+
 def prebuilt_tangent(B, ins, dirs, outs, coeffs, stream):
     """ctypes arguments of one pw_advect_tangent_ex call, built once."""
     from paper_2301_13016_amd.binding import _dtype_code, _grid_from, _layout_from
@@ -298,6 +334,16 @@ def main():
         kernel_ms=round(acc_ms, 4), over_plain=round(acc_ms / k_ms, 3),
         ideal_ratio_from_bytes=round(nbytes_acc / nbytes, 3), hbm_gbs=round(nbytes_acc / (acc_ms * 1e-3) / 1e9, 1))
     log("c1 fused accumulate (out += F): %.4f ms, %.3f x the plain step" % (acc_ms, acc_ms / k_ms))
+    # the step before: halo fill of u, v, w (periodic x, y; free-slip lid:
+    # u, v zero-gradient, w zero), on the same buffers
+    hmodes = [(1, 1, 2), (1, 1, 2), (1, 1, B_HALO_ZERO)]
+    halo_calls = [prebuilt_halo(B, kp[0], hmodes, stream) for kp in keep]
+    _, halo_ms = time_launches(torch, lambda i: halo_calls[i](), nsets, 200, 20, stream)
+    del halo_calls
+    hb = halo_bytes(nx, ny, nz, h, 4, hmodes)
+    forms["halo_fill_512x512x64"] = dict(kernel_ms=round(halo_ms, 4), over_plain=round(halo_ms / k_ms, 3),
+                                         bytes=hb, hbm_gbs=round(hb / (halo_ms * 1e-3) / 1e9, 1))
+    log("c1 halo fill (u, v, w): %.4f ms, %.3f x the plain step" % (halo_ms, halo_ms / k_ms))
     del keep, calls, sets3
     torch.cuda.empty_cache()
 

@@ -324,6 +324,50 @@ pw_status pw_batch_info(const pw_batch *batch, pw_tile *tile, int64_t *work_item
 /* Frees the batch (device work list, counter, graph).  NULL is a no-op. */
 pw_status pw_batch_destroy(pw_batch *batch);
 
+/* ------------------------------------------------------------- halo fill
+ * The step before the stencil: fill the halo of padded arrays from their
+ * interiors.  The stencil (Sec. 2.2) reads one layer of neighbours, which a
+ * model provides by a periodic or neighbour exchange in the horizontal and a
+ * boundary condition at the surface and lid (Sec. 2.1 places the scheme in
+ * such a model; the paper fixes no rule, these are the library's).
+ *
+ * Per axis, with n interior cells and halo width h, halo cell p (padded
+ * index, p < h or p >= n+h) becomes:
+ *   PW_HALO_KEEP         untouched
+ *   PW_HALO_PERIODIC     interior cell h + ((p - h) mod n)
+ *   PW_HALO_COPY         nearest interior cell (zero normal gradient)
+ *   PW_HALO_ZERO         0 (+0.0)
+ *   PW_HALO_REFLECT      the mirror image across the boundary face,
+ *                        2h-1-p below and 2(n+h)-1-p above; needs n >= h
+ *   PW_HALO_REFLECT_NEG  minus that mirror image (exact sign flip), so the
+ *                        field's linear interpolant vanishes on the face
+ * The result equals filling x first (all rows and planes), then y (whole
+ * rows, x-halo included), then z (whole planes), so edges and corners take
+ * the value of a sequential exchange.  E.g. a free-slip rigid lid: u, v with
+ * z = COPY and w with z = ZERO; a no-slip wall: u, v with z = REFLECT_NEG.
+ *
+ * fields[f] (f < nfields, 1 <= nfields <= 8) are distinct padded arrays of
+ * `dtype` on the current device, in the input layout of `layout` (in_sy,
+ * in_sz; out_* ignored; NULL = dense), updated in place on `hip_stream`;
+ * modes[f] gives field f's x, y, z rules.  Interior cells are never written
+ * and are the only cells read (on KEEP axes, the cell's own line), so the
+ * fill is one kernel with no ordering between its writes.  Errors
+ * (PW_ERR_INVALID_ARG): NULL or misaligned fields, overlapping fields, an
+ * unknown mode, REFLECT with n < h, nfields out of range. */
+typedef enum {
+    PW_HALO_KEEP = 0,
+    PW_HALO_PERIODIC = 1,
+    PW_HALO_COPY = 2,
+    PW_HALO_ZERO = 3,
+    PW_HALO_REFLECT = 4,
+    PW_HALO_REFLECT_NEG = 5
+} pw_halo_mode;
+typedef struct {
+    int32_t x, y, z; /* pw_halo_mode per axis */
+} pw_halo_modes;
+pw_status pw_halo_fill(const pw_grid *grid, const pw_layout *layout, pw_dtype dtype, void *const fields[],
+                       const pw_halo_modes modes[], int32_t nfields, void *hip_stream);
+
 /* Library version string (static storage). */
 const char *pw_version(void);
 

@@ -68,6 +68,13 @@ class pw_epilogue(ctypes.Structure):
     _fields_ = [("alpha", ctypes.c_double), ("cu", ctypes.c_void_p), ("cv", ctypes.c_void_p), ("cw", ctypes.c_void_p)]
 
 
+class pw_halo_modes(ctypes.Structure):
+    _fields_ = [("x", ctypes.c_int32), ("y", ctypes.c_int32), ("z", ctypes.c_int32)]
+
+
+HALO_MODES = {"keep": 0, "periodic": 1, "copy": 2, "zero": 3, "reflect": 4, "reflect_neg": 5}
+
+
 class pw_batch_item(ctypes.Structure):
     _fields_ = [("grid", pw_grid), ("layout", pw_layout), ("u", ctypes.c_void_p), ("v", ctypes.c_void_p),
                 ("w", ctypes.c_void_p), ("coeffs", pw_coeffs), ("su", ctypes.c_void_p), ("sv", ctypes.c_void_p),
@@ -99,6 +106,8 @@ _SIGNATURES = {
     "pw_advect_coeff_grad_workspace": [ctypes.POINTER(pw_grid), ctypes.c_int, ctypes.POINTER(ctypes.c_int64)],
     "pw_advect_coeff_grad": [ctypes.POINTER(pw_grid), ctypes.POINTER(pw_layout), ctypes.c_int,
                              _P, _P, _P, _P, _P, _P, _P, _P, ctypes.c_int64, _P],
+    "pw_halo_fill": [ctypes.POINTER(pw_grid), ctypes.POINTER(pw_layout), ctypes.c_int, ctypes.POINTER(_P),
+                     ctypes.POINTER(pw_halo_modes), ctypes.c_int32, _P],
     "pw_stream_copy": [_P, _P, ctypes.c_int64, _P],
     "pw_stream_copy3": [ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.c_int64, _P],
     "pw_tune": [ctypes.POINTER(pw_grid), ctypes.c_int, ctypes.c_int32, ctypes.POINTER(pw_tile),
@@ -194,6 +203,14 @@ def pw_advect_tangent_ex(grid, layout, dtype, u, v, w, coeffs, du, dv, dw, tu, t
     return lib().pw_advect_tangent_ex(ctypes.byref(grid), ctypes.byref(layout) if layout is not None else None,
                                       int(dtype), u, v, w, ctypes.byref(coeffs), du, dv, dw, tu, tv, tw,
                                       ctypes.byref(tile) if tile is not None else None, stream)
+
+
+def pw_halo_fill(grid, layout, dtype, fields, modes, stream=None):
+    """fields: device addresses; modes: (x, y, z) mode codes per field."""
+    n = len(fields)
+    f = (_P * max(n, 1))(*fields)
+    m = (pw_halo_modes * max(n, 1))(*[pw_halo_modes(*mm) for mm in modes])
+    return lib().pw_halo_fill(grid, layout, dtype, f, m, n, stream)
 
 
 def pw_stream_copy(src, dst, nbytes, stream=None):
@@ -481,6 +498,39 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def _halo_code(m):
+    if isinstance(m, str):
+        if m not in HALO_MODES:
+            raise ValueError("unknown halo mode %r (one of %s)" % (m, ", ".join(HALO_MODES)))
+        return HALO_MODES[m]
+    return int(m)
+
+
+def halo_fill(fields, modes, halo=1, stream=None):
+    """Fill the halo of padded tensors in place (same shape, strides and dtype,
+    on the GPU).  ``modes`` is one (x, y, z) triple for every field or a list
+    of triples, one per field; each entry is a name from HALO_MODES or its
+    code.  Returns ``fields``."""
+    fields = list(fields)
+    if not fields:
+        return fields
+    u = fields[0]
+    if any(f.shape != u.shape or f.stride() != u.stride() or f.dtype != u.dtype for f in fields):
+        raise ValueError("fields must share shape, strides and dtype")
+    if len(modes) == 3 and all(isinstance(m, (str, int)) for m in modes):
+        modes = [modes] * len(fields)
+    if len(modes) != len(fields):
+        raise ValueError("one (x, y, z) mode triple per field")
+    codes = [tuple(_halo_code(m) for m in mm) for mm in modes]
+    grid = _grid_from(u, halo)
+    if u.stride(-1) != 1:
+        raise ValueError("x (last) dimension must be contiguous")
+    layout = pw_layout(u.stride(1), u.stride(0), grid.nx, grid.nx * grid.ny)
+    _check(pw_halo_fill(grid, layout, _dtype_code(u), [f.data_ptr() for f in fields], codes,
+                        _stream_handle(stream)), "pw_halo_fill")
+    return fields
 
 
 def stream_copy(src, dst, stream=None):

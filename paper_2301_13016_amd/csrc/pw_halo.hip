@@ -1,0 +1,150 @@
+// Halo fill of padded arrays: the step before the stencil, which reads one
+// layer of neighbours around the interior (Sec. 2.2).  The per-axis rules are
+// documented with pw_halo_fill in pwadv.h.
+//
+// Every written cell lies in the halo of some axis whose rule is not KEEP,
+// and its source lies in the interior of every such axis, so no cell is both
+// read and written: one kernel fills all three axes with no ordering between
+// its writes, and the result equals the sequential x, y, z fill.  The work of
+// one field is three segments: the z-halo planes (whole planes), the y-halo
+// rows of the remaining planes (whole rows) and the x-halo cells of the
+// remaining rows.  Values move as raw bits (2, 4 or 8 bytes); a negated
+// mirror flips the sign bit, which is exact negation.
+#include <algorithm>
+
+#include "pw_internal.h"
+
+namespace pw {
+namespace {
+
+struct HaloSeg {
+    int64_t nzs, nys, nxs;  // work items of the three segments
+    int64_t k0, kn;         // planes covered by the y and x segments
+    int64_t j0, jn;         // rows covered by the x segment
+    int32_t mode[3];        // x, y, z
+};
+
+struct HaloK {
+    void *f[kMaxHaloFields];
+    HaloSeg seg[kMaxHaloFields];
+    int64_t nx, ny, nz, sy, sz;
+    int32_t h;
+};
+
+// Source coordinate of padded coordinate p on an axis of n interior cells;
+// `sign` becomes 0 for a zeroed cell and flips for a negated mirror.
+__device__ inline int64_t source(int64_t p, int64_t n, int64_t h, int mode, int &sign) {
+    if (p >= h && p < n + h) return p;
+    switch (mode) {
+        case PW_HALO_PERIODIC: {
+            int64_t q = (p - h) % n;
+            return h + (q < 0 ? q + n : q);
+        }
+        case PW_HALO_COPY: return p < h ? h : n + h - 1;
+        case PW_HALO_ZERO: sign = 0; return p;
+        case PW_HALO_REFLECT_NEG: sign = -sign; [[fallthrough]];
+        case PW_HALO_REFLECT: return p < h ? 2 * h - 1 - p : 2 * (n + h) - 1 - p;
+        default: return p;  // KEEP
+    }
+}
+
+// I: index type of the work decomposition (32-bit when every count fits, to
+// keep the divisions cheap).  Grid: x strides over a field's work, y = field.
+template <typename U, typename I>
+__global__ __launch_bounds__(256) void halo_kernel(HaloK a) {
+    const int f = blockIdx.y;
+    U *const base = static_cast<U *>(a.f[f]);
+    const HaloSeg &s = a.seg[f];
+    const I h = I(a.h), h2 = I(2 * a.h);
+    const I px = I(a.nx + 2 * a.h), py = I(a.ny + 2 * a.h);
+    const I nzs = I(s.nzs), nzys = I(s.nzs + s.nys), total = I(s.nzs + s.nys + s.nxs);
+    const I jn = I(s.jn);
+    const U signbit = U(1) << (8 * sizeof(U) - 1);
+    const I stride = I(gridDim.x) * I(blockDim.x);
+    for (I t = I(blockIdx.x) * I(blockDim.x) + I(threadIdx.x); t < total; t += stride) {
+        int64_t k, j, i;
+        if (t < nzs) {
+            const I r = t / px, q = r / py;
+            i = t - r * px;
+            j = r - q * py;
+            k = q < h ? q : a.nz + q;
+        } else if (t < nzys) {
+            const I u = t - nzs, r = u / px, c = r / h2, q = r - c * h2;
+            i = u - r * px;
+            k = s.k0 + c;
+            j = q < h ? q : a.ny + q;
+        } else {
+            const I u = t - nzys, r = u / h2, c = r / jn, q = u - r * h2;
+            j = s.j0 + (r - c * jn);
+            k = s.k0 + c;
+            i = q < h ? q : a.nx + q;
+        }
+        int sign = 1;
+        const int64_t si = source(i, a.nx, a.h, s.mode[0], sign);
+        const int64_t sj = source(j, a.ny, a.h, s.mode[1], sign);
+        const int64_t sk = source(k, a.nz, a.h, s.mode[2], sign);
+        U val = 0;
+        if (sign != 0) {
+            val = base[sk * a.sz + sj * a.sy + si];
+            if (sign < 0) val ^= signbit;
+        }
+        base[k * a.sz + j * a.sy + i] = val;
+    }
+}
+
+template <typename U>
+hipError_t launch_u(const HaloK &k, int nf, int64_t most, bool small, hipStream_t s) {
+    const int64_t blocks = std::min<int64_t>((most + 255) / 256, 2048);
+    const dim3 grid(unsigned(std::max<int64_t>(blocks, 1)), unsigned(nf));
+    if (small)
+        hipLaunchKernelGGL((halo_kernel<U, uint32_t>), grid, dim3(256), 0, s, k);
+    else
+        hipLaunchKernelGGL((halo_kernel<U, uint64_t>), grid, dim3(256), 0, s, k);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+pw_status launch_halo(const HaloArgs &a, hipStream_t s) {
+    HaloK k{};
+    k.nx = a.nx;
+    k.ny = a.ny;
+    k.nz = a.nz;
+    k.sy = a.sy;
+    k.sz = a.sz;
+    k.h = a.h;
+    const int64_t h = a.h, px = a.nx + 2 * h, py = a.ny + 2 * h, pz = a.nz + 2 * h;
+    int64_t most = 0;
+    int nf = 0;
+    for (int f = 0; f < a.nf; ++f) {
+        const int32_t *m = a.mode[f];
+        if (m[0] == PW_HALO_KEEP && m[1] == PW_HALO_KEEP && m[2] == PW_HALO_KEEP) continue;
+        HaloSeg g{};
+        const bool fz = m[2] != PW_HALO_KEEP, fy = m[1] != PW_HALO_KEEP, fx = m[0] != PW_HALO_KEEP;
+        g.k0 = fz ? h : 0;
+        g.kn = fz ? a.nz : pz;
+        g.j0 = fy ? h : 0;
+        g.jn = fy ? a.ny : py;
+        g.nzs = fz ? 2 * h * py * px : 0;
+        g.nys = fy ? g.kn * 2 * h * px : 0;
+        g.nxs = fx ? g.kn * g.jn * 2 * h : 0;
+        for (int d = 0; d < 3; ++d) g.mode[d] = m[d];
+        k.f[nf] = a.f[f];
+        k.seg[nf] = g;
+        most = std::max(most, g.nzs + g.nys + g.nxs);
+        ++nf;
+    }
+    if (nf == 0) return PW_OK;
+    // 32-bit decomposition when every count and the loop's last increment fit
+    const bool small = most + 2048 * 256 < (int64_t(1) << 32) && px * py < (int64_t(1) << 32);
+    hipError_t e = hipSuccess;
+    switch (a.es) {
+        case 2: e = launch_u<uint16_t>(k, nf, most, small, s); break;
+        case 4: e = launch_u<uint32_t>(k, nf, most, small, s); break;
+        case 8: e = launch_u<uint64_t>(k, nf, most, small, s); break;
+        default: return fail(PW_ERR_INVALID_ARG, "element size %d", a.es);
+    }
+    return hip_fail(e, "halo_kernel launch");
+}
+
+}  // namespace pw

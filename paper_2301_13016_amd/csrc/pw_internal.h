@@ -72,6 +72,19 @@ struct CgArgs {
     int64_t in_sy, in_sz, out_sy, out_sz;
 };
 
+// Operands of one halo fill (validated): up to kMaxHaloFields distinct
+// padded arrays of element size es sharing one layout, with per-field x, y, z
+// rules (pw_halo_mode).
+constexpr int kMaxHaloFields = 8;
+struct HaloArgs {
+    void *f[kMaxHaloFields];
+    int32_t mode[kMaxHaloFields][3];
+    int32_t nf, es;
+    int64_t nx, ny, nz;
+    int32_t h;
+    int64_t sy, sz;
+};
+
 // Columns of gradient produced by one adjoint wavefront: 64 lanes load 64
 // consecutive padded columns and the 62 inner lanes own an output each.
 constexpr int kWaveCols = 62;
@@ -93,6 +106,7 @@ pw_status launch_adjoint(const AdjArgs &a, pw_dtype dt, const TileCfg &cfg, hipS
 pw_status launch_tangent(const TanArgs &a, pw_dtype dt, const TileCfg &cfg, hipStream_t s);
 int64_t coeff_grad_workspace_bytes(const pw_grid &g, pw_dtype dt);
 pw_status launch_coeff_grad(const CgArgs &a, pw_dtype dt, hipStream_t s);
+pw_status launch_halo(const HaloArgs &a, hipStream_t s);
 pw_status launch_copy(const void *src, void *dst, int64_t nbytes, hipStream_t s);
 pw_status launch_copy3(const void *const *src, void *const *dst, int64_t nbytes, hipStream_t s);
 

@@ -448,3 +448,30 @@ def test_tune_argument_errors(lib):
     assert B.pw_tune(g, B.PW_F32, flags=8) == B.PW_ERR_INVALID_ARG
     assert B.pw_tune(g, B.PW_F32) in (B.PW_ERR_NO_DEVICE, B.PW_OK)   # OK where a GPU is present
     assert B.pw_tune_reset() == B.PW_OK
+
+
+def test_halo_fill_validation(lib):
+    g = B.pw_grid(8, 8, 8, 1)
+    f = [A + i * MB for i in range(3)]
+    per = [(1, 1, 2), (1, 1, 2), (1, 1, 3)]
+    assert B.pw_halo_fill(g, None, B.PW_F32, f, per) in _no_gpu_status()
+    assert B.pw_halo_fill(g, None, B.PW_F32, f, [(0, 0, 0)] * 3) in _no_gpu_status()
+    assert B.pw_halo_fill(g, None, B.PW_F32, [], []) == B.PW_ERR_INVALID_ARG
+    assert B.pw_halo_fill(g, None, B.PW_F32, [A + i * MB for i in range(9)], [(1, 1, 1)] * 9) == B.PW_ERR_INVALID_ARG
+    assert B.pw_halo_fill(g, None, B.PW_F32, f, [(1, 1, 6)] * 3) == B.PW_ERR_INVALID_ARG
+    assert "mode" in B.pw_last_error()
+    assert B.pw_halo_fill(g, None, B.PW_F32, f, [(1, 1, -1)] * 3) == B.PW_ERR_INVALID_ARG
+    assert B.pw_halo_fill(g, None, B.PW_F32, [f[0], 0, f[2]], per) == B.PW_ERR_INVALID_ARG
+    assert B.pw_halo_fill(g, None, B.PW_F32, [f[0], f[1] + 2, f[2]], per) == B.PW_ERR_INVALID_ARG  # misaligned
+    assert B.pw_halo_fill(g, None, B.PW_F32, [f[0], f[0] + 3996, f[2]], per) == B.PW_ERR_INVALID_ARG
+    assert "overlap" in B.pw_last_error()
+    assert B.pw_halo_fill(g, None, 9, f, per) == B.PW_ERR_INVALID_ARG
+    # reflect needs n >= h on that axis; periodic, copy and zero do not
+    g2 = B.pw_grid(8, 8, 2, 3)
+    assert B.pw_halo_fill(g2, None, B.PW_F32, f, [(1, 1, 4)] * 3) == B.PW_ERR_INVALID_ARG
+    assert "reflect" in B.pw_last_error()
+    assert B.pw_halo_fill(g2, None, B.PW_F32, f, [(4, 5, 1)] * 3) in _no_gpu_status()
+    # input strides: in_sy < nx + 2h is rejected; the output strides are ignored
+    assert B.pw_halo_fill(g, B.pw_layout(9, 100, 0, 0), B.PW_F32, f, per) == B.PW_ERR_INVALID_ARG
+    assert B.pw_halo_fill(g, B.pw_layout(16, 160, 0, 0), B.PW_F32, f, per) in _no_gpu_status()
+    assert lib.pw_halo_fill(ctypes.byref(g), None, B.PW_F32, None, None, 1, None) == B.PW_ERR_INVALID_ARG

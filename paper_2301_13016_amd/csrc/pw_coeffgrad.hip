@@ -257,14 +257,16 @@ __global__ __launch_bounds__(256) void pw_coeffgrad_reduce_kernel(const double *
     if (threadIdx.x == 0) out[blockIdx.x] = part[0];
 }
 
-// Pass 3: out[6*nz + 0/1] = sum over levels of the tcx / tcy level shares.
-__global__ __launch_bounds__(64) void pw_coeffgrad_total_kernel(double *__restrict__ out, int nz) {
-    const int q = threadIdx.x;   // 0: tcx, 1: tcy
-    if (q < 2) {
-        double s = 0.0;
-        for (int k = 0; k < nz; ++k) s += out[(4 + q) * nz + k];
-        out[6 * nz + q] = s;
-    }
+// Pass 3: out[6*nz + q] = sum over levels of the tcx (q = 0) / tcy (q = 1)
+// level shares; wavefront q adds lane-strided levels, then a butterfly (a
+// fixed order).
+__global__ __launch_bounds__(128) void pw_coeffgrad_total_kernel(double *__restrict__ out, int nz) {
+    const int q = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const double *lv = out + (4 + q) * nz;
+    double s = 0.0;
+    for (int k = lane; k < nz; k += 64) s += lv[k];
+    s = wave_sum(s);
+    if (lane == 0) out[6 * nz + q] = s;
 }
 
 template <typename T> CgK<T> make_args(const CgArgs &g, int64_t *nstrips_out, int64_t *nblocks_out) {
@@ -319,7 +321,7 @@ template <typename T> pw_status launch_cg_t(const CgArgs &g, hipStream_t s) {
                        static_cast<const double *>(g.workspace), nstrips, static_cast<double *>(g.grad));
     st = hip_fail(hipGetLastError(), "coefficient gradient reduction launch");
     if (st != PW_OK) return st;
-    hipLaunchKernelGGL(pw_coeffgrad_total_kernel, dim3(1), dim3(64), 0, s, static_cast<double *>(g.grad),
+    hipLaunchKernelGGL(pw_coeffgrad_total_kernel, dim3(1), dim3(128), 0, s, static_cast<double *>(g.grad),
                        static_cast<int>(g.nz));
     return hip_fail(hipGetLastError(), "coefficient gradient total launch");
 }

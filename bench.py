@@ -161,6 +161,26 @@ def prebuilt_epilogue(B, ins, outs, coeffs, alpha, stream):
     return call
 
 
+def prebuilt_zfast(B, ins, outs, coeffs, stream):
+    """ctypes arguments of one pw_advect_zfast call (arrays stored z-fastest,
+    indexed [i, j, k]), built once."""
+    from paper_2301_13016_amd.binding import _dtype_code
+    u, v, w = ins
+    pi, pj, pk = u.shape
+    keep = (B.pw_grid(pi - 2, pj - 2, pk - 2, 1),
+            B.pw_layout_zfast(u.stride(1), u.stride(0), outs[0].stride(1), outs[0].stride(0)), coeffs.c_struct())
+    args = (ctypes.byref(keep[0]), ctypes.byref(keep[1]), _dtype_code(u), u.data_ptr(), v.data_ptr(), w.data_ptr(),
+            ctypes.byref(keep[2]), *(o.data_ptr() for o in outs), None, ctypes.c_void_p(stream.cuda_stream))
+    fn = B.lib().pw_advect_zfast
+
+    def call():
+        st = fn(*args)
+        if st != B.PW_OK:
+            raise B.PWError(st, B.pw_last_error(), "pw_advect_zfast")
+    call.keep = keep
+    return call
+
+
 def prebuilt_halo(B, fields, modes, stream):
     """ctypes arguments of one pw_halo_fill call over ``fields``, built once."""
     from paper_2301_13016_amd.binding import _dtype_code, _grid_from
@@ -344,6 +364,17 @@ def main():
     forms["halo_fill_512x512x64"] = dict(kernel_ms=round(halo_ms, 4), over_plain=round(halo_ms / k_ms, 3),
                                          bytes=hb, hbm_gbs=round(hb / (halo_ms * 1e-3) / 1e9, 1))
     log("c1 halo fill (u, v, w): %.4f ms, %.3f x the plain step" % (halo_ms, halo_ms / k_ms))
+    # the same grid stored z-fastest (column-major, [i, j, k])
+    zsets = [(tuple(x.permute(2, 1, 0).contiguous() for x in kp[0]),
+              tuple(torch.empty((nx, ny, nz), device=dev) for _ in range(3))) for kp in keep]
+    zf_calls = [prebuilt_zfast(B, zi, zo, coeffs, stream) for zi, zo in zsets]
+    _, zf_ms = time_launches(torch, lambda i: zf_calls[i](), nsets, 200, 20, stream)
+    zshape = B.launch_shape("zfast", nx, ny, nz, torch.float32)
+    del zf_calls, zsets
+    forms["zfast_512x512x64"] = dict(kernel_ms=round(zf_ms, 4), over_xfast=round(zf_ms / k_ms, 3),
+                                     gpts=round(pts / (zf_ms * 1e-3) / 1e9, 2),
+                                     hbm_gbs=round(nbytes / (zf_ms * 1e-3) / 1e9, 1), tile=list(zshape))
+    log("c1 z-fastest layout: %.4f ms, %.3f x the x-fastest step (tile %s)" % (zf_ms, zf_ms / k_ms, zshape))
     del keep, calls, sets3
     torch.cuda.empty_cache()
 

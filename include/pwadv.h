@@ -238,9 +238,10 @@ pw_status pw_advect_coeff_grad(const pw_grid *grid, const pw_layout *layout, pw_
                                void *hip_stream);
 
 /* Autotuner for single-grid launches.  Times candidate launch shapes of the
- * forward kernel (flags & PW_TUNE_FORWARD) and, for PW_F32 / PW_F64, of the
- * adjoint (flags & PW_TUNE_ADJOINT) and tangent (flags & PW_TUNE_TANGENT)
- * kernels; flags == 0 means all three.  The candidates run on scratch grids
+ * forward kernel (flags & PW_TUNE_FORWARD), the z-fastest forward kernel
+ * (flags & PW_TUNE_ZFAST) and, for PW_F32 / PW_F64, of the adjoint
+ * (flags & PW_TUNE_ADJOINT) and tangent (flags & PW_TUNE_TANGENT) kernels;
+ * flags == 0 means forward, adjoint and tangent.  The candidates run on scratch grids
  * of this extent (allocated and freed here, contents zero), rotating over as
  * many copies as span about 1 GiB so that repeats are not served by the
  * MALL.  The fastest shape per shape class -- kernel, dtype and the
@@ -257,13 +258,14 @@ pw_status pw_advect_coeff_grad(const pw_grid *grid, const pw_layout *layout, pw_
 #define PW_TUNE_FORWARD 1
 #define PW_TUNE_ADJOINT 2
 #define PW_TUNE_TANGENT 4
+#define PW_TUNE_ZFAST 8
 pw_status pw_tune(const pw_grid *grid, pw_dtype dtype, int32_t flags, pw_tile *fwd_best, pw_tile *adj_best);
 
 /* The launch shape a kernel takes for this grid and dtype when called with
  * tile == NULL: the tuned entry of its shape class if there is one, else the
  * library's default.  No device work.  PW_ERR_UNSUPPORTED for an adjoint or
  * tangent of a 16-bit dtype. */
-typedef enum { PW_KERNEL_FORWARD = 0, PW_KERNEL_ADJOINT = 1, PW_KERNEL_TANGENT = 2 } pw_kernel;
+typedef enum { PW_KERNEL_FORWARD = 0, PW_KERNEL_ADJOINT = 1, PW_KERNEL_TANGENT = 2, PW_KERNEL_ZFAST = 3 } pw_kernel;
 pw_status pw_launch_shape(pw_kernel kind, const pw_grid *grid, pw_dtype dtype, pw_tile *out);
 
 /* Empties the process-wide tuning table, built-in entries included (the
@@ -323,6 +325,30 @@ pw_status pw_batch_info(const pw_batch *batch, pw_tile *tile, int64_t *work_item
 
 /* Frees the batch (device work list, counter, graph).  NULL is a no-op. */
 pw_status pw_batch_destroy(pw_batch *batch);
+
+/* ------------------------------------------------------- z-fastest layout
+ * The forward operator (the same equations and, per point, the same
+ * arithmetic as pw_advect, so the results are bit-identical) on arrays stored
+ * with z contiguous -- column-major, the way a model keeps its columns
+ * (Sec. 2.1 names the host model; its Fortran arrays are indexed (k, j, i)):
+ *   input   (k, j, i), padded indices, at  i*in_si  + j*in_sj  + k
+ *   output  (kk, jj, ii), interior indices, at  ii*out_si + jj*out_sj + kk
+ * Strides in elements; layout NULL means dense (in_sj = nz+2h,
+ * in_si = (ny+2h)*in_sj, out_sj = nz, out_si = ny*nz).  in_sj >= nz+2h,
+ * in_si >= (ny+2h)*in_sj, out_sj >= nz, out_si >= ny*out_sj, and one x-plane
+ * (in_si, out_si elements) below 2 GiB.  dtype, coefficients, ownership,
+ * streams and errors as for pw_advect_ex.  The tile's fields mean: levels per
+ * lane (1, 2, or 4 except PW_F64), y-rows per strip (1, 2; 4 with at most 2
+ * levels per lane; 8 with 1), x-columns per work item (zlen),
+ * waves_per_group 1..8, prefetch 1 or 2 x-planes.  tile NULL: the tuned
+ * shape (PW_KERNEL_ZFAST) or the default. */
+typedef struct {
+    int64_t in_sj, in_si;
+    int64_t out_sj, out_si;
+} pw_layout_zfast;
+pw_status pw_advect_zfast(const pw_grid *grid, const pw_layout_zfast *layout, pw_dtype in_dtype,
+                          const void *u, const void *v, const void *w, const pw_coeffs *coeffs,
+                          void *su, void *sv, void *sw, const pw_tile *tile, void *hip_stream);
 
 /* ------------------------------------------------------------- halo fill
  * The step before the stencil: fill the halo of padded arrays from their

@@ -68,6 +68,11 @@ class pw_epilogue(ctypes.Structure):
     _fields_ = [("alpha", ctypes.c_double), ("cu", ctypes.c_void_p), ("cv", ctypes.c_void_p), ("cw", ctypes.c_void_p)]
 
 
+class pw_layout_zfast(ctypes.Structure):
+    _fields_ = [("in_sj", ctypes.c_int64), ("in_si", ctypes.c_int64),
+                ("out_sj", ctypes.c_int64), ("out_si", ctypes.c_int64)]
+
+
 class pw_halo_modes(ctypes.Structure):
     _fields_ = [("x", ctypes.c_int32), ("y", ctypes.c_int32), ("z", ctypes.c_int32)]
 
@@ -81,8 +86,8 @@ class pw_batch_item(ctypes.Structure):
                 ("sw", ctypes.c_void_p)]
 
 
-PW_TUNE_FORWARD, PW_TUNE_ADJOINT, PW_TUNE_TANGENT = 1, 2, 4
-PW_KERNEL_FORWARD, PW_KERNEL_ADJOINT, PW_KERNEL_TANGENT = 0, 1, 2
+PW_TUNE_FORWARD, PW_TUNE_ADJOINT, PW_TUNE_TANGENT, PW_TUNE_ZFAST = 1, 2, 4, 8
+PW_KERNEL_FORWARD, PW_KERNEL_ADJOINT, PW_KERNEL_TANGENT, PW_KERNEL_ZFAST = 0, 1, 2, 3
 
 _P = ctypes.c_void_p
 _SIGNATURES = {
@@ -106,6 +111,8 @@ _SIGNATURES = {
     "pw_advect_coeff_grad_workspace": [ctypes.POINTER(pw_grid), ctypes.c_int, ctypes.POINTER(ctypes.c_int64)],
     "pw_advect_coeff_grad": [ctypes.POINTER(pw_grid), ctypes.POINTER(pw_layout), ctypes.c_int,
                              _P, _P, _P, _P, _P, _P, _P, _P, ctypes.c_int64, _P],
+    "pw_advect_zfast": [ctypes.POINTER(pw_grid), ctypes.POINTER(pw_layout_zfast), ctypes.c_int,
+                        _P, _P, _P, ctypes.POINTER(pw_coeffs), _P, _P, _P, ctypes.POINTER(pw_tile), _P],
     "pw_halo_fill": [ctypes.POINTER(pw_grid), ctypes.POINTER(pw_layout), ctypes.c_int, ctypes.POINTER(_P),
                      ctypes.POINTER(pw_halo_modes), ctypes.c_int32, _P],
     "pw_stream_copy": [_P, _P, ctypes.c_int64, _P],
@@ -203,6 +210,10 @@ def pw_advect_tangent_ex(grid, layout, dtype, u, v, w, coeffs, du, dv, dw, tu, t
     return lib().pw_advect_tangent_ex(ctypes.byref(grid), ctypes.byref(layout) if layout is not None else None,
                                       int(dtype), u, v, w, ctypes.byref(coeffs), du, dv, dw, tu, tv, tw,
                                       ctypes.byref(tile) if tile is not None else None, stream)
+
+
+def pw_advect_zfast(grid, layout, dtype, u, v, w, coeffs, su, sv, sw, tile=None, stream=None):
+    return lib().pw_advect_zfast(grid, layout, dtype, u, v, w, coeffs, su, sv, sw, tile, stream)
 
 
 def pw_halo_fill(grid, layout, dtype, fields, modes, stream=None):
@@ -328,6 +339,32 @@ def advect(u, v, w, coeffs: Coeffs, halo=1, out=None, tile=None, stream=None):
     return su, sv, sw
 
 
+def advect_zfast(u, v, w, coeffs: Coeffs, halo=1, out=None, tile=None, stream=None):
+    """su, sv, sw of winds stored z-fastest: u, v, w have shape
+    (nx+2h, ny+2h, nz+2h) indexed [i, j, k] with k contiguous; the outputs
+    (nx, ny, nz) likewise.  Bit-identical to advect() on the transposed
+    arrays."""
+    import torch
+    if not (u.shape == v.shape == w.shape and u.stride() == v.stride() == w.stride()
+            and u.dtype == v.dtype == w.dtype):
+        raise ValueError("u, v, w must share shape, strides and dtype")
+    pi, pj, pk = u.shape
+    grid = pw_grid(pi - 2 * halo, pj - 2 * halo, pk - 2 * halo, halo)
+    odt = torch.float64 if u.dtype == torch.float64 else torch.float32
+    if out is None:
+        out = tuple(torch.empty((grid.nx, grid.ny, grid.nz), dtype=odt, device=u.device) for _ in range(3))
+    su, sv, sw = out
+    if u.stride(-1) != 1 or su.stride(-1) != 1:
+        raise ValueError("z (last) dimension must be contiguous")
+    layout = pw_layout_zfast(u.stride(1), u.stride(0), su.stride(1), su.stride(0))
+    c = coeffs.c_struct()
+    tl = None if tile is None else pw_tile(*tile)
+    st = pw_advect_zfast(grid, layout, _dtype_code(u), u.data_ptr(), v.data_ptr(), w.data_ptr(), c,
+                         su.data_ptr(), sv.data_ptr(), sw.data_ptr(), tl, _stream_handle(stream))
+    _check(st, "pw_advect_zfast")
+    return su, sv, sw
+
+
 def advect_epilogue(u, v, w, coeffs: Coeffs, addends, alpha=1.0, halo=1, out=None, tile=None, stream=None):
     """out = addends + alpha * F(u, v, w) with one rounding per element.
     ``addends`` is (cu, cv, cw) in the outputs' layout and compute dtype;
@@ -436,12 +473,13 @@ def tune(nx, ny, nz, dtype, halo=1, flags=0):
 
 
 def launch_shape(kind, nx, ny, nz, dtype, halo=1):
-    """The launch shape ``kind`` ("forward", "adjoint" or "tangent") takes
-    for this grid when called without a tile, as (cols_per_lane,
+    """The launch shape ``kind`` ("forward", "adjoint", "tangent" or "zfast")
+    takes for this grid when called without a tile, as (cols_per_lane,
     rows_per_strip, zlen, waves_per_group, prefetch)."""
     import torch
     code = {torch.float32: PW_F32, torch.float64: PW_F64, torch.bfloat16: PW_BF16, torch.float16: PW_F16}[dtype]
-    k = {"forward": PW_KERNEL_FORWARD, "adjoint": PW_KERNEL_ADJOINT, "tangent": PW_KERNEL_TANGENT}[kind]
+    k = {"forward": PW_KERNEL_FORWARD, "adjoint": PW_KERNEL_ADJOINT, "tangent": PW_KERNEL_TANGENT,
+         "zfast": PW_KERNEL_ZFAST}[kind]
     t = pw_tile()
     _check(lib().pw_launch_shape(k, ctypes.byref(pw_grid(nx, ny, nz, halo)), code, ctypes.byref(t)),
            "pw_launch_shape")

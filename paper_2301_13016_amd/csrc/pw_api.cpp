@@ -459,6 +459,68 @@ pw_status pw_advect_adjoint_ex(const pw_grid *grid, const pw_layout *layout, pw_
     return launch_adjoint(a, dtype, cfg, static_cast<hipStream_t>(hip_stream));
 }
 
+pw_status pw_advect_zfast(const pw_grid *grid, const pw_layout_zfast *layout, pw_dtype in_dtype,
+                          const void *u, const void *v, const void *w, const pw_coeffs *coeffs,
+                          void *su, void *sv, void *sw, const pw_tile *tile, void *hip_stream) {
+    g_err[0] = 0;
+    PW_TRY(check_grid(grid));
+    const int64_t es = elem_size(in_dtype);
+    if (!es) return fail(PW_ERR_INVALID_ARG, "unknown dtype %d", (int)in_dtype);
+    const int64_t cs = compute_size(in_dtype);
+    if (!coeffs) return fail(PW_ERR_INVALID_ARG, "coeffs is NULL");
+    const int64_t h = grid->halo, px = grid->nx + 2 * h, py = grid->ny + 2 * h, pz = grid->nz + 2 * h;
+    int64_t isj = pz, isi = py * pz, osj = grid->nz, osi = grid->ny * grid->nz;
+    if (layout) {
+        isj = layout->in_sj;
+        isi = layout->in_si;
+        osj = layout->out_sj;
+        osi = layout->out_si;
+        if (isj < pz) return fail(PW_ERR_INVALID_ARG, "in_sj %lld < nz+2h %lld", (long long)isj, (long long)pz);
+        if (isi / py < isj) return fail(PW_ERR_INVALID_ARG, "in_si too small for in_sj*(ny+2h)");
+        if (osj < grid->nz) return fail(PW_ERR_INVALID_ARG, "out_sj %lld < nz", (long long)osj);
+        if (osi / grid->ny < osj) return fail(PW_ERR_INVALID_ARG, "out_si too small for out_sj*ny");
+    }
+    if (isi * es >= (int64_t(1) << 31) || osi * cs >= (int64_t(1) << 31))
+        return fail(PW_ERR_UNSUPPORTED, "an x-plane larger than 2 GiB is not supported");
+    const char *names[] = {"u", "v", "w", "su", "sv", "sw", "tzc1", "tzc2", "tzd1", "tzd2"};
+    const void *ptrs[] = {u, v, w, su, sv, sw, coeffs->tzc1, coeffs->tzc2, coeffs->tzd1, coeffs->tzd2};
+    for (int i = 0; i < 10; ++i) PW_TRY(check_aligned(names[i], ptrs[i], i < 3 ? es : cs));
+    const int64_t ilast = (px - 1) * isi + (py - 1) * isj + (pz - 1);
+    const int64_t olast = (grid->nx - 1) * osi + (grid->ny - 1) * osj + (grid->nz - 1);
+    auto span = [](const char *n, const void *p, int64_t last, int64_t e) {
+        const uintptr_t lo = reinterpret_cast<uintptr_t>(p);
+        return Range{n, lo, lo + uintptr_t((last + 1) * e)};
+    };
+    const Range rin[3] = {span("u", u, ilast, es), span("v", v, ilast, es), span("w", w, ilast, es)};
+    const Range rout[3] = {span("su", su, olast, cs), span("sv", sv, olast, cs), span("sw", sw, olast, cs)};
+    for (const Range &o : rout) {
+        for (const Range &i : rin)
+            if (overlap(o, i)) return fail(PW_ERR_INVALID_ARG, "output %s overlaps input %s", o.name, i.name);
+        for (const Range &o2 : rout)
+            if (&o != &o2 && overlap(o, o2)) return fail(PW_ERR_INVALID_ARG, "outputs %s and %s overlap", o.name, o2.name);
+    }
+    PW_TRY(check_coeffs_apart(coeffs, grid->nz, cs, rout, 3));
+    if (tile && !zfast_tile_supported(to_cfg(*tile), in_dtype))
+        return fail(PW_ERR_INVALID_ARG, "unsupported z-fastest tile levels=%d rows=%d xlen=%d waves=%d prefetch=%d",
+                    tile->cols_per_lane, tile->rows_per_strip, tile->zlen, tile->waves_per_group, tile->prefetch);
+    FwdArgs a;
+    a.u = u; a.v = v; a.w = w;
+    a.su = su; a.sv = sv; a.sw = sw;
+    a.tzc1 = coeffs->tzc1; a.tzc2 = coeffs->tzc2; a.tzd1 = coeffs->tzd1; a.tzd2 = coeffs->tzd2;
+    a.tcx = coeffs->tcx; a.tcy = coeffs->tcy;
+    a.nx = grid->nx; a.ny = grid->ny; a.nz = grid->nz; a.h = grid->halo;
+    a.in_sy = isj; a.in_sz = isi; a.out_sy = osj; a.out_sz = osi;
+    a.in_bytes = es;
+    a.out_bytes = cs;
+    PW_TRY(check_forward_on_device(a));
+    TileCfg cfg;
+    if (tile)
+        cfg = to_cfg(*tile);
+    else if (!lookup_tuned(TuneKind::Zfast, grid, in_dtype, &cfg))
+        cfg = default_zfast_tile(a, in_dtype);
+    return launch_zfast(a, in_dtype, cfg, static_cast<hipStream_t>(hip_stream));
+}
+
 pw_status pw_halo_fill(const pw_grid *grid, const pw_layout *layout, pw_dtype dtype, void *const fields[],
                        const pw_halo_modes modes[], int32_t nfields, void *hip_stream) {
     using namespace pw;

@@ -107,6 +107,12 @@ pw_status launch_tangent(const TanArgs &a, pw_dtype dt, const TileCfg &cfg, hipS
 int64_t coeff_grad_workspace_bytes(const pw_grid &g, pw_dtype dt);
 pw_status launch_coeff_grad(const CgArgs &a, pw_dtype dt, hipStream_t s);
 pw_status launch_halo(const HaloArgs &a, hipStream_t s);
+// z-fastest forward (pw_zfast.hip): FwdArgs carry the column stride in
+// in_sy / out_sy and the x-plane stride in in_sz / out_sz; tile px = levels
+// per lane, ry = y-rows per strip, zlen = x-columns per work item.
+bool zfast_tile_supported(const TileCfg &c, pw_dtype dt);
+TileCfg default_zfast_tile(const FwdArgs &a, pw_dtype dt);
+pw_status launch_zfast(const FwdArgs &a, pw_dtype dt, const TileCfg &cfg, hipStream_t s);
 pw_status launch_copy(const void *src, void *dst, int64_t nbytes, hipStream_t s);
 pw_status launch_copy3(const void *const *src, void *const *dst, int64_t nbytes, hipStream_t s);
 
@@ -122,7 +128,7 @@ void forward_ranges(const FwdArgs &a, uintptr_t (*in)[2], uintptr_t (*out)[2]);
 
 // Autotune cache (pw_tune.cpp): best launch shape per kernel kind, dtype and
 // shape class, filled by pw_tune and consulted when no tile is given.
-enum class TuneKind { Forward = 0, Adjoint = 1, Tangent = 2 };
+enum class TuneKind { Forward = 0, Adjoint = 1, Tangent = 2, Zfast = 3 };
 bool lookup_tuned(TuneKind kind, const pw_grid *grid, pw_dtype dt, TileCfg *cfg);
 void store_tuned(TuneKind kind, const pw_grid *grid, pw_dtype dt, const TileCfg &cfg);
 

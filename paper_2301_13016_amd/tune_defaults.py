@@ -13,18 +13,18 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(HERE))
 
 # (nx, ny, nz, dtype name, flags): forward for all storage types, adjoint and
-# tangent for FP32/FP64
+# tangent for FP32/FP64, the z-fastest forward for the FP32 / FP64 classes
 SHAPES = [
-    (512, 512, 64, "float32", 7),
-    (1024, 1024, 256, "float32", 1),
+    (512, 512, 64, "float32", 15),
+    (1024, 1024, 256, "float32", 9),
     (1024, 1024, 256, "bfloat16", 1),
     (1024, 1024, 256, "float16", 1),
-    (256, 256, 128, "float32", 7),
-    (64, 64, 64, "float64", 7),
+    (256, 256, 128, "float32", 15),
+    (64, 64, 64, "float64", 15),
     (16, 16, 16, "float64", 7),
-    (128, 128, 128, "float32", 7),
-    (256, 256, 256, "float32", 1),
-    (512, 512, 128, "float32", 1),
+    (128, 128, 128, "float32", 15),
+    (256, 256, 256, "float32", 9),
+    (512, 512, 128, "float32", 9),
 ]
 
 
@@ -38,12 +38,14 @@ def main(out_path):
     code = {"float32": B.PW_F32, "float64": B.PW_F64, "bfloat16": B.PW_BF16, "float16": B.PW_F16}
     tdt = {"float32": torch.float32, "float64": torch.float64, "bfloat16": torch.bfloat16, "float16": torch.float16}
     lines = ["// kind, dtype, log2 nx, log2 ny, log2 nz, cols/lane, rows/strip, z-chunks, waves/group, prefetch",
+             "// (kind 3, z-fastest: levels/lane, rows/strip, x-chunks, waves/group, prefetch)",
              "// generated on %s by paper_2301_13016_amd/tune_defaults.py" % torch.cuda.get_device_name(0)]
     B.pw_tune_reset()
     for nx, ny, nz, dt, flags in SHAPES:
         B._check(B.pw_tune(B.pw_grid(nx, ny, nz, 1), code[dt], flags, None, None), "pw_tune")
         key = (ceil_log2(nx), ceil_log2(ny), ceil_log2(nz))
-        for kind, name, bit, zext in ((0, "forward", 1, nz), (1, "adjoint", 2, nz + 2), (2, "tangent", 4, nz)):
+        for kind, name, bit, zext in ((0, "forward", 1, nz), (1, "adjoint", 2, nz + 2), (2, "tangent", 4, nz),
+                                      (3, "zfast", 8, nx)):
             if not flags & bit:
                 continue
             t = B.launch_shape(name, nx, ny, nz, tdt[dt])

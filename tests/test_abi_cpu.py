@@ -445,7 +445,7 @@ def test_tune_argument_errors(lib):
     assert B.pw_tune(g, B.PW_F32) == B.PW_ERR_INVALID_ARG
     g = B.pw_grid(8, 8, 8, 1)
     assert B.pw_tune(g, 9) == B.PW_ERR_INVALID_ARG
-    assert B.pw_tune(g, B.PW_F32, flags=8) == B.PW_ERR_INVALID_ARG
+    assert B.pw_tune(g, B.PW_F32, flags=16) == B.PW_ERR_INVALID_ARG
     assert B.pw_tune(g, B.PW_F32) in (B.PW_ERR_NO_DEVICE, B.PW_OK)   # OK where a GPU is present
     assert B.pw_tune_reset() == B.PW_OK
 
@@ -475,3 +475,42 @@ def test_halo_fill_validation(lib):
     assert B.pw_halo_fill(g, B.pw_layout(9, 100, 0, 0), B.PW_F32, f, per) == B.PW_ERR_INVALID_ARG
     assert B.pw_halo_fill(g, B.pw_layout(16, 160, 0, 0), B.PW_F32, f, per) in _no_gpu_status()
     assert lib.pw_halo_fill(ctypes.byref(g), None, B.PW_F32, None, None, 1, None) == B.PW_ERR_INVALID_ARG
+
+
+def test_zfast_validation(lib):
+    """z-fastest forward: dense default strides, stride checks, overlap,
+    tile rules; valid arguments reach the device check."""
+    g, c, p = _args(nx=8, ny=6, nz=5)
+    call = lambda layout=None, tile=None, ptrs=p, dt=B.PW_F32: B.pw_advect_zfast(  # noqa: E731
+        g, layout, dt, *ptrs[:3], c, *ptrs[3:], tile, None)
+    assert call() in _no_gpu_status()
+    assert call(B.pw_layout_zfast(7, 7 * 8, 5, 30)) in _no_gpu_status()      # exact dense strides
+    assert call(B.pw_layout_zfast(6, 6 * 8, 5, 30)) == B.PW_ERR_INVALID_ARG  # in_sj < nz + 2h
+    assert "in_sj" in B.pw_last_error()
+    assert call(B.pw_layout_zfast(7, 7 * 8 - 1, 5, 30)) == B.PW_ERR_INVALID_ARG
+    assert call(B.pw_layout_zfast(7, 56, 4, 30)) == B.PW_ERR_INVALID_ARG     # out_sj < nz
+    assert call(B.pw_layout_zfast(7, 56, 5, 29)) == B.PW_ERR_INVALID_ARG     # out_si < ny * out_sj
+    assert call(B.pw_layout_zfast(7, 1 << 30, 5, 30)) == B.PW_ERR_UNSUPPORTED   # x-plane over 2 GiB
+    # the dense input spans 10 * 8 * 7 floats = 2240 B: an output 2236 B after u overlaps it
+    bad = list(p); bad[3] = p[0] + 2236
+    assert call(ptrs=bad) == B.PW_ERR_INVALID_ARG and "overlaps" in B.pw_last_error()
+    bad = list(p); bad[3] = p[0] + 2240
+    assert call(ptrs=bad) in _no_gpu_status()
+    assert call(tile=B.pw_tile(4, 2, 8, 1, 1)) in _no_gpu_status()
+    assert call(tile=B.pw_tile(4, 4, 8, 1, 1)) == B.PW_ERR_INVALID_ARG   # 4 rows need <= 2 levels per lane
+    assert call(tile=B.pw_tile(4, 1, 8, 1, 1), dt=B.PW_F64) == B.PW_ERR_INVALID_ARG
+    assert call(tile=B.pw_tile(1, 2, 8, 1, 3)) == B.PW_ERR_INVALID_ARG   # prefetch 1 or 2
+    assert call(tile=B.pw_tile(1, 8, 8, 1, 2)) in _no_gpu_status()
+    assert call(tile=B.pw_tile(2, 8, 8, 1, 1)) == B.PW_ERR_INVALID_ARG
+    assert call(tile=B.pw_tile(1, 2, 0, 1, 1)) == B.PW_ERR_INVALID_ARG
+    assert call(tile=B.pw_tile(1, 3, 8, 1, 1)) == B.PW_ERR_INVALID_ARG
+
+
+def test_zfast_launch_shape(lib):
+    torch = pytest.importorskip("torch")
+    row = _table_row(3, B.PW_F32, 512, 512, 64)
+    assert row is not None
+    pz, rj, nxc, wpb, depth = row
+    assert B.launch_shape("zfast", 512, 512, 64, torch.float32) == (pz, rj, -(-512 // nxc), wpb, depth)
+    shape = B.launch_shape("zfast", 10, 3, 200, torch.bfloat16)
+    assert shape[0] in (1, 2, 4) and 1 <= shape[2] <= 10

@@ -377,7 +377,11 @@ pw_status pw_advect_zfast(const pw_grid *grid, const pw_layout_zfast *layout, pw
  * in_sz; out_* ignored; NULL = dense), updated in place on `hip_stream`;
  * modes[f] gives field f's x, y, z rules.  Interior cells are never written
  * and are the only cells read (on KEEP axes, the cell's own line), so the
- * fill is one kernel with no ordering between its writes.  Errors
+ * fill is one kernel with no ordering between its writes.  The rules are
+ * per axis, so arrays stored z-fastest (pw_advect_zfast's layout) are filled
+ * by passing nx and nz exchanged in `grid` and the x and z rules exchanged
+ * in `modes`, with in_sy = the column stride and in_sz = the x-plane stride.
+ * Errors
  * (PW_ERR_INVALID_ARG): NULL or misaligned fields, overlapping fields, an
  * unknown mode, REFLECT with n < h, nfields out of range. */
 typedef enum {

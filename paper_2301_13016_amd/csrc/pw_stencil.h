@@ -107,6 +107,9 @@ template <typename T> __device__ __forceinline__ T uniform_load(const T *p, int 
 // (element) alignment.
 #define PW_GLOAD(V, p) (*(const __attribute__((address_space(1))) V *)(p))
 #define PW_GSTORE_NT(V, x, p) __builtin_nontemporal_store((x), (__attribute__((address_space(1))) V *)(p))
+// Streaming read of data used once (the epilogue's addends): non-temporal, so
+// it does not displace the y-halo rows that neighbouring strips re-read from L2.
+#define PW_GLOAD_NT(V, p) __builtin_nontemporal_load((const __attribute__((address_space(1))) V *)(p))
 
 template <typename T> __device__ __forceinline__ T fma_(T a, T b, T c);
 template <> __device__ __forceinline__ float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
@@ -216,17 +219,17 @@ __device__ __forceinline__ void load_epi(EpiRows<Tin, PX, RY> &E, const FwdK<Tin
     for (int r = 0; r < RY; ++r) {
         if constexpr (Full || PX == 1) {
             using VT = typename Vec<Tc, PX>::type;
-            E.u[r] = PW_GLOAD(VT, bu + ooff[r]);
-            E.v[r] = PW_GLOAD(VT, bv + ooff[r]);
-            E.w[r] = PW_GLOAD(VT, bw + ooff[r]);
+            E.u[r] = PW_GLOAD_NT(VT, bu + ooff[r]);
+            E.v[r] = PW_GLOAD_NT(VT, bv + ooff[r]);
+            E.w[r] = PW_GLOAD_NT(VT, bw + ooff[r]);
         } else {
             // ooff is at column ic = min(ii0, nx-1); columns ic+m clamped to nx-1
 #pragma unroll
             for (int m = 0; m < PX; ++m) {
                 const int64_t d = static_cast<int64_t>(min(ic + m, a.nx - 1) - ic) * sizeof(Tc);
-                E.u[r][m] = PW_GLOAD(Tc, bu + ooff[r] + d);
-                E.v[r][m] = PW_GLOAD(Tc, bv + ooff[r] + d);
-                E.w[r][m] = PW_GLOAD(Tc, bw + ooff[r] + d);
+                E.u[r][m] = PW_GLOAD_NT(Tc, bu + ooff[r] + d);
+                E.v[r][m] = PW_GLOAD_NT(Tc, bv + ooff[r] + d);
+                E.w[r][m] = PW_GLOAD_NT(Tc, bw + ooff[r] + d);
             }
         }
     }
@@ -377,7 +380,8 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
 // and each lane stores only its columns inside the grid.  Depth: planes in
 // flight ahead of the three a level reads (1 or 2).  Epi: the fused
 // epilogue out = c + alpha * F; the addend rows of level kk are loaded at the
-// start of the level, before that level's plane prefetch, so waiting for them
+// start of the level, before that level's plane prefetch (a scheduling
+// barrier keeps the compiler from moving them after it), so waiting for them
 // never waits for the prefetch.
 template <typename Tin, int PX, int RY, bool Full, int Depth, bool Epi>
 __device__ __forceinline__ void strip_march_t(const FwdK<Tin> &a, int tx, int ty, int cz) {
@@ -427,7 +431,10 @@ __device__ __forceinline__ void strip_march_t(const FwdK<Tin> &a, int tx, int ty
 #define PW_PLOAD(P, kp) load_plane<Tin, PX, RY, Full>(P, a, min((kp), k1) + h, s, last_col)
 #define PW_LOAD(P, kp)                                                   \
     do {                                                                 \
-        if constexpr (Epi) load_epi<Tin, PX, RY, Full>(Ep, a, kk, ooff, ic); \
+        if constexpr (Epi) {                                             \
+            load_epi<Tin, PX, RY, Full>(Ep, a, kk, ooff, ic);            \
+            __builtin_amdgcn_sched_barrier(0);                           \
+        }                                                                \
         load_plane<Tin, PX, RY, Full>(P, a, min((kp), k1) + h, s, last_col); \
     } while (0)
 #define PW_LEVEL(M, C, P) level<Tin, PX, RY, Full, Epi>(M, C, P, a, kk, lane0, lane63, nvalid, ooff, row_ok, Ep)

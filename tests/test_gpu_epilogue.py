@@ -103,3 +103,29 @@ def test_epilogue_argument_errors():
         B.advect_epilogue(u, v, w, c, [out[1], out[1], out[2]], out=out)
     with pytest.raises(B.PWError):
         B.advect_epilogue(u, v, w, c, out, alpha=float("nan"), out=out)
+
+
+def test_epilogue_is_one_fma_of_the_plain_output():
+    """out = fma(alpha, F_plain, c) with F_plain the plain kernel's output
+    bit for bit: alpha a power of two makes alpha * F_plain exact, so the
+    float64 sum with c is exact wherever the exponents are close (checked per
+    point) and its rounding to float32 is the fma's single rounding."""
+    g = wl.make_grid(190, 23, 17, seed=905)
+    (u, v, w), c = dev_grid(g)
+    plain = [x.cpu().numpy() for x in B.advect(u, v, w, c)]
+    rng = np.random.default_rng(906)
+    c0 = [rng.uniform(-5, 5, plain[0].shape).astype(np.float32) for _ in range(3)]
+    alpha = -0.25
+    out = [torch.from_numpy(x).cuda() for x in c0]
+    B.advect_epilogue(u, v, w, c, out, alpha=alpha, out=out)
+    torch.cuda.synchronize()
+    checked = 0
+    for o, f, cc in zip(out, plain, c0):
+        prod = alpha * f.astype(np.float64)
+        s = prod + cc.astype(np.float64)
+        exact = (s - cc.astype(np.float64)) == prod
+        want = s.astype(np.float32)
+        got = o.cpu().numpy()
+        assert np.array_equal(got[exact], want[exact])
+        checked += int(exact.sum())
+    assert checked >= 0.99 * 3 * plain[0].size

@@ -227,9 +227,10 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
     return x * q + min(x, rem) + i;
 }
 
+// Depth: planes in flight ahead of the three a level reads (1 or 2).
 // MaxT: workgroup size bound (built for 256 and 512 threads; see the forward
 // kernel).
-template <typename T, int RY, int MaxT>
+template <typename T, int RY, int Depth, int MaxT>
 __global__ __launch_bounds__(MaxT) void pw_adjoint_kernel(AdjK<T> a) {
     const int lane = threadIdx.x & 63;
     // wavefront index as a scalar, so that per-strip conditions stay scalar
@@ -272,31 +273,63 @@ __global__ __launch_bounds__(MaxT) void pw_adjoint_kernel(AdjK<T> a) {
 
     const int k0 = cz * a.zlen;
     const int k1 = min(pz, k0 + a.zlen);
-    APlane<T, RY> A, B, C, D;
-    load_aplane<T, RY>(A, a, k0 - 1, s);
-    load_aplane<T, RY>(B, a, k0, s);
-    load_aplane<T, RY>(C, a, k0 + 1, s);
-    mask_aplane<T, RY>(A, s);
-    mask_aplane<T, RY>(B, s);
-    // Unconditional prefetch of plane k+2 (past the chunk's last level it
-    // re-reads plane k1, a cache hit, into a slot no level uses): a
-    // conditional load would join two paths with different loads in flight,
-    // and the wait at the join drains the prefetch.
+    // Unconditional prefetch (past the chunk's last level it re-reads plane
+    // k1, a cache hit, into a slot no level uses): a conditional load would
+    // join two paths with different loads in flight, and the wait at the join
+    // drains the prefetch.
+#define PW_ALEVEL(M, C, P) adj_level<T, RY>(M, C, P, a, s, k, lane_ok, goff, row_ok)
     int k = k0;
-    for (;;) {
-        load_aplane<T, RY>(D, a, min(k + 2, k1), s);
-        adj_level<T, RY>(A, B, C, a, s, k, lane_ok, goff, row_ok);
-        if (++k >= k1) break;
-        load_aplane<T, RY>(A, a, min(k + 2, k1), s);
-        adj_level<T, RY>(B, C, D, a, s, k, lane_ok, goff, row_ok);
-        if (++k >= k1) break;
-        load_aplane<T, RY>(B, a, min(k + 2, k1), s);
-        adj_level<T, RY>(C, D, A, a, s, k, lane_ok, goff, row_ok);
-        if (++k >= k1) break;
-        load_aplane<T, RY>(C, a, min(k + 2, k1), s);
-        adj_level<T, RY>(D, A, B, a, s, k, lane_ok, goff, row_ok);
-        if (++k >= k1) break;
+    if constexpr (Depth == 1) {
+        // four-plane ring: planes k-1, k, k+1 feed level k, k+2 in flight
+        APlane<T, RY> A, B, C, D;
+        load_aplane<T, RY>(A, a, k0 - 1, s);
+        load_aplane<T, RY>(B, a, k0, s);
+        load_aplane<T, RY>(C, a, k0 + 1, s);
+        mask_aplane<T, RY>(A, s);
+        mask_aplane<T, RY>(B, s);
+        for (;;) {
+            load_aplane<T, RY>(D, a, min(k + 2, k1), s);
+            PW_ALEVEL(A, B, C);
+            if (++k >= k1) break;
+            load_aplane<T, RY>(A, a, min(k + 2, k1), s);
+            PW_ALEVEL(B, C, D);
+            if (++k >= k1) break;
+            load_aplane<T, RY>(B, a, min(k + 2, k1), s);
+            PW_ALEVEL(C, D, A);
+            if (++k >= k1) break;
+            load_aplane<T, RY>(C, a, min(k + 2, k1), s);
+            PW_ALEVEL(D, A, B);
+            if (++k >= k1) break;
+        }
+    } else {
+        // five-plane ring: planes k+2 and k+3 in flight
+        static_assert(Depth == 2, "prefetch depth 1 or 2");
+        APlane<T, RY> A, B, C, D, E;
+        load_aplane<T, RY>(A, a, k0 - 1, s);
+        load_aplane<T, RY>(B, a, k0, s);
+        load_aplane<T, RY>(C, a, k0 + 1, s);
+        load_aplane<T, RY>(D, a, min(k0 + 2, k1), s);
+        mask_aplane<T, RY>(A, s);
+        mask_aplane<T, RY>(B, s);
+        for (;;) {
+            load_aplane<T, RY>(E, a, min(k + 3, k1), s);
+            PW_ALEVEL(A, B, C);
+            if (++k >= k1) break;
+            load_aplane<T, RY>(A, a, min(k + 3, k1), s);
+            PW_ALEVEL(B, C, D);
+            if (++k >= k1) break;
+            load_aplane<T, RY>(B, a, min(k + 3, k1), s);
+            PW_ALEVEL(C, D, E);
+            if (++k >= k1) break;
+            load_aplane<T, RY>(C, a, min(k + 3, k1), s);
+            PW_ALEVEL(D, E, A);
+            if (++k >= k1) break;
+            load_aplane<T, RY>(D, a, min(k + 3, k1), s);
+            PW_ALEVEL(E, A, B);
+            if (++k >= k1) break;
+        }
     }
+#undef PW_ALEVEL
 }
 
 template <typename T, int RY>
@@ -334,12 +367,18 @@ pw_status launch_adj_t(const AdjArgs &g, const TileCfg &cfg, hipStream_t s) {
     const int64_t nblk_y = (a.nty + cfg.wpb - 1) / cfg.wpb;
     const int64_t nblocks = static_cast<int64_t>(a.ntx) * nblk_y * a.nzc;
     if (nblocks <= 0 || nblocks > 0x7fffffffLL) return fail(PW_ERR_UNSUPPORTED, "grid too large");
-    if (cfg.wpb <= 4)
-        hipLaunchKernelGGL((pw_adjoint_kernel<T, RY, 256>), dim3(static_cast<unsigned>(nblocks)), dim3(64 * cfg.wpb), 0,
-                           s, a);
-    else
-        hipLaunchKernelGGL((pw_adjoint_kernel<T, RY, 512>), dim3(static_cast<unsigned>(nblocks)), dim3(64 * cfg.wpb), 0,
-                           s, a);
+    const dim3 grid(static_cast<unsigned>(nblocks)), block(64 * cfg.wpb);
+    if (cfg.depth == 2) {
+        if (cfg.wpb <= 4)
+            hipLaunchKernelGGL((pw_adjoint_kernel<T, RY, 2, 256>), grid, block, 0, s, a);
+        else
+            hipLaunchKernelGGL((pw_adjoint_kernel<T, RY, 2, 512>), grid, block, 0, s, a);
+    } else {
+        if (cfg.wpb <= 4)
+            hipLaunchKernelGGL((pw_adjoint_kernel<T, RY, 1, 256>), grid, block, 0, s, a);
+        else
+            hipLaunchKernelGGL((pw_adjoint_kernel<T, RY, 1, 512>), grid, block, 0, s, a);
+    }
     return hip_fail(hipGetLastError(), "adjoint kernel launch");
 }
 
@@ -356,7 +395,8 @@ pw_status launch_adj_dt(const AdjArgs &g, const TileCfg &cfg, hipStream_t s) {
 }  // namespace
 
 bool adjoint_tile_supported(const TileCfg &c) {
-    return c.px == 1 && c.depth == 1 && (c.ry == 1 || c.ry == 2 || c.ry == 4) && c.zlen >= 1 && c.wpb >= 1 && c.wpb <= 8;
+    return c.px == 1 && (c.depth == 1 || c.depth == 2) && (c.ry == 1 || c.ry == 2 || c.ry == 4) && c.zlen >= 1 &&
+           c.wpb >= 1 && c.wpb <= 8;
 }
 
 TileCfg default_adjoint_tile(const AdjArgs &a, pw_dtype dt) {

@@ -48,7 +48,7 @@ SHAPES = [(130, 70, 20), (64, 64, 64), (1, 1, 1), (65, 3, 1), (1, 200, 5), (61, 
           (128, 4, 3), (129, 5, 2), (257, 3, 4)]
 
 
-@pytest.mark.parametrize("tile", [None, (1, 1, 5, 4), (1, 2, 9, 1), (1, 4, 64, 8)])
+@pytest.mark.parametrize("tile", [None, (1, 1, 5, 4), (1, 2, 9, 1), (1, 4, 64, 8), (1, 2, 7, 4, 2), (1, 4, 3, 1, 2)])
 @pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "x".join(map(str, s)))
 def test_f32_adjoint_matches_oracle(shape, tile):
     nx, ny, nz = shape
@@ -58,10 +58,11 @@ def test_f32_adjoint_matches_oracle(shape, tile):
     assert max(errs) <= 2e-6, errs
 
 
-def test_f64_adjoint_matches_oracle():
+@pytest.mark.parametrize("tile", [None, (1, 2, 4, 4, 2)])
+def test_f64_adjoint_matches_oracle(tile):
     g = wl.make_grid(70, 33, 21, seed=201, dtype=np.float64)
     r = wl.cotangents(70, 33, 21, seed=301, dtype=np.float64)
-    errs, _ = adj_errors(gpu_adjoint(g, r), g, r)
+    errs, _ = adj_errors(gpu_adjoint(g, r, tile=tile), g, r)
     assert max(errs) <= 1e-13, errs
 
 
@@ -80,7 +81,8 @@ def test_adjoint_tile_invariance_bitwise():
     g = wl.make_grid(150, 37, 23, seed=203)
     r = wl.cotangents(150, 37, 23, seed=303)
     base = gpu_adjoint(g, r, tile=(1, 2, 16, 4))
-    for t in [(1, 1, 1, 1), (1, 1, 9, 4), (1, 2, 5, 8), (1, 4, 64, 4), (1, 4, 3, 2), (1, 1, 7, 8), (1, 2, 130, 1)]:
+    for t in [(1, 1, 1, 1), (1, 1, 9, 4), (1, 2, 5, 8), (1, 4, 64, 4), (1, 4, 3, 2), (1, 1, 7, 8), (1, 2, 130, 1),
+              (1, 1, 1, 1, 2), (1, 2, 6, 4, 2), (1, 4, 130, 8, 2)]:
         got = gpu_adjoint(g, r, tile=t)
         for a, b in zip(base, got):
             assert np.array_equal(a, b), t

@@ -158,3 +158,16 @@ def test_halo_fill_argument_errors():
     g = _fields((2 + 6, 7 + 6, 7 + 6), 1, 707, torch.float32)
     with pytest.raises(B.PWError):
         B.halo_fill(g, ("keep", "keep", "reflect"), halo=3)   # nz = 2 < h = 3
+
+
+def test_zfast_arrays_with_axes_exchanged():
+    """A z-fastest array ([i, j, k], k contiguous) is filled by the same call
+    with the x and z rules exchanged: the result is the x-fastest fill,
+    transposed, bit for bit."""
+    rng = np.random.default_rng(708)
+    a = torch.from_numpy(rng.uniform(-2, 2, (9 + 2, 5 + 2, 70 + 2))).to(torch.float32).cuda()   # (k, j, i)
+    z = a.permute(2, 1, 0).contiguous()                                                         # (i, j, k)
+    B.halo_fill([a], ("periodic", "copy", "reflect_neg"))
+    B.halo_fill([z], ("reflect_neg", "copy", "periodic"))
+    torch.cuda.synchronize()
+    assert torch.equal(z.permute(2, 1, 0), a)

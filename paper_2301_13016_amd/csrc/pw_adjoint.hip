@@ -215,9 +215,9 @@ __device__ __forceinline__ void adj_level(const APlane<T, RY> &m, const APlane<T
         gw = fma_(tcy, gyw, gw);
 
         if (lane_ok && row_ok[r]) {
-            __builtin_nontemporal_store(gu, reinterpret_cast<T *>(ogu + goff[r]));
-            __builtin_nontemporal_store(gv, reinterpret_cast<T *>(ogv + goff[r]));
-            __builtin_nontemporal_store(gw, reinterpret_cast<T *>(ogw + goff[r]));
+            *reinterpret_cast<T *>(ogu + goff[r]) = gu;
+            *reinterpret_cast<T *>(ogv + goff[r]) = gv;
+            *reinterpret_cast<T *>(ogw + goff[r]) = gw;
         }
     }
 }

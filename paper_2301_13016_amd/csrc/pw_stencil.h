@@ -107,6 +107,11 @@ template <typename T> __device__ __forceinline__ T uniform_load(const T *p, int 
 // (element) alignment.
 #define PW_GLOAD(V, p) (*(const __attribute__((address_space(1))) V *)(p))
 #define PW_GSTORE_NT(V, x, p) __builtin_nontemporal_store((x), (__attribute__((address_space(1))) V *)(p))
+// Ordinary (write-back) store, for writes that cover only part of a cache
+// line per instruction: L2 merges the pieces of a line before it is written
+// to HBM, where separate non-temporal partial-line writes each cost HBM
+// bandwidth of their own.
+#define PW_GSTORE(V, x, p) (*(__attribute__((address_space(1))) V *)(p) = (x))
 // Streaming read of data used once (the epilogue's addends): non-temporal, so
 // it does not displace the y-halo rows that neighbouring strips re-read from L2.
 #define PW_GLOAD_NT(V, p) __builtin_nontemporal_load((const __attribute__((address_space(1))) V *)(p))
@@ -351,9 +356,9 @@ __device__ __forceinline__ void level(const Plane<Tin, PX, RY> &m, const Plane<T
 #pragma unroll
                 for (int x = 0; x < PX; ++x) {
                     if (x < nvalid) {
-                        PW_GSTORE_NT(Tc, rsu[x], osu + ooff[r] + x * sizeof(Tc));
-                        PW_GSTORE_NT(Tc, rsv[x], osv + ooff[r] + x * sizeof(Tc));
-                        PW_GSTORE_NT(Tc, rsw[x], osw + ooff[r] + x * sizeof(Tc));
+                        PW_GSTORE(Tc, rsu[x], osu + ooff[r] + x * sizeof(Tc));
+                        PW_GSTORE(Tc, rsv[x], osv + ooff[r] + x * sizeof(Tc));
+                        PW_GSTORE(Tc, rsw[x], osw + ooff[r] + x * sizeof(Tc));
                     }
                 }
             }

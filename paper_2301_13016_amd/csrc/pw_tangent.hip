@@ -151,9 +151,9 @@ __device__ __forceinline__ void level_tl(const Plane<T, PX, RY> &xm, const Plane
 #pragma unroll
                 for (int x = 0; x < PX; ++x) {
                     if (x < nvalid) {
-                        __builtin_nontemporal_store(rtu[x], reinterpret_cast<T *>(otu + ooff[r]) + x);
-                        __builtin_nontemporal_store(rtv[x], reinterpret_cast<T *>(otv + ooff[r]) + x);
-                        __builtin_nontemporal_store(rtw[x], reinterpret_cast<T *>(otw + ooff[r]) + x);
+                        reinterpret_cast<T *>(otu + ooff[r])[x] = rtu[x];
+                        reinterpret_cast<T *>(otv + ooff[r])[x] = rtv[x];
+                        reinterpret_cast<T *>(otw + ooff[r])[x] = rtw[x];
                     }
                 }
             }

@@ -188,9 +188,9 @@ __device__ __forceinline__ void column(const ZPlane<Tin, PZ, RJ> &m, const ZPlan
 #pragma unroll
                 for (int x = 0; x < PZ; ++x) {
                     if (x < nvalid) {
-                        PW_GSTORE_NT(Tc, rsu[x], osu + ooff[r] + x * sizeof(Tc));
-                        PW_GSTORE_NT(Tc, rsv[x], osv + ooff[r] + x * sizeof(Tc));
-                        PW_GSTORE_NT(Tc, rsw[x], osw + ooff[r] + x * sizeof(Tc));
+                        PW_GSTORE(Tc, rsu[x], osu + ooff[r] + x * sizeof(Tc));
+                        PW_GSTORE(Tc, rsv[x], osv + ooff[r] + x * sizeof(Tc));
+                        PW_GSTORE(Tc, rsw[x], osw + ooff[r] + x * sizeof(Tc));
                     }
                 }
             }

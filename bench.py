@@ -161,17 +161,20 @@ def prebuilt_epilogue(B, ins, outs, coeffs, alpha, stream):
     return call
 
 
-def prebuilt_zfast(B, ins, outs, coeffs, stream):
+def prebuilt_zfast(B, ins, outs, coeffs, stream, accumulate=False):
     """ctypes arguments of one pw_advect_zfast call (arrays stored z-fastest,
-    indexed [i, j, k]), built once."""
+    indexed [i, j, k]), built once; with ``accumulate`` the fused epilogue
+    out += F (pw_advect_zfast_epilogue)."""
     from paper_2301_13016_amd.binding import _dtype_code
     u, v, w = ins
     pi, pj, pk = u.shape
     keep = (B.pw_grid(pi - 2, pj - 2, pk - 2, 1),
-            B.pw_layout_zfast(u.stride(1), u.stride(0), outs[0].stride(1), outs[0].stride(0)), coeffs.c_struct())
+            B.pw_layout_zfast(u.stride(1), u.stride(0), outs[0].stride(1), outs[0].stride(0)), coeffs.c_struct(),
+            B.pw_epilogue(1.0, *(o.data_ptr() for o in outs)))
+    ep = (ctypes.byref(keep[3]),) if accumulate else ()
     args = (ctypes.byref(keep[0]), ctypes.byref(keep[1]), _dtype_code(u), u.data_ptr(), v.data_ptr(), w.data_ptr(),
-            ctypes.byref(keep[2]), *(o.data_ptr() for o in outs), None, ctypes.c_void_p(stream.cuda_stream))
-    fn = B.lib().pw_advect_zfast
+            ctypes.byref(keep[2]), *ep, *(o.data_ptr() for o in outs), None, ctypes.c_void_p(stream.cuda_stream))
+    fn = B.lib().pw_advect_zfast_epilogue if accumulate else B.lib().pw_advect_zfast
 
     def call():
         st = fn(*args)
@@ -371,9 +374,12 @@ def main():
     _, zf_ms = time_launches(torch, lambda i: zf_calls[i](), nsets, 500, 100, stream)
     # the x-fastest step again, under the same conditions
     _, xf_ms = time_launches(torch, lambda i: calls[i](), nsets, 500, 100, stream)
+    zacc_calls = [prebuilt_zfast(B, zi, zo, coeffs, stream, accumulate=True) for zi, zo in zsets]
+    _, zacc_ms = time_launches(torch, lambda i: zacc_calls[i](), nsets, 200, 20, stream)
     zshape = B.launch_shape("zfast", nx, ny, nz, torch.float32)
-    del zf_calls, zsets
+    del zf_calls, zacc_calls, zsets
     forms["zfast_512x512x64"] = dict(kernel_ms=round(zf_ms, 4), over_xfast=round(zf_ms / xf_ms, 3),
+                                     accumulate_ms=round(zacc_ms, 4),
                                      gpts=round(pts / (zf_ms * 1e-3) / 1e9, 2),
                                      hbm_gbs=round(nbytes / (zf_ms * 1e-3) / 1e9, 1), tile=list(zshape))
     log("c1 z-fastest layout: %.4f ms, %.3f x the x-fastest step timed after it (%.4f ms; tile %s)"

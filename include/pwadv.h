@@ -350,6 +350,16 @@ pw_status pw_advect_zfast(const pw_grid *grid, const pw_layout_zfast *layout, pw
                           const void *u, const void *v, const void *w, const pw_coeffs *coeffs,
                           void *su, void *sv, void *sw, const pw_tile *tile, void *hip_stream);
 
+/* The fused epilogue of pw_advect_epilogue (out = c + alpha * F, one fma per
+ * element) on z-fastest arrays: cu/cv/cw in the output layout (out_sj,
+ * out_si) and compute type, each either its own output (accumulation into a
+ * model's source terms) or overlapping no output.  Results are bit-identical
+ * to pw_advect_epilogue on the transposed arrays. */
+pw_status pw_advect_zfast_epilogue(const pw_grid *grid, const pw_layout_zfast *layout, pw_dtype in_dtype,
+                                   const void *u, const void *v, const void *w, const pw_coeffs *coeffs,
+                                   const pw_epilogue *ep, void *su, void *sv, void *sw, const pw_tile *tile,
+                                   void *hip_stream);
+
 /* ------------------------------------------------------------- halo fill
  * The step before the stencil: fill the halo of padded arrays from their
  * interiors.  The stencil (Sec. 2.2) reads one layer of neighbours, which a

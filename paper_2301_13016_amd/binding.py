@@ -113,6 +113,9 @@ _SIGNATURES = {
                              _P, _P, _P, _P, _P, _P, _P, _P, ctypes.c_int64, _P],
     "pw_advect_zfast": [ctypes.POINTER(pw_grid), ctypes.POINTER(pw_layout_zfast), ctypes.c_int,
                         _P, _P, _P, ctypes.POINTER(pw_coeffs), _P, _P, _P, ctypes.POINTER(pw_tile), _P],
+    "pw_advect_zfast_epilogue": [ctypes.POINTER(pw_grid), ctypes.POINTER(pw_layout_zfast), ctypes.c_int,
+                                 _P, _P, _P, ctypes.POINTER(pw_coeffs), ctypes.POINTER(pw_epilogue), _P, _P, _P,
+                                 ctypes.POINTER(pw_tile), _P],
     "pw_halo_fill": [ctypes.POINTER(pw_grid), ctypes.POINTER(pw_layout), ctypes.c_int, ctypes.POINTER(_P),
                      ctypes.POINTER(pw_halo_modes), ctypes.c_int32, _P],
     "pw_stream_copy": [_P, _P, ctypes.c_int64, _P],
@@ -362,6 +365,39 @@ def advect_zfast(u, v, w, coeffs: Coeffs, halo=1, out=None, tile=None, stream=No
     st = pw_advect_zfast(grid, layout, _dtype_code(u), u.data_ptr(), v.data_ptr(), w.data_ptr(), c,
                          su.data_ptr(), sv.data_ptr(), sw.data_ptr(), tl, _stream_handle(stream))
     _check(st, "pw_advect_zfast")
+    return su, sv, sw
+
+
+def advect_zfast_epilogue(u, v, w, coeffs: Coeffs, addends, alpha=1.0, halo=1, out=None, tile=None, stream=None):
+    """out = addends + alpha * F(u, v, w) on z-fastest arrays (see
+    advect_zfast); ``addends`` are (nx, ny, nz)-indexed tensors in the output
+    dtype, each either its output (accumulation in place) or disjoint from
+    the outputs."""
+    import torch
+    if not (u.shape == v.shape == w.shape and u.stride() == v.stride() == w.stride()
+            and u.dtype == v.dtype == w.dtype):
+        raise ValueError("u, v, w must share shape, strides and dtype")
+    pi, pj, pk = u.shape
+    grid = pw_grid(pi - 2 * halo, pj - 2 * halo, pk - 2 * halo, halo)
+    odt = torch.float64 if u.dtype == torch.float64 else torch.float32
+    cu, cv, cw = addends
+    if any(c.dtype != odt or c.shape != (grid.nx, grid.ny, grid.nz) or c.stride() != cu.stride() for c in addends):
+        raise ValueError("addends must be %s tensors of shape (nx, ny, nz) with one set of strides" % odt)
+    if out is None:
+        out = tuple(torch.empty((grid.nx, grid.ny, grid.nz), dtype=odt, device=u.device) for _ in range(3))
+    su, sv, sw = out
+    if u.stride(-1) != 1 or su.stride(-1) != 1:
+        raise ValueError("z (last) dimension must be contiguous")
+    if su.stride() != cu.stride():
+        raise ValueError("addends and outputs must share strides")
+    layout = pw_layout_zfast(u.stride(1), u.stride(0), su.stride(1), su.stride(0))
+    c = coeffs.c_struct()
+    ep = pw_epilogue(float(alpha), cu.data_ptr(), cv.data_ptr(), cw.data_ptr())
+    tl = None if tile is None else pw_tile(*tile)
+    st = lib().pw_advect_zfast_epilogue(grid, layout, _dtype_code(u), u.data_ptr(), v.data_ptr(), w.data_ptr(),
+                                        c, ep, su.data_ptr(), sv.data_ptr(), sw.data_ptr(), tl,
+                                        _stream_handle(stream))
+    _check(st, "pw_advect_zfast_epilogue")
     return su, sv, sw
 
 

@@ -92,6 +92,17 @@ Range out_range(const char *name, const void *p, const pw_grid *g, const Layout 
 
 bool overlap(const Range &a, const Range &b) { return a.lo < b.hi && b.lo < a.hi; }
 
+// Bytes [p, p + (last+1)*es) of an array whose last element is at offset `last`.
+Range zspan(const char *name, const void *p, int64_t last, int64_t es) {
+    const uintptr_t lo = reinterpret_cast<uintptr_t>(p);
+    return Range{name, lo, lo + uintptr_t((last + 1) * es)};
+}
+
+// Offset of the last interior output of a z-fastest array.
+int64_t zfast_out_last(const pw_grid *g, int64_t osj, int64_t osi) {
+    return (g->nx - 1) * osi + (g->ny - 1) * osj + (g->nz - 1);
+}
+
 // The kernels read the coefficient arrays through the scalar cache, which is
 // only valid if nothing they write overlaps them.
 pw_status check_coeffs_apart(const pw_coeffs *c, int64_t nz, int64_t cs, const Range *outs, int nout) {
@@ -459,10 +470,16 @@ pw_status pw_advect_adjoint_ex(const pw_grid *grid, const pw_layout *layout, pw_
     return launch_adjoint(a, dtype, cfg, static_cast<hipStream_t>(hip_stream));
 }
 
-pw_status pw_advect_zfast(const pw_grid *grid, const pw_layout_zfast *layout, pw_dtype in_dtype,
-                          const void *u, const void *v, const void *w, const pw_coeffs *coeffs,
-                          void *su, void *sv, void *sw, const pw_tile *tile, void *hip_stream) {
-    g_err[0] = 0;
+}  // extern "C"
+
+namespace pw {
+namespace {
+
+// Validation shared by the z-fastest entry points: fills the launch operands
+// (strides in FwdArgs' row / plane fields) and the output byte ranges.
+pw_status validate_zfast(const pw_grid *grid, const pw_layout_zfast *layout, pw_dtype in_dtype, const void *u,
+                         const void *v, const void *w, const pw_coeffs *coeffs, void *su, void *sv, void *sw,
+                         const pw_tile *tile, FwdArgs *out, Range (&rout)[3]) {
     PW_TRY(check_grid(grid));
     const int64_t es = elem_size(in_dtype);
     if (!es) return fail(PW_ERR_INVALID_ARG, "unknown dtype %d", (int)in_dtype);
@@ -486,13 +503,11 @@ pw_status pw_advect_zfast(const pw_grid *grid, const pw_layout_zfast *layout, pw
     const void *ptrs[] = {u, v, w, su, sv, sw, coeffs->tzc1, coeffs->tzc2, coeffs->tzd1, coeffs->tzd2};
     for (int i = 0; i < 10; ++i) PW_TRY(check_aligned(names[i], ptrs[i], i < 3 ? es : cs));
     const int64_t ilast = (px - 1) * isi + (py - 1) * isj + (pz - 1);
-    const int64_t olast = (grid->nx - 1) * osi + (grid->ny - 1) * osj + (grid->nz - 1);
-    auto span = [](const char *n, const void *p, int64_t last, int64_t e) {
-        const uintptr_t lo = reinterpret_cast<uintptr_t>(p);
-        return Range{n, lo, lo + uintptr_t((last + 1) * e)};
-    };
-    const Range rin[3] = {span("u", u, ilast, es), span("v", v, ilast, es), span("w", w, ilast, es)};
-    const Range rout[3] = {span("su", su, olast, cs), span("sv", sv, olast, cs), span("sw", sw, olast, cs)};
+    const Range rin[3] = {zspan("u", u, ilast, es), zspan("v", v, ilast, es), zspan("w", w, ilast, es)};
+    const int64_t olast = zfast_out_last(grid, osj, osi);
+    rout[0] = zspan("su", su, olast, cs);
+    rout[1] = zspan("sv", sv, olast, cs);
+    rout[2] = zspan("sw", sw, olast, cs);
     for (const Range &o : rout) {
         for (const Range &i : rin)
             if (overlap(o, i)) return fail(PW_ERR_INVALID_ARG, "output %s overlaps input %s", o.name, i.name);
@@ -503,7 +518,7 @@ pw_status pw_advect_zfast(const pw_grid *grid, const pw_layout_zfast *layout, pw
     if (tile && !zfast_tile_supported(to_cfg(*tile), in_dtype))
         return fail(PW_ERR_INVALID_ARG, "unsupported z-fastest tile levels=%d rows=%d xlen=%d waves=%d prefetch=%d",
                     tile->cols_per_lane, tile->rows_per_strip, tile->zlen, tile->waves_per_group, tile->prefetch);
-    FwdArgs a;
+    FwdArgs &a = *out;
     a.u = u; a.v = v; a.w = w;
     a.su = su; a.sv = sv; a.sw = sw;
     a.tzc1 = coeffs->tzc1; a.tzc2 = coeffs->tzc2; a.tzd1 = coeffs->tzd1; a.tzd2 = coeffs->tzd2;
@@ -512,6 +527,11 @@ pw_status pw_advect_zfast(const pw_grid *grid, const pw_layout_zfast *layout, pw
     a.in_sy = isj; a.in_sz = isi; a.out_sy = osj; a.out_sz = osi;
     a.in_bytes = es;
     a.out_bytes = cs;
+    return PW_OK;
+}
+
+pw_status launch_zfast_tuned(const pw_grid *grid, pw_dtype in_dtype, const FwdArgs &a, const pw_tile *tile,
+                             void *hip_stream) {
     PW_TRY(check_forward_on_device(a));
     TileCfg cfg;
     if (tile)
@@ -519,6 +539,57 @@ pw_status pw_advect_zfast(const pw_grid *grid, const pw_layout_zfast *layout, pw
     else if (!lookup_tuned(TuneKind::Zfast, grid, in_dtype, &cfg))
         cfg = default_zfast_tile(a, in_dtype);
     return launch_zfast(a, in_dtype, cfg, static_cast<hipStream_t>(hip_stream));
+}
+
+}  // namespace
+}  // namespace pw
+
+extern "C" {
+
+pw_status pw_advect_zfast(const pw_grid *grid, const pw_layout_zfast *layout, pw_dtype in_dtype,
+                          const void *u, const void *v, const void *w, const pw_coeffs *coeffs,
+                          void *su, void *sv, void *sw, const pw_tile *tile, void *hip_stream) {
+    g_err[0] = 0;
+    FwdArgs a;
+    Range rout[3];
+    PW_TRY(validate_zfast(grid, layout, in_dtype, u, v, w, coeffs, su, sv, sw, tile, &a, rout));
+    return launch_zfast_tuned(grid, in_dtype, a, tile, hip_stream);
+}
+
+pw_status pw_advect_zfast_epilogue(const pw_grid *grid, const pw_layout_zfast *layout, pw_dtype in_dtype,
+                                   const void *u, const void *v, const void *w, const pw_coeffs *coeffs,
+                                   const pw_epilogue *ep, void *su, void *sv, void *sw, const pw_tile *tile,
+                                   void *hip_stream) {
+    g_err[0] = 0;
+    if (!ep) return fail(PW_ERR_INVALID_ARG, "epilogue is NULL");
+    FwdArgs a;
+    Range rout[3];
+    PW_TRY(validate_zfast(grid, layout, in_dtype, u, v, w, coeffs, su, sv, sw, tile, &a, rout));
+    // the addends: output layout, compute type; each either is its output
+    // (accumulation in place) or overlaps no output at all
+    const int64_t cs = a.out_bytes;
+    const int64_t olast = zfast_out_last(grid, a.out_sy, a.out_sz);
+    const char *cn[3] = {"cu", "cv", "cw"};
+    const void *cp[3] = {ep->cu, ep->cv, ep->cw};
+    void *op[3] = {su, sv, sw};
+    for (int i = 0; i < 3; ++i) {
+        PW_TRY(check_aligned(cn[i], cp[i], cs));
+        const Range rc = zspan(cn[i], cp[i], olast, cs);
+        for (int o = 0; o < 3; ++o) {
+            if (o == i && cp[i] == op[o]) continue;   // in place
+            if (overlap(rc, rout[o]))
+                return fail(PW_ERR_INVALID_ARG, "%s overlaps output %s (only %s itself may be given)", cn[i],
+                            rout[o].name, rout[i].name);
+        }
+    }
+    if (!std::isfinite(ep->alpha)) return fail(PW_ERR_INVALID_ARG, "alpha is not finite");
+    int dev = 0;
+    PW_TRY(current_device(&dev));
+    for (int i = 0; i < 3; ++i) PW_TRY(check_on_device(cn[i], cp[i], dev));
+    a.epilogue = true;
+    a.cu = ep->cu; a.cv = ep->cv; a.cw = ep->cw;
+    a.alpha = ep->alpha;
+    return launch_zfast_tuned(grid, in_dtype, a, tile, hip_stream);
 }
 
 pw_status pw_halo_fill(const pw_grid *grid, const pw_layout *layout, pw_dtype dtype, void *const fields[],

@@ -113,6 +113,11 @@ pw_status launch_halo(const HaloArgs &a, hipStream_t s);
 bool zfast_tile_supported(const TileCfg &c, pw_dtype dt);
 TileCfg default_zfast_tile(const FwdArgs &a, pw_dtype dt);
 pw_status launch_zfast(const FwdArgs &a, pw_dtype dt, const TileCfg &cfg, hipStream_t s);
+// per storage type (pw_zfast_f32.hip, ...); launch_zfast dispatches to these
+pw_status launch_zfast_f32(const FwdArgs &a, const TileCfg &cfg, hipStream_t s);
+pw_status launch_zfast_f64(const FwdArgs &a, const TileCfg &cfg, hipStream_t s);
+pw_status launch_zfast_bf16(const FwdArgs &a, const TileCfg &cfg, hipStream_t s);
+pw_status launch_zfast_f16(const FwdArgs &a, const TileCfg &cfg, hipStream_t s);
 pw_status launch_copy(const void *src, void *dst, int64_t nbytes, hipStream_t s);
 pw_status launch_copy3(const void *const *src, void *const *dst, int64_t nbytes, hipStream_t s);
 

@@ -1,0 +1,8 @@
+// z-fastest forward kernel instantiated for FP64 storage.
+#include "pw_zfast_impl.h"
+
+namespace pw {
+
+pw_status launch_zfast_f64(const FwdArgs &a, const TileCfg &cfg, hipStream_t s) { return zf::launch_dt<double>(a, cfg, s); }
+
+}  // namespace pw

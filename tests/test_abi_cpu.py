@@ -517,3 +517,17 @@ def test_zfast_launch_shape(lib):
     assert B.launch_shape("zfast", 512, 512, 64, torch.float32) == (pz, rj, -(-512 // nxc), wpb, depth)
     shape = B.launch_shape("zfast", 10, 3, 200, torch.bfloat16)
     assert shape[0] in (1, 2, 4) and 1 <= shape[2] <= 10
+
+
+def test_zfast_epilogue_validation(lib):
+    g, c, p = _args(nx=8, ny=6, nz=5)
+    q = [A + (20 + i) * MB for i in range(3)]   # addends
+    call = lambda ep, ptrs=p: lib.pw_advect_zfast_epilogue(  # noqa: E731
+        ctypes.byref(g), None, B.PW_F32, *ptrs[:3], ctypes.byref(c), ep, *ptrs[3:], None, None)
+    assert call(ctypes.byref(B.pw_epilogue(1.0, *q))) in _no_gpu_status()
+    assert call(ctypes.byref(B.pw_epilogue(1.0, *p[3:]))) in _no_gpu_status()        # in place
+    assert call(None) == B.PW_ERR_INVALID_ARG
+    assert call(ctypes.byref(B.pw_epilogue(1.0, p[4], p[4], p[5]))) == B.PW_ERR_INVALID_ARG   # cu is sv
+    assert "overlaps output" in B.pw_last_error()
+    assert call(ctypes.byref(B.pw_epilogue(float("inf"), *q))) == B.PW_ERR_INVALID_ARG
+    assert call(ctypes.byref(B.pw_epilogue(1.0, q[0] + 2, q[1], q[2]))) == B.PW_ERR_INVALID_ARG   # misaligned

@@ -154,3 +154,44 @@ def test_zfast_argument_errors():
     bad = zv.view(-1)[:20 * 8 * 4].view(20, 8, 4)
     with pytest.raises(B.PWError):
         B.advect_zfast(zu, zv, zw, c, out=(out[0], bad, out[2]))
+
+
+@pytest.mark.parametrize("storage", [None, "bfloat16"])
+@pytest.mark.parametrize("tile", [None, (1, 4, 9, 4, 2), (2, 2, 64, 1, 1), (4, 1, 5, 8, 2), (1, 8, 3, 4, 1)], ids=str)
+@pytest.mark.parametrize("shape", [(37, 9, 70), (64, 8, 64), (5, 3, 150)], ids=lambda s: "x".join(map(str, s)))
+def test_zfast_epilogue_bitwise_with_xfast(shape, tile, storage):
+    """out = c + alpha F on z-fastest arrays equals the x-fastest epilogue on
+    the transposed arrays bit for bit: accumulation in place (alpha = 1) and
+    a separate addend with alpha = -0.25."""
+    nx, ny, nz = shape
+    g = wl.make_grid(nx, ny, nz, seed=820 + nz)
+    (u, v, w), c = dev_grid(g, storage=None if storage is None else getattr(torch, storage))
+    rng = np.random.default_rng(821 + nz)
+    c0 = [torch.from_numpy(rng.uniform(-5, 5, (nz, ny, nx)).astype(np.float32)).cuda() for _ in range(3)]
+    zin = [_zf(x) for x in (u, v, w)]
+    # accumulation in place
+    xo = [x.clone() for x in c0]
+    B.advect_epilogue(u, v, w, c, xo, alpha=1.0, out=xo)
+    zo = [_zf(x) for x in c0]
+    B.advect_zfast_epilogue(*zin, c, zo, alpha=1.0, out=zo, tile=tile)
+    # separate addends, alpha = -0.25
+    xs = B.advect_epilogue(u, v, w, c, c0, alpha=-0.25)
+    zs = B.advect_zfast_epilogue(*zin, c, [_zf(x) for x in c0], alpha=-0.25, tile=tile)
+    torch.cuda.synchronize()
+    for a, b in zip(zo, xo):
+        assert torch.equal(a.permute(2, 1, 0), b)
+    for a, b in zip(zs, xs):
+        assert torch.equal(a.permute(2, 1, 0), b)
+
+
+def test_zfast_epilogue_argument_errors():
+    g = wl.make_grid(20, 8, 4, seed=822)
+    (u, v, w), c = dev_grid(g)
+    zin = [_zf(x) for x in (u, v, w)]
+    out = [torch.zeros((20, 8, 4), device="cuda") for _ in range(3)]
+    with pytest.raises(B.PWError):   # addend cu is the output sv: neither its own output nor disjoint
+        B.advect_zfast_epilogue(*zin, c, [out[1], out[1], out[2]], out=out)
+    with pytest.raises(B.PWError):
+        B.advect_zfast_epilogue(*zin, c, out, alpha=float("nan"), out=out)
+    with pytest.raises(ValueError):
+        B.advect_zfast_epilogue(*zin, c, [x.double() for x in out], out=out)

@@ -48,9 +48,9 @@ __global__ void batch_reset_kernel(unsigned long long *counter) {
     if (threadIdx.x < kXcds) counter[threadIdx.x * kCtrStride] = 0ull;
 }
 
-// MaxT: workgroup size bound (built for 256 and 512 threads, as the
-// single-grid kernels).
-template <typename Tin, int PX, int RY, int MaxT>
+// Depth: planes in flight (1 or 2).  MaxT: workgroup size bound (built for
+// 256 and 512 threads, as the single-grid kernels).
+template <typename Tin, int PX, int RY, int Depth, int MaxT>
 __global__ __launch_bounds__(MaxT) void pw_batch_kernel(const BatchSub<Tin> *__restrict__ subs, int nsub,
                                                        int64_t nitems, unsigned long long *counter) {
     const int lane = threadIdx.x & 63;
@@ -79,61 +79,45 @@ __global__ __launch_bounds__(MaxT) void pw_batch_kernel(const BatchSub<Tin> *__r
         const int64_t t2 = local / a.nzc;
         const int tx = static_cast<int>(t2 % a.ntx);
         const int ty = static_cast<int>(t2 / a.ntx);
-        strip_march<Tin, PX, RY, 1>(a, tx, ty, cz);
+        strip_march<Tin, PX, RY, Depth>(a, tx, ty, cz);
       }
     }
 }
 
 using Tin = float;   // the batched form runs FP32 storage
 
-template <int PX, int RY, int MaxT> const void *kernel_ptr() {
-    return reinterpret_cast<const void *>(&pw_batch_kernel<Tin, PX, RY, MaxT>);
+template <int PX, int RY, int Depth, int MaxT> const void *kernel_ptr() {
+    return reinterpret_cast<const void *>(&pw_batch_kernel<Tin, PX, RY, Depth, MaxT>);
 }
 
-template <int MaxT> const void *batch_kernel_t(const TileCfg &c) {
+template <int Depth, int MaxT> const void *batch_kernel_t(const TileCfg &c) {
     switch (c.px * 16 + c.ry) {
-        case 16 + 1: return kernel_ptr<1, 1, MaxT>();
-        case 16 + 2: return kernel_ptr<1, 2, MaxT>();
-        case 16 + 4: return kernel_ptr<1, 4, MaxT>();
-        case 32 + 1: return kernel_ptr<2, 1, MaxT>();
-        case 32 + 2: return kernel_ptr<2, 2, MaxT>();
-        case 32 + 4: return kernel_ptr<2, 4, MaxT>();
-        case 64 + 1: return kernel_ptr<4, 1, MaxT>();
-        case 64 + 2: return kernel_ptr<4, 2, MaxT>();
+        case 16 + 1: return kernel_ptr<1, 1, Depth, MaxT>();
+        case 16 + 2: return kernel_ptr<1, 2, Depth, MaxT>();
+        case 16 + 4: return kernel_ptr<1, 4, Depth, MaxT>();
+        case 32 + 1: return kernel_ptr<2, 1, Depth, MaxT>();
+        case 32 + 2: return kernel_ptr<2, 2, Depth, MaxT>();
+        case 32 + 4: return kernel_ptr<2, 4, Depth, MaxT>();
+        case 64 + 1: return kernel_ptr<4, 1, Depth, MaxT>();
+        case 64 + 2: return kernel_ptr<4, 2, Depth, MaxT>();
     }
     return nullptr;
 }
 
+// The instantiation a tile runs (nullptr: none).
 const void *batch_kernel(const TileCfg &c) {
-    return c.wpb <= 4 ? batch_kernel_t<256>(c) : batch_kernel_t<512>(c);
+    if (c.depth == 2) return c.wpb <= 4 ? batch_kernel_t<2, 256>(c) : batch_kernel_t<2, 512>(c);
+    if (c.depth == 1) return c.wpb <= 4 ? batch_kernel_t<1, 256>(c) : batch_kernel_t<1, 512>(c);
+    return nullptr;
 }
 
-template <int PX, int RY, int MaxT>
-void launch_t(dim3 g, dim3 b, hipStream_t s, const BatchSub<Tin> *d, int n, int64_t items, unsigned long long *c) {
-    hipLaunchKernelGGL((pw_batch_kernel<Tin, PX, RY, MaxT>), g, b, 0, s, d, n, items, c);
-}
-
-template <int MaxT>
-void launch_batch_t(const TileCfg &c, dim3 g, dim3 b, hipStream_t s, const BatchSub<Tin> *d, int n, int64_t items,
-                    unsigned long long *ctr) {
-    switch (c.px * 16 + c.ry) {
-        case 16 + 1: launch_t<1, 1, MaxT>(g, b, s, d, n, items, ctr); break;
-        case 16 + 2: launch_t<1, 2, MaxT>(g, b, s, d, n, items, ctr); break;
-        case 16 + 4: launch_t<1, 4, MaxT>(g, b, s, d, n, items, ctr); break;
-        case 32 + 1: launch_t<2, 1, MaxT>(g, b, s, d, n, items, ctr); break;
-        case 32 + 2: launch_t<2, 2, MaxT>(g, b, s, d, n, items, ctr); break;
-        case 32 + 4: launch_t<2, 4, MaxT>(g, b, s, d, n, items, ctr); break;
-        case 64 + 1: launch_t<4, 1, MaxT>(g, b, s, d, n, items, ctr); break;
-        case 64 + 2: launch_t<4, 2, MaxT>(g, b, s, d, n, items, ctr); break;
-    }
-}
-
-void launch_batch(const TileCfg &c, dim3 g, dim3 b, hipStream_t s, const BatchSub<Tin> *d, int n, int64_t items,
-                  unsigned long long *ctr) {
-    if (c.wpb <= 4)
-        launch_batch_t<256>(c, g, b, s, d, n, items, ctr);
-    else
-        launch_batch_t<512>(c, g, b, s, d, n, items, ctr);
+hipError_t launch_batch(const TileCfg &c, dim3 g, dim3 b, hipStream_t s, const BatchSub<Tin> *d, int n,
+                        int64_t items, unsigned long long *ctr) {
+    // every instantiation has the same signature: launch through its pointer
+    const void *k = batch_kernel(c);
+    if (!k) return hipErrorInvalidDeviceFunction;
+    void *args[] = {&d, &n, &items, &ctr};
+    return hipLaunchKernel(k, g, b, args, 0, s);
 }
 
 TileCfg default_batch_tile() {
@@ -241,13 +225,14 @@ pw_status enqueue(pw_batch *b, hipStream_t s) {
     hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, s, b->d_counter);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "counter reset launch");
-    launch_batch(b->tile, dim3(static_cast<unsigned>(b->blocks)), dim3(64 * b->tile.wpb), s, b->d_table,
-                 static_cast<int>(b->subs.size()), b->nitems, b->d_counter);
-    return hip_fail(hipGetLastError(), "batched kernel launch");
+    e = launch_batch(b->tile, dim3(static_cast<unsigned>(b->blocks)), dim3(64 * b->tile.wpb), s, b->d_table,
+                     static_cast<int>(b->subs.size()), b->nitems, b->d_counter);
+    if (e == hipSuccess) e = hipGetLastError();
+    return hip_fail(e, "batched kernel launch");
 }
 
 bool batch_tile_ok(const TileCfg &c) {
-    return c.depth == 1 && tile_supported(c, PW_F32) && batch_kernel(c) != nullptr;
+    return tile_supported(c, PW_F32) && batch_kernel(c) != nullptr;
 }
 
 }  // namespace
@@ -407,12 +392,14 @@ pw_status pw_batch_tune(pw_batch *b, void *hip_stream, pw_tile *chosen) {
     for (int px : {1, 2, 4})
         for (int ry : {1, 2, 4})
             for (int zl : {32, 64, 128, 256})
-                for (int wpb : {1, 4}) {
+                for (int wpb : {1, 4})
+                  for (int depth : {1, 2}) {
                     TileCfg c;
                     c.px = px;
                     c.ry = ry;
                     c.zlen = zl;
                     c.wpb = wpb;
+                    c.depth = depth;
                     if (!batch_tile_ok(c)) continue;
                     if ((st = build_table(b, c)) != PW_OK) break;
                     if ((st = enqueue(b, s)) != PW_OK) break;   // warm-up

@@ -199,8 +199,8 @@ def test_adjoint_gradient_overlap_rejected(lib):
 
 
 def test_prefetch_depth_validation(lib):
-    """prefetch: 0 (= 1) or 1 or 2 for the forward and the adjoint; 0 or 1
-    for the tangent and the batched form."""
+    """prefetch: 0 (= 1) or 1 or 2 for the forward, the adjoint and the
+    batched form; 0 or 1 for the tangent."""
     g, c, p = _args()
     for pf, ok in [(0, True), (1, True), (2, True), (3, False), (-1, False)]:
         st = _call(g, None, B.PW_F32, c, p, B.pw_tile(4, 2, 8, 1, pf))
@@ -215,7 +215,7 @@ def test_prefetch_depth_validation(lib):
     assert B.pw_advect_tangent_ex(g, None, B.PW_F32, *q[:3], c, *q[3:6], *q[6:9],
                                   B.pw_tile(1, 2, 8, 1, 1)) in _no_gpu_status()
     h = ctypes.c_void_p()
-    assert B.pw_batch_create(_items(2), 2, B.PW_F32, B.pw_tile(1, 2, 8, 4, 2), h) == B.PW_ERR_INVALID_ARG
+    assert B.pw_batch_create(_items(2), 2, B.PW_F32, B.pw_tile(1, 2, 8, 4, 3), h) == B.PW_ERR_INVALID_ARG
 
 
 def test_tangent_validation(lib):

@@ -292,8 +292,8 @@ def main():
                     help="approximate host time spent timing the oracle")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on exactly one GPU (the stencil's multi-GPU halo "
-              "exchange is a design, not an implementation); use --gpus 1", file=sys.stderr)
+        print("bench.py: libpwadv runs on one GPU (the stencil's multi-GPU halo exchange is a "
+              "design, not an implementation); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch

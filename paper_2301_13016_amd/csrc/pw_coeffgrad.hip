@@ -38,11 +38,28 @@ template <> struct CgShape<double> {
     static constexpr int PX = 1, RY = 2;
 };
 
+// x moved across lanes by a DPP control that gives every lane a source (a
+// permutation within quads or rows), both halves of the double.
+template <int Ctrl> __device__ __forceinline__ double dpp_move(double x) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), Ctrl, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), Ctrl, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+constexpr int kQuadXor1 = 0xB1;   // quad_perm [1,0,3,2]
+constexpr int kQuadXor2 = 0x4E;   // quad_perm [2,3,0,1]
+constexpr int kRowRor4 = 0x124;   // rotate by 4 within a row of 16 lanes
+constexpr int kRowRor8 = 0x128;   // rotate by 8
+
+// Sum over the 64 lanes, the same value in every lane and the same order on
+// every run: pairs and quads (quad permutations), the four quads of each
+// 16-lane row (row rotations), then the four row sums in a fixed order.  All
+// register moves (DPP, readlane): no LDS traffic and no waits.
 __device__ __forceinline__ double wave_sum(double x) {
-    // butterfly over the 64 lanes: the same order on every run
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) x += __shfl_xor(x, m, 64);
-    return x;
+    x += dpp_move<kQuadXor1>(x);
+    x += dpp_move<kQuadXor2>(x);
+    x += dpp_move<kRowRor4>(x);
+    x += dpp_move<kRowRor8>(x);
+    return (lane_value(x, 0) + lane_value(x, 16)) + (lane_value(x, 32) + lane_value(x, 48));
 }
 
 // Cotangent rows of one output level: RY rows x PX columns, clamped (rows and
@@ -79,7 +96,9 @@ __device__ __forceinline__ void load_cot(CotRows<T, PX, RY> &R, const CgK<T> &g,
 }
 
 // The six cotangent-weighted term groups of level kk, summed over the lane's
-// points into acc (FP64).
+// PX x RY points in the compute type (a handful of terms: at most three
+// roundings of 2^-24 relative to the sum of magnitudes in FP32) and handed
+// over in FP64, in which the wavefront and the strips are summed.
 template <typename T, int PX, int RY, bool Full>
 __device__ __forceinline__ void level_cg(const Plane<T, PX, RY> &m, const Plane<T, PX, RY> &c,
                                          const Plane<T, PX, RY> &p, const CotRows<T, PX, RY> &R, bool lane0,
@@ -99,6 +118,7 @@ __device__ __forceinline__ void level_cg(const Plane<T, PX, RY> &m, const Plane<
     }
 #define XM(arr, L, r, x) ((x) == 0 ? L[r] : G(arr, r, (x) - 1))
 #define XP(arr, Rr, r, x) ((x) == PX - 1 ? Rr[r] : G(arr, r, (x) + 1))
+    T s[kQ] = {T(0), T(0), T(0), T(0), T(0), T(0)};
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
         const int q = r + 1;
@@ -128,14 +148,16 @@ __device__ __forceinline__ void level_cg(const Plane<T, PX, RY> &m, const Plane<
                               G(c.w, q - 1, x) * (G(c.v, q - 1, x) + G(p.v, q - 1, x)));
             const T cz1 = G(m.w, q, x) * (wc + G(m.w, q, x));
             const T cz2 = G(p.w, q, x) * (wc + G(p.w, q, x));
-            acc[0] += static_cast<double>(fma_(a, az1, b * bz1));
-            acc[1] -= static_cast<double>(fma_(a, az2, b * bz2));
-            acc[2] += static_cast<double>(e * cz1);
-            acc[3] -= static_cast<double>(e * cz2);
-            acc[4] += static_cast<double>(fma_(a, ax, fma_(b, bx, e * cx)));
-            acc[5] += static_cast<double>(fma_(a, ay, fma_(b, by, e * cy)));
+            s[0] += fma_(a, az1, b * bz1);
+            s[1] -= fma_(a, az2, b * bz2);
+            s[2] += e * cz1;
+            s[3] -= e * cz2;
+            s[4] += fma_(a, ax, fma_(b, bx, e * cx));
+            s[5] += fma_(a, ay, fma_(b, by, e * cy));
         }
     }
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) acc[q] = static_cast<double>(s[q]);
 #undef G
 #undef XM
 #undef XP

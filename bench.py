@@ -406,6 +406,7 @@ def main():
     log("generating the 1024x1024x256 grid ...")
     g2 = wl.config_grid(c2)
     co2 = B.Coeffs.from_host(g2.coeffs, device=dev)
+    co2_64 = B.Coeffs.from_host(g2.coeffs, device=dev, dtype=torch.float64)
     f32 = [torch.from_numpy(x).to(dev) for x in (g2.u, g2.v, g2.w)]
     del g2
     outs2 = tuple(torch.empty((n2[2], n2[1], n2[0]), device=dev) for _ in range(3))
@@ -421,10 +422,20 @@ def main():
         log("c2 %s: kernel %.4f ms, %.1f Gpt/s" % (name, kms2, res2[name]["gpts"]))
         if dt != torch.float32:
             del ins
-    for name in ("bf16", "fp16"):
+    # FP64 storage and arithmetic (the FP32 values widened exactly)
+    del outs2
+    outs64 = tuple(torch.empty((n2[2], n2[1], n2[0]), device=dev, dtype=torch.float64) for _ in range(3))
+    ins64 = [x.double() for x in f32]
+    call = prebuilt_forward(B, ins64, outs64, co2_64, stream)
+    _, kms64 = time_launches(torch, lambda i: call(), 1, 30, 3, stream)
+    res2["fp64"] = dict(gpts=round(pts2 / (kms64 * 1e-3) / 1e9, 2), kernel_ms=round(kms64, 4),
+                        hbm_gbs=round(algo_bytes(*n2, 1, 8, 8) / (kms64 * 1e-3) / 1e9, 1))
+    log("c2 fp64: kernel %.4f ms, %.1f Gpt/s" % (kms64, res2["fp64"]["gpts"]))
+    del call, ins64, outs64
+    for name in ("bf16", "fp16", "fp64"):
         res2[name]["speed_vs_fp32"] = round(res2["fp32"]["kernel_ms"] / res2[name]["kernel_ms"], 3)
     forms["precision_1024x1024x256"] = res2
-    del f32, outs2
+    del f32
     torch.cuda.empty_cache()
 
     # ------------------------------------------------------------ differentiation form: c4

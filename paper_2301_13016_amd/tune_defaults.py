@@ -25,6 +25,8 @@ SHAPES = [
     (128, 128, 128, "float32", 15),
     (256, 256, 256, "float32", 9),
     (512, 512, 128, "float32", 9),
+    (1024, 1024, 256, "float64", 1),
+    (512, 512, 64, "float64", 1),
 ]
 
 

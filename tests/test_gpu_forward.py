@@ -198,6 +198,23 @@ def test_precision_grid_sampled_parity(grid_1024, storage, report):
     assert max(worst) <= bound, worst
 
 
+def test_precision_grid_fp64_sampled_parity(grid_1024, report):
+    """The same grid in FP64 storage and arithmetic (the FP32 values widened
+    exactly, FP64 coefficients holding the same values), as the benchmark
+    times it: sampled sub-boxes against the oracle at the FP64 bar."""
+    g = grid_1024
+    (u, v, w), _ = dev_grid(g)
+    c = B.Coeffs.from_host(g.coeffs, dtype=torch.float64)
+    out = B.advect(u.double(), v.double(), w.double(), c)
+    torch.cuda.synchronize()
+    assert all(o.dtype == torch.float64 for o in out)
+    boxes = sample_boxes(g.nx, g.ny, g.nz, n_random=8, seed=3)
+    worst = subbox_errors(out, g, boxes)
+    report.setdefault("precision_1024x1024x256", {})["float64"] = dict(zip(("su", "sv", "sw"), worst),
+                                                                       boxes=len(boxes))
+    assert max(worst) <= 1e-13, worst
+
+
 def test_headline_grid_sampled_parity(report):
     """The 512 x 512 x 64 FP32 grid in the launch shape the benchmark times,
     checked on corner, edge and random sub-boxes against the oracle."""

@@ -39,11 +39,14 @@ def oracle_errors(outs, u, v, w, coeffs, halo=1):
     return [(a_scaled_error(o, r, m), normwise_error(o, r)) for o, r, m in zip(outs, ref, mag)]
 
 
-def subbox_errors(outs_dev, g, boxes, halo=1, inputs=None):
-    """Errors of device outputs on interior sub-boxes (k0, k1, j0, j1, i0, i1):
-    the oracle is run on each box with its halo cut out of the padded inputs."""
+def subbox_errors(outs_dev, g, boxes, halo=1, inputs=None, normwise=None):
+    """Worst A-scaled error per field of device outputs on interior sub-boxes
+    (k0, k1, j0, j1, i0, i1): the oracle is run on each box with its halo cut
+    out of the padded inputs.  If ``normwise`` is a list, the worst
+    max|got - ref| / max|ref| per field (over the boxes) is appended to it."""
     u, v, w = (g.u, g.v, g.w) if inputs is None else inputs
     worst = [0.0, 0.0, 0.0]
+    dmax, rmax = [0.0, 0.0, 0.0], [0.0, 0.0, 0.0]
     for (k0, k1, j0, j1, i0, i1) in boxes:
         sl = (slice(k0, k1 + 2 * halo), slice(j0, j1 + 2 * halo), slice(i0, i1 + 2 * halo))
         c = dict(tcx=g.tcx, tcy=g.tcy, **{n: getattr(g, n)[k0:k1] for n in ("tzc1", "tzc2", "tzd1", "tzd2")})
@@ -51,6 +54,10 @@ def subbox_errors(outs_dev, g, boxes, halo=1, inputs=None):
         for f in range(3):
             got = outs_dev[f][k0:k1, j0:j1, i0:i1].cpu().numpy()
             worst[f] = max(worst[f], a_scaled_error(got, ref[f], mag[f]))
+            dmax[f] = max(dmax[f], float(np.max(np.abs(got.astype(np.float64) - ref[f]))))
+            rmax[f] = max(rmax[f], float(np.max(np.abs(ref[f]))))
+    if normwise is not None:
+        normwise.extend(d / r if r > 0 else d for d, r in zip(dmax, rmax))
     return worst
 
 

@@ -8,8 +8,11 @@
 // its writes, and the result equals the sequential x, y, z fill.  The work of
 // one field is three segments: the z-halo planes (whole planes), the y-halo
 // rows of the remaining planes (whole rows) and the x-halo cells of the
-// remaining rows.  Values move as raw bits (2, 4 or 8 bytes); a negated
-// mirror flips the sign bit, which is exact negation.
+// remaining rows.  The first two are whole rows: one wavefront takes a row,
+// finds its source row once, and its lanes move consecutive cells (coalesced
+// loads and stores, per-cell work only on the x axis).  The x-halo cells are
+// scattered, one per thread.  Values move as raw bits (2, 4 or 8 bytes); a
+// negated mirror flips the sign bit, which is exact negation.
 #include <algorithm>
 
 #include "pw_internal.h"
@@ -18,7 +21,7 @@ namespace pw {
 namespace {
 
 struct HaloSeg {
-    int64_t nzs, nys, nxs;  // work items of the three segments
+    int64_t nzs, nys, nxs;  // rows of the z and y segments, cells of the x segment
     int64_t k0, kn;         // planes covered by the y and x segments
     int64_t j0, jn;         // rows covered by the x segment
     int32_t mode[3];        // x, y, z
@@ -57,28 +60,50 @@ __global__ __launch_bounds__(256) void halo_kernel(HaloK a) {
     const HaloSeg &s = a.seg[f];
     const I h = I(a.h), h2 = I(2 * a.h);
     const I px = I(a.nx + 2 * a.h), py = I(a.ny + 2 * a.h);
-    const I nzs = I(s.nzs), nzys = I(s.nzs + s.nys), total = I(s.nzs + s.nys + s.nxs);
-    const I jn = I(s.jn);
     const U signbit = U(1) << (8 * sizeof(U) - 1);
-    const I stride = I(gridDim.x) * I(blockDim.x);
-    for (I t = I(blockIdx.x) * I(blockDim.x) + I(threadIdx.x); t < total; t += stride) {
-        int64_t k, j, i;
-        if (t < nzs) {
-            const I r = t / px, q = r / py;
-            i = t - r * px;
+
+    // whole rows: the z-halo planes (row index r < nzs) and the y-halo rows of
+    // the other planes; one wavefront per row
+    const I rows = I(s.nzs + s.nys), nzs = I(s.nzs);
+    const int lane = static_cast<int>(threadIdx.x & 63);
+    const I nwaves = I(gridDim.x) * I(blockDim.x >> 6);
+    const I wave0 = I(blockIdx.x) * I(blockDim.x >> 6) + I(__builtin_amdgcn_readfirstlane(threadIdx.x >> 6));
+    for (I r = wave0; r < rows; r += nwaves) {
+        int64_t k, j;
+        if (r < nzs) {
+            const I q = r / py;
             j = r - q * py;
             k = q < h ? q : a.nz + q;
-        } else if (t < nzys) {
-            const I u = t - nzs, r = u / px, c = r / h2, q = r - c * h2;
-            i = u - r * px;
+        } else {
+            const I u = r - nzs, c = u / h2, q = u - c * h2;
             k = s.k0 + c;
             j = q < h ? q : a.ny + q;
-        } else {
-            const I u = t - nzys, r = u / h2, c = r / jn, q = u - r * h2;
-            j = s.j0 + (r - c * jn);
-            k = s.k0 + c;
-            i = q < h ? q : a.nx + q;
         }
+        int sign_kj = 1;
+        const int64_t sj = source(j, a.ny, a.h, s.mode[1], sign_kj);
+        const int64_t sk = source(k, a.nz, a.h, s.mode[2], sign_kj);
+        const U *src = base + sk * a.sz + sj * a.sy;
+        U *dst = base + k * a.sz + j * a.sy;
+        for (int64_t i = lane; i < int64_t(px); i += 64) {
+            int sign = sign_kj;
+            const int64_t si = source(i, a.nx, a.h, s.mode[0], sign);
+            U val = 0;
+            if (sign != 0) {
+                val = src[si];
+                if (sign < 0) val ^= signbit;
+            }
+            dst[i] = val;
+        }
+    }
+
+    // the x-halo cells of the remaining rows, one per thread
+    const I cells = I(s.nxs), jn = I(s.jn);
+    const I stride = I(gridDim.x) * I(blockDim.x);
+    for (I t = I(blockIdx.x) * I(blockDim.x) + I(threadIdx.x); t < cells; t += stride) {
+        const I r = t / h2, c = r / jn, q = t - r * h2;
+        const int64_t j = s.j0 + (r - c * jn);
+        const int64_t k = s.k0 + c;
+        const int64_t i = q < h ? q : a.nx + q;
         int sign = 1;
         const int64_t si = source(i, a.nx, a.h, s.mode[0], sign);
         const int64_t sj = source(j, a.ny, a.h, s.mode[1], sign);
@@ -92,9 +117,10 @@ __global__ __launch_bounds__(256) void halo_kernel(HaloK a) {
     }
 }
 
+// `most`: the largest number of blocks any field's work asks for.
 template <typename U>
 hipError_t launch_u(const HaloK &k, int nf, int64_t most, bool small, hipStream_t s) {
-    const int64_t blocks = std::min<int64_t>((most + 255) / 256, 2048);
+    const int64_t blocks = std::min<int64_t>(most, 2048);
     const dim3 grid(unsigned(std::max<int64_t>(blocks, 1)), unsigned(nf));
     if (small)
         hipLaunchKernelGGL((halo_kernel<U, uint32_t>), grid, dim3(256), 0, s, k);
@@ -125,18 +151,21 @@ pw_status launch_halo(const HaloArgs &a, hipStream_t s) {
         g.kn = fz ? a.nz : pz;
         g.j0 = fy ? h : 0;
         g.jn = fy ? a.ny : py;
-        g.nzs = fz ? 2 * h * py * px : 0;
-        g.nys = fy ? g.kn * 2 * h * px : 0;
-        g.nxs = fx ? g.kn * g.jn * 2 * h : 0;
+        g.nzs = fz ? 2 * h * py : 0;        // rows
+        g.nys = fy ? g.kn * 2 * h : 0;      // rows
+        g.nxs = fx ? g.kn * g.jn * 2 * h : 0;   // cells
         for (int d = 0; d < 3; ++d) g.mode[d] = m[d];
         k.f[nf] = a.f[f];
         k.seg[nf] = g;
-        most = std::max(most, g.nzs + g.nys + g.nxs);
+        // four rows per block (one per wavefront), 256 cells per block
+        most = std::max({most, (g.nzs + g.nys + 3) / 4, (g.nxs + 255) / 256});
         ++nf;
     }
     if (nf == 0) return PW_OK;
-    // 32-bit decomposition when every count and the loop's last increment fit
-    const bool small = most + 2048 * 256 < (int64_t(1) << 32) && px * py < (int64_t(1) << 32);
+    // 32-bit decomposition when every count and a loop's last increment fit
+    int64_t biggest = 0;
+    for (int f = 0; f < nf; ++f) biggest = std::max({biggest, k.seg[f].nzs + k.seg[f].nys, k.seg[f].nxs});
+    const bool small = biggest + 2048 * 256 < (int64_t(1) << 32) && px * py < (int64_t(1) << 32);
     hipError_t e = hipSuccess;
     switch (a.es) {
         case 2: e = launch_u<uint16_t>(k, nf, most, small, s); break;

@@ -409,6 +409,22 @@ typedef struct {
 pw_status pw_halo_fill(const pw_grid *grid, const pw_layout *layout, pw_dtype dtype, void *const fields[],
                        const pw_halo_modes modes[], int32_t nfields, void *hip_stream);
 
+/* ------------------------------------------------ boundaries by addressing
+ * The forward operator, optionally with the fused epilogue, with the halo's
+ * boundary rules applied by addressing instead of a halo fill: the result is
+ * bit for bit that of pw_halo_fill(u, v, w with rules *bc) followed by
+ * pw_advect_ex / pw_advect_epilogue, but the halo is neither written nor (on
+ * axes whose rule is not KEEP) read -- a read of a halo cell goes to its
+ * periodic or nearest-interior source.  Rules per axis: PW_HALO_KEEP (read
+ * the stored halo), PW_HALO_PERIODIC, PW_HALO_COPY; the others change values
+ * (zero, negation) rather than addresses and return PW_ERR_UNSUPPORTED --
+ * fill the halo for those.  A periodic x-y domain on one GPU then needs no
+ * fill step at all.  ep == NULL: out = F; otherwise as pw_advect_epilogue.
+ * Same layouts, dtypes, tiles, ownership and errors as pw_advect_ex. */
+pw_status pw_advect_bc(const pw_grid *grid, const pw_layout *layout, pw_dtype in_dtype, const void *u,
+                       const void *v, const void *w, const pw_coeffs *coeffs, const pw_halo_modes *bc,
+                       const pw_epilogue *ep, void *su, void *sv, void *sw, const pw_tile *tile, void *hip_stream);
+
 /* Library version string (static storage). */
 const char *pw_version(void);
 

@@ -116,6 +116,9 @@ _SIGNATURES = {
     "pw_advect_zfast_epilogue": [ctypes.POINTER(pw_grid), ctypes.POINTER(pw_layout_zfast), ctypes.c_int,
                                  _P, _P, _P, ctypes.POINTER(pw_coeffs), ctypes.POINTER(pw_epilogue), _P, _P, _P,
                                  ctypes.POINTER(pw_tile), _P],
+    "pw_advect_bc": [ctypes.POINTER(pw_grid), ctypes.POINTER(pw_layout), ctypes.c_int, _P, _P, _P,
+                     ctypes.POINTER(pw_coeffs), ctypes.POINTER(pw_halo_modes), ctypes.POINTER(pw_epilogue),
+                     _P, _P, _P, ctypes.POINTER(pw_tile), _P],
     "pw_halo_fill": [ctypes.POINTER(pw_grid), ctypes.POINTER(pw_layout), ctypes.c_int, ctypes.POINTER(_P),
                      ctypes.POINTER(pw_halo_modes), ctypes.c_int32, _P],
     "pw_stream_copy": [_P, _P, ctypes.c_int64, _P],
@@ -365,6 +368,34 @@ def advect_zfast(u, v, w, coeffs: Coeffs, halo=1, out=None, tile=None, stream=No
     st = pw_advect_zfast(grid, layout, _dtype_code(u), u.data_ptr(), v.data_ptr(), w.data_ptr(), c,
                          su.data_ptr(), sv.data_ptr(), sw.data_ptr(), tl, _stream_handle(stream))
     _check(st, "pw_advect_zfast")
+    return su, sv, sw
+
+
+def advect_bc(u, v, w, coeffs: Coeffs, bc, halo=1, out=None, addends=None, alpha=1.0, tile=None, stream=None):
+    """The forward (with ``addends``: out = addends + alpha * F) with boundary
+    rules applied by addressing: ``bc`` is an (x, y, z) triple of "keep",
+    "periodic" or "copy" (names or codes).  Equals halo_fill with the same
+    rules followed by advect / advect_epilogue, without touching the halo."""
+    import torch
+    if not (u.shape == v.shape == w.shape and u.stride() == v.stride() == w.stride()
+            and u.dtype == v.dtype == w.dtype):
+        raise ValueError("u, v, w must share shape, strides and dtype")
+    grid = _grid_from(u, halo)
+    odt = torch.float64 if u.dtype == torch.float64 else torch.float32
+    if out is None:
+        out = tuple(torch.empty((grid.nz, grid.ny, grid.nx), dtype=odt, device=u.device) for _ in range(3))
+    su, sv, sw = out
+    layout = _layout_from(u, su)
+    modes = pw_halo_modes(*(_halo_code(m) for m in bc))
+    ep = None
+    if addends is not None:
+        if any(c.stride() != su.stride() or c.dtype != odt for c in addends):
+            raise ValueError("addends must share the outputs' strides and dtype")
+        ep = pw_epilogue(float(alpha), *(c.data_ptr() for c in addends))
+    tl = None if tile is None else pw_tile(*tile)
+    st = lib().pw_advect_bc(grid, layout, _dtype_code(u), u.data_ptr(), v.data_ptr(), w.data_ptr(), coeffs.c_struct(),
+                            modes, ep, su.data_ptr(), sv.data_ptr(), sw.data_ptr(), tl, _stream_handle(stream))
+    _check(st, "pw_advect_bc")
     return su, sv, sw
 
 

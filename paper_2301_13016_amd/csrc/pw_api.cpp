@@ -228,6 +228,69 @@ void forward_ranges(const FwdArgs &a, uintptr_t (*in)[2], uintptr_t (*out)[2]) {
     }
 }
 
+// Forward with optional boundary rules (bc, NULL: read the stored halo) and
+// optional fused epilogue (ep, NULL: out = F): validation and launch.
+pw_status advect_general(const pw_grid *grid, const pw_layout *layout, pw_dtype in_dtype, const void *u,
+                         const void *v, const void *w, const pw_coeffs *coeffs, const pw_halo_modes *bc,
+                         const pw_epilogue *ep, void *su, void *sv, void *sw, const pw_tile *tile,
+                         void *hip_stream) {
+    FwdArgs a;
+    PW_TRY(validate_forward(grid, layout, in_dtype, u, v, w, coeffs, su, sv, sw, &a));
+    if (tile && !tile_supported(to_cfg(*tile), in_dtype))
+        return fail(PW_ERR_INVALID_ARG, "unsupported forward tile cols=%d rows=%d zlen=%d waves=%d prefetch=%d",
+                    tile->cols_per_lane, tile->rows_per_strip, tile->zlen, tile->waves_per_group, tile->prefetch);
+    if (bc) {
+        const int32_t m[3] = {bc->x, bc->y, bc->z};
+        for (int d = 0; d < 3; ++d)
+            if (m[d] != PW_HALO_KEEP && m[d] != PW_HALO_PERIODIC && m[d] != PW_HALO_COPY)
+                return fail(m[d] >= 0 && m[d] <= PW_HALO_REFLECT_NEG ? PW_ERR_UNSUPPORTED : PW_ERR_INVALID_ARG,
+                            "boundary rule %d on axis %c: only keep, periodic and copy are applied by addressing",
+                            m[d], "xyz"[d]);
+        a.bcx = m[0];
+        a.bcy = m[1];
+        a.bcz = m[2];
+    }
+    int dev = 0;
+    if (ep) {
+        // the addends: output layout, compute type; each either is its output
+        // (accumulation in place) or overlaps no output at all (inputs may be
+        // overlapped: they are only read)
+        const int64_t cs = a.out_bytes;
+        Layout L;
+        PW_TRY(resolve_layout(grid, layout, a.in_bytes, cs, &L));
+        const char *cn[3] = {"cu", "cv", "cw"};
+        const void *cp[3] = {ep->cu, ep->cv, ep->cw};
+        void *op[3] = {su, sv, sw};
+        const Range rout[3] = {out_range("su", su, grid, L, cs), out_range("sv", sv, grid, L, cs),
+                               out_range("sw", sw, grid, L, cs)};
+        for (int i = 0; i < 3; ++i) {
+            PW_TRY(check_aligned(cn[i], cp[i], cs));
+            const Range rc = out_range(cn[i], cp[i], grid, L, cs);
+            for (int o = 0; o < 3; ++o) {
+                if (o == i && cp[i] == op[o]) continue;   // in place
+                if (overlap(rc, rout[o]))
+                    return fail(PW_ERR_INVALID_ARG, "%s overlaps output %s (only %s itself may be given)", cn[i],
+                                rout[o].name, rout[i].name);
+            }
+        }
+        if (!std::isfinite(ep->alpha)) return fail(PW_ERR_INVALID_ARG, "alpha is not finite");
+        PW_TRY(check_forward_on_device(a));
+        PW_TRY(current_device(&dev));
+        for (int i = 0; i < 3; ++i) PW_TRY(check_on_device(cn[i], cp[i], dev));
+        a.epilogue = true;
+        a.cu = ep->cu; a.cv = ep->cv; a.cw = ep->cw;
+        a.alpha = ep->alpha;
+    } else {
+        PW_TRY(check_forward_on_device(a));
+    }
+    TileCfg cfg;
+    if (tile)
+        cfg = to_cfg(*tile);
+    else if (!lookup_tuned(TuneKind::Forward, grid, in_dtype, &cfg))
+        cfg = default_forward_tile(a, in_dtype);
+    return launch_forward(a, in_dtype, cfg, static_cast<hipStream_t>(hip_stream));
+}
+
 }  // namespace pw
 
 using namespace pw;
@@ -268,46 +331,15 @@ pw_status pw_advect_epilogue(const pw_grid *grid, const pw_layout *layout, pw_dt
                              void *hip_stream) {
     g_err[0] = 0;
     if (!ep) return fail(PW_ERR_INVALID_ARG, "epilogue is NULL");
-    FwdArgs a;
-    PW_TRY(validate_forward(grid, layout, in_dtype, u, v, w, coeffs, su, sv, sw, &a));
-    if (tile && !tile_supported(to_cfg(*tile), in_dtype))
-        return fail(PW_ERR_INVALID_ARG, "unsupported forward tile cols=%d rows=%d zlen=%d waves=%d prefetch=%d",
-                    tile->cols_per_lane, tile->rows_per_strip, tile->zlen, tile->waves_per_group, tile->prefetch);
-    // the addends: output layout, compute type; each either is its output
-    // (accumulation in place) or overlaps no output at all (inputs may be
-    // overlapped: they are only read)
-    const int64_t cs = a.out_bytes;
-    Layout L;
-    PW_TRY(resolve_layout(grid, layout, a.in_bytes, cs, &L));
-    const char *cn[3] = {"cu", "cv", "cw"};
-    const void *cp[3] = {ep->cu, ep->cv, ep->cw};
-    void *op[3] = {su, sv, sw};
-    const Range rout[3] = {out_range("su", su, grid, L, cs), out_range("sv", sv, grid, L, cs),
-                           out_range("sw", sw, grid, L, cs)};
-    for (int i = 0; i < 3; ++i) {
-        PW_TRY(check_aligned(cn[i], cp[i], cs));
-        const Range rc = out_range(cn[i], cp[i], grid, L, cs);
-        for (int o = 0; o < 3; ++o) {
-            if (o == i && cp[i] == op[o]) continue;   // in place
-            if (overlap(rc, rout[o]))
-                return fail(PW_ERR_INVALID_ARG, "%s overlaps output %s (only %s itself may be given)", cn[i],
-                            rout[o].name, rout[i].name);
-        }
-    }
-    if (!std::isfinite(ep->alpha)) return fail(PW_ERR_INVALID_ARG, "alpha is not finite");
-    PW_TRY(check_forward_on_device(a));
-    int dev = 0;
-    PW_TRY(current_device(&dev));
-    for (int i = 0; i < 3; ++i) PW_TRY(check_on_device(cn[i], cp[i], dev));
-    a.epilogue = true;
-    a.cu = ep->cu; a.cv = ep->cv; a.cw = ep->cw;
-    a.alpha = ep->alpha;
-    TileCfg cfg;
-    if (tile)
-        cfg = to_cfg(*tile);
-    else if (!lookup_tuned(TuneKind::Forward, grid, in_dtype, &cfg))
-        cfg = default_forward_tile(a, in_dtype);
-    return launch_forward(a, in_dtype, cfg, static_cast<hipStream_t>(hip_stream));
+    return advect_general(grid, layout, in_dtype, u, v, w, coeffs, nullptr, ep, su, sv, sw, tile, hip_stream);
+}
+
+pw_status pw_advect_bc(const pw_grid *grid, const pw_layout *layout, pw_dtype in_dtype, const void *u,
+                       const void *v, const void *w, const pw_coeffs *coeffs, const pw_halo_modes *bc,
+                       const pw_epilogue *ep, void *su, void *sv, void *sw, const pw_tile *tile, void *hip_stream) {
+    g_err[0] = 0;
+    if (!bc) return fail(PW_ERR_INVALID_ARG, "bc is NULL");
+    return advect_general(grid, layout, in_dtype, u, v, w, coeffs, bc, ep, su, sv, sw, tile, hip_stream);
 }
 
 pw_status pw_advect_tangent(const pw_grid *grid, const pw_layout *layout, pw_dtype dtype,

@@ -45,11 +45,13 @@ using namespace dev;
 // Depth: planes in flight ahead of the level being computed (1 or 2).
 // Epi: fused epilogue, out = c + alpha * F (accumulation into the outputs
 // when c is the output itself, or a time update c + dt * F).
+// Bc: boundary rules applied by addressing (pw_advect_bc); the plain
+// instantiations carry no mapping code.
 // MaxT: the workgroup size bound the kernel is compiled for.  Every shape is
 // built twice: for up to 256 threads (four wavefronts, one per SIMD, so a
 // wavefront may use the whole 512-entry register file: the large strips keep
 // their planes in registers instead of spilling) and for up to 512.
-template <typename Tin, int PX, int RY, int Depth, bool Epi, int MaxT>
+template <typename Tin, int PX, int RY, int Depth, bool Epi, bool Bc, int MaxT>
 __global__ __launch_bounds__(MaxT) void pw_forward_kernel(FwdK<Tin> a) {
     // wavefront index as a scalar, so that per-strip conditions stay scalar
     const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
@@ -59,22 +61,30 @@ __global__ __launch_bounds__(MaxT) void pw_forward_kernel(FwdK<Tin> a) {
     const int tx = t2 % a.ntx;
     const int ty = (t2 / a.ntx) * a.wpb + wave;
     if (ty >= a.nty) return;   // whole wavefront
-    strip_march<Tin, PX, RY, Depth, Epi>(a, tx, ty, cz);
+    strip_march<Tin, PX, RY, Depth, Epi, Bc>(a, tx, ty, cz);
+}
+
+template <typename Tin, int PX, int RY, bool Epi, bool Bc>
+void launch_fwd_b(const FwdK<Tin> &a, const TileCfg &cfg, dim3 grid, dim3 block, hipStream_t s) {
+    if (cfg.depth == 2) {
+        if (cfg.wpb <= 4)
+            hipLaunchKernelGGL((pw_forward_kernel<Tin, PX, RY, 2, Epi, Bc, 256>), grid, block, 0, s, a);
+        else
+            hipLaunchKernelGGL((pw_forward_kernel<Tin, PX, RY, 2, Epi, Bc, 512>), grid, block, 0, s, a);
+    } else {
+        if (cfg.wpb <= 4)
+            hipLaunchKernelGGL((pw_forward_kernel<Tin, PX, RY, 1, Epi, Bc, 256>), grid, block, 0, s, a);
+        else
+            hipLaunchKernelGGL((pw_forward_kernel<Tin, PX, RY, 1, Epi, Bc, 512>), grid, block, 0, s, a);
+    }
 }
 
 template <typename Tin, int PX, int RY, bool Epi>
 void launch_fwd_k(const FwdK<Tin> &a, const TileCfg &cfg, dim3 grid, dim3 block, hipStream_t s) {
-    if (cfg.depth == 2) {
-        if (cfg.wpb <= 4)
-            hipLaunchKernelGGL((pw_forward_kernel<Tin, PX, RY, 2, Epi, 256>), grid, block, 0, s, a);
-        else
-            hipLaunchKernelGGL((pw_forward_kernel<Tin, PX, RY, 2, Epi, 512>), grid, block, 0, s, a);
-    } else {
-        if (cfg.wpb <= 4)
-            hipLaunchKernelGGL((pw_forward_kernel<Tin, PX, RY, 1, Epi, 256>), grid, block, 0, s, a);
-        else
-            hipLaunchKernelGGL((pw_forward_kernel<Tin, PX, RY, 1, Epi, 512>), grid, block, 0, s, a);
-    }
+    if (a.bcx != PW_HALO_KEEP || a.bcy != PW_HALO_KEEP || a.bcz != PW_HALO_KEEP)
+        launch_fwd_b<Tin, PX, RY, Epi, true>(a, cfg, grid, block, s);
+    else
+        launch_fwd_b<Tin, PX, RY, Epi, false>(a, cfg, grid, block, s);
 }
 
 template <typename Tin, int PX, int RY>
@@ -110,6 +120,9 @@ pw_status launch_fwd_t(const FwdArgs &g, const TileCfg &cfg, hipStream_t s) {
     a.cv = static_cast<const Tc *>(g.cv);
     a.cw = static_cast<const Tc *>(g.cw);
     a.alpha = static_cast<Tc>(g.alpha);
+    a.bcx = g.bcx;
+    a.bcy = g.bcy;
+    a.bcz = g.bcz;
     const int64_t nblk_y = (a.nty + cfg.wpb - 1) / cfg.wpb;
     const int64_t nblocks = static_cast<int64_t>(a.ntx) * nblk_y * a.nzc;
     if (nblocks <= 0 || nblocks > 0x7fffffffLL) return fail(PW_ERR_UNSUPPORTED, "grid too large");

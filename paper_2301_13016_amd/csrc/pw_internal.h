@@ -41,6 +41,8 @@ struct FwdArgs {
     bool epilogue = false;
     const void *cu = nullptr, *cv = nullptr, *cw = nullptr;
     double alpha = 1.0;
+    // boundary rules applied by addressing (pw_halo_mode per axis)
+    int32_t bcx = PW_HALO_KEEP, bcy = PW_HALO_KEEP, bcz = PW_HALO_KEEP;
 };
 
 struct AdjArgs {

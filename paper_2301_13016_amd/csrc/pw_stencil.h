@@ -134,7 +134,37 @@ template <typename Tin> struct FwdK {
     // fused epilogue (used by the Epi instantiations only): out = c + alpha * F
     const Tc *cu, *cv, *cw;
     Tc alpha;
+    // boundary rules applied by addressing (pw_halo_mode per axis; KEEP reads
+    // the stored halo): a read of a halo cell goes to its periodic or
+    // nearest-interior source instead
+    int32_t bcx = PW_HALO_KEEP, bcy = PW_HALO_KEEP, bcz = PW_HALO_KEEP;
 };
+
+// Padded index that a read of padded index p (0 <= p < n+2h) uses on an axis
+// of n interior cells and halo h: p itself (an interior cell, or the stored
+// halo under KEEP), or for a halo cell its source under the periodic or
+// zero-gradient rule -- for the cells the depth-one stencil reads (p = h-1,
+// p = n+h) the same map as the halo fill's, and in bounds for every p.
+// Selects only, no branches: a branch between loads in flight would make the
+// compiler wait for all of them where the paths join.
+__device__ __forceinline__ int bc_src(int p, int n, int h, int mode) {
+    const bool lo = p < h, hi = p >= n + h;
+    const int per = lo ? p + n : (hi ? p - n : p);
+    const int cpy = lo ? h : (hi ? n + h - 1 : p);
+    return mode == PW_HALO_PERIODIC ? per : (mode == PW_HALO_COPY ? cpy : p);
+}
+// bc_src when the kernel is built for boundary rules (Bc), else p unchanged:
+// the plain kernels carry no mapping code at all.
+template <bool Bc> __device__ __forceinline__ int bc_map(int p, int n, int h, int mode) {
+    if constexpr (Bc) {
+        return bc_src(p, n, h, mode);
+    } else {
+        (void)n;
+        (void)h;
+        (void)mode;
+        return p;
+    }
+}
 
 // One z-plane of the strip as loaded: rows 0..RY+1 are the strip's rows
 // jj0-1 .. jj0+RY (interior numbering), each the lane's PX columns in storage
@@ -157,24 +187,36 @@ template <int RY> struct StripAddr {
 // one vector load; in the strip at the x end of the grid every lane reads
 // element-wise with the columns clamped into the row (every column a stored
 // output reads is in range, so clamping only affects values that are not
-// used).  The choice is made per wavefront, so neither path branches per lane.
-template <typename Tin, int PX, bool Full>
+// used) and, in kernels built for boundary rules (Bc), then mapped by the
+// axis' rule (bc_src over n interior columns, halo h).  One-column lanes need
+// no clamping beyond their start column unless mapped.  The choice is made
+// per wavefront, so neither path branches per lane.
+template <typename Tin, int PX, bool Full, bool Bc = false>
 __device__ __forceinline__ void load_row(typename Vec<Tin, PX>::type &dst, const char *plane, uint32_t off, int col,
-                                         int last_col) {
-    if constexpr (Full || PX == 1) {
+                                         int last_col, int n, int h, int bc) {
+    if constexpr (Full || (PX == 1 && !Bc)) {
         (void)col;
         (void)last_col;
+        (void)n;
+        (void)h;
+        (void)bc;
         using VT = typename Vec<Tin, PX>::type;
         dst = PW_GLOAD(VT, plane + off);
     } else {
         const char *row = plane + off - static_cast<int64_t>(col) * static_cast<int64_t>(sizeof(Tin));
 #pragma unroll
-        for (int m = 0; m < PX; ++m)
-            dst[m] = PW_GLOAD(Tin, row + static_cast<int64_t>(min(col + m, last_col)) * sizeof(Tin));
+        for (int m = 0; m < PX; ++m) {
+            const Tin x = PW_GLOAD(Tin, row + static_cast<int64_t>(bc_map<Bc>(min(col + m, last_col), n, h, bc)) *
+                                               static_cast<int64_t>(sizeof(Tin)));
+            if constexpr (PX == 1)
+                dst = x;
+            else
+                dst[m] = x;
+        }
     }
 }
 
-template <typename Tin, int PX, int RY, bool Full>
+template <typename Tin, int PX, int RY, bool Full, bool Bc = false>
 __device__ __forceinline__ void load_plane(Plane<Tin, PX, RY> &P, const FwdK<Tin> &a,
                                            int kp, const StripAddr<RY> &s, int last_col) {
     const int64_t pb = static_cast<int64_t>(kp) * a.in_sz * static_cast<int64_t>(sizeof(Tin));
@@ -183,9 +225,9 @@ __device__ __forceinline__ void load_plane(Plane<Tin, PX, RY> &P, const FwdK<Tin
     const char *bw = reinterpret_cast<const char *>(a.w) + pb;
 #pragma unroll
     for (int r = 0; r < RY + 2; ++r) {
-        load_row<Tin, PX, Full>(P.u[r], bu, s.roff[r], s.col, last_col);
-        load_row<Tin, PX, Full>(P.v[r], bv, s.roff[r], s.col, last_col);
-        load_row<Tin, PX, Full>(P.w[r], bw, s.roff[r], s.col, last_col);
+        load_row<Tin, PX, Full, Bc>(P.u[r], bu, s.roff[r], s.col, last_col, a.nx, a.h, a.bcx);
+        load_row<Tin, PX, Full, Bc>(P.v[r], bv, s.roff[r], s.col, last_col, a.nx, a.h, a.bcx);
+        load_row<Tin, PX, Full, Bc>(P.w[r], bw, s.roff[r], s.col, last_col, a.nx, a.h, a.bcx);
     }
     P.hu = PW_GLOAD(Tin, bu + s.hoff);
     P.hv = PW_GLOAD(Tin, bv + s.hoff);
@@ -388,7 +430,7 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
 // start of the level, before that level's plane prefetch (a scheduling
 // barrier keeps the compiler from moving them after it), so waiting for them
 // never waits for the prefetch.
-template <typename Tin, int PX, int RY, bool Full, int Depth, bool Epi>
+template <typename Tin, int PX, int RY, bool Full, int Depth, bool Epi, bool Bc>
 __device__ __forceinline__ void strip_march_t(const FwdK<Tin> &a, int tx, int ty, int cz) {
     using Tc = typename Storage<Tin>::Tc;
     const int lane = threadIdx.x & 63;
@@ -401,15 +443,18 @@ __device__ __forceinline__ void strip_march_t(const FwdK<Tin> &a, int tx, int ty
 
     StripAddr<RY> s;
     s.col = min(ii0 + a.h, last_col);
+    // halo rows, the packed halo columns and halo planes go through the
+    // boundary rules (identity under KEEP)
 #pragma unroll
     for (int r = 0; r < RY + 2; ++r) {
-        const int prow = min(jj0 - 1 + a.h + r, prows - 1);
+        const int prow = bc_map<Bc>(min(jj0 - 1 + a.h + r, prows - 1), a.ny, a.h, a.bcy);
         s.roff[r] = static_cast<uint32_t>((prow * a.in_sy + s.col) * static_cast<int>(sizeof(Tin)));
     }
     {   // packed halo: lane r -> left halo of row r, lane 32+r -> right halo of row r
         const int hr = min(lane & 31, RY + 1);
-        const int hrow = min(jj0 - 1 + a.h + hr, prows - 1);
-        const int hcol = (lane & 32) ? min(tx * 64 * PX + 64 * PX + a.h, last_col) : tx * 64 * PX + a.h - 1;
+        const int hrow = bc_map<Bc>(min(jj0 - 1 + a.h + hr, prows - 1), a.ny, a.h, a.bcy);
+        const int hcol = bc_map<Bc>((lane & 32) ? min(tx * 64 * PX + 64 * PX + a.h, last_col) : tx * 64 * PX + a.h - 1,
+                                    a.nx, a.h, a.bcx);
         s.hoff = static_cast<uint32_t>((hrow * a.in_sy + hcol) * static_cast<int>(sizeof(Tin)));
     }
     uint32_t ooff[RY];
@@ -433,21 +478,21 @@ __device__ __forceinline__ void strip_march_t(const FwdK<Tin> &a, int tx, int ty
     // re-reads plane k1, a cache hit): a conditional load would merge two
     // paths with different loads in flight, and the wait inserted at such a
     // merge drains every outstanding load, prefetch included.
-#define PW_PLOAD(P, kp) load_plane<Tin, PX, RY, Full>(P, a, min((kp), k1) + h, s, last_col)
+#define PW_PLOAD(P, kp) load_plane<Tin, PX, RY, Full, Bc>(P, a, bc_map<Bc>(min((kp), k1) + h, a.nz, h, a.bcz), s, last_col)
 #define PW_LOAD(P, kp)                                                   \
     do {                                                                 \
         if constexpr (Epi) {                                             \
             load_epi<Tin, PX, RY, Full>(Ep, a, kk, ooff, ic);            \
             __builtin_amdgcn_sched_barrier(0);                           \
         }                                                                \
-        load_plane<Tin, PX, RY, Full>(P, a, min((kp), k1) + h, s, last_col); \
+        load_plane<Tin, PX, RY, Full, Bc>(P, a, bc_map<Bc>(min((kp), k1) + h, a.nz, h, a.bcz), s, last_col); \
     } while (0)
 #define PW_LEVEL(M, C, P) level<Tin, PX, RY, Full, Epi>(M, C, P, a, kk, lane0, lane63, nvalid, ooff, row_ok, Ep)
     int kk = k0;
     if constexpr (Depth == 1) {
         // four-plane ring: planes kk-1, kk, kk+1 feed level kk, kk+2 in flight
         Plane<Tin, PX, RY> A, B, C, D;
-        load_plane<Tin, PX, RY, Full>(A, a, k0 - 1 + h, s, last_col);
+        load_plane<Tin, PX, RY, Full, Bc>(A, a, bc_map<Bc>(k0 - 1 + h, a.nz, h, a.bcz), s, last_col);
         PW_PLOAD(B, k0);
         PW_PLOAD(C, k0 + 1);
         for (;;) {
@@ -468,7 +513,7 @@ __device__ __forceinline__ void strip_march_t(const FwdK<Tin> &a, int tx, int ty
         // five-plane ring: planes kk+2 and kk+3 in flight
         static_assert(Depth == 2, "prefetch depth 1 or 2");
         Plane<Tin, PX, RY> A, B, C, D, E;
-        load_plane<Tin, PX, RY, Full>(A, a, k0 - 1 + h, s, last_col);
+        load_plane<Tin, PX, RY, Full, Bc>(A, a, bc_map<Bc>(k0 - 1 + h, a.nz, h, a.bcz), s, last_col);
         PW_PLOAD(B, k0);
         PW_PLOAD(C, k0 + 1);
         PW_PLOAD(D, k0 + 2);
@@ -495,16 +540,17 @@ __device__ __forceinline__ void strip_march_t(const FwdK<Tin> &a, int tx, int ty
 #undef PW_LEVEL
 }
 
-template <typename Tin, int PX, int RY, int Depth, bool Epi = false>
+// Bc: reads go through the boundary rules a.bcx/bcy/bcz (pw_advect_bc).
+template <typename Tin, int PX, int RY, int Depth, bool Epi = false, bool Bc = false>
 __device__ __forceinline__ void strip_march(const FwdK<Tin> &a, int tx, int ty, int cz) {
     if constexpr (PX == 1) {
         // one-column lanes: loads never need clamping beyond the start column,
         // and one masked store per row is cheap, so one path serves every strip
-        strip_march_t<Tin, PX, RY, false, Depth, Epi>(a, tx, ty, cz);
+        strip_march_t<Tin, PX, RY, false, Depth, Epi, Bc>(a, tx, ty, cz);
     } else if ((tx + 1) * 64 * PX <= a.nx) {
-        strip_march_t<Tin, PX, RY, true, Depth, Epi>(a, tx, ty, cz);
+        strip_march_t<Tin, PX, RY, true, Depth, Epi, Bc>(a, tx, ty, cz);
     } else {
-        strip_march_t<Tin, PX, RY, false, Depth, Epi>(a, tx, ty, cz);
+        strip_march_t<Tin, PX, RY, false, Depth, Epi, Bc>(a, tx, ty, cz);
     }
 }
 

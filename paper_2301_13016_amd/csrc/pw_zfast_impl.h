@@ -75,9 +75,9 @@ __device__ __forceinline__ void load_xplane(ZPlane<Tin, PZ, RJ> &P, const ZfK<Ti
     const char *bw = reinterpret_cast<const char *>(a.w) + pb;
 #pragma unroll
     for (int r = 0; r < RJ + 2; ++r) {
-        load_row<Tin, PZ, Full>(P.u[r], bu, s.roff[r], s.kcol, last_k);
-        load_row<Tin, PZ, Full>(P.v[r], bv, s.roff[r], s.kcol, last_k);
-        load_row<Tin, PZ, Full>(P.w[r], bw, s.roff[r], s.kcol, last_k);
+        load_row<Tin, PZ, Full>(P.u[r], bu, s.roff[r], s.kcol, last_k, a.nz, a.h, PW_HALO_KEEP);
+        load_row<Tin, PZ, Full>(P.v[r], bv, s.roff[r], s.kcol, last_k, a.nz, a.h, PW_HALO_KEEP);
+        load_row<Tin, PZ, Full>(P.w[r], bw, s.roff[r], s.kcol, last_k, a.nz, a.h, PW_HALO_KEEP);
     }
     P.hu = PW_GLOAD(Tin, bu + s.hoff);
     P.hv = PW_GLOAD(Tin, bv + s.hoff);

@@ -531,3 +531,20 @@ def test_zfast_epilogue_validation(lib):
     assert "overlaps output" in B.pw_last_error()
     assert call(ctypes.byref(B.pw_epilogue(float("inf"), *q))) == B.PW_ERR_INVALID_ARG
     assert call(ctypes.byref(B.pw_epilogue(1.0, q[0] + 2, q[1], q[2]))) == B.PW_ERR_INVALID_ARG   # misaligned
+
+
+def test_advect_bc_validation(lib):
+    g, c, p = _args()
+    call = lambda bc, ep=None: lib.pw_advect_bc(ctypes.byref(g), None, B.PW_F32, *p[:3], ctypes.byref(c),  # noqa
+                                                bc, ep, *p[3:], None, None)
+    assert call(ctypes.byref(B.pw_halo_modes(1, 1, 2))) in _no_gpu_status()
+    assert call(ctypes.byref(B.pw_halo_modes(0, 0, 0))) in _no_gpu_status()
+    assert call(None) == B.PW_ERR_INVALID_ARG
+    assert call(ctypes.byref(B.pw_halo_modes(3, 1, 1))) == B.PW_ERR_UNSUPPORTED      # zero: a value rule
+    assert "addressing" in B.pw_last_error()
+    assert call(ctypes.byref(B.pw_halo_modes(1, 5, 1))) == B.PW_ERR_UNSUPPORTED      # negated mirror
+    assert call(ctypes.byref(B.pw_halo_modes(1, 1, 9))) == B.PW_ERR_INVALID_ARG      # unknown rule
+    q = [A + (20 + i) * MB for i in range(3)]
+    assert call(ctypes.byref(B.pw_halo_modes(1, 1, 1)), ctypes.byref(B.pw_epilogue(0.5, *q))) in _no_gpu_status()
+    assert call(ctypes.byref(B.pw_halo_modes(1, 1, 1)),
+                ctypes.byref(B.pw_epilogue(float("nan"), *q))) == B.PW_ERR_INVALID_ARG

@@ -1,0 +1,123 @@
+"""GPU tests of boundary rules applied by addressing (pw_advect_bc): the
+result equals halo fill + forward bit for bit, the halo is never written,
+and a periodic domain conserves energy exactly without any fill."""
+import itertools
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import dev_grid
+from paper_2301_13016_amd import binding as B
+from paper_2301_13016_amd import workloads as wl
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("no GPU", allow_module_level=True)
+
+
+@pytest.fixture(autouse=True)
+def _announce(request):
+    sys.__stderr__.write("\n[gpu-test] %s\n" % request.node.nodeid)
+    sys.__stderr__.flush()
+    yield
+
+
+RULES = ["keep", "periodic", "copy"]
+
+
+def _fill_then_advect(ins, c, bc, halo, tile, addends=None, alpha=1.0):
+    filled = [x.clone() for x in ins]
+    B.halo_fill(filled, bc, halo=halo)
+    if addends is None:
+        return B.advect(*filled, c, halo=halo, tile=tile)
+    return B.advect_epilogue(*filled, c, [a.clone() for a in addends], alpha=alpha, halo=halo, tile=tile)
+
+
+@pytest.mark.parametrize("storage", [None, "float64", "bfloat16", "float16"])
+@pytest.mark.parametrize("shape", [(130, 7, 9), (64, 5, 3), (1, 1, 1), (65, 3, 2), (300, 2, 5)],
+                         ids=lambda s: "x".join(map(str, s)))
+def test_every_rule_combination_bitwise(shape, storage):
+    nx, ny, nz = shape
+    dt = np.float64 if storage == "float64" else np.float32
+    g = wl.make_grid(nx, ny, nz, seed=900 + nx + ny, dtype=dt)
+    sdt = None if storage in (None, "float64") else getattr(torch, storage)
+    (u, v, w), c = dev_grid(g, storage=sdt)
+    before = [x.clone() for x in (u, v, w)]
+    for bc in itertools.product(RULES, RULES, RULES):
+        got = B.advect_bc(u, v, w, c, bc)
+        ref = _fill_then_advect((u, v, w), c, bc, 1, None)
+        torch.cuda.synchronize()
+        for a, b in zip(got, ref):
+            assert torch.equal(a, b), bc
+    for x, y in zip((u, v, w), before):   # inputs, halo included, untouched
+        assert torch.equal(x, y)
+
+
+@pytest.mark.parametrize("tile", [(4, 2, 64, 1, 2), (1, 1, 5, 4, 1), (2, 4, 3, 8, 1), (4, 1, 7, 2, 2), (1, 2, 9, 1, 2)],
+                         ids=str)
+def test_launch_shapes_and_epilogue(tile):
+    """Every strip kind (full, x-edge, one column per lane), z-chunks and both
+    prefetch depths; with the fused epilogue as a periodic time step."""
+    g = wl.make_grid(197, 13, 22, seed=910)
+    (u, v, w), c = dev_grid(g)
+    rng = np.random.default_rng(911)
+    adds = [torch.from_numpy(rng.uniform(-3, 3, (22, 13, 197)).astype(np.float32)).cuda() for _ in range(3)]
+    for bc in [("periodic", "periodic", "copy"), ("copy", "periodic", "periodic"), ("periodic", "keep", "copy")]:
+        got = B.advect_bc(u, v, w, c, bc, tile=tile)
+        ref = _fill_then_advect((u, v, w), c, bc, 1, tile)
+        got_e = B.advect_bc(u, v, w, c, bc, addends=adds, alpha=-0.5, tile=tile)
+        ref_e = _fill_then_advect((u, v, w), c, bc, 1, tile, addends=adds, alpha=-0.5)
+        torch.cuda.synchronize()
+        for a, b in zip(got + got_e, ref + ref_e):
+            assert torch.equal(a, b), (bc, tile)
+
+
+@pytest.mark.parametrize("halo", [2, 3])
+def test_wider_halo(halo):
+    g = wl.make_grid(70, 9, 6, seed=912, halo=halo)
+    (u, v, w), c = dev_grid(g)
+    for bc in [("periodic",) * 3, ("copy", "periodic", "keep")]:
+        got = B.advect_bc(u, v, w, c, bc, halo=halo)
+        ref = _fill_then_advect((u, v, w), c, bc, halo, None)
+        torch.cuda.synchronize()
+        for a, b in zip(got, ref):
+            assert torch.equal(a, b), bc
+
+
+def test_periodic_domain_conserves_energy_without_a_fill():
+    """Integer winds whose halo holds garbage, FP64, cyclic dyadic
+    coefficients: with periodic rules on all axes sum(u su + v sv + w sw) is
+    exactly zero and the outputs equal the oracle on the periodically filled
+    grid."""
+    from oracle import halo as H
+    rng = np.random.default_rng(913)
+    nz, ny, nx = 8, 12, 70
+    pads = []
+    for _ in range(3):
+        a = rng.uniform(-9, 9, (nz + 2, ny + 2, nx + 2))
+        a[1:-1, 1:-1, 1:-1] = rng.integers(-4, 5, (nz, ny, nx))
+        pads.append(a)
+    tzc2 = rng.choice([0.5, 0.25, 0.125], nz)
+    tzd2 = rng.choice([0.5, 0.25, 0.125], nz)
+    coeffs = dict(tcx=0.25, tcy=0.125, tzc1=np.roll(tzc2, 1), tzc2=tzc2, tzd1=np.roll(tzd2, 1), tzd2=tzd2)
+    dev = [torch.from_numpy(a).cuda() for a in pads]
+    out = B.advect_bc(*dev, B.Coeffs.from_host(coeffs, dtype=torch.float64), ("periodic",) * 3)
+    torch.cuda.synchronize()
+    e = sum(float(torch.sum(p[1:-1, 1:-1, 1:-1] * s)) for p, s in zip(dev, out))
+    assert e == 0.0
+    ref = oracle.forward(*[H.fill(a, 1, ("periodic",) * 3) for a in pads], coeffs)
+    for a, b in zip(out, ref):
+        assert np.array_equal(a.cpu().numpy(), b)
+
+
+def test_value_rules_are_unsupported():
+    g = wl.make_grid(20, 8, 4, seed=914)
+    (u, v, w), c = dev_grid(g)
+    for bc in [("zero", "keep", "keep"), ("keep", "reflect", "keep"), ("keep", "keep", "reflect_neg")]:
+        with pytest.raises(B.PWError) as ei:
+            B.advect_bc(u, v, w, c, bc)
+        assert ei.value.status == B.PW_ERR_UNSUPPORTED

@@ -18,6 +18,14 @@ interior cells, halo cell p (padded index, p < h or p >= n+h) takes:
                2(n+h)-1-p above (needs n >= h)
   reflect_neg  minus that mirror image (the field vanishes on the face)
   keep         its own value (the axis is left alone)
+
+fold() is the adjoint (transpose) of fill(): the fill is linear, fill = Fz Fy
+Fx with one map per axis, so its transpose applies the per-axis transposes
+in the reverse order z, y, x.  Each adds every halo cell of its axis, times
+the sign of its rule, into the cell it was copied from and clears the halo
+cell (zero: the halo value is dropped; keep: the axis is left alone).  It
+turns gradients with respect to filled arrays into gradients with respect to
+the arrays before the fill.
 """
 from __future__ import annotations
 
@@ -59,4 +67,29 @@ def fill(a, halo, modes):
             src = [slice(None)] * 3
             src[ax] = _source_index(p, n, h, mode)
             out[tuple(dst)] = -out[tuple(src)] if mode == "reflect_neg" else out[tuple(src)]
+    return out
+
+
+def fold(g, halo, modes):
+    """The adjoint of fill(., halo, modes) applied to padded array ``g``."""
+    out = np.array(g, dtype=np.float64, copy=True)
+    h = halo
+    for ax, mode in reversed(list(zip((2, 1, 0), modes))):
+        if mode not in MODES:
+            raise ValueError("unknown halo mode %r" % mode)
+        if mode == "keep":
+            continue
+        size = out.shape[ax]
+        n = size - 2 * h
+        if mode in ("reflect", "reflect_neg") and n < h:
+            raise ValueError("reflect needs at least as many interior cells as the halo is wide")
+        for p in list(range(h)) + list(range(n + h, size)):
+            dst = [slice(None)] * 3
+            dst[ax] = p
+            if mode != "zero":
+                src = [slice(None)] * 3
+                src[ax] = _source_index(p, n, h, mode)
+                sign = -1.0 if mode == "reflect_neg" else 1.0
+                out[tuple(src)] += sign * out[tuple(dst)]
+            out[tuple(dst)] = 0.0
     return out

@@ -368,3 +368,39 @@ def test_periodic_fill_conserves_energy():
     c = dict(tcx=0.25, tcy=0.125, tzc1=np.roll(tzc2, 1), tzc2=tzc2, tzd1=np.roll(tzd2, 1), tzd2=tzd2)
     su, sv, sw = oracle.forward(*pads, c)
     assert np.sum(ui * su) + np.sum(vi * sv) + np.sum(wi * sw) == 0
+
+
+
+def test_halo_fold_is_the_transpose_of_the_fill():
+    """fold = fill^T, checked against the explicit matrix of the fill built
+    column by column from unit vectors on tiny grids (exact: every entry of
+    the matrix is 0 or +-1), for every mode combination."""
+    from oracle import halo as H
+    rng = np.random.default_rng(36)
+    for h, shape in ((1, (2 + 2, 1 + 2, 3 + 2)), (2, (2 + 4, 2 + 4, 3 + 4))):
+        size = int(np.prod(shape))
+        for modes in itertools.product(H.MODES, repeat=3):
+            if any(m.startswith("reflect") and n < h for m, n in zip(modes, (shape[2] - 2 * h, shape[1] - 2 * h,
+                                                                              shape[0] - 2 * h))):
+                continue
+            M = np.empty((size, size))
+            for c in range(size):
+                e = np.zeros(size)
+                e[c] = 1.0
+                M[:, c] = H.fill(e.reshape(shape), h, modes).ravel()
+            y = rng.integers(-5, 6, shape).astype(np.float64)
+            assert np.array_equal(H.fold(y, h, modes).ravel(), M.T @ y.ravel()), (h, modes)
+
+
+def test_halo_fold_dot_product_identity():
+    """<fill(x), y> = <x, fold(y)> on random data, larger grids, mixed rules."""
+    from oracle import halo as H
+    rng = np.random.default_rng(37)
+    for h, modes in ((1, ("periodic", "copy", "reflect_neg")), (2, ("reflect", "periodic", "zero")),
+                     (3, ("periodic", "periodic", "periodic")), (1, ("keep", "zero", "copy"))):
+        shape = (5 + 2 * h, 4 + 2 * h, 7 + 2 * h)
+        x = rng.uniform(-1, 1, shape)
+        y = rng.uniform(-1, 1, shape)
+        lhs = float(np.sum(H.fill(x, h, modes) * y))
+        rhs = float(np.sum(x * H.fold(y, h, modes)))
+        assert abs(lhs - rhs) <= 1e-12 * max(1.0, abs(lhs)), (h, modes)

@@ -409,6 +409,20 @@ typedef struct {
 pw_status pw_halo_fill(const pw_grid *grid, const pw_layout *layout, pw_dtype dtype, void *const fields[],
                        const pw_halo_modes modes[], int32_t nfields, void *hip_stream);
 
+/* The adjoint (transpose) of pw_halo_fill with the same rules, in place:
+ * gradients with respect to filled arrays become gradients with respect to
+ * the arrays before the fill.  The fill is x, then y, then z; the fold takes
+ * the per-axis transposes in the order z, y, x: every halo cell of the axis
+ * is added, times the sign of its rule (-1 for REFLECT_NEG), into the cell it
+ * was copied from, in ascending order of its index, and then set to zero
+ * (ZERO: only set to zero; KEEP: the axis is left alone).  On one GPU this
+ * is the reverse of the halo exchange: halo gradients go back to their
+ * owners.  PW_F32 / PW_F64 only (PW_ERR_UNSUPPORTED otherwise); other
+ * arguments and errors as pw_halo_fill.  Three small launches on
+ * hip_stream. */
+pw_status pw_halo_fold(const pw_grid *grid, const pw_layout *layout, pw_dtype dtype, void *const fields[],
+                       const pw_halo_modes modes[], int32_t nfields, void *hip_stream);
+
 /* ------------------------------------------------ boundaries by addressing
  * The forward operator, optionally with the fused epilogue, with the halo's
  * boundary rules applied by addressing instead of a halo fill: the result is

@@ -121,6 +121,8 @@ _SIGNATURES = {
                      _P, _P, _P, ctypes.POINTER(pw_tile), _P],
     "pw_halo_fill": [ctypes.POINTER(pw_grid), ctypes.POINTER(pw_layout), ctypes.c_int, ctypes.POINTER(_P),
                      ctypes.POINTER(pw_halo_modes), ctypes.c_int32, _P],
+    "pw_halo_fold": [ctypes.POINTER(pw_grid), ctypes.POINTER(pw_layout), ctypes.c_int, ctypes.POINTER(_P),
+                     ctypes.POINTER(pw_halo_modes), ctypes.c_int32, _P],
     "pw_stream_copy": [_P, _P, ctypes.c_int64, _P],
     "pw_stream_copy3": [ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.c_int64, _P],
     "pw_tune": [ctypes.POINTER(pw_grid), ctypes.c_int, ctypes.c_int32, ctypes.POINTER(pw_tile),
@@ -228,6 +230,14 @@ def pw_halo_fill(grid, layout, dtype, fields, modes, stream=None):
     f = (_P * max(n, 1))(*fields)
     m = (pw_halo_modes * max(n, 1))(*[pw_halo_modes(*mm) for mm in modes])
     return lib().pw_halo_fill(grid, layout, dtype, f, m, n, stream)
+
+
+def pw_halo_fold(grid, layout, dtype, fields, modes, stream=None):
+    """fields: device addresses; modes: (x, y, z) mode codes per field."""
+    n = len(fields)
+    f = (_P * max(n, 1))(*fields)
+    m = (pw_halo_modes * max(n, 1))(*[pw_halo_modes(*mm) for mm in modes])
+    return lib().pw_halo_fold(grid, layout, dtype, f, m, n, stream)
 
 
 def pw_stream_copy(src, dst, nbytes, stream=None):
@@ -613,11 +623,7 @@ def _halo_code(m):
     return int(m)
 
 
-def halo_fill(fields, modes, halo=1, stream=None):
-    """Fill the halo of padded tensors in place (same shape, strides and dtype,
-    on the GPU).  ``modes`` is one (x, y, z) triple for every field or a list
-    of triples, one per field; each entry is a name from HALO_MODES or its
-    code.  Returns ``fields``."""
+def _halo_call(fn, name, fields, modes, halo, stream):
     fields = list(fields)
     if not fields:
         return fields
@@ -633,9 +639,34 @@ def halo_fill(fields, modes, halo=1, stream=None):
     if u.stride(-1) != 1:
         raise ValueError("x (last) dimension must be contiguous")
     layout = pw_layout(u.stride(1), u.stride(0), grid.nx, grid.nx * grid.ny)
-    _check(pw_halo_fill(grid, layout, _dtype_code(u), [f.data_ptr() for f in fields], codes,
-                        _stream_handle(stream)), "pw_halo_fill")
+    _check(fn(grid, layout, _dtype_code(u), [f.data_ptr() for f in fields], codes, _stream_handle(stream)), name)
     return fields
+
+
+def halo_fold(fields, modes, halo=1, stream=None):
+    """The adjoint of halo_fill with the same rules, in place on float32 /
+    float64 gradient tensors shaped like the padded fields.  Returns
+    ``fields``."""
+    return _halo_call(pw_halo_fold, "pw_halo_fold", fields, modes, halo, stream)
+
+
+def advect_bc_adjoint(u, v, w, coeffs: Coeffs, bc, gsu, gsv, gsw, halo=1, stream=None):
+    """Gradients of <advect_bc(u, v, w, bc), (gsu, gsv, gsw)> with respect to
+    the padded u, v, w as given (before the boundary rules): the adjoint
+    kernel at the filled state, then the fold.  Halo entries on axes whose
+    rule is not keep come out zero."""
+    filled = [x.clone() for x in (u, v, w)]
+    halo_fill(filled, bc, halo=halo, stream=stream)
+    grads = advect_adjoint(*filled, coeffs, gsu, gsv, gsw, halo=halo, stream=stream)
+    return tuple(halo_fold(list(grads), bc, halo=halo, stream=stream))
+
+
+def halo_fill(fields, modes, halo=1, stream=None):
+    """Fill the halo of padded tensors in place (same shape, strides and dtype,
+    on the GPU).  ``modes`` is one (x, y, z) triple for every field or a list
+    of triples, one per field; each entry is a name from HALO_MODES or its
+    code.  Returns ``fields``."""
+    return _halo_call(pw_halo_fill, "pw_halo_fill", fields, modes, halo, stream)
 
 
 def stream_copy(src, dst, stream=None):
@@ -694,6 +725,52 @@ def _autograd_function():
 
 _PWAdvect = None
 _PWAdvectCoeffs = None
+_PWAdvectBC = None
+
+
+def _autograd_function_bc():
+    import torch
+
+    class PWAdvectBC(torch.autograd.Function):
+        """PW advection with boundary rules applied by addressing:
+        apply(u, v, w, coeffs, bc, halo=1) = advect_bc.  Reverse mode = the
+        adjoint kernel at the filled state followed by the halo fold, so the
+        gradients are with respect to u, v, w as given (zero in the halo on
+        axes whose rule is not keep); forward mode = the tangent kernel on the
+        filled state and direction."""
+
+        @staticmethod
+        def forward(ctx, u, v, w, coeffs, bc, halo=1):
+            ctx.save_for_backward(u, v, w)
+            ctx.save_for_forward(u, v, w)
+            ctx.coeffs, ctx.bc, ctx.halo = coeffs, bc, halo
+            return advect_bc(u, v, w, coeffs, bc, halo=halo)
+
+        @staticmethod
+        def jvp(ctx, du, dv, dw, _dcoeffs=None, _dbc=None, _dhalo=None):
+            u, v, w = ctx.saved_tensors
+            d = [torch.zeros_like(u) if x is None else x.clone() for x in (du, dv, dw)]
+            xf = [x.clone() for x in (u, v, w)]
+            halo_fill(xf, ctx.bc, halo=ctx.halo)
+            halo_fill(d, ctx.bc, halo=ctx.halo)
+            return advect_tangent(*xf, ctx.coeffs, *d, halo=ctx.halo)
+
+        @staticmethod
+        def backward(ctx, gsu, gsv, gsw):
+            u, v, w = ctx.saved_tensors
+            gu, gv, gw = advect_bc_adjoint(u, v, w, ctx.coeffs, ctx.bc, gsu.contiguous(), gsv.contiguous(),
+                                           gsw.contiguous(), halo=ctx.halo)
+            return gu, gv, gw, None, None, None
+
+    return PWAdvectBC
+
+
+def PWAdvectBC():
+    """The autograd Function of advect_bc (created on first use)."""
+    global _PWAdvectBC
+    if _PWAdvectBC is None:
+        _PWAdvectBC = _autograd_function_bc()
+    return _PWAdvectBC
 
 
 def _autograd_function_coeffs():

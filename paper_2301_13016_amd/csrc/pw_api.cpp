@@ -228,6 +228,54 @@ void forward_ranges(const FwdArgs &a, uintptr_t (*in)[2], uintptr_t (*out)[2]) {
     }
 }
 
+// Validation shared by the halo fill and fold: fills the launch operands.
+pw_status validate_halo(const pw_grid *grid, const pw_layout *layout, pw_dtype dtype, void *const fields[],
+                        const pw_halo_modes modes[], int32_t nfields, HaloArgs *out) {
+    PW_TRY(check_grid(grid));
+    const int64_t es = elem_size(dtype);
+    if (!es) return fail(PW_ERR_INVALID_ARG, "unknown dtype %d", int(dtype));
+    if (!fields || !modes) return fail(PW_ERR_INVALID_ARG, "fields or modes is NULL");
+    if (nfields < 1 || nfields > kMaxHaloFields)
+        return fail(PW_ERR_INVALID_ARG, "nfields must be in 1..%d, got %d", kMaxHaloFields, nfields);
+    const int64_t px = grid->nx + 2 * grid->halo, py = grid->ny + 2 * grid->halo;
+    HaloArgs &a = *out;
+    a.nf = nfields;
+    a.es = int32_t(es);
+    a.nx = grid->nx;
+    a.ny = grid->ny;
+    a.nz = grid->nz;
+    a.h = grid->halo;
+    a.sy = layout ? layout->in_sy : px;
+    a.sz = layout ? layout->in_sz : px * py;
+    if (a.sy < px) return fail(PW_ERR_INVALID_ARG, "in_sy %lld < nx+2h %lld", (long long)a.sy, (long long)px);
+    if (a.sz / py < a.sy) return fail(PW_ERR_INVALID_ARG, "in_sz too small for in_sy*(ny+2h)");
+    const int64_t n[3] = {grid->nx, grid->ny, grid->nz};
+    const Layout L{a.sy, a.sz, grid->nx, grid->nx * grid->ny};
+    Range r[kMaxHaloFields];
+    static const char *const names[kMaxHaloFields] = {"fields[0]", "fields[1]", "fields[2]", "fields[3]",
+                                                      "fields[4]", "fields[5]", "fields[6]", "fields[7]"};
+    for (int f = 0; f < nfields; ++f) {
+        PW_TRY(check_aligned(names[f], fields[f], es));
+        const int32_t m[3] = {modes[f].x, modes[f].y, modes[f].z};
+        for (int d = 0; d < 3; ++d) {
+            if (m[d] < PW_HALO_KEEP || m[d] > PW_HALO_REFLECT_NEG)
+                return fail(PW_ERR_INVALID_ARG, "modes[%d]: unknown halo mode %d", f, m[d]);
+            if ((m[d] == PW_HALO_REFLECT || m[d] == PW_HALO_REFLECT_NEG) && n[d] < grid->halo)
+                return fail(PW_ERR_INVALID_ARG, "modes[%d]: reflect on an axis of %lld cells needs halo <= %lld",
+                            f, (long long)n[d], (long long)n[d]);
+            a.mode[f][d] = m[d];
+        }
+        a.f[f] = fields[f];
+        r[f] = in_range(names[f], fields[f], grid, L, es);
+        for (int g = 0; g < f; ++g)
+            if (overlap(r[f], r[g])) return fail(PW_ERR_INVALID_ARG, "%s overlaps %s", r[f].name, r[g].name);
+    }
+    int dev = 0;
+    PW_TRY(current_device(&dev));
+    for (int f = 0; f < nfields; ++f) PW_TRY(check_on_device(names[f], fields[f], dev));
+    return PW_OK;
+}
+
 // Forward with optional boundary rules (bc, NULL: read the stored halo) and
 // optional fused epilogue (ep, NULL: out = F): validation and launch.
 pw_status advect_general(const pw_grid *grid, const pw_layout *layout, pw_dtype in_dtype, const void *u,
@@ -626,50 +674,20 @@ pw_status pw_advect_zfast_epilogue(const pw_grid *grid, const pw_layout_zfast *l
 
 pw_status pw_halo_fill(const pw_grid *grid, const pw_layout *layout, pw_dtype dtype, void *const fields[],
                        const pw_halo_modes modes[], int32_t nfields, void *hip_stream) {
-    using namespace pw;
-    PW_TRY(check_grid(grid));
-    const int64_t es = elem_size(dtype);
-    if (!es) return fail(PW_ERR_INVALID_ARG, "unknown dtype %d", int(dtype));
-    if (!fields || !modes) return fail(PW_ERR_INVALID_ARG, "fields or modes is NULL");
-    if (nfields < 1 || nfields > kMaxHaloFields)
-        return fail(PW_ERR_INVALID_ARG, "nfields must be in 1..%d, got %d", kMaxHaloFields, nfields);
-    const int64_t px = grid->nx + 2 * grid->halo, py = grid->ny + 2 * grid->halo;
+    g_err[0] = 0;
     HaloArgs a{};
-    a.nf = nfields;
-    a.es = int32_t(es);
-    a.nx = grid->nx;
-    a.ny = grid->ny;
-    a.nz = grid->nz;
-    a.h = grid->halo;
-    a.sy = layout ? layout->in_sy : px;
-    a.sz = layout ? layout->in_sz : px * py;
-    if (a.sy < px) return fail(PW_ERR_INVALID_ARG, "in_sy %lld < nx+2h %lld", (long long)a.sy, (long long)px);
-    if (a.sz / py < a.sy) return fail(PW_ERR_INVALID_ARG, "in_sz too small for in_sy*(ny+2h)");
-    const int64_t n[3] = {grid->nx, grid->ny, grid->nz};
-    const Layout L{a.sy, a.sz, grid->nx, grid->nx * grid->ny};
-    Range r[kMaxHaloFields];
-    static const char *const names[kMaxHaloFields] = {"fields[0]", "fields[1]", "fields[2]", "fields[3]",
-                                                      "fields[4]", "fields[5]", "fields[6]", "fields[7]"};
-    for (int f = 0; f < nfields; ++f) {
-        PW_TRY(check_aligned(names[f], fields[f], es));
-        const int32_t m[3] = {modes[f].x, modes[f].y, modes[f].z};
-        for (int d = 0; d < 3; ++d) {
-            if (m[d] < PW_HALO_KEEP || m[d] > PW_HALO_REFLECT_NEG)
-                return fail(PW_ERR_INVALID_ARG, "modes[%d]: unknown halo mode %d", f, m[d]);
-            if ((m[d] == PW_HALO_REFLECT || m[d] == PW_HALO_REFLECT_NEG) && n[d] < grid->halo)
-                return fail(PW_ERR_INVALID_ARG, "modes[%d]: reflect on an axis of %lld cells needs halo <= %lld",
-                            f, (long long)n[d], (long long)n[d]);
-            a.mode[f][d] = m[d];
-        }
-        a.f[f] = fields[f];
-        r[f] = in_range(names[f], fields[f], grid, L, es);
-        for (int g = 0; g < f; ++g)
-            if (overlap(r[f], r[g])) return fail(PW_ERR_INVALID_ARG, "%s overlaps %s", r[f].name, r[g].name);
-    }
-    int dev = 0;
-    PW_TRY(current_device(&dev));
-    for (int f = 0; f < nfields; ++f) PW_TRY(check_on_device(names[f], fields[f], dev));
+    PW_TRY(validate_halo(grid, layout, dtype, fields, modes, nfields, &a));
     return launch_halo(a, static_cast<hipStream_t>(hip_stream));
+}
+
+pw_status pw_halo_fold(const pw_grid *grid, const pw_layout *layout, pw_dtype dtype, void *const fields[],
+                       const pw_halo_modes modes[], int32_t nfields, void *hip_stream) {
+    g_err[0] = 0;
+    if (dtype != PW_F32 && dtype != PW_F64)
+        return fail(PW_ERR_UNSUPPORTED, "the halo fold (a gradient operation) supports PW_F32 and PW_F64 only");
+    HaloArgs a{};
+    PW_TRY(validate_halo(grid, layout, dtype, fields, modes, nfields, &a));
+    return launch_halo_fold(a, static_cast<hipStream_t>(hip_stream));
 }
 
 pw_status pw_stream_copy(const void *src, void *dst, int64_t nbytes, void *hip_stream) {

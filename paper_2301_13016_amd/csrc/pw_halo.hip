@@ -129,7 +129,82 @@ hipError_t launch_u(const HaloK &k, int nf, int64_t most, bool small, hipStream_
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ fold
+// The adjoint of the fill, one axis per launch in the order z, y, x (the
+// fill is x, y, z).  A thread owns one whole line along the axis -- every
+// combination of the other two padded coordinates -- and, for each halo cell
+// of the line in ascending order, adds it (times the sign of the rule) into
+// its source cell and clears it.  Lines are disjoint, so nothing races, and
+// the order of the additions is the definition's.
+struct FoldK {
+    void *f[kMaxHaloFields];
+    int32_t mode[kMaxHaloFields];   // rule of this axis per field
+    int64_t n;                      // interior cells along the axis
+    int64_t lines, inner;           // lines per field; padded extent of the faster other axis
+    int64_t s_outer, s_inner, s_axis;   // strides (elements) of the slower other axis, faster other axis, the axis
+    int32_t h;
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void fold_kernel(FoldK a) {
+    const int f = blockIdx.y;
+    const int mode = a.mode[f];
+    if (mode == PW_HALO_KEEP) return;   // whole workgroup
+    T *const base = static_cast<T *>(a.f[f]);
+    const int64_t h = a.h, n = a.n;
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+    for (int64_t l = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; l < a.lines; l += stride) {
+        const int64_t o = l / a.inner, in = l - o * a.inner;
+        T *const line = base + o * a.s_outer + in * a.s_inner;
+        for (int64_t q = 0; q < 2 * h; ++q) {
+            const int64_t p = q < h ? q : n + q;
+            T *const cell = line + p * a.s_axis;
+            if (mode != PW_HALO_ZERO) {
+                int sign = 1;
+                const int64_t sp = source(p, n, h, mode, sign);
+                T *const dst = line + sp * a.s_axis;
+                *dst = sign < 0 ? *dst - *cell : *dst + *cell;
+            }
+            *cell = T(0);
+        }
+    }
+}
+
 }  // namespace
+
+pw_status launch_halo_fold(const HaloArgs &a, hipStream_t s) {
+    const int64_t h = a.h, px = a.nx + 2 * h, py = a.ny + 2 * h, pz = a.nz + 2 * h;
+    for (int axis = 2; axis >= 0; --axis) {
+        FoldK k{};
+        bool any = false;
+        for (int f = 0; f < a.nf; ++f) {
+            k.f[f] = a.f[f];
+            k.mode[f] = a.mode[f][axis];
+            any = any || k.mode[f] != PW_HALO_KEEP;
+        }
+        if (!any) continue;
+        k.h = a.h;
+        if (axis == 2) {   // lines along z over (j, i)
+            k.n = a.nz; k.lines = py * px; k.inner = px;
+            k.s_outer = a.sy; k.s_inner = 1; k.s_axis = a.sz;
+        } else if (axis == 1) {   // along y over (k, i)
+            k.n = a.ny; k.lines = pz * px; k.inner = px;
+            k.s_outer = a.sz; k.s_inner = 1; k.s_axis = a.sy;
+        } else {   // along x over (k, j)
+            k.n = a.nx; k.lines = pz * py; k.inner = py;
+            k.s_outer = a.sz; k.s_inner = a.sy; k.s_axis = 1;
+        }
+        const int64_t blocks = std::min<int64_t>((k.lines + 255) / 256, 4096);
+        const dim3 grid(unsigned(std::max<int64_t>(blocks, 1)), unsigned(a.nf));
+        if (a.es == 8)
+            hipLaunchKernelGGL(fold_kernel<double>, grid, dim3(256), 0, s, k);
+        else
+            hipLaunchKernelGGL(fold_kernel<float>, grid, dim3(256), 0, s, k);
+        const pw_status st = hip_fail(hipGetLastError(), "fold kernel launch");
+        if (st != PW_OK) return st;
+    }
+    return PW_OK;
+}
 
 pw_status launch_halo(const HaloArgs &a, hipStream_t s) {
     HaloK k{};

@@ -109,6 +109,7 @@ pw_status launch_tangent(const TanArgs &a, pw_dtype dt, const TileCfg &cfg, hipS
 int64_t coeff_grad_workspace_bytes(const pw_grid &g, pw_dtype dt);
 pw_status launch_coeff_grad(const CgArgs &a, pw_dtype dt, hipStream_t s);
 pw_status launch_halo(const HaloArgs &a, hipStream_t s);
+pw_status launch_halo_fold(const HaloArgs &a, hipStream_t s);   // es 4 or 8
 // z-fastest forward (pw_zfast.hip): FwdArgs carry the column stride in
 // in_sy / out_sy and the x-plane stride in in_sz / out_sz; tile px = levels
 // per lane, ry = y-rows per strip, zlen = x-columns per work item.

@@ -548,3 +548,15 @@ def test_advect_bc_validation(lib):
     assert call(ctypes.byref(B.pw_halo_modes(1, 1, 1)), ctypes.byref(B.pw_epilogue(0.5, *q))) in _no_gpu_status()
     assert call(ctypes.byref(B.pw_halo_modes(1, 1, 1)),
                 ctypes.byref(B.pw_epilogue(float("nan"), *q))) == B.PW_ERR_INVALID_ARG
+
+
+def test_halo_fold_validation(lib):
+    g = B.pw_grid(8, 8, 8, 1)
+    f = [A + i * MB for i in range(3)]
+    per = [(1, 1, 2), (1, 1, 2), (1, 1, 3)]
+    assert B.pw_halo_fold(g, None, B.PW_F32, f, per) in _no_gpu_status()
+    assert B.pw_halo_fold(g, None, B.PW_F64, f, per) in _no_gpu_status()
+    assert B.pw_halo_fold(g, None, B.PW_BF16, f, per) == B.PW_ERR_UNSUPPORTED
+    assert B.pw_halo_fold(g, None, B.PW_F32, f, [(1, 1, 7)] * 3) == B.PW_ERR_INVALID_ARG
+    assert B.pw_halo_fold(g, None, B.PW_F32, [f[0], f[0] + 100, f[2]], per) == B.PW_ERR_INVALID_ARG
+    assert B.pw_halo_fold(B.pw_grid(8, 8, 2, 3), None, B.PW_F32, f, [(1, 1, 4)] * 3) == B.PW_ERR_INVALID_ARG

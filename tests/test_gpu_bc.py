@@ -121,3 +121,16 @@ def test_value_rules_are_unsupported():
         with pytest.raises(B.PWError) as ei:
             B.advect_bc(u, v, w, c, bc)
         assert ei.value.status == B.PW_ERR_UNSUPPORTED
+
+
+def test_autograd_through_boundaries_gradcheck():
+    """torch.autograd.gradcheck of PWAdvectBC in FP64 (reverse and forward
+    mode) on a small periodic / zero-gradient domain."""
+    PW = B.PWAdvectBC()
+    g = wl.make_grid(9, 5, 4, seed=930, dtype=np.float64)
+    (u, v, w), c = dev_grid(g)
+    ins = [x.clone().requires_grad_(True) for x in (u, v, w)]
+    for bc in [("periodic", "periodic", "copy"), ("copy", "keep", "periodic")]:
+        f = lambda a, b, d: PW.apply(a, b, d, c, bc)  # noqa: E731
+        assert torch.autograd.gradcheck(f, tuple(ins), eps=1e-6, atol=1e-8, rtol=1e-6, fast_mode=True,
+                                        check_forward_ad=True)

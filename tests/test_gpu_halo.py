@@ -171,3 +171,85 @@ def test_zfast_arrays_with_axes_exchanged():
     B.halo_fill([z], ("reflect_neg", "copy", "periodic"))
     torch.cuda.synchronize()
     assert torch.equal(z.permute(2, 1, 0), a)
+
+
+# ------------------------------------------------------------------ fold
+
+@pytest.mark.parametrize("dt", ["float32", "float64"])
+@pytest.mark.parametrize("halo", [1, 2])
+def test_fold_every_rule_combination_integer_bitwise(dt, halo):
+    """Integer gradients (every sum exact): the GPU fold equals the oracle's
+    bit for bit for all 6^3 rule combinations, three fields per call."""
+    rng = np.random.default_rng(720 + halo)
+    shape = (5 + 2 * halo, 4 + 2 * halo, 9 + 2 * halo)
+    combos = list(itertools.product(MODES, MODES, MODES))
+    for i in range(0, len(combos), 3):
+        cs = combos[i:i + 3]
+        host = [rng.integers(-9, 10, shape).astype(np.float64) for _ in cs]
+        dev = [torch.from_numpy(x).to(TDT[dt]).cuda() for x in host]
+        B.halo_fold(dev, cs, halo=halo)
+        torch.cuda.synchronize()
+        for d, x, m in zip(dev, host, cs):
+            assert np.array_equal(d.cpu().to(torch.float64).numpy(), H.fold(x, halo, m)), m
+
+
+def test_fold_random_and_dot_product_fp64():
+    rng = np.random.default_rng(722)
+    shape = (9 + 2, 7 + 2, 130 + 2)
+    for modes in [("periodic", "periodic", "copy"), ("reflect_neg", "copy", "reflect"), ("copy", "zero", "periodic")]:
+        x = rng.uniform(-1, 1, shape)
+        y = rng.uniform(-1, 1, shape)
+        fx = torch.from_numpy(x).cuda()
+        fy = torch.from_numpy(y).cuda()
+        B.halo_fill([fx], modes)
+        B.halo_fold([fy], modes)
+        torch.cuda.synchronize()
+        assert np.allclose(fy.cpu().numpy(), H.fold(y, 1, modes), rtol=0, atol=1e-15)
+        lhs = float(torch.sum(fx * torch.from_numpy(y).cuda()))
+        rhs = float(torch.sum(torch.from_numpy(x).cuda() * fy))
+        assert abs(lhs - rhs) <= 1e-12 * abs(lhs), modes
+
+
+def test_fold_strided_layout_leaves_outside_cells_alone():
+    nz, ny, nx = 6, 5, 67
+    rng = np.random.default_rng(723)
+    big = [torch.from_numpy(rng.integers(-5, 6, (nz + 3, ny + 5, nx + 15)).astype(np.float32)).cuda()
+           for _ in range(2)]
+    keep = [b.clone() for b in big]
+    views = [b[:nz + 2, :ny + 2, :nx + 2] for b in big]
+    modes = [("periodic", "copy", "zero"), ("reflect", "periodic", "reflect_neg")]
+    ref = [H.fold(v.cpu().numpy().astype(np.float64), 1, m) for v, m in zip(views, modes)]
+    B.halo_fold(views, modes)
+    torch.cuda.synchronize()
+    for v, r, b, k in zip(views, ref, big, keep):
+        assert np.array_equal(v.cpu().numpy().astype(np.float64), r)
+        assert torch.equal(b[nz + 2:], k[nz + 2:]) and torch.equal(b[:, ny + 2:], k[:, ny + 2:])
+        assert torch.equal(b[:, :, nx + 2:], k[:, :, nx + 2:])
+
+
+def test_adjoint_of_the_forward_with_boundaries():
+    """<J_bc d, r> = <d, J_bc^T r> in FP64 with J_bc = tangent at fill(x) on
+    fill(d), and J_bc^T r (adjoint kernel + fold) against the oracle's
+    fold(adjoint(fill(x), r))."""
+    g = wl.make_grid(70, 12, 9, seed=724, dtype=np.float64)
+    r = wl.cotangents(70, 12, 9, seed=725, dtype=np.float64)
+    d = wl.direction(70, 12, 9, seed=726)
+    from gpu_util import dev_grid
+    (u, v, w), c = dev_grid(g)
+    rd = [torch.from_numpy(x).cuda() for x in r]
+    dd = [torch.from_numpy(np.ascontiguousarray(x)).cuda() for x in d]
+    for bc in [("periodic", "periodic", "copy"), ("copy", "periodic", "periodic")]:
+        grads = B.advect_bc_adjoint(u, v, w, c, bc, *rd)
+        xf = [x.clone() for x in (u, v, w)]
+        df = [x.clone() for x in dd]
+        B.halo_fill(xf, bc)
+        B.halo_fill(df, bc)
+        tl = B.advect_tangent(*xf, c, *df)
+        torch.cuda.synchronize()
+        lhs = sum(float(torch.sum(a * b)) for a, b in zip(tl, rd))
+        rhs = sum(float(torch.sum(a * b)) for a, b in zip(dd, grads))
+        assert abs(lhs - rhs) <= 1e-11 * abs(rhs), bc
+        filled = [H.fill(x, 1, bc) for x in (g.u, g.v, g.w)]
+        ref = [H.fold(x, 1, bc) for x in oracle.adjoint(*filled, g.coeffs, *r)]
+        for a, b in zip(grads, ref):
+            assert np.allclose(a.cpu().numpy(), b, rtol=0, atol=1e-12 * np.max(np.abs(b)))

@@ -117,8 +117,8 @@ pw_status pw_advect(const pw_grid *grid, const pw_layout *layout, pw_dtype in_dt
  * waves_per_group strips are stacked in y per workgroup.
  * Forward (pw_advect_ex):
  *   cols_per_lane 1 or 2: rows_per_strip in {1, 2, 4};
- *   cols_per_lane 4 (not PW_F64): rows_per_strip in {1, 2}, and 4 for
- *   16-bit storage; cols_per_lane 8 (16-bit storage): rows_per_strip in {1, 2};
+ *   cols_per_lane 4 (not PW_F64): rows_per_strip in {1, 2, 4};
+ *   cols_per_lane 8 (16-bit storage): rows_per_strip in {1, 2};
  *   PW_F64: cols_per_lane in {1, 2}, rows_per_strip in {1, 2};
  *   prefetch 1 or 2 (0 means 1).  A deeper prefetch keeps more bytes in
  *   flight per wavefront; it pays when few wavefronts run.

@@ -41,7 +41,7 @@ bool tile_supported(const TileCfg &c, pw_dtype dt) {
     const bool half = dt == PW_BF16 || dt == PW_F16;
     if (dt == PW_F64) return (c.px == 1 || c.px == 2) && (c.ry == 1 || c.ry == 2);
     if (c.px == 8) return half && (c.ry == 1 || c.ry == 2);
-    if (c.px == 4) return c.ry == 1 || c.ry == 2 || (half && c.ry == 4);
+    if (c.px == 4) return c.ry == 1 || c.ry == 2 || c.ry == 4;
     return (c.px == 1 || c.px == 2) && (c.ry == 1 || c.ry == 2 || c.ry == 4);
 }
 

@@ -156,13 +156,14 @@ def test_huge_plane_unsupported(lib):
 
 
 @pytest.mark.parametrize("tile", [(1, 3, 8, 4), (1, 4, 0, 4), (1, 4, 8, 0), (1, 4, 8, 9), (3, 1, 8, 4),
-                                  (4, 4, 8, 4), (8, 1, 8, 1), (0, 1, 8, 1)])
+                                  (4, 8, 8, 4), (8, 1, 8, 1), (0, 1, 8, 1)])
 def test_bad_tile(lib, tile):
     g, c, p = _args()
     assert _call(g, None, B.PW_F32, c, p, B.pw_tile(*tile)) == B.PW_ERR_INVALID_ARG
 
 
-@pytest.mark.parametrize("tile", [(1, 1, 1, 1), (1, 4, 8, 8), (2, 4, 3, 4), (4, 1, 16, 1), (4, 2, 64, 2)])
+@pytest.mark.parametrize("tile", [(1, 1, 1, 1), (1, 4, 8, 8), (2, 4, 3, 4), (4, 1, 16, 1), (4, 2, 64, 2),
+                                  (4, 4, 8, 4)])
 def test_good_tile(lib, tile):
     g, c, p = _args()
     assert _call(g, None, B.PW_F32, c, p, B.pw_tile(*tile)) in _no_gpu_status()

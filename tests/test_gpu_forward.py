@@ -80,7 +80,9 @@ def test_integer_inputs_bitwise_all_dtypes(storage, shape):
 TILES = [(1, 1, 1, 1), (1, 1, 7, 4), (1, 2, 3, 8), (1, 4, 16, 4), (2, 4, 5, 2), (2, 1, 64, 4), (2, 2, 2, 1),
          (4, 1, 64, 8), (4, 2, 5, 1), (4, 1, 1, 4), (4, 2, 16, 2),
          # two planes prefetched: short chunks (1, 2, 3 levels) exercise the five-plane ring's clamping
-         (1, 1, 1, 1, 2), (1, 2, 2, 8, 2), (2, 4, 3, 1, 2), (4, 2, 7, 1, 2), (4, 1, 64, 4, 2), (2, 2, 5, 8, 2)]
+         (1, 1, 1, 1, 2), (1, 2, 2, 8, 2), (2, 4, 3, 1, 2), (4, 2, 7, 1, 2), (4, 1, 64, 4, 2), (2, 2, 5, 8, 2),
+         # four columns x four rows
+         (4, 4, 9, 1), (4, 4, 23, 4, 2), (4, 4, 2, 8, 1)]
 
 
 @pytest.mark.parametrize("shape", [(150, 37, 23), (300, 9, 7), (259, 5, 6), (513, 3, 4)],

@@ -33,7 +33,9 @@ def _announce(request):
 def gpu_adjoint(g, r, tile=None, halo=1):
     (u, v, w), c = dev_grid(g)
     rd = [torch.from_numpy(np.ascontiguousarray(x)).to("cuda") for x in r]
-    out = B.advect_adjoint(u, v, w, c, *rd, halo=halo, tile=tile)
+    # NaN-filled outputs: every padded entry must be written
+    pre = tuple(torch.full_like(u, float("nan")) for _ in range(3))
+    out = B.advect_adjoint(u, v, w, c, *rd, halo=halo, tile=tile, out=pre)
     torch.cuda.synchronize()
     return [o.cpu().numpy() for o in out]
 
@@ -88,11 +90,14 @@ def test_adjoint_tile_invariance_bitwise():
             assert np.array_equal(a, b), t
 
 
+@pytest.mark.parametrize("tile", [None, (1, 1, 4, 4), (1, 4, 5, 1, 2)])
 @pytest.mark.parametrize("halo", [2, 3])
-def test_adjoint_wider_halo(halo):
+def test_adjoint_wider_halo(halo, tile):
+    """x-halo columns beyond the first get no contribution and are written as
+    zeros (the gradient buffers start as garbage)."""
     g = wl.make_grid(70, 20, 9, seed=204, halo=halo)
     r = wl.cotangents(70, 20, 9, seed=304)
-    errs, ref = adj_errors(gpu_adjoint(g, r, halo=halo), g, r, halo=halo)
+    errs, ref = adj_errors(gpu_adjoint(g, r, halo=halo, tile=tile), g, r, halo=halo)
     assert max(errs) <= 2e-6, errs
 
 

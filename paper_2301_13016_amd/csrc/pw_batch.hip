@@ -39,6 +39,7 @@ using namespace dev;
 template <typename Tin> struct BatchSub {
     FwdK<Tin> k;
     int64_t first;   // index of the subdomain's first work item
+    int32_t px;      // columns per lane of its strips
 };
 
 constexpr int kXcds = 8;         // XCDs of an MI355X
@@ -49,7 +50,9 @@ __global__ void batch_reset_kernel(unsigned long long *counter) {
 }
 
 // Depth: planes in flight (1 or 2).  MaxT: workgroup size bound (built for
-// 256 and 512 threads, as the single-grid kernels).
+// 256 and 512 threads, as the single-grid kernels).  PX 0: each subdomain's
+// strips have the width its work-list entry names (1 or 2 columns per lane;
+// the choice is wave-uniform, made per work item).
 template <typename Tin, int PX, int RY, int Depth, int MaxT>
 __global__ __launch_bounds__(MaxT) void pw_batch_kernel(const BatchSub<Tin> *__restrict__ subs, int nsub,
                                                        int64_t nitems, unsigned long long *counter) {
@@ -79,7 +82,14 @@ __global__ __launch_bounds__(MaxT) void pw_batch_kernel(const BatchSub<Tin> *__r
         const int64_t t2 = local / a.nzc;
         const int tx = static_cast<int>(t2 % a.ntx);
         const int ty = static_cast<int>(t2 / a.ntx);
-        strip_march<Tin, PX, RY, Depth>(a, tx, ty, cz);
+        if constexpr (PX == 0) {
+            if (subs[lo].px == 2)
+                strip_march<Tin, 2, RY, Depth>(a, tx, ty, cz);
+            else
+                strip_march<Tin, 1, RY, Depth>(a, tx, ty, cz);
+        } else {
+            strip_march<Tin, PX, RY, Depth>(a, tx, ty, cz);
+        }
       }
     }
 }
@@ -92,6 +102,9 @@ template <int PX, int RY, int Depth, int MaxT> const void *kernel_ptr() {
 
 template <int Depth, int MaxT> const void *batch_kernel_t(const TileCfg &c) {
     switch (c.px * 16 + c.ry) {
+        case 0 + 1: return kernel_ptr<0, 1, Depth, MaxT>();
+        case 0 + 2: return kernel_ptr<0, 2, Depth, MaxT>();
+        case 0 + 4: return kernel_ptr<0, 4, Depth, MaxT>();
         case 16 + 1: return kernel_ptr<1, 1, Depth, MaxT>();
         case 16 + 2: return kernel_ptr<1, 2, Depth, MaxT>();
         case 16 + 4: return kernel_ptr<1, 4, Depth, MaxT>();
@@ -157,6 +170,15 @@ void drop_graph(pw_batch *b) {
     b->graph = nullptr;
 }
 
+// Columns per lane of a subdomain nx wide under the per-subdomain choice:
+// 2 where that leaves no more lanes idle than 1 (fewer, wider vector loads
+// per point), else 1 (e.g. 33..64 or 129..192 columns: half a 128-column
+// strip would be empty).
+int sub_columns(int64_t nx) {
+    const int64_t s1 = (nx + 63) / 64 * 64, s2 = (nx + 127) / 128 * 128;
+    return s2 == s1 ? 2 : 1;
+}
+
 // Builds and uploads the work list for `tile` (synchronous upload).
 pw_status build_table(pw_batch *b, const TileCfg &tile) {
     std::vector<BatchSub<Tin>> h(b->subs.size());
@@ -184,7 +206,9 @@ pw_status build_table(pw_batch *b, const TileCfg &tile) {
         a.out_sz = g.out_sz;
         a.in_sy = static_cast<int32_t>(g.in_sy);
         a.out_sy = static_cast<int32_t>(g.out_sy);
-        a.ntx = static_cast<int32_t>((g.nx + 64 * tile.px - 1) / (64 * tile.px));
+        const int px = tile.px > 0 ? tile.px : sub_columns(g.nx);
+        h[i].px = px;
+        a.ntx = static_cast<int32_t>((g.nx + 64 * px - 1) / (64 * px));
         a.nty = static_cast<int32_t>((g.ny + tile.ry - 1) / tile.ry);
         // split nz evenly into chunks of at most tile.zlen levels
         const int64_t chunks = (g.nz + tile.zlen - 1) / tile.zlen;
@@ -232,6 +256,12 @@ pw_status enqueue(pw_batch *b, hipStream_t s) {
 }
 
 bool batch_tile_ok(const TileCfg &c) {
+    if (c.px == 0) {
+        TileCfg c1 = c, c2 = c;
+        c1.px = 1;
+        c2.px = 2;
+        return tile_supported(c1, PW_F32) && tile_supported(c2, PW_F32) && batch_kernel(c) != nullptr;
+    }
     return tile_supported(c, PW_F32) && batch_kernel(c) != nullptr;
 }
 
@@ -389,7 +419,7 @@ pw_status pw_batch_tune(pw_batch *b, void *hip_stream, pw_tile *chosen) {
     TileCfg best = start;
     float best_ms = -1.f;
     pw_status st = PW_OK;
-    for (int px : {1, 2, 4})
+    for (int px : {0, 1, 2, 4})
         for (int ry : {1, 2, 4})
             for (int zl : {32, 64, 128, 256})
                 for (int wpb : {1, 4})

@@ -413,6 +413,9 @@ def test_batch_argument_errors(lib):
     assert lib.pw_batch_create(_items(2), 2, B.PW_F32, None, None) == B.PW_ERR_INVALID_ARG
     assert B.pw_batch_create(_items(2), 2, B.PW_BF16, None, h) == B.PW_ERR_UNSUPPORTED
     assert B.pw_batch_create(_items(2), 2, B.PW_F32, B.pw_tile(4, 4, 8, 4), h) == B.PW_ERR_INVALID_ARG
+    # columns per lane 0 (chosen per subdomain): rows per strip as for 1 and 2 columns
+    assert B.pw_batch_create(_items(2), 2, B.PW_F32, B.pw_tile(0, 8, 8, 4), h) == B.PW_ERR_INVALID_ARG
+    assert B.pw_batch_create(_items(2), 2, B.PW_F32, B.pw_tile(0, 4, 8, 4, 3), h) == B.PW_ERR_INVALID_ARG
     bad = _items(3)
     bad[2].grid.halo = 0
     assert B.pw_batch_create(bad, 3, B.PW_F32, None, h) == B.PW_ERR_INVALID_ARG

@@ -166,8 +166,9 @@ __device__ __forceinline__ void level_tl(const Plane<T, PX, RY> &xm, const Plane
 
 // One work item: strip (tx, ty) of the tangent marched up z-chunk cz (the
 // forward kernel's march, loading the value and direction planes together;
-// see strip_march_t for the ring and the unconditional prefetch).
-template <typename T, int PX, int RY, bool Full>
+// see strip_march_t for the ring and the unconditional prefetch).  Depth:
+// planes in flight ahead of the three a level reads (1 or 2).
+template <typename T, int PX, int RY, int Depth, bool Full>
 __device__ __forceinline__ void tl_march(const FwdK<T> &a, const FwdK<T> &d, int tx, int ty, int cz) {
     const int lane = threadIdx.x & 63;
     const int pcols = a.nx + 2 * a.h, prows = a.ny + 2 * a.h;
@@ -203,7 +204,6 @@ __device__ __forceinline__ void tl_march(const FwdK<T> &a, const FwdK<T> &d, int
     const int k1 = min(a.nz, k0 + a.zlen);
     const int h = a.h;
 
-    Plane<T, PX, RY> XA, XB, XC, XD, DA, DB, DC, DD;
 #define PW_LOAD(Xp, Dp, kp)                                          \
     do {                                                             \
         load_plane<T, PX, RY, Full>(Xp, a, (kp), s, last_col);       \
@@ -211,30 +211,59 @@ __device__ __forceinline__ void tl_march(const FwdK<T> &a, const FwdK<T> &d, int
     } while (0)
 #define PW_LEVEL(M, C, P) \
     level_tl<T, PX, RY, Full>(X##M, X##C, X##P, D##M, D##C, D##P, a, kk, lane0, lane63, nvalid, ooff, row_ok)
-    PW_LOAD(XA, DA, k0 - 1 + h);
-    PW_LOAD(XB, DB, k0 + h);
-    PW_LOAD(XC, DC, k0 + 1 + h);
     int kk = k0;
-    for (;;) {
-        PW_LOAD(XD, DD, min(kk + 2, k1) + h);
-        PW_LEVEL(A, B, C);
-        if (++kk >= k1) break;
-        PW_LOAD(XA, DA, min(kk + 2, k1) + h);
-        PW_LEVEL(B, C, D);
-        if (++kk >= k1) break;
-        PW_LOAD(XB, DB, min(kk + 2, k1) + h);
-        PW_LEVEL(C, D, A);
-        if (++kk >= k1) break;
-        PW_LOAD(XC, DC, min(kk + 2, k1) + h);
-        PW_LEVEL(D, A, B);
-        if (++kk >= k1) break;
+    if constexpr (Depth == 1) {
+        // four-plane rings: planes kk-1, kk, kk+1 feed level kk, kk+2 in flight
+        Plane<T, PX, RY> XA, XB, XC, XD, DA, DB, DC, DD;
+        PW_LOAD(XA, DA, k0 - 1 + h);
+        PW_LOAD(XB, DB, k0 + h);
+        PW_LOAD(XC, DC, k0 + 1 + h);
+        for (;;) {
+            PW_LOAD(XD, DD, min(kk + 2, k1) + h);
+            PW_LEVEL(A, B, C);
+            if (++kk >= k1) break;
+            PW_LOAD(XA, DA, min(kk + 2, k1) + h);
+            PW_LEVEL(B, C, D);
+            if (++kk >= k1) break;
+            PW_LOAD(XB, DB, min(kk + 2, k1) + h);
+            PW_LEVEL(C, D, A);
+            if (++kk >= k1) break;
+            PW_LOAD(XC, DC, min(kk + 2, k1) + h);
+            PW_LEVEL(D, A, B);
+            if (++kk >= k1) break;
+        }
+    } else {
+        // five-plane rings: planes kk+2 and kk+3 in flight
+        static_assert(Depth == 2, "prefetch depth 1 or 2");
+        Plane<T, PX, RY> XA, XB, XC, XD, XE, DA, DB, DC, DD, DE;
+        PW_LOAD(XA, DA, k0 - 1 + h);
+        PW_LOAD(XB, DB, k0 + h);
+        PW_LOAD(XC, DC, k0 + 1 + h);
+        PW_LOAD(XD, DD, min(k0 + 2, k1) + h);
+        for (;;) {
+            PW_LOAD(XE, DE, min(kk + 3, k1) + h);
+            PW_LEVEL(A, B, C);
+            if (++kk >= k1) break;
+            PW_LOAD(XA, DA, min(kk + 3, k1) + h);
+            PW_LEVEL(B, C, D);
+            if (++kk >= k1) break;
+            PW_LOAD(XB, DB, min(kk + 3, k1) + h);
+            PW_LEVEL(C, D, E);
+            if (++kk >= k1) break;
+            PW_LOAD(XC, DC, min(kk + 3, k1) + h);
+            PW_LEVEL(D, E, A);
+            if (++kk >= k1) break;
+            PW_LOAD(XD, DD, min(kk + 3, k1) + h);
+            PW_LEVEL(E, A, B);
+            if (++kk >= k1) break;
+        }
     }
 #undef PW_LOAD
 #undef PW_LEVEL
 }
 
 // MaxT: workgroup size bound (built for 256 and 512 threads, as the forward).
-template <typename T, int PX, int RY, int MaxT>
+template <typename T, int PX, int RY, int Depth, int MaxT>
 __global__ __launch_bounds__(MaxT) void pw_tangent_kernel(TanK<T> k) {
     const FwdK<T> &a = k.x;
     FwdK<T> d = k.x;
@@ -249,11 +278,11 @@ __global__ __launch_bounds__(MaxT) void pw_tangent_kernel(TanK<T> k) {
     const int ty = (t2 / a.ntx) * a.wpb + wave;
     if (ty >= a.nty) return;   // whole wavefront
     if constexpr (PX == 1) {
-        tl_march<T, PX, RY, false>(a, d, tx, ty, cz);
+        tl_march<T, PX, RY, Depth, false>(a, d, tx, ty, cz);
     } else if ((tx + 1) * 64 * PX <= a.nx) {
-        tl_march<T, PX, RY, true>(a, d, tx, ty, cz);
+        tl_march<T, PX, RY, Depth, true>(a, d, tx, ty, cz);
     } else {
-        tl_march<T, PX, RY, false>(a, d, tx, ty, cz);
+        tl_march<T, PX, RY, Depth, false>(a, d, tx, ty, cz);
     }
 }
 
@@ -292,12 +321,18 @@ pw_status launch_tl_t(const TanArgs &g, const TileCfg &cfg, hipStream_t s) {
     const int64_t nblk_y = (a.nty + cfg.wpb - 1) / cfg.wpb;
     const int64_t nblocks = static_cast<int64_t>(a.ntx) * nblk_y * a.nzc;
     if (nblocks <= 0 || nblocks > 0x7fffffffLL) return fail(PW_ERR_UNSUPPORTED, "grid too large");
-    if (cfg.wpb <= 4)
-        hipLaunchKernelGGL((pw_tangent_kernel<T, PX, RY, 256>), dim3(static_cast<unsigned>(nblocks)),
-                           dim3(64 * cfg.wpb), 0, s, k);
-    else
-        hipLaunchKernelGGL((pw_tangent_kernel<T, PX, RY, 512>), dim3(static_cast<unsigned>(nblocks)),
-                           dim3(64 * cfg.wpb), 0, s, k);
+    const dim3 grid(static_cast<unsigned>(nblocks)), block(64 * cfg.wpb);
+    if (cfg.depth == 2) {
+        if (cfg.wpb <= 4)
+            hipLaunchKernelGGL((pw_tangent_kernel<T, PX, RY, 2, 256>), grid, block, 0, s, k);
+        else
+            hipLaunchKernelGGL((pw_tangent_kernel<T, PX, RY, 2, 512>), grid, block, 0, s, k);
+    } else {
+        if (cfg.wpb <= 4)
+            hipLaunchKernelGGL((pw_tangent_kernel<T, PX, RY, 1, 256>), grid, block, 0, s, k);
+        else
+            hipLaunchKernelGGL((pw_tangent_kernel<T, PX, RY, 1, 512>), grid, block, 0, s, k);
+    }
     return hip_fail(hipGetLastError(), "tangent kernel launch");
 }
 
@@ -324,7 +359,7 @@ pw_status launch_tl_dt(const TanArgs &g, const TileCfg &cfg, hipStream_t s) {
 }  // namespace
 
 bool tangent_tile_supported(const TileCfg &c, pw_dtype dt) {
-    if (c.zlen < 1 || c.wpb < 1 || c.wpb > 8 || c.depth != 1) return false;
+    if (c.zlen < 1 || c.wpb < 1 || c.wpb > 8 || (c.depth != 1 && c.depth != 2)) return false;
     if (c.ry != 1 && c.ry != 2) return false;
     if (dt == PW_F64) return c.px == 1;
     return c.px == 1 || c.px == 2;

@@ -200,8 +200,8 @@ def test_adjoint_gradient_overlap_rejected(lib):
 
 
 def test_prefetch_depth_validation(lib):
-    """prefetch: 0 (= 1) or 1 or 2 for the forward, the adjoint and the
-    batched form; 0 or 1 for the tangent."""
+    """prefetch: 0 (= 1), 1 or 2 for the forward, the adjoint, the tangent
+    and the batched form."""
     g, c, p = _args()
     for pf, ok in [(0, True), (1, True), (2, True), (3, False), (-1, False)]:
         st = _call(g, None, B.PW_F32, c, p, B.pw_tile(4, 2, 8, 1, pf))
@@ -212,6 +212,8 @@ def test_prefetch_depth_validation(lib):
     st = B.pw_advect_adjoint_ex(g, None, B.PW_F32, *q[:3], c, *q[3:6], *q[6:9], B.pw_tile(1, 2, 8, 1, 3))
     assert st == B.PW_ERR_INVALID_ARG
     st = B.pw_advect_tangent_ex(g, None, B.PW_F32, *q[:3], c, *q[3:6], *q[6:9], B.pw_tile(1, 2, 8, 1, 2))
+    assert st in _no_gpu_status()
+    st = B.pw_advect_tangent_ex(g, None, B.PW_F32, *q[:3], c, *q[3:6], *q[6:9], B.pw_tile(1, 2, 8, 1, 3))
     assert st == B.PW_ERR_INVALID_ARG
     assert B.pw_advect_tangent_ex(g, None, B.PW_F32, *q[:3], c, *q[3:6], *q[6:9],
                                   B.pw_tile(1, 2, 8, 1, 1)) in _no_gpu_status()

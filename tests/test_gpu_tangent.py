@@ -65,7 +65,8 @@ SHAPES = [(130, 70, 20), (64, 64, 64), (1, 1, 1), (65, 3, 1), (1, 200, 5), (61, 
           (129, 5, 2), (257, 3, 4), (300, 7, 9)]
 
 
-@pytest.mark.parametrize("tile", [None, (1, 1, 5, 4), (1, 2, 9, 1), (2, 1, 7, 8), (2, 2, 64, 2)])
+@pytest.mark.parametrize("tile", [None, (1, 1, 5, 4), (1, 2, 9, 1), (2, 1, 7, 8), (2, 2, 64, 2), (1, 2, 6, 4, 2),
+                                  (2, 2, 9, 1, 2), (2, 1, 64, 8, 2)])
 @pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "x".join(map(str, s)))
 def test_f32_tangent_matches_oracle(shape, tile):
     nx, ny, nz = shape
@@ -75,7 +76,7 @@ def test_f32_tangent_matches_oracle(shape, tile):
     assert max(errs) <= 2e-6, errs
 
 
-@pytest.mark.parametrize("tile", [None, (1, 1, 3, 1), (1, 2, 64, 8)])
+@pytest.mark.parametrize("tile", [None, (1, 1, 3, 1), (1, 2, 64, 8), (1, 2, 5, 4, 2)])
 def test_f64_tangent_matches_oracle(tile):
     g = wl.make_grid(70, 33, 21, seed=401, dtype=np.float64)
     d = wl.direction(70, 33, 21, seed=501)
@@ -98,7 +99,8 @@ def test_tangent_tile_invariance_bitwise():
     g = wl.make_grid(150, 37, 23, seed=403)
     d = wl.direction(150, 37, 23, seed=503)
     base = gpu_tangent(g, d, tile=(1, 2, 16, 4))
-    for t in [(1, 1, 1, 1), (1, 1, 9, 4), (1, 2, 5, 8), (2, 1, 64, 4), (2, 2, 3, 2), (2, 2, 23, 1)]:
+    for t in [(1, 1, 1, 1), (1, 1, 9, 4), (1, 2, 5, 8), (2, 1, 64, 4), (2, 2, 3, 2), (2, 2, 23, 1), (1, 1, 2, 4, 2),
+              (2, 2, 23, 1, 2), (2, 1, 7, 8, 2)]:
         got = gpu_tangent(g, d, tile=t)
         for a, b in zip(base, got):
             assert np.array_equal(a, b), t

@@ -68,19 +68,43 @@ template <typename T, int RY> struct StripAddr {
     bool rcol;               // cotangent column inside the interior (per lane)
 };
 
+// Buffer descriptor of one z-plane (base: the plane; range: its bytes, below
+// 2 GiB; word 3 as the GFX9 family wants it for untyped access).  Loads and
+// stores then take the row offset as a 32-bit offset and need no 64-bit
+// address arithmetic per access; an offset past the range would read 0 and
+// drop a write.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void *p, int64_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), 0, static_cast<int>(bytes), 0x00020000);
+}
+template <typename T> __device__ __forceinline__ T bload(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    if constexpr (sizeof(T) == 4)
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+    else
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+template <typename T> __device__ __forceinline__ void bstore(T x, __amdgpu_buffer_rsrc_t r, uint32_t off) {
+    if constexpr (sizeof(T) == 4) {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, x), r, off, 0, 0);
+    } else {
+        using V2 = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, x), r, off, 0, 0);
+    }
+}
+
 template <typename T, int RY>
 __device__ __forceinline__ void load_aplane(APlane<T, RY> &P, const AdjK<T> &a, int kp, const StripAddr<T, RY> &s) {
     const int pz = a.nz + 2 * a.h;
     const int kv = min(max(kp, 0), pz - 1);
     const int64_t pb = static_cast<int64_t>(kv) * a.in_sz * static_cast<int64_t>(sizeof(T));
-    const char *bu = reinterpret_cast<const char *>(a.u) + pb;
-    const char *bv = reinterpret_cast<const char *>(a.v) + pb;
-    const char *bw = reinterpret_cast<const char *>(a.w) + pb;
+    const int64_t vbytes = a.in_sz * static_cast<int64_t>(sizeof(T));
+    const auto bu = plane_rsrc(reinterpret_cast<const char *>(a.u) + pb, vbytes);
+    const auto bv = plane_rsrc(reinterpret_cast<const char *>(a.v) + pb, vbytes);
+    const auto bw = plane_rsrc(reinterpret_cast<const char *>(a.w) + pb, vbytes);
 #pragma unroll
     for (int r = 0; r < RY + 2; ++r) {
-        P.u[r] = *reinterpret_cast<const T *>(bu + s.voff[r]);
-        P.v[r] = *reinterpret_cast<const T *>(bv + s.voff[r]);
-        P.w[r] = *reinterpret_cast<const T *>(bw + s.voff[r]);
+        P.u[r] = bload<T>(bu, s.voff[r]);
+        P.v[r] = bload<T>(bv, s.voff[r]);
+        P.w[r] = bload<T>(bw, s.voff[r]);
     }
     // Cotangents: every load from a clamped (valid) address and without a
     // branch, so that the plane's loads stay in flight until its first use,
@@ -89,14 +113,15 @@ __device__ __forceinline__ void load_aplane(APlane<T, RY> &P, const AdjK<T> &a, 
     P.zok = kk >= 0 && kk < a.nz;
     const int kc = min(max(kk, 0), a.nz - 1);
     const int64_t ob = static_cast<int64_t>(kc) * a.out_sz * static_cast<int64_t>(sizeof(T));
-    const char *cu = reinterpret_cast<const char *>(a.ru) + ob;
-    const char *cv = reinterpret_cast<const char *>(a.rv) + ob;
-    const char *cw = reinterpret_cast<const char *>(a.rw) + ob;
+    const int64_t obytes = a.out_sz * static_cast<int64_t>(sizeof(T));
+    const auto cu = plane_rsrc(reinterpret_cast<const char *>(a.ru) + ob, obytes);
+    const auto cv = plane_rsrc(reinterpret_cast<const char *>(a.rv) + ob, obytes);
+    const auto cw = plane_rsrc(reinterpret_cast<const char *>(a.rw) + ob, obytes);
 #pragma unroll
     for (int r = 0; r < RY + 2; ++r) {
-        P.ru[r] = *reinterpret_cast<const T *>(cu + s.roff[r]);
-        P.rv[r] = *reinterpret_cast<const T *>(cv + s.roff[r]);
-        P.rw[r] = *reinterpret_cast<const T *>(cw + s.roff[r]);
+        P.ru[r] = bload<T>(cu, s.roff[r]);
+        P.rv[r] = bload<T>(cv, s.roff[r]);
+        P.rw[r] = bload<T>(cw, s.roff[r]);
     }
 }
 
@@ -148,9 +173,10 @@ __device__ __forceinline__ void adj_level(const APlane<T, RY> &m, const APlane<T
 
     const int64_t gb = static_cast<int64_t>(min(max(kp, 0), a.nz + 2 * a.h - 1)) * a.in_sz *
                        static_cast<int64_t>(sizeof(T));
-    char *ogu = reinterpret_cast<char *>(a.gu) + gb;
-    char *ogv = reinterpret_cast<char *>(a.gv) + gb;
-    char *ogw = reinterpret_cast<char *>(a.gw) + gb;
+    const int64_t gbytes = a.in_sz * static_cast<int64_t>(sizeof(T));
+    const auto ogu = plane_rsrc(reinterpret_cast<char *>(a.gu) + gb, gbytes);
+    const auto ogv = plane_rsrc(reinterpret_cast<char *>(a.gv) + gb, gbytes);
+    const auto ogw = plane_rsrc(reinterpret_cast<char *>(a.gw) + gb, gbytes);
 
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
@@ -215,9 +241,9 @@ __device__ __forceinline__ void adj_level(const APlane<T, RY> &m, const APlane<T
         gw = fma_(tcy, gyw, gw);
 
         if (lane_ok && row_ok[r]) {
-            *reinterpret_cast<T *>(ogu + goff[r]) = gu;
-            *reinterpret_cast<T *>(ogv + goff[r]) = gv;
-            *reinterpret_cast<T *>(ogw + goff[r]) = gw;
+            bstore<T>(gu, ogu, goff[r]);
+            bstore<T>(gv, ogv, goff[r]);
+            bstore<T>(gw, ogw, goff[r]);
         }
     }
 }

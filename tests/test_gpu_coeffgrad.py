@@ -104,6 +104,29 @@ def test_coeff_grad_reproducible_bitwise():
         assert torch.equal(a[k], b[k]), k
 
 
+def test_coeff_grad_strided_layout_bitwise():
+    """Values and cotangents as views into larger buffers (extra columns and
+    rows per plane): the same gradients bit for bit as dense arrays."""
+    g = wl.make_grid(150, 37, 23, seed=704)
+    r = wl.cotangents(150, 37, 23, seed=804)
+    (u, v, w), _ = dev_grid(g)
+    rd = _dev(r)
+    dense = B.advect_coeff_grad(u, v, w, *rd)
+
+    def view(src, extra_rows, extra_cols):
+        big = torch.full((src.shape[0], src.shape[1] + extra_rows, src.shape[2] + extra_cols), 5.0,
+                         dtype=src.dtype, device=src.device)
+        big[:, :src.shape[1], :src.shape[2]] = src
+        return big[:, :src.shape[1], :src.shape[2]]
+
+    vs = [view(x, 3, 7) for x in (u, v, w)]
+    cs = [view(x, 1, 2) for x in rd]
+    assert vs[0].stride(1) == u.shape[2] + 7 and cs[0].stride(1) == rd[0].shape[2] + 2
+    got = B.advect_coeff_grad(*vs, *cs)
+    for k in dense:
+        assert torch.equal(dense[k], got[k]), k
+
+
 def test_c4_coeff_grad_parity(report):
     """256 x 256 x 128 FP32, every coefficient gradient against the oracle."""
     cfg = wl.C4

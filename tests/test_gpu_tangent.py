@@ -95,6 +95,35 @@ def test_integer_tangent_bitwise(dtype):
         assert np.array_equal(a.astype(np.float64), b)
 
 
+def test_tangent_strided_layout_bitwise():
+    """Values, direction and outputs as views into larger buffers (extra
+    columns and rows per plane): the dense result bit for bit, nothing outside
+    the output views written."""
+    g = wl.make_grid(150, 37, 23, seed=404)
+    d = wl.direction(150, 37, 23, seed=504)
+    dense = gpu_tangent(g, d)
+    (u, v, w), c = dev_grid(g)
+    dd = [x.to(u.dtype) for x in _dev(d)]
+
+    def view(src, extra_rows, extra_cols, fill):
+        big = torch.full((src.shape[0], src.shape[1] + extra_rows, src.shape[2] + extra_cols), fill,
+                         dtype=src.dtype, device=src.device)
+        big[:, :src.shape[1], :src.shape[2]] = src
+        return big, big[:, :src.shape[1], :src.shape[2]]
+
+    xs = [view(x, 2, 5, 3.0)[1] for x in (u, v, w)]
+    ds = [view(x, 2, 5, 3.0)[1] for x in dd]
+    outs = [view(torch.full((23, 37, 150), float("nan"), device="cuda"), 1, 4, -2.0) for _ in range(3)]
+    got = B.advect_tangent(*xs, c, *ds, out=tuple(vw for _, vw in outs))
+    torch.cuda.synchronize()
+    for a, (b, vw) in zip(dense, outs):
+        assert np.array_equal(a, vw.cpu().numpy())
+        outside = b.clone()
+        outside[:, :37, :150] = -2.0
+        assert bool((outside == -2.0).all())
+    assert all(x is vw for x, (_, vw) in zip(got, outs))
+
+
 def test_tangent_tile_invariance_bitwise():
     g = wl.make_grid(150, 37, 23, seed=403)
     d = wl.direction(150, 37, 23, seed=503)

@@ -134,3 +134,41 @@ def test_autograd_through_boundaries_gradcheck():
         f = lambda a, b, d: PW.apply(a, b, d, c, bc)  # noqa: E731
         assert torch.autograd.gradcheck(f, tuple(ins), eps=1e-6, atol=1e-8, rtol=1e-6, fast_mode=True,
                                         check_forward_ad=True)
+
+
+def _pitched(src, extra_rows, extra_cols, fill):
+    """A view of src's contents inside a larger buffer (extra columns and rows
+    per plane), and the buffer."""
+    big = torch.full((src.shape[0], src.shape[1] + extra_rows, src.shape[2] + extra_cols), fill,
+                     dtype=src.dtype, device=src.device)
+    big[:, :src.shape[1], :src.shape[2]] = src
+    return big, big[:, :src.shape[1], :src.shape[2]]
+
+
+def _outside_unchanged(big, shape, fill):
+    t = big.clone()
+    t[:, :shape[1], :shape[2]] = fill
+    return bool((t == fill).all())
+
+
+def test_bc_strided_layout_bitwise():
+    """Boundary rules by addressing on views into larger buffers (inputs,
+    outputs and addends): the dense result bit for bit, nothing outside the
+    output views written, the inputs' halo untouched."""
+    g = wl.make_grid(150, 37, 23, seed=907)
+    (u, v, w), c = dev_grid(g)
+    rng = np.random.default_rng(908)
+    add = [torch.from_numpy(rng.uniform(-1, 1, (23, 37, 150)).astype(np.float32)).to("cuda") for _ in range(3)]
+    bc = ("periodic", "periodic", "copy")
+    dense = B.advect_bc(u, v, w, c, bc, addends=add, alpha=0.5)
+    ins = [_pitched(x, 2, 5, 1.5) for x in (u, v, w)]
+    adds = [_pitched(x, 1, 3, 0.0)[1] for x in add]
+    outs = [_pitched(torch.empty_like(x), 1, 3, -4.0) for x in add]
+    got = B.advect_bc(*(vw for _, vw in ins), c, bc, out=tuple(vw for _, vw in outs), addends=adds, alpha=0.5)
+    torch.cuda.synchronize()
+    for d, gv, (b, vw) in zip(dense, got, outs):
+        assert gv is vw
+        assert torch.equal(d, vw)
+        assert _outside_unchanged(b, d.shape, -4.0)
+    for x, (_, vw) in zip((u, v, w), ins):
+        assert torch.equal(x, vw)

@@ -129,3 +129,37 @@ def test_epilogue_is_one_fma_of_the_plain_output():
         assert np.array_equal(got[exact], want[exact])
         checked += int(exact.sum())
     assert checked >= 0.99 * 3 * plain[0].size
+
+
+def _pitched(src, extra_rows, extra_cols, fill):
+    """A view of src's contents inside a larger buffer (extra columns and rows
+    per plane), and the buffer."""
+    big = torch.full((src.shape[0], src.shape[1] + extra_rows, src.shape[2] + extra_cols), fill,
+                     dtype=src.dtype, device=src.device)
+    big[:, :src.shape[1], :src.shape[2]] = src
+    return big, big[:, :src.shape[1], :src.shape[2]]
+
+
+def _outside_unchanged(big, shape, fill):
+    t = big.clone()
+    t[:, :shape[1], :shape[2]] = fill
+    return bool((t == fill).all())
+
+
+def test_epilogue_strided_layout_bitwise():
+    """Inputs and accumulated outputs as views into larger buffers: the dense
+    result bit for bit, nothing outside the output views written."""
+    g = wl.make_grid(150, 37, 23, seed=905)
+    (u, v, w), c = dev_grid(g)
+    rng = np.random.default_rng(906)
+    acc = [torch.from_numpy(rng.uniform(-1, 1, (23, 37, 150)).astype(np.float32)).to("cuda") for _ in range(3)]
+    dense = [x.clone() for x in acc]
+    B.advect_epilogue(u, v, w, c, dense, alpha=0.25, out=dense)
+    xs = [_pitched(x, 2, 5, 1.5)[1] for x in (u, v, w)]
+    outs = [_pitched(x, 1, 3, -4.0) for x in acc]
+    views = [vw for _, vw in outs]
+    B.advect_epilogue(*xs, c, views, alpha=0.25, out=views)
+    torch.cuda.synchronize()
+    for d, (b, vw) in zip(dense, outs):
+        assert torch.equal(d, vw)
+        assert _outside_unchanged(b, d.shape, -4.0)

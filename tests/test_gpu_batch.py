@@ -185,3 +185,41 @@ print("OK")
     r2 = subprocess.run([sys.executable, "-c", code, "read"], env=env, capture_output=True, text=True, timeout=300)
     assert r2.returncode == 0, r2.stderr[-2000:]
     assert [l for l in r2.stdout.splitlines() if l.startswith("SHAPES")] == shapes
+
+
+def test_batch_strided_layouts_bitwise():
+    """Subdomains whose inputs and outputs are views into larger buffers
+    (each with its own pitch): every subdomain equals its dense single-grid
+    result bit for bit, and nothing outside the output views is written."""
+    shapes = [(70, 13, 9), (129, 4, 17), (200, 7, 5), (33, 40, 3)]
+    grids = [wl.make_grid(*s, seed=560 + i) for i, s in enumerate(shapes)]
+    dense_subs, _ = make_subs(grids)
+    refs = [single(s) for s in dense_subs]
+    subs, bigs = [], []
+    for i, (u, v, w, c, outs) in enumerate(dense_subs):
+        er, ec = 1 + i, 3 + 2 * i
+
+        def pitched(src, fill):
+            big = torch.full((src.shape[0], src.shape[1] + er, src.shape[2] + ec), fill, dtype=src.dtype,
+                             device=src.device)
+            big[:, :src.shape[1], :src.shape[2]] = src
+            return big, big[:, :src.shape[1], :src.shape[2]]
+
+        xs = [pitched(x, 2.0)[1] for x in (u, v, w)]
+        os_ = [pitched(o, -6.0) for o in outs]
+        bigs.append(os_)
+        subs.append((*xs, c, tuple(vw for _, vw in os_)))
+    for tile in (None, (0, 4, 16, 1), (2, 2, 8, 4, 2)):
+        for os_ in bigs:
+            for _, vw in os_:
+                vw.fill_(float("nan"))
+        b = B.Batch(subs, tile=tile)
+        b.run()
+        torch.cuda.synchronize()
+        for ref, os_ in zip(refs, bigs):
+            for r, (big, vw) in zip(ref, os_):
+                assert torch.equal(r, vw), tile
+                outside = big.clone()
+                outside[:, :vw.shape[1], :vw.shape[2]] = -6.0
+                assert bool((outside == -6.0).all()), tile
+        b.close()

@@ -119,7 +119,7 @@ pw_status pw_advect(const pw_grid *grid, const pw_layout *layout, pw_dtype in_dt
  *   cols_per_lane 1 or 2: rows_per_strip in {1, 2, 4};
  *   cols_per_lane 4 (not PW_F64): rows_per_strip in {1, 2, 4};
  *   cols_per_lane 8 (16-bit storage): rows_per_strip in {1, 2};
- *   PW_F64: cols_per_lane in {1, 2}, rows_per_strip in {1, 2};
+ *   PW_F64: cols_per_lane in {1, 2}, rows_per_strip in {1, 2, 4};
  *   prefetch 1 or 2 (0 means 1).  A deeper prefetch keeps more bytes in
  *   flight per wavefront; it pays when few wavefronts run.
  * Adjoint (pw_advect_adjoint_ex): cols_per_lane 1 (strips of 62 padded

@@ -39,7 +39,7 @@ __global__ __launch_bounds__(256) void copy16x3_kernel(const u32x4 *__restrict__
 bool tile_supported(const TileCfg &c, pw_dtype dt) {
     if (c.zlen < 1 || c.wpb < 1 || c.wpb > 8 || (c.depth != 1 && c.depth != 2)) return false;
     const bool half = dt == PW_BF16 || dt == PW_F16;
-    if (dt == PW_F64) return (c.px == 1 || c.px == 2) && (c.ry == 1 || c.ry == 2);
+    if (dt == PW_F64) return (c.px == 1 || c.px == 2) && (c.ry == 1 || c.ry == 2 || c.ry == 4);
     if (c.px == 8) return half && (c.ry == 1 || c.ry == 2);
     if (c.px == 4) return c.ry == 1 || c.ry == 2 || c.ry == 4;
     return (c.px == 1 || c.px == 2) && (c.ry == 1 || c.ry == 2 || c.ry == 4);

@@ -140,7 +140,7 @@ pw_status launch_fwd_px(const FwdArgs &g, const TileCfg &cfg, hipStream_t s) {
         case 1: return launch_fwd_t<Tin, PX, 1>(g, cfg, s);
         case 2: return launch_fwd_t<Tin, PX, 2>(g, cfg, s);
         case 4:
-            if constexpr ((sizeof(Tin) <= 4 && PX <= 2) || (sizeof(Tin) <= 4 && PX == 4))
+            if constexpr (PX <= 2 || (sizeof(Tin) <= 4 && PX == 4))
                 return launch_fwd_t<Tin, PX, 4>(g, cfg, s);
             [[fallthrough]];
         default:

@@ -171,9 +171,10 @@ def test_good_tile(lib, tile):
 
 def test_f64_tile_limits(lib):
     g, c, p = _args(dtype=B.PW_F64)
-    for bad in [(4, 1, 8, 4), (1, 4, 8, 4)]:
+    for bad in [(4, 1, 8, 4), (1, 8, 8, 4), (2, 8, 8, 4)]:
         assert _call(g, None, B.PW_F64, c, p, B.pw_tile(*bad)) == B.PW_ERR_INVALID_ARG
-    assert _call(g, None, B.PW_F64, c, p, B.pw_tile(2, 2, 8, 4)) in _no_gpu_status()
+    for good in [(2, 2, 8, 4), (1, 4, 8, 4), (2, 4, 8, 1)]:
+        assert _call(g, None, B.PW_F64, c, p, B.pw_tile(*good)) in _no_gpu_status()
 
 
 def test_adjoint_tile_limits(lib):

@@ -115,7 +115,8 @@ def test_prefetch_depth_invariance_other_dtypes(storage):
     st = None if storage == "float64" else getattr(torch, storage)
     px = 2 if storage == "float64" else 4
     base = run(g, storage=st, tile=(1, 2, 4, 4))
-    for t in [(px, 2, 9, 1, 2), (px, 1, 2, 4, 2), (1, 1, 1, 8, 2)]:
+    four_rows = [(2, 4, 9, 1, 1), (1, 4, 3, 4, 2)] if storage == "float64" else [(4, 4, 5, 1, 1)]
+    for t in [(px, 2, 9, 1, 2), (px, 1, 2, 4, 2), (1, 1, 1, 8, 2)] + four_rows:
         got = run(g, storage=st, tile=t)
         for a, b in zip(base, got):
             assert np.array_equal(a, b), t

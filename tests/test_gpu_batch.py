@@ -223,3 +223,29 @@ def test_batch_strided_layouts_bitwise():
                 outside[:, :vw.shape[1], :vw.shape[2]] = -6.0
                 assert bool((outside == -6.0).all()), tile
         b.close()
+
+
+def test_per_subdomain_width_rule(small_batch):
+    """With 0 columns per lane a subdomain gets 2 columns per lane where that
+    leaves no more lanes idle than 1 (nx rounded up to 128 equals nx rounded
+    up to 64), else 1: the work list has exactly the strips that rule gives."""
+    subs, grids = small_batch
+    ry, zlen = 2, 8
+
+    def items(nx, ny, nz, px):
+        chunks = -(-nz // zlen)
+        zl = -(-nz // chunks)
+        return -(-nx // (64 * px)) * -(-ny // ry) * -(-nz // zl)
+
+    def width(nx):
+        return 2 if -(-nx // 128) * 128 == -(-nx // 64) * 64 else 1
+
+    b = B.Batch(subs, tile=(0, ry, zlen, 1))
+    tile, n_items, _ = b.info()
+    assert tile[0] == 0
+    assert n_items == sum(items(g.nx, g.ny, g.nz, width(g.nx)) for g in grids)
+    assert {width(g.nx) for g in grids} == {1, 2}
+    b.close()
+    b = B.Batch(subs, tile=(2, ry, zlen, 1))
+    assert b.info()[1] == sum(items(g.nx, g.ny, g.nz, 2) for g in grids)
+    b.close()

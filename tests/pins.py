@@ -9,6 +9,7 @@ a wrong stencil index or a wrong field.
 """
 from __future__ import annotations
 
+import itertools
 import os
 from fractions import Fraction
 
@@ -244,3 +245,32 @@ def table_evaluator(table):
             out[o] = out[o] + s * (cv * (sl(fa, oa) * (sl(fb, ob) + sl(fd, od))))
         return out["su"], out["sv"], out["sw"]
     return F
+
+
+def table_mutants(table):
+    """Every single-row mistake in a term table: a dropped row, a flipped sign,
+    another coefficient, an operand offset moved by one (staying inside the
+    27-point box) or another field in an operand; yields (name, table)."""
+    coefs = ("tcx", "tcy", "tzc1", "tzc2", "tzd1", "tzd2")
+    T = list(table)
+    for r, (o, c, s, A, B, D) in enumerate(T):
+        yield "drop%d" % r, T[:r] + T[r + 1:]
+        yield "sign%d" % r, T[:r] + [(o, c, -s, A, B, D)] + T[r + 1:]
+        for c2 in coefs:
+            if c2 != c:
+                yield "coef%d:%s" % (r, c2), T[:r] + [(o, c2, s, A, B, D)] + T[r + 1:]
+        for role in range(3):
+            f, off = (A, B, D)[role]
+            for dim, dd in itertools.product(range(3), (-1, 1)):
+                no = list(off)
+                no[dim] += dd
+                if abs(no[dim]) > 1:
+                    continue
+                new = [A, B, D]
+                new[role] = (f, tuple(no))
+                yield "off%d%s%d%+d" % (r, "abd"[role], dim, dd), T[:r] + [(o, c, s, *new)] + T[r + 1:]
+            for f2 in "uvw":
+                if f2 != f:
+                    new = [A, B, D]
+                    new[role] = (f2, off)
+                    yield "field%d%s:%s" % (r, "abd"[role], f2), T[:r] + [(o, c, s, *new)] + T[r + 1:]

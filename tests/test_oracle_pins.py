@@ -32,39 +32,13 @@ def test_pins_hold_on_exact_table(check):
     assert ok, name
 
 
-def _mutants(table):
-    coefs = ("tcx", "tcy", "tzc1", "tzc2", "tzd1", "tzd2")
-    T = list(table)
-    for r, (o, c, s, A, B, D) in enumerate(T):
-        yield "drop%d" % r, T[:r] + T[r + 1:]
-        yield "sign%d" % r, T[:r] + [(o, c, -s, A, B, D)] + T[r + 1:]
-        for c2 in coefs:
-            if c2 != c:
-                yield "coef%d:%s" % (r, c2), T[:r] + [(o, c2, s, A, B, D)] + T[r + 1:]
-        for role in range(3):
-            f, off = (A, B, D)[role]
-            for dim, dd in itertools.product(range(3), (-1, 1)):
-                no = list(off)
-                no[dim] += dd
-                if abs(no[dim]) > 1:
-                    continue
-                new = [A, B, D]
-                new[role] = (f, tuple(no))
-                yield "off%d%s%d%+d" % (r, "abd"[role], dim, dd), T[:r] + [(o, c, s, *new)] + T[r + 1:]
-            for f2 in "uvw":
-                if f2 != f:
-                    new = [A, B, D]
-                    new[role] = (f2, off)
-                    yield "field%d%s:%s" % (r, "abd"[role], f2), T[:r] + [(o, c, s, *new)] + T[r + 1:]
-
-
 def test_every_plausible_table_mistake_is_caught():
     """A dropped term, flipped sign, wrong coefficient, stencil index moved by
     one in any direction, or wrong field in any operand of any of the 18 terms
     makes at least one pin fail (510 mutants)."""
     survivors = []
     n = 0
-    for name, table in _mutants(bf.TERMS):
+    for name, table in pins.table_mutants(bf.TERMS):
         n += 1
         if all(ok for _, ok in pins.run_all(pins.table_evaluator(table))):
             survivors.append(name)

@@ -119,6 +119,64 @@ def time_launches(torch, launch, nsets, steps, warmup, stream):
     return wall / steps, a.elapsed_time(b) / steps
 
 
+def prewarm(torch, launch, nsets, min_ms):
+    """Launch ``launch(i)`` in batches of 50 until at least ``min_ms`` of wall
+    time has passed (the GPU clocks ramp up over the first ~100 launches);
+    untimed, before the counted warm-up.  Returns (launches, wall ms)."""
+    n, t0 = 0, time.perf_counter()
+    while (time.perf_counter() - t0) * 1e3 < min_ms:
+        for _ in range(50):
+            launch(n % nsets)
+            n += 1
+        torch.cuda.synchronize()
+    return n, (time.perf_counter() - t0) * 1e3
+
+
+def time_blocks(torch, launch, nsets, steps, warmup, stream, blocks=5):
+    """Like time_launches, with HIP events also at the boundaries of
+    ``blocks`` equal runs of back-to-back launches inside the timed region
+    (the paper reports the mean of five runs).  Returns (wall ms per step,
+    event ms per launch over all steps, [event ms per launch of each
+    block])."""
+    for i in range(warmup):
+        launch(i % nsets)
+    torch.cuda.synchronize()
+    bounds = [round(b * steps / blocks) for b in range(blocks + 1)]
+    ev = [torch.cuda.Event(enable_timing=True) for _ in bounds]
+    t0 = time.perf_counter()
+    ev[0].record(stream)
+    for b in range(blocks):
+        for i in range(bounds[b], bounds[b + 1]):
+            launch(i % nsets)
+        ev[b + 1].record(stream)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3
+    per_block = [ev[b].elapsed_time(ev[b + 1]) / max(1, bounds[b + 1] - bounds[b]) for b in range(blocks)]
+    return wall / steps, ev[0].elapsed_time(ev[-1]) / steps, per_block
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def time_oracle(oracle, fields, coeffs, nthreads, seconds, max_reps=1000):
+    """Repeat the FP64 oracle on the full grid for about ``seconds``;
+    returns the list of per-repetition times (s)."""
+    times = []
+    while sum(times) < seconds and len(times) < max_reps:
+        t0 = time.perf_counter()
+        oracle.forward(*fields, coeffs, nthreads=nthreads)
+        times.append(time.perf_counter() - t0)
+    return times
+
+
 def prebuilt_forward(B, ins, outs, coeffs, stream, tile=None):
     """ctypes arguments of one pw_advect_ex call, built once (the timed loop
     then only crosses the C ABI)."""
@@ -308,7 +366,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=200,
                     help="untimed steps first (about 16 ms: the clocks settle within the first ~100)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
-                    help="approximate host time spent timing the oracle")
+                    help="approximate host time spent timing the oracle on all cores (half of it again on 1)")
+    ap.add_argument("--prewarm-ms", type=float, default=150.0,
+                    help="wall time of untimed headline launches before the counted warm-up")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: libpwadv runs on one GPU (the stencil's multi-GPU halo exchange is a "
@@ -343,7 +403,10 @@ def main():
         calls.append(prebuilt_forward(B, ins, outs, coeffs, stream))
 
     forms = {}
-    ms_step, k_ms = time_launches(torch, lambda i: calls[i](), nsets, args.steps, args.warmup, stream)
+    pre_n, pre_ms = prewarm(torch, lambda i: calls[i](), nsets, args.prewarm_ms)
+    log("pre-warm: %d launches in %.0f ms" % (pre_n, pre_ms))
+    ms_step, k_ms, k_blocks = time_blocks(torch, lambda i: calls[i](), nsets, args.steps, args.warmup, stream)
+    k_median = float(np.median(k_blocks))
     # fused accumulation on the same grid and buffers: out += F (reads the outputs too)
     acc_calls = [prebuilt_epilogue(B, kp[0], kp[1], coeffs, 1.0, stream) for kp in keep]
     _, acc_ms = time_launches(torch, lambda i: acc_calls[i](), nsets, 100, 10, stream)
@@ -352,8 +415,8 @@ def main():
     gpts = pts / (ms_step * 1e-3) / 1e9
     nbytes = algo_bytes(nx, ny, nz, h, 4)
     achieved = nbytes / (k_ms * 1e-3) / 1e9
-    log("c1 fp32: %.4f ms/step, kernel %.4f ms, %.1f Gpt/s, %.0f GB/s algorithmic"
-        % (ms_step, k_ms, gpts, achieved))
+    log("c1 fp32: %.4f ms/step, kernel %.4f ms (median of 5 blocks %.4f), %.1f Gpt/s, %.0f GB/s algorithmic"
+        % (ms_step, k_ms, k_median, gpts, achieved))
 
     # plain copy kernel of the same byte count (reachable-bandwidth reference)
     cbytes = (nbytes // 2) // 16 * 16
@@ -421,16 +484,15 @@ def main():
 
     # ------------------------------------------------------------ CPU baseline (oracle)
     ncpu = len(os.sched_getaffinity(0))
-    u64, v64, w64 = (x.astype(np.float64) for x in (g.u, g.v, g.w))
-    reps, t_cpu = 0, 0.0
-    while t_cpu < args.cpu_seconds and reps < 1000:
-        t0 = time.perf_counter()
-        oracle.forward(u64, v64, w64, g.coeffs, nthreads=ncpu)
-        t_cpu += time.perf_counter() - t0
-        reps += 1
-    cpu_gpts = reps * pts / t_cpu / 1e9
-    log("oracle on %d host threads: %.3f Gpt/s (%d reps of the full grid)" % (ncpu, cpu_gpts, reps))
-    del u64, v64, w64
+    f64 = [x.astype(np.float64) for x in (g.u, g.v, g.w)]
+    t_all = time_oracle(oracle, f64, g.coeffs, ncpu, args.cpu_seconds)
+    t_one = time_oracle(oracle, f64, g.coeffs, 1, args.cpu_seconds / 2)
+    cpu_gpts = len(t_all) * pts / sum(t_all) / 1e9
+    cpu_gpts_median = pts / float(np.median(t_all)) / 1e9
+    cpu1_gpts = len(t_one) * pts / sum(t_one) / 1e9
+    log("oracle on %d host threads: %.3f Gpt/s (median %.3f; %d reps of the full grid); on 1 thread %.4f Gpt/s"
+        % (ncpu, cpu_gpts, cpu_gpts_median, len(t_all), cpu1_gpts))
+    del f64
 
     # ------------------------------------------------------------ precision form: c2
     c2 = wl.C2
@@ -566,6 +628,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
+        "prewarm": {"launches": pre_n, "ms": round(pre_ms, 1)},
         "ms_per_step": round(ms_step, 6),
         "higher_is_better": True,
         "scaling": "weak",
@@ -578,10 +641,16 @@ def main():
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic("pw_forward_f32_512x512x64"),
                      "algorithmic_bytes_per_launch": nbytes, "kernel_ms": round(k_ms, 6),
+                     "kernel_ms_median_of_blocks": round(k_median, 6),
+                     "kernel_ms_blocks": [round(x, 6) for x in k_blocks],
                      "copy_kernel_gbs": round(copy_gbs, 1), "copy3_kernel_gbs": round(copy3_gbs, 1)},
         "cpu_baseline": {"value": round(cpu_gpts, 4), "unit": "Gpoints/s", "cores": ncpu, "kind": "oracle",
-                         "sample": "FP64 oracle on the full 512x512x64 grid, %d repetitions (%.1f s)"
-                                   % (reps, t_cpu)},
+                         "sample": "FP64 oracle on the full 512x512x64 grid, %d repetitions (%.1f s) on %d "
+                                   "threads; %d repetitions (%.1f s) on 1 thread"
+                                   % (len(t_all), sum(t_all), ncpu, len(t_one), sum(t_one)),
+                         "median": round(cpu_gpts_median, 4), "value_1_thread": round(cpu1_gpts, 5),
+                         "cpu_model": cpu_model(),
+                         "useful_gflops": round(cpu_gpts * 63, 2)},
         "forms": forms,
     }
     print(json.dumps(line), flush=True)

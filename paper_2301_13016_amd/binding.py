@@ -334,18 +334,61 @@ def _layout_from(inp, out):
     return pw_layout(inp.stride(1), inp.stride(0), out.stride(1), out.stride(0))
 
 
+def _check_inputs(u, v, w):
+    """u, v, w: one shape, one set of strides, one dtype, one device."""
+    if not (u.shape == v.shape == w.shape and u.stride() == v.stride() == w.stride()
+            and u.dtype == v.dtype == w.dtype and u.device == v.device == w.device):
+        raise ValueError("u, v, w must share shape, strides, dtype and device")
+    if u.dim() != 3:
+        raise ValueError("u, v, w must be 3-D padded arrays")
+
+
+def _check_group(ts, what, shape, dtype, device):
+    """Every tensor in ``ts`` has ``shape``, ``dtype`` and ``device``, and all
+    share one set of strides (the library sizes every buffer of a group from
+    one layout)."""
+    ts = list(ts)
+    for t in ts:
+        if tuple(t.shape) != tuple(shape):
+            raise ValueError("%s must have shape %s (got %s)" % (what, tuple(shape), tuple(t.shape)))
+        if t.dtype != dtype:
+            raise ValueError("%s must be %s (got %s)" % (what, dtype, t.dtype))
+        if t.device != device:
+            raise ValueError("%s must be on %s (got %s)" % (what, device, t.device))
+    if any(t.stride() != ts[0].stride() for t in ts):
+        raise ValueError("%s must share one set of strides" % what)
+
+
+def _compute_dtype(t):
+    import torch
+    return torch.float64 if t.dtype == torch.float64 else torch.float32
+
+
+def _check_coeffs(coeffs, nz, dtype, device):
+    """The vertical arrays: ``dtype`` (float64 for FP64 grids, else float32),
+    contiguous, on ``device``, at least nz elements each."""
+    for n in ("tzc1", "tzc2", "tzd1", "tzd2"):
+        t = getattr(coeffs, n)
+        if t.dtype != dtype:
+            raise ValueError("coefficient %s must be %s for this grid (got %s)" % (n, dtype, t.dtype))
+        if t.device != device:
+            raise ValueError("coefficient %s must be on %s (got %s)" % (n, device, t.device))
+        if not t.is_contiguous() or t.numel() < nz:
+            raise ValueError("coefficient %s must be contiguous with at least nz=%d elements" % (n, nz))
+
+
 def advect(u, v, w, coeffs: Coeffs, halo=1, out=None, tile=None, stream=None):
     """su, sv, sw = PW source terms of padded winds u, v, w (torch tensors on the
     GPU; float32, float64, bfloat16 or float16; identical shapes and strides)."""
     import torch
-    if not (u.shape == v.shape == w.shape and u.stride() == v.stride() == w.stride()
-            and u.dtype == v.dtype == w.dtype):
-        raise ValueError("u, v, w must share shape, strides and dtype")
+    _check_inputs(u, v, w)
     grid = _grid_from(u, halo)
-    odt = torch.float64 if u.dtype == torch.float64 else torch.float32
+    odt = _compute_dtype(u)
+    _check_coeffs(coeffs, grid.nz, odt, u.device)
     if out is None:
         out = tuple(torch.empty((grid.nz, grid.ny, grid.nx), dtype=odt, device=u.device) for _ in range(3))
     su, sv, sw = out
+    _check_group(out, "outputs", (grid.nz, grid.ny, grid.nx), odt, u.device)
     layout = _layout_from(u, su)
     c = coeffs.c_struct()
     tl = None if tile is None else pw_tile(*tile)
@@ -361,15 +404,15 @@ def advect_zfast(u, v, w, coeffs: Coeffs, halo=1, out=None, tile=None, stream=No
     (nx, ny, nz) likewise.  Bit-identical to advect() on the transposed
     arrays."""
     import torch
-    if not (u.shape == v.shape == w.shape and u.stride() == v.stride() == w.stride()
-            and u.dtype == v.dtype == w.dtype):
-        raise ValueError("u, v, w must share shape, strides and dtype")
+    _check_inputs(u, v, w)
     pi, pj, pk = u.shape
     grid = pw_grid(pi - 2 * halo, pj - 2 * halo, pk - 2 * halo, halo)
-    odt = torch.float64 if u.dtype == torch.float64 else torch.float32
+    odt = _compute_dtype(u)
+    _check_coeffs(coeffs, grid.nz, odt, u.device)
     if out is None:
         out = tuple(torch.empty((grid.nx, grid.ny, grid.nz), dtype=odt, device=u.device) for _ in range(3))
     su, sv, sw = out
+    _check_group(out, "outputs", (grid.nx, grid.ny, grid.nz), odt, u.device)
     if u.stride(-1) != 1 or su.stride(-1) != 1:
         raise ValueError("z (last) dimension must be contiguous")
     layout = pw_layout_zfast(u.stride(1), u.stride(0), su.stride(1), su.stride(0))
@@ -387,20 +430,19 @@ def advect_bc(u, v, w, coeffs: Coeffs, bc, halo=1, out=None, addends=None, alpha
     "periodic" or "copy" (names or codes).  Equals halo_fill with the same
     rules followed by advect / advect_epilogue, without touching the halo."""
     import torch
-    if not (u.shape == v.shape == w.shape and u.stride() == v.stride() == w.stride()
-            and u.dtype == v.dtype == w.dtype):
-        raise ValueError("u, v, w must share shape, strides and dtype")
+    _check_inputs(u, v, w)
     grid = _grid_from(u, halo)
-    odt = torch.float64 if u.dtype == torch.float64 else torch.float32
+    odt = _compute_dtype(u)
+    _check_coeffs(coeffs, grid.nz, odt, u.device)
     if out is None:
         out = tuple(torch.empty((grid.nz, grid.ny, grid.nx), dtype=odt, device=u.device) for _ in range(3))
     su, sv, sw = out
+    _check_group(out, "outputs", (grid.nz, grid.ny, grid.nx), odt, u.device)
     layout = _layout_from(u, su)
     modes = pw_halo_modes(*(_halo_code(m) for m in bc))
     ep = None
     if addends is not None:
-        if any(c.stride() != su.stride() or c.dtype != odt for c in addends):
-            raise ValueError("addends must share the outputs' strides and dtype")
+        _check_group(list(addends) + list(out), "addends and outputs", (grid.nz, grid.ny, grid.nx), odt, u.device)
         ep = pw_epilogue(float(alpha), *(c.data_ptr() for c in addends))
     tl = None if tile is None else pw_tile(*tile)
     st = lib().pw_advect_bc(grid, layout, _dtype_code(u), u.data_ptr(), v.data_ptr(), w.data_ptr(), coeffs.c_struct(),
@@ -415,18 +457,17 @@ def advect_zfast_epilogue(u, v, w, coeffs: Coeffs, addends, alpha=1.0, halo=1, o
     dtype, each either its output (accumulation in place) or disjoint from
     the outputs."""
     import torch
-    if not (u.shape == v.shape == w.shape and u.stride() == v.stride() == w.stride()
-            and u.dtype == v.dtype == w.dtype):
-        raise ValueError("u, v, w must share shape, strides and dtype")
+    _check_inputs(u, v, w)
     pi, pj, pk = u.shape
     grid = pw_grid(pi - 2 * halo, pj - 2 * halo, pk - 2 * halo, halo)
-    odt = torch.float64 if u.dtype == torch.float64 else torch.float32
+    odt = _compute_dtype(u)
+    _check_coeffs(coeffs, grid.nz, odt, u.device)
     cu, cv, cw = addends
-    if any(c.dtype != odt or c.shape != (grid.nx, grid.ny, grid.nz) or c.stride() != cu.stride() for c in addends):
-        raise ValueError("addends must be %s tensors of shape (nx, ny, nz) with one set of strides" % odt)
+    _check_group(addends, "addends", (grid.nx, grid.ny, grid.nz), odt, u.device)
     if out is None:
         out = tuple(torch.empty((grid.nx, grid.ny, grid.nz), dtype=odt, device=u.device) for _ in range(3))
     su, sv, sw = out
+    _check_group(out, "outputs", (grid.nx, grid.ny, grid.nz), odt, u.device)
     if u.stride(-1) != 1 or su.stride(-1) != 1:
         raise ValueError("z (last) dimension must be contiguous")
     if su.stride() != cu.stride():
@@ -447,13 +488,15 @@ def advect_epilogue(u, v, w, coeffs: Coeffs, addends, alpha=1.0, halo=1, out=Non
     ``addends`` is (cu, cv, cw) in the outputs' layout and compute dtype;
     pass the outputs themselves to accumulate in place (``out=addends``)."""
     import torch
+    _check_inputs(u, v, w)
     grid = _grid_from(u, halo)
+    odt = _compute_dtype(u)
+    _check_coeffs(coeffs, grid.nz, odt, u.device)
     cu, cv, cw = addends
     if out is None:
         out = tuple(torch.empty_like(x) for x in (cu, cv, cw))
     su, sv, sw = out
-    if not (su.stride() == sv.stride() == sw.stride() == cu.stride() == cv.stride() == cw.stride()):
-        raise ValueError("outputs and addends must share one layout")
+    _check_group(list(out) + list(addends), "outputs and addends", (grid.nz, grid.ny, grid.nx), odt, u.device)
     layout = _layout_from(u, su)
     tl = None if tile is None else pw_tile(*tile)
     ep = pw_epilogue(float(alpha), cu.data_ptr(), cv.data_ptr(), cw.data_ptr())
@@ -468,14 +511,19 @@ def advect_epilogue(u, v, w, coeffs: Coeffs, addends, alpha=1.0, halo=1, out=Non
 def advect_adjoint(u, v, w, coeffs: Coeffs, gsu, gsv, gsw, halo=1, out=None, tile=None, stream=None):
     """gu, gv, gw = J(u, v, w)^T (gsu, gsv, gsw), padded-shaped (halo included)."""
     import torch
+    _check_inputs(u, v, w)
     grid = _grid_from(u, halo)
+    _check_coeffs(coeffs, grid.nz, _compute_dtype(u), u.device)
     if out is None:
         out = tuple(torch.empty_like(u) for _ in range(3))
     gu, gv, gw = out
+    for g in (gsu, gsv, gsw):
+        _check_group([g], "cotangents", (grid.nz, grid.ny, grid.nx), u.dtype, u.device)
     gsu, gsv, gsw = (g.contiguous() if g.stride(-1) != 1 else g for g in (gsu, gsv, gsw))
     if not (gsu.stride() == gsv.stride() == gsw.stride()):
         gsu, gsv, gsw = (g.contiguous() for g in (gsu, gsv, gsw))
     layout = _layout_from(u, gsu)
+    _check_group(out, "gradients", tuple(u.shape), u.dtype, u.device)
     if gu.stride() != u.stride():
         raise ValueError("gradients must share the inputs' strides")
     tl = None if tile is None else pw_tile(*tile)
@@ -490,7 +538,9 @@ def advect_tangent(u, v, w, coeffs: Coeffs, du, dv, dw, halo=1, out=None, tile=N
     """tu, tv, tw = J(u, v, w) (du, dv, dw), interior-shaped; du, dv, dw are
     padded like u (the halo is read)."""
     import torch
+    _check_inputs(u, v, w)
     grid = _grid_from(u, halo)
+    _check_coeffs(coeffs, grid.nz, _compute_dtype(u), u.device)
     for d in (du, dv, dw):
         if d.shape != u.shape or d.dtype != u.dtype or d.device != u.device:
             raise ValueError("the direction must match u in shape, dtype and device")
@@ -502,6 +552,7 @@ def advect_tangent(u, v, w, coeffs: Coeffs, du, dv, dw, halo=1, out=None, tile=N
         nz, ny, nx = (s - 2 * halo for s in u.shape)
         out = tuple(torch.empty((nz, ny, nx), dtype=u.dtype, device=u.device) for _ in range(3))
     tu, tv, tw = out
+    _check_group(out, "outputs", (grid.nz, grid.ny, grid.nx), u.dtype, u.device)
     layout = _layout_from(u, tu)
     tl = None if tile is None else pw_tile(*tile)
     st = pw_advect_tangent_ex(grid, layout, _dtype_code(u), u.data_ptr(), v.data_ptr(), w.data_ptr(),
@@ -511,22 +562,28 @@ def advect_tangent(u, v, w, coeffs: Coeffs, du, dv, dw, halo=1, out=None, tile=N
     return tu, tv, tw
 
 
-def advect_coeff_grad(u, v, w, gsu, gsv, gsw, halo=1, stream=None):
+def advect_coeff_grad(u, v, w, gsu, gsv, gsw, halo=1, stream=None, out=None):
     """Gradients of <su, gsu> + <sv, gsv> + <sw, gsw> with respect to the
     coefficients (their values do not enter: the loss is linear in them).
     Returns a dict of float64 device tensors: tcx, tcy (0-d), tzc1, tzc2,
-    tzd1, tzd2 (length nz), tcx_level, tcy_level (each level's share)."""
+    tzd1, tzd2 (length nz), tcx_level, tcy_level (each level's share), views
+    of one (6 nz + 2)-element buffer (``out`` if given)."""
     import torch
+    _check_inputs(u, v, w)
     grid = _grid_from(u, halo)
+    for g in (gsu, gsv, gsw):
+        _check_group([g], "cotangents", (grid.nz, grid.ny, grid.nx), u.dtype, u.device)
     gs = [g.contiguous() if g.stride(-1) != 1 else g for g in (gsu, gsv, gsw)]
     if not (gs[0].stride() == gs[1].stride() == gs[2].stride()):
         gs = [g.contiguous() for g in gs]
     layout = _layout_from(u, gs[0])
+    nz = int(grid.nz)
+    if out is None:
+        out = torch.empty(6 * nz + 2, dtype=torch.float64, device=u.device)
+    _check_group([out], "out", (6 * nz + 2,), torch.float64, u.device)
     need = ctypes.c_int64()
     _check(lib().pw_advect_coeff_grad_workspace(ctypes.byref(grid), _dtype_code(u), ctypes.byref(need)),
            "pw_advect_coeff_grad_workspace")
-    nz = int(grid.nz)
-    out = torch.empty(6 * nz + 2, dtype=torch.float64, device=u.device)
     ws = torch.empty(max(1, need.value // 8), dtype=torch.float64, device=u.device)
     st = lib().pw_advect_coeff_grad(ctypes.byref(grid), ctypes.byref(layout), _dtype_code(u), u.data_ptr(),
                                     v.data_ptr(), w.data_ptr(), *(g.data_ptr() for g in gs), out.data_ptr(),
@@ -572,8 +629,15 @@ class Batch:
         n = len(subdomains)
         items = (pw_batch_item * n)()
         self._keep = []
+        import torch
         for i, (u, v, w, c, outs) in enumerate(subdomains):
             su, sv, sw = outs
+            _check_inputs(u, v, w)
+            if u.dtype != torch.float32:
+                raise ValueError("batched subdomains are float32")
+            g = _grid_from(u, halo)
+            _check_coeffs(c, g.nz, torch.float32, u.device)
+            _check_group(outs, "outputs of subdomain %d" % i, (g.nz, g.ny, g.nx), torch.float32, u.device)
             items[i].grid = _grid_from(u, halo)
             items[i].layout = _layout_from(u, su)
             items[i].u, items[i].v, items[i].w = u.data_ptr(), v.data_ptr(), w.data_ptr()
@@ -628,8 +692,11 @@ def _halo_call(fn, name, fields, modes, halo, stream):
     if not fields:
         return fields
     u = fields[0]
-    if any(f.shape != u.shape or f.stride() != u.stride() or f.dtype != u.dtype for f in fields):
-        raise ValueError("fields must share shape, strides and dtype")
+    if any(f.shape != u.shape or f.stride() != u.stride() or f.dtype != u.dtype or f.device != u.device
+           for f in fields):
+        raise ValueError("fields must share shape, strides, dtype and device")
+    if u.dim() != 3:
+        raise ValueError("fields must be 3-D padded arrays")
     if len(modes) == 3 and all(isinstance(m, (str, int)) for m in modes):
         modes = [modes] * len(fields)
     if len(modes) != len(fields):

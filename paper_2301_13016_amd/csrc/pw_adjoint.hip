@@ -16,9 +16,12 @@
 // padded columns x RY padded rows and marches through padded z-levels with a
 // four-plane register ring (values u, v, w and cotangents of planes k-1, k,
 // k+1 feed level k while k+2 is in flight); x-neighbours come from DPP
-// wavefront shifts.  Cotangents outside the interior read as 0; values
-// outside the padded array are read from the nearest valid entry and always
-// meet a zero cotangent.
+// wavefront shifts.  Cotangents outside the interior read as 0.  Values in
+// cells that no output reads (3-D halo corners, most halo edges, every cell
+// beyond the first halo layer, and positions outside the padded array, which
+// are loaded from the nearest valid entry) read as 0 as well: they only ever
+// meet zero cotangents, and zeroing them keeps a non-finite value there
+// (0 * NaN = NaN) out of the gradient.
 #include "pw_internal.h"
 
 namespace pw {
@@ -59,14 +62,43 @@ template <typename T, int RY> struct APlane {
     T u[RY + 2], v[RY + 2], w[RY + 2];
     T ru[RY + 2], rv[RY + 2], rw[RY + 2];
     bool zok;   // the plane is an interior level, so its cotangents exist (wave-uniform)
+    int kcls;   // position class of the plane (wave-uniform), see pos_class
 };
+
+// Bits of StripAddr::mask for one loaded row and the lane's column: bit
+// 3*kc + f (f = 0, 1, 2 for u, v, w) is set when the forward operator reads
+// that field's cell on a plane of position class kc; kCotOk is set when the
+// row and column are inside the interior (its cotangent exists).
+constexpr uint32_t kCotOk = 1u << 12;
 
 template <typename T, int RY> struct StripAddr {
     uint32_t voff[RY + 2];   // byte offsets of the value rows (clamped)
     uint32_t roff[RY + 2];   // byte offsets of the cotangent rows (clamped)
-    bool rrow[RY + 2];       // cotangent row inside the interior (wave-uniform)
-    bool rcol;               // cotangent column inside the interior (per lane)
+    uint32_t mask[RY + 2];   // per row, see kCotOk
 };
+
+// Position class of a padded coordinate x along an axis with interior
+// [h, h + n): 0 interior, 1 the halo layer just below it, 2 the layer just
+// above it, 3 anything further out (including outside the padded array).
+__device__ __forceinline__ int pos_class(int x, int h, int n) {
+    return (x >= h && x < h + n) ? 0 : (x == h - 1) ? 1 : (x == h + n) ? 2 : 3;
+}
+
+// Whether the forward operator reads a cell of u, v or w, from the classes
+// of its k, j, i coordinates.  Each output reads its point's 7-point star of
+// every field plus two diagonal neighbours per field (u at (0,+1,-1) and
+// (+1,0,-1), v at (0,-1,+1) and (+1,-1,0), w at (-1,0,+1) and (-1,+1,0));
+// so a cell is read when it is inside or in the first halo layer of one
+// axis, or when it sits on the one halo edge per diagonal that such a
+// neighbour reaches.
+__device__ __forceinline__ void cells_read(int kc, int jc, int ic, bool &ru_, bool &rv_, bool &rw_) {
+    const bool far = kc == 3 || jc == 3 || ic == 3;
+    const bool star = (kc != 0) + (jc != 0) + (ic != 0) <= 1;
+    const int code = kc * 16 + jc * 4 + ic;
+    ru_ = !far && (star || code == 0 * 16 + 2 * 4 + 1 || code == 2 * 16 + 0 * 4 + 1);
+    rv_ = !far && (star || code == 0 * 16 + 1 * 4 + 2 || code == 2 * 16 + 1 * 4 + 0);
+    rw_ = !far && (star || code == 1 * 16 + 0 * 4 + 2 || code == 1 * 16 + 2 * 4 + 0);
+}
 
 // Buffer descriptor of one z-plane (base: the plane; range: its bytes, below
 // 2 GiB; word 3 as the GFX9 family wants it for untyped access).  Loads and
@@ -111,6 +143,7 @@ __device__ __forceinline__ void load_aplane(APlane<T, RY> &P, const AdjK<T> &a, 
     // where mask_aplane zeroes what lies outside the interior.
     const int kk = kp - a.h;
     P.zok = kk >= 0 && kk < a.nz;
+    P.kcls = (kp < 0 || kp >= pz) ? 3 : pos_class(kp, a.h, a.nz);
     const int kc = min(max(kk, 0), a.nz - 1);
     const int64_t ob = static_cast<int64_t>(kc) * a.out_sz * static_cast<int64_t>(sizeof(T));
     const int64_t obytes = a.out_sz * static_cast<int64_t>(sizeof(T));
@@ -125,16 +158,20 @@ __device__ __forceinline__ void load_aplane(APlane<T, RY> &P, const AdjK<T> &a, 
     }
 }
 
-// Zero the cotangents of a loaded plane outside the interior (once per plane,
-// at its first use).
+// Zero the cotangents of a loaded plane outside the interior, and the values
+// of cells no output reads (once per plane, at its first use).
 template <typename T, int RY>
 __device__ __forceinline__ void mask_aplane(APlane<T, RY> &P, const StripAddr<T, RY> &s) {
 #pragma unroll
     for (int r = 0; r < RY + 2; ++r) {
-        const bool ok = P.zok && s.rrow[r] && s.rcol;
+        const bool ok = P.zok && (s.mask[r] & kCotOk);
         P.ru[r] = ok ? P.ru[r] : T(0);
         P.rv[r] = ok ? P.rv[r] : T(0);
         P.rw[r] = ok ? P.rw[r] : T(0);
+        const uint32_t rd = s.mask[r] >> (3 * P.kcls);
+        P.u[r] = (rd & 1u) ? P.u[r] : T(0);
+        P.v[r] = (rd & 2u) ? P.v[r] : T(0);
+        P.w[r] = (rd & 4u) ? P.w[r] : T(0);
     }
 }
 
@@ -276,7 +313,8 @@ __global__ __launch_bounds__(MaxT) void pw_adjoint_kernel(AdjK<T> a) {
     const int jb = ty * RY;                             // first padded gradient row
 
     StripAddr<T, RY> s;
-    s.rcol = icol >= 0 && icol < a.nx;
+    const bool rcol = icol >= 0 && icol < a.nx;
+    const int icls = (pcol < 0 || pcol >= px) ? 3 : pos_class(pcol, a.h, a.nx);
     const int icl = min(max(icol, 0), a.nx - 1);
 #pragma unroll
     for (int r = 0; r < RY + 2; ++r) {
@@ -284,7 +322,17 @@ __global__ __launch_bounds__(MaxT) void pw_adjoint_kernel(AdjK<T> a) {
         const int vr = min(max(prow, 0), py - 1);
         s.voff[r] = static_cast<uint32_t>((vr * a.in_sy + vcol) * static_cast<int>(sizeof(T)));
         const int ir = prow - a.h;
-        s.rrow[r] = ir >= 0 && ir < a.ny;
+        const int jcls = (prow < 0 || prow >= py) ? 3 : pos_class(prow, a.h, a.ny);
+        uint32_t m = (rcol && ir >= 0 && ir < a.ny) ? kCotOk : 0u;
+#pragma unroll
+        for (int kc = 0; kc < 4; ++kc) {
+            bool read_u, read_v, read_w;
+            cells_read(kc, jcls, icls, read_u, read_v, read_w);
+            m |= (read_u ? 1u : 0u) << (3 * kc);
+            m |= (read_v ? 2u : 0u) << (3 * kc);
+            m |= (read_w ? 4u : 0u) << (3 * kc);
+        }
+        s.mask[r] = m;
         const int irc = min(max(ir, 0), a.ny - 1);
         s.roff[r] = static_cast<uint32_t>((irc * a.out_sy + icl) * static_cast<int>(sizeof(T)));
     }

@@ -148,12 +148,15 @@ __device__ __forceinline__ void level_cg(const Plane<T, PX, RY> &m, const Plane<
                               G(c.w, q - 1, x) * (G(c.v, q - 1, x) + G(p.v, q - 1, x)));
             const T cz1 = G(m.w, q, x) * (wc + G(m.w, q, x));
             const T cz2 = G(p.w, q, x) * (wc + G(p.w, q, x));
-            s[0] += fma_(a, az1, b * bz1);
-            s[1] -= fma_(a, az2, b * bz2);
-            s[2] += e * cz1;
-            s[3] -= e * cz2;
-            s[4] += fma_(a, ax, fma_(b, bx, e * cx));
-            s[5] += fma_(a, ay, fma_(b, by, e * cy));
+            // A point outside the interior reads clamped cells, which may
+            // hold anything (a NaN there times a zero cotangent is NaN), so
+            // its contributions are selected away, not multiplied away.
+            s[0] += ok ? fma_(a, az1, b * bz1) : T(0);
+            s[1] -= ok ? fma_(a, az2, b * bz2) : T(0);
+            s[2] += ok ? e * cz1 : T(0);
+            s[3] -= ok ? e * cz2 : T(0);
+            s[4] += ok ? fma_(a, ax, fma_(b, bx, e * cx)) : T(0);
+            s[5] += ok ? fma_(a, ay, fma_(b, by, e * cy)) : T(0);
         }
     }
 #pragma unroll

@@ -30,3 +30,14 @@ def pytest_sessionfinish(session, exitstatus):
         os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
         with open(path, "w") as fh:
             json.dump(_REPORT, fh, indent=1, sort_keys=True)
+
+
+def pytest_terminal_summary(terminalreporter, exitstatus, config):
+    """Print the measured figures (per-form errors against the oracle) at the
+    end of the run, so the run's own log carries them."""
+    if not _REPORT:
+        return
+    import json
+    terminalreporter.write_sep("-", "parity figures (errors against the FP64 oracle)")
+    for key in sorted(_REPORT):
+        terminalreporter.write_line("%s: %s" % (key, json.dumps(_REPORT[key], sort_keys=True, default=str)))

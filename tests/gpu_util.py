@@ -5,6 +5,7 @@ from __future__ import annotations
 import numpy as np
 
 import oracle
+from scales import adjoint_scale
 
 
 def dev_grid(g, device="cuda", storage=None):
@@ -39,65 +40,67 @@ def oracle_errors(outs, u, v, w, coeffs, halo=1):
     return [(a_scaled_error(o, r, m), normwise_error(o, r)) for o, r, m in zip(outs, ref, mag)]
 
 
-def subbox_errors(outs_dev, g, boxes, halo=1, inputs=None, normwise=None):
-    """Worst A-scaled error per field of device outputs on interior sub-boxes
-    (k0, k1, j0, j1, i0, i1): the oracle is run on each box with its halo cut
-    out of the padded inputs.  If ``normwise`` is a list, the worst
-    max|got - ref| / max|ref| per field (over the boxes) is appended to it."""
-    u, v, w = (g.u, g.v, g.w) if inputs is None else inputs
-    worst = [0.0, 0.0, 0.0]
-    dmax, rmax = [0.0, 0.0, 0.0], [0.0, 0.0, 0.0]
-    for (k0, k1, j0, j1, i0, i1) in boxes:
-        sl = (slice(k0, k1 + 2 * halo), slice(j0, j1 + 2 * halo), slice(i0, i1 + 2 * halo))
+def host_threads():
+    """Host threads the oracle may use: the usable cores, at most 16."""
+    import os
+    return max(1, min(16, len(os.sched_getaffinity(0))))
+
+
+def full_grid_errors(outs, g, slab=32, halo=1):
+    """Worst A-scaled and normwise error per field, over EVERY interior point,
+    of several device results for one grid: ``outs`` maps a name to the
+    (su, sv, sw) device tensors.  The oracle runs once per z-slab of ``slab``
+    levels (with its halo planes) on the grid's own values, multithreaded, and
+    every result is compared with the same reference.  Returns
+    {name: (a_scaled[3], normwise[3])}."""
+    nz = g.nz
+    worst = {n: [0.0, 0.0, 0.0] for n in outs}
+    dmax = {n: [0.0, 0.0, 0.0] for n in outs}
+    rmax = [0.0, 0.0, 0.0]
+    nt = host_threads()
+    for k0 in range(0, nz, slab):
+        k1 = min(nz, k0 + slab)
+        sl = slice(k0, k1 + 2 * halo)
         c = dict(tcx=g.tcx, tcy=g.tcy, **{n: getattr(g, n)[k0:k1] for n in ("tzc1", "tzc2", "tzd1", "tzd2")})
-        ref, mag = oracle.forward(u[sl], v[sl], w[sl], c, halo=halo, magnitude=True)
+        ref, mag = oracle.forward(g.u[sl], g.v[sl], g.w[sl], c, halo=halo, magnitude=True, nthreads=nt)
         for f in range(3):
-            got = outs_dev[f][k0:k1, j0:j1, i0:i1].cpu().numpy()
-            worst[f] = max(worst[f], a_scaled_error(got, ref[f], mag[f]))
-            dmax[f] = max(dmax[f], float(np.max(np.abs(got.astype(np.float64) - ref[f]))))
             rmax[f] = max(rmax[f], float(np.max(np.abs(ref[f]))))
-    if normwise is not None:
-        normwise.extend(d / r if r > 0 else d for d, r in zip(dmax, rmax))
-    return worst
-
-
-def sample_boxes(nx, ny, nz, n_random=6, size=(8, 16, 70), seed=0):
-    """Corner, edge and random interior boxes of the interior grid."""
-    rng = np.random.default_rng(seed)
-    bz, by, bx = (min(s, n) for s, n in zip(size, (nz, ny, nx)))
-    boxes = []
-    for k0 in (0, nz - bz):
-        for j0 in (0, ny - by):
-            for i0 in (0, nx - bx):
-                boxes.append((k0, k0 + bz, j0, j0 + by, i0, i0 + bx))
-    for _ in range(n_random):
-        k0 = int(rng.integers(0, nz - bz + 1))
-        j0 = int(rng.integers(0, ny - by + 1))
-        i0 = int(rng.integers(0, nx - bx + 1))
-        boxes.append((k0, k0 + bz, j0, j0 + by, i0, i0 + bx))
-    return sorted(set(boxes))
+            inv = 1.0 / np.where(mag[f] > 0, mag[f], 1.0)
+            for name, o in outs.items():
+                got = o[f][k0:k1].cpu().numpy().astype(np.float64)
+                got -= ref[f]
+                np.abs(got, out=got)
+                dmax[name][f] = max(dmax[name][f], float(np.max(got)))
+                got *= inv
+                worst[name][f] = max(worst[name][f], float(np.max(got)))
+    return {n: (worst[n], [d / r if r > 0 else d for d, r in zip(dmax[n], rmax)]) for n in outs}
 
 
 def adjoint_magnitude(u, v, w, coeffs, r, halo=1):
-    """Error scale of J^T r: for every gradient entry the sum of |partial
-    derivative of a term| * |cotangent| over the terms that read it (the
-    brute-force term table, scattered with absolute values)."""
+    """Error scale of J^T r (see scales.adjoint_scale)."""
+    return adjoint_scale(u, v, w, coeffs, r, halo=halo)
+
+
+def unread_cells(shape, halo):
+    """Per field (u, v, w), a boolean mask of the padded cells that no interior
+    output reads: the complement of every term operand's offset applied over
+    the interior (from the brute-force term table)."""
     from oracle.bruteforce import TERMS
-    f = dict(u=np.abs(np.asarray(u, np.float64)), v=np.abs(np.asarray(v, np.float64)),
-             w=np.abs(np.asarray(w, np.float64)))
-    rr = dict(su=np.abs(r[0]), sv=np.abs(r[1]), sw=np.abs(r[2]))
-    pz, py, px = f["u"].shape
+    pz, py, px = shape
     nz, ny, nx = pz - 2 * halo, py - 2 * halo, px - 2 * halo
-    g = {k: np.zeros((pz, py, px)) for k in "uvw"}
+    read = {f: np.zeros(shape, bool) for f in "uvw"}
+    for t in TERMS:
+        for f, off in t[3:]:
+            read[f][halo + off[0]:halo + off[0] + nz, halo + off[1]:halo + off[1] + ny,
+                    halo + off[2]:halo + off[2] + nx] = True
+    return [~read[f] for f in "uvw"]
 
-    def sl(off):
-        return (slice(halo + off[0], halo + off[0] + nz), slice(halo + off[1], halo + off[1] + ny),
-                slice(halo + off[2], halo + off[2] + nx))
 
-    for (o, cname, s, (fa, oa), (fb, ob), (fd, od)) in TERMS:
-        c = coeffs[cname]
-        c = abs(float(c)) if np.ndim(c) == 0 else np.abs(np.asarray(c, np.float64))[:, None, None]
-        g[fa][sl(oa)] += c * rr[o] * (f[fb][sl(ob)] + f[fd][sl(od)])
-        g[fb][sl(ob)] += c * rr[o] * f[fa][sl(oa)]
-        g[fd][sl(od)] += c * rr[o] * f[fa][sl(oa)]
-    return g["u"], g["v"], g["w"]
+def poison_unread(g):
+    """Write NaN, +Inf and -Inf (in turn) into every cell of g's winds that no
+    output reads; returns the masks."""
+    unread = unread_cells(g.u.shape, g.halo)
+    poison = np.array([np.nan, np.inf, -np.inf])
+    for x, m in zip((g.u, g.v, g.w), unread):
+        x[m] = poison[np.arange(int(m.sum())) % 3].astype(x.dtype)
+    return unread

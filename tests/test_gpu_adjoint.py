@@ -3,8 +3,9 @@ the FP64 oracle's scatter-form adjoint, plus the finite-difference and
 dot-product checks of the differentiation form.
 
 Tolerances: A-scaled (A = sum over the terms reading an entry of |partial| *
-|cotangent|) 2e-6 in FP32 (at most ~12 roundings of 2^-24 along any gradient
-sum) and 1e-13 in FP64; bit for bit on integer data with dyadic coefficients.
+|cotangent|, scales.adjoint_scale, pinned on the CPU) 1e-6 in FP32 (at most
+~12 roundings of 2^-24 = 6e-8 along any gradient sum, so about 7e-7) and
+1e-13 in FP64; bit for bit on integer data with dyadic coefficients.
 """
 import sys
 
@@ -12,7 +13,7 @@ import numpy as np
 import pytest
 
 import oracle
-from gpu_util import a_scaled_error, adjoint_magnitude, dev_grid
+from gpu_util import a_scaled_error, adjoint_magnitude, dev_grid, poison_unread
 from paper_2301_13016_amd import binding as B
 from paper_2301_13016_amd import workloads as wl
 
@@ -57,7 +58,7 @@ def test_f32_adjoint_matches_oracle(shape, tile):
     g = wl.make_grid(nx, ny, nz, seed=200 + nx + ny + nz)
     r = wl.cotangents(nx, ny, nz, seed=300 + nx)
     errs, ref = adj_errors(gpu_adjoint(g, r, tile=tile), g, r)
-    assert max(errs) <= 2e-6, errs
+    assert max(errs) <= 1e-6, errs
 
 
 @pytest.mark.parametrize("tile", [None, (1, 2, 4, 4, 2)])
@@ -98,7 +99,7 @@ def test_adjoint_wider_halo(halo, tile):
     g = wl.make_grid(70, 20, 9, seed=204, halo=halo)
     r = wl.cotangents(70, 20, 9, seed=304)
     errs, ref = adj_errors(gpu_adjoint(g, r, halo=halo, tile=tile), g, r, halo=halo)
-    assert max(errs) <= 2e-6, errs
+    assert max(errs) <= 1e-6, errs
 
 
 def test_adjoint_strided_layout_bitwise():
@@ -177,7 +178,7 @@ def test_c4_adjoint_full_grid_parity(grid_c4, report):
     g, r = grid_c4
     errs, _ = adj_errors(gpu_adjoint(g, r), g, r)
     report["adjoint_f32_256x256x128"] = dict(zip(("gu", "gv", "gw"), errs))
-    assert max(errs) <= 2e-6, errs
+    assert max(errs) <= 1e-6, errs
 
 
 def test_c4_dot_product_fp32(grid_c4, report):
@@ -232,3 +233,23 @@ def test_autograd_function_and_gradcheck():
     (a, b, e), c2 = dev_grid(small)
     inp = tuple(x.clone().requires_grad_(True) for x in (a, b, e))
     assert torch.autograd.gradcheck(lambda p, q, s: PW.apply(p, q, s, c2), inp, fast_mode=True)
+
+
+@pytest.mark.parametrize("tile", [None, (1, 1, 5, 4), (1, 4, 3, 1, 2)])
+@pytest.mark.parametrize("shape,halo", [((70, 13, 9), 1), ((130, 5, 3), 1), ((61, 9, 17), 2), ((3, 2, 2), 1)],
+                         ids=lambda x: "x".join(map(str, x)) if isinstance(x, tuple) else "h%d" % x)
+def test_unread_cells_do_not_reach_the_gradient(shape, halo, tile):
+    """NaN and +-Inf in every padded cell that no output reads (halo corners
+    and edges, the outer halo layers) change nothing: the gradient is finite,
+    matches the oracle, and is exactly zero in those cells."""
+    nx, ny, nz = shape
+    g = wl.make_grid(nx, ny, nz, seed=207 + nx, halo=halo)
+    r = wl.cotangents(nx, ny, nz, seed=307 + nx)
+    unread = poison_unread(g)
+    got = gpu_adjoint(g, r, tile=tile, halo=halo)
+    for a, m in zip(got, unread):
+        assert np.all(np.isfinite(a))
+        assert np.all(a[m] == 0)
+    errs, ref = adj_errors(got, g, r, halo=halo)
+    assert all(np.all(np.isfinite(x)) for x in ref)
+    assert max(errs) <= 1e-6, errs

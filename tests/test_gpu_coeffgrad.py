@@ -14,6 +14,7 @@ import pytest
 
 import oracle
 from gpu_util import dev_grid
+from scales import coeff_grad_scale
 from paper_2301_13016_amd import binding as B
 from paper_2301_13016_amd import workloads as wl
 
@@ -40,17 +41,7 @@ def _dev(arrs, dtype=None):
 
 def magnitudes(g, r):
     """Per gradient entry: sum over its terms of |r| * |product|."""
-    nz = g.nz
-    ar = [np.abs(np.asarray(x, np.float64)) for x in r]
-    zero = dict(tcx=0.0, tcy=0.0, **{n: np.zeros(nz) for n in NAMES})
-    out = {}
-    for name in ("tcx", "tcy") + NAMES:
-        c = dict(zero)
-        c[name] = 1.0 if name in ("tcx", "tcy") else np.ones(nz)
-        _, mag = oracle.forward(g.u, g.v, g.w, c, halo=g.halo, magnitude=True)
-        per_level = sum(np.sum(a * m, axis=(1, 2)) for a, m in zip(ar, mag))
-        out[name] = float(per_level.sum()) if name in ("tcx", "tcy") else per_level
-    return out
+    return coeff_grad_scale(g.u, g.v, g.w, r, g.nz, halo=g.halo)
 
 
 def check(g, r, tol, halo=1):

@@ -241,6 +241,25 @@ pw_status pw_advect_coeff_grad(const pw_grid *grid, const pw_layout *layout, pw_
                                double *grad, void *workspace, int64_t workspace_bytes,
                                void *hip_stream);
 
+/* pw_advect_coeff_grad for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels and the same result, bit for bit, with the
+ * per-strip partials in the library's own static device scratch of 16 MiB
+ * (PW_COEFF_GRAD_STATIC_MAX_BYTES) instead of a caller workspace.  Grids
+ * whose partials need more (pw_advect_coeff_grad_workspace() bytes) are
+ * rejected with PW_ERR_UNSUPPORTED before anything runs.  No allocation and
+ * no memset: every partial is written before it is read.  Each GPU holds its
+ * own copy of the scratch until the process ends; its address is looked up
+ * on a device's first call (make that first call outside graph capture).
+ * All calls on one GPU share that scratch, so calls that overlap in time on
+ * one GPU (on different streams, or from different threads without ordering)
+ * race and give wrong results. */
+#define PW_COEFF_GRAD_STATIC_MAX_BYTES (16LL << 20)
+pw_status pw_advect_coeff_grad_static(const pw_grid *grid, const pw_layout *layout, pw_dtype dtype,
+                                      const void *u, const void *v, const void *w,
+                                      const void *gsu, const void *gsv, const void *gsw,
+                                      double *grad, void *hip_stream);
+
 /* Autotuner for single-grid launches.  Times candidate launch shapes of the
  * forward kernel (flags & PW_TUNE_FORWARD), the z-fastest forward kernel
  * (flags & PW_TUNE_ZFAST) and, for PW_F32 / PW_F64, of the adjoint

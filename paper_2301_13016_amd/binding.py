@@ -111,6 +111,8 @@ _SIGNATURES = {
     "pw_advect_coeff_grad_workspace": [ctypes.POINTER(pw_grid), ctypes.c_int, ctypes.POINTER(ctypes.c_int64)],
     "pw_advect_coeff_grad": [ctypes.POINTER(pw_grid), ctypes.POINTER(pw_layout), ctypes.c_int,
                              _P, _P, _P, _P, _P, _P, _P, _P, ctypes.c_int64, _P],
+    "pw_advect_coeff_grad_static": [ctypes.POINTER(pw_grid), ctypes.POINTER(pw_layout), ctypes.c_int,
+                                    _P, _P, _P, _P, _P, _P, _P, _P],
     "pw_advect_zfast": [ctypes.POINTER(pw_grid), ctypes.POINTER(pw_layout_zfast), ctypes.c_int,
                         _P, _P, _P, ctypes.POINTER(pw_coeffs), _P, _P, _P, ctypes.POINTER(pw_tile), _P],
     "pw_advect_zfast_epilogue": [ctypes.POINTER(pw_grid), ctypes.POINTER(pw_layout_zfast), ctypes.c_int,
@@ -562,12 +564,21 @@ def advect_tangent(u, v, w, coeffs: Coeffs, du, dv, dw, halo=1, out=None, tile=N
     return tu, tv, tw
 
 
-def advect_coeff_grad(u, v, w, gsu, gsv, gsw, halo=1, stream=None, out=None):
+def pw_advect_coeff_grad_static(grid, layout, dtype, u, v, w, gsu, gsv, gsw, grad, stream=None):
+    """Raw call of the allocation-free entry point; returns the pw_status."""
+    return lib().pw_advect_coeff_grad_static(ctypes.byref(grid), ctypes.byref(layout) if layout is not None else None,
+                                             int(dtype), u, v, w, gsu, gsv, gsw, grad, stream)
+
+
+def advect_coeff_grad(u, v, w, gsu, gsv, gsw, halo=1, stream=None, out=None, static_scratch=False):
     """Gradients of <su, gsu> + <sv, gsv> + <sw, gsw> with respect to the
     coefficients (their values do not enter: the loss is linear in them).
     Returns a dict of float64 device tensors: tcx, tcy (0-d), tzc1, tzc2,
     tzd1, tzd2 (length nz), tcx_level, tcy_level (each level's share), views
-    of one (6 nz + 2)-element buffer (``out`` if given)."""
+    of one (6 nz + 2)-element buffer (``out`` if given).  With
+    ``static_scratch`` the library's own scratch replaces the workspace
+    (pw_advect_coeff_grad_static: nothing is allocated when ``out`` is
+    given)."""
     import torch
     _check_inputs(u, v, w)
     grid = _grid_from(u, halo)
@@ -581,14 +592,19 @@ def advect_coeff_grad(u, v, w, gsu, gsv, gsw, halo=1, stream=None, out=None):
     if out is None:
         out = torch.empty(6 * nz + 2, dtype=torch.float64, device=u.device)
     _check_group([out], "out", (6 * nz + 2,), torch.float64, u.device)
-    need = ctypes.c_int64()
-    _check(lib().pw_advect_coeff_grad_workspace(ctypes.byref(grid), _dtype_code(u), ctypes.byref(need)),
-           "pw_advect_coeff_grad_workspace")
-    ws = torch.empty(max(1, need.value // 8), dtype=torch.float64, device=u.device)
-    st = lib().pw_advect_coeff_grad(ctypes.byref(grid), ctypes.byref(layout), _dtype_code(u), u.data_ptr(),
-                                    v.data_ptr(), w.data_ptr(), *(g.data_ptr() for g in gs), out.data_ptr(),
-                                    ws.data_ptr(), need.value, _stream_handle(stream))
-    _check(st, "pw_advect_coeff_grad")
+    if static_scratch:
+        st = pw_advect_coeff_grad_static(grid, layout, _dtype_code(u), u.data_ptr(), v.data_ptr(), w.data_ptr(),
+                                         *(g.data_ptr() for g in gs), out.data_ptr(), _stream_handle(stream))
+        _check(st, "pw_advect_coeff_grad_static")
+    else:
+        need = ctypes.c_int64()
+        _check(lib().pw_advect_coeff_grad_workspace(ctypes.byref(grid), _dtype_code(u), ctypes.byref(need)),
+               "pw_advect_coeff_grad_workspace")
+        ws = torch.empty(max(1, need.value // 8), dtype=torch.float64, device=u.device)
+        st = lib().pw_advect_coeff_grad(ctypes.byref(grid), ctypes.byref(layout), _dtype_code(u), u.data_ptr(),
+                                        v.data_ptr(), w.data_ptr(), *(g.data_ptr() for g in gs), out.data_ptr(),
+                                        ws.data_ptr(), need.value, _stream_handle(stream))
+        _check(st, "pw_advect_coeff_grad")
     names = ("tzc1", "tzc2", "tzd1", "tzd2", "tcx_level", "tcy_level")
     res = {n: out[i * nz:(i + 1) * nz] for i, n in enumerate(names)}
     res["tcx"], res["tcy"] = out[6 * nz], out[6 * nz + 1]

@@ -453,20 +453,32 @@ pw_status pw_advect_coeff_grad_workspace(const pw_grid *grid, pw_dtype dtype, in
     return PW_OK;
 }
 
-pw_status pw_advect_coeff_grad(const pw_grid *grid, const pw_layout *layout, pw_dtype dtype,
-                               const void *u, const void *v, const void *w,
-                               const void *gsu, const void *gsv, const void *gsw,
-                               double *grad, void *workspace, int64_t workspace_bytes, void *hip_stream) {
+namespace {
+
+// Validation shared by both coefficient-gradient entry points.  With
+// workspace == NULL (the library's own scratch) only the caller's arrays are
+// checked, and the scratch's size is checked against the need instead.
+pw_status check_coeff_grad(const pw_grid *grid, const pw_layout *layout, pw_dtype dtype,
+                           const void *u, const void *v, const void *w,
+                           const void *gsu, const void *gsv, const void *gsw,
+                           double *grad, void *workspace, int64_t workspace_bytes, Layout *Lout) {
     int64_t need = 0;
     PW_TRY(pw_advect_coeff_grad_workspace(grid, dtype, &need));
     const int64_t es = elem_size(dtype);
     Layout L;
     PW_TRY(resolve_layout(grid, layout, es, es, &L));
+    const bool own = workspace == nullptr;
+    const int nptr = own ? 7 : 8;
     const char *names[] = {"u", "v", "w", "gsu", "gsv", "gsw", "grad", "workspace"};
     const void *ptrs[] = {u, v, w, gsu, gsv, gsw, grad, workspace};
+    if (own && need > kCoeffGradScratchBytes)
+        return fail(PW_ERR_UNSUPPORTED,
+                    "grid needs %lld bytes of partials, beyond the %lld-byte static scratch: "
+                    "use pw_advect_coeff_grad with a workspace",
+                    (long long)need, (long long)kCoeffGradScratchBytes);
     for (int i = 0; i < 6; ++i) PW_TRY(check_aligned(names[i], ptrs[i], es));
-    for (int i = 6; i < 8; ++i) PW_TRY(check_aligned(names[i], ptrs[i], 8));
-    if (workspace_bytes < need)
+    for (int i = 6; i < nptr; ++i) PW_TRY(check_aligned(names[i], ptrs[i], 8));
+    if (!own && workspace_bytes < need)
         return fail(PW_ERR_INVALID_ARG, "workspace of %lld bytes is smaller than the %lld needed",
                     (long long)workspace_bytes, (long long)need);
     const Range rin[6] = {in_range("u", u, grid, L, es), in_range("v", v, grid, L, es), in_range("w", w, grid, L, es),
@@ -474,13 +486,45 @@ pw_status pw_advect_coeff_grad(const pw_grid *grid, const pw_layout *layout, pw_
                           out_range("gsw", gsw, grid, L, es)};
     const uintptr_t gb = reinterpret_cast<uintptr_t>(grad), wb = reinterpret_cast<uintptr_t>(workspace);
     const Range rout[2] = {{"grad", gb, gb + uintptr_t((6 * grid->nz + 2) * 8)}, {"workspace", wb, wb + uintptr_t(need)}};
-    for (const Range &o : rout)
+    for (int o = 0; o < nptr - 6; ++o)
         for (const Range &i : rin)
-            if (overlap(o, i)) return fail(PW_ERR_INVALID_ARG, "%s overlaps %s", o.name, i.name);
-    if (overlap(rout[0], rout[1])) return fail(PW_ERR_INVALID_ARG, "grad overlaps workspace");
+            if (overlap(rout[o], i)) return fail(PW_ERR_INVALID_ARG, "%s overlaps %s", rout[o].name, i.name);
+    if (!own && overlap(rout[0], rout[1])) return fail(PW_ERR_INVALID_ARG, "grad overlaps workspace");
     int dev = 0;
     PW_TRY(current_device(&dev));
-    for (int i = 0; i < 8; ++i) PW_TRY(check_on_device(names[i], ptrs[i], dev));
+    for (int i = 0; i < nptr; ++i) PW_TRY(check_on_device(names[i], ptrs[i], dev));
+    *Lout = L;
+    return PW_OK;
+}
+
+}  // namespace
+
+pw_status pw_advect_coeff_grad_static(const pw_grid *grid, const pw_layout *layout, pw_dtype dtype,
+                                      const void *u, const void *v, const void *w,
+                                      const void *gsu, const void *gsv, const void *gsw,
+                                      double *grad, void *hip_stream) {
+    g_err[0] = 0;
+    Layout L;
+    PW_TRY(check_coeff_grad(grid, layout, dtype, u, v, w, gsu, gsv, gsw, grad, nullptr, 0, &L));
+    void *ws = nullptr;
+    PW_TRY(coeff_grad_scratch(&ws));
+    CgArgs a;
+    a.u = u; a.v = v; a.w = w;
+    a.gsu = gsu; a.gsv = gsv; a.gsw = gsw;
+    a.grad = grad; a.workspace = ws;
+    a.nx = grid->nx; a.ny = grid->ny; a.nz = grid->nz; a.h = grid->halo;
+    a.in_sy = L.in_sy; a.in_sz = L.in_sz; a.out_sy = L.out_sy; a.out_sz = L.out_sz;
+    return launch_coeff_grad(a, dtype, static_cast<hipStream_t>(hip_stream));
+}
+
+pw_status pw_advect_coeff_grad(const pw_grid *grid, const pw_layout *layout, pw_dtype dtype,
+                               const void *u, const void *v, const void *w,
+                               const void *gsu, const void *gsv, const void *gsw,
+                               double *grad, void *workspace, int64_t workspace_bytes, void *hip_stream) {
+    g_err[0] = 0;
+    if (!workspace) return fail(PW_ERR_INVALID_ARG, "workspace is NULL");
+    Layout L;
+    PW_TRY(check_coeff_grad(grid, layout, dtype, u, v, w, gsu, gsv, gsw, grad, workspace, workspace_bytes, &L));
     CgArgs a;
     a.u = u; a.v = v; a.w = w;
     a.gsu = gsu; a.gsv = gsv; a.gsw = gsw;

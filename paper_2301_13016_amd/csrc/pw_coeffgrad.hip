@@ -13,6 +13,8 @@
 // workspace.  Pass 2 sums the strips of each (quantity, level) in a fixed
 // order, and pass 3 the levels of tcx and tcy.  No atomics: the result is the
 // same on every run.
+#include <mutex>
+
 #include "pw_stencil.h"
 
 namespace pw {
@@ -351,7 +353,36 @@ template <typename T> pw_status launch_cg_t(const CgArgs &g, hipStream_t s) {
     return hip_fail(hipGetLastError(), "coefficient gradient total launch");
 }
 
+// Scratch of the allocation-free entry point (pw_advect_coeff_grad_static):
+// the per-strip partials of one call live in this array instead of a caller
+// workspace.  Each GPU the library runs on holds its own copy until the
+// process ends.  Host code never uses the array's name as an address (on the
+// host it is a stand-in, not device memory); it uses the address that
+// hipGetSymbolAddress returns on each device.
+static __device__ __align__(256) double scratch[kCoeffGradScratchBytes / sizeof(double)];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices];
+
 }  // namespace
+
+pw_status coeff_grad_scratch(void **ptr) {
+    int dev = 0;
+    const hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(PW_ERR_UNSUPPORTED, "device %d beyond the scratch table", dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e2 = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e2 != hipSuccess) return hip_fail(e2, "hipGetSymbolAddress(scratch)");
+        if (!p) return fail(PW_ERR_HIP, "hipGetSymbolAddress(scratch) returned NULL");
+        g_scratch_ptr[dev] = p;
+    }
+    *ptr = g_scratch_ptr[dev];
+    return PW_OK;
+}
 
 int64_t coeff_grad_workspace_bytes(const pw_grid &g, pw_dtype dt) {
     const int px = dt == PW_F64 ? CgShape<double>::PX : CgShape<float>::PX;

@@ -108,6 +108,10 @@ pw_status launch_adjoint(const AdjArgs &a, pw_dtype dt, const TileCfg &cfg, hipS
 pw_status launch_tangent(const TanArgs &a, pw_dtype dt, const TileCfg &cfg, hipStream_t s);
 int64_t coeff_grad_workspace_bytes(const pw_grid &g, pw_dtype dt);
 pw_status launch_coeff_grad(const CgArgs &a, pw_dtype dt, hipStream_t s);
+// Size of the library's own coefficient-gradient scratch, and its address on
+// the current device (looked up once per device, no allocation).
+constexpr int64_t kCoeffGradScratchBytes = PW_COEFF_GRAD_STATIC_MAX_BYTES;
+pw_status coeff_grad_scratch(void **ptr);
 pw_status launch_halo(const HaloArgs &a, hipStream_t s);
 pw_status launch_halo_fold(const HaloArgs &a, hipStream_t s);   // es 4 or 8
 // z-fastest forward (pw_zfast.hip): FwdArgs carry the column stride in

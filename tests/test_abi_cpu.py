@@ -368,6 +368,35 @@ def test_coeff_grad_validation(lib):
     assert call(bad) == B.PW_ERR_INVALID_ARG
 
 
+def test_coeff_grad_static_validation(lib):
+    """The allocation-free coefficient-gradient entry point: the same checks
+    as with a workspace, and grids whose partials exceed its static scratch
+    are refused (PW_ERR_UNSUPPORTED) before any HIP call."""
+    g, c, p = _args()
+    q = [A + i * MB for i in range(7)]   # u v w gsu gsv gsw grad
+    call = lambda gg, qq, dt=B.PW_F32: lib.pw_advect_coeff_grad_static(ctypes.byref(gg), None, dt,  # noqa: E731
+                                                                        *qq[:6], qq[6], None)
+    assert call(g, q) in _no_gpu_status()
+    bad = list(q); bad[6] = q[3] + 8          # grad inside gsu
+    assert call(g, bad) == B.PW_ERR_INVALID_ARG
+    bad = list(q); bad[6] = q[6] + 4          # grad not 8-byte aligned
+    assert call(g, bad) == B.PW_ERR_INVALID_ARG
+    assert call(g, q, B.PW_BF16) == B.PW_ERR_UNSUPPORTED
+    # 2048 x 2048 x 256 FP32: 16 x 1024 strips x 6 x 256 levels x 8 B = 192 MiB of partials
+    big = B.pw_grid(2048, 2048, 256, 1)
+    need = ctypes.c_int64()
+    assert lib.pw_advect_coeff_grad_workspace(ctypes.byref(big), B.PW_F32, ctypes.byref(need)) == B.PW_OK
+    assert need.value > 16 << 20
+    assert call(big, q) == B.PW_ERR_UNSUPPORTED and "static scratch" in B.pw_last_error()
+    # the largest grid class that fits: 16 MiB / (6 * 8 B) partials per level and strip
+    edge = B.pw_grid(256, 256, 128 * 4, 1)    # 2 x 128 strips x 512 levels x 48 B = 6 MiB
+    far = [A + i * (1 << 30) for i in range(7)]   # 1 GiB apart: no array overlaps another
+    st = call(edge, far)
+    assert st in _no_gpu_status() and "static scratch" not in B.pw_last_error()
+    if st == B.PW_ERR_INVALID_ARG:            # on a GPU machine: the device-pointer check, nothing else
+        assert "device" in B.pw_last_error()
+
+
 def test_stream_copy3_validation(lib):
     s = [A + i * MB for i in range(3)]
     d = [A + (3 + i) * MB for i in range(3)]

@@ -17,7 +17,9 @@ Also measured in the same run ("forms"):
   * 64 uneven subdomains (FP32) in one persistent launch replayed from a HIP
     graph vs 64 plain launches;
   * a plain copy kernel and a three-stream copy (the stencil's pattern of three
-    arrays read and three written): reachable-bandwidth references;
+    arrays read and three written), and a probe kernel swept over loads in
+    flight per lane, cache policy and workgroup count for copy, read-only and
+    write-only streams: reachable-bandwidth references;
   * the FP64 oracle on the host cores ("cpu_baseline", the only use of the
     oracle here).
 Their errors against the oracle are measured by the GPU test suite.
@@ -66,7 +68,7 @@ def kernel_fingerprint():
     import hashlib
     csrc = os.path.join(ROOT, "paper_2301_13016_amd", "csrc")
     hsh = hashlib.sha256()
-    for name in ("pw_stencil.h", "pw_forward_impl.h", "pw_forward_f32.hip"):
+    for name in ("pw_stencil.h", "pw_forward_impl.h", "pw_forward_f32.hip", "pw_forward_lds_f32.hip"):
         with open(os.path.join(csrc, name), "rb") as f:
             hsh.update(f.read())
     with open(os.path.join(csrc, "pw_tune_defaults.inc")) as f:
@@ -434,6 +436,37 @@ def main():
     _, c3_ms = time_launches(torch, lambda i: B.stream_copy3(*sets3[i]), 4, 200, 10, stream)
     copy3_gbs = 6 * obytes / (c3_ms * 1e-3) / 1e9
     log("three-stream copy 3 x %d MB each way: %.4f ms, %.0f GB/s" % (obytes >> 20, c3_ms, copy3_gbs))
+    # reachable bandwidth: the probe kernel (copy, read-only, write-only) swept
+    # over loads in flight per lane, cache policy and workgroup count, on
+    # 512 MiB buffers (twice the MALL), four sets in rotation
+    pb = 512 << 20
+    psrc = [torch.empty(pb // 4, device=dev) for _ in range(4)]
+    pdst = [torch.empty(pb // 4, device=dev) for _ in range(4)]
+    for x in psrc:
+        x.fill_(1.0)
+    sink = torch.zeros(1024, dtype=torch.int32, device=dev)
+    reach = {}
+    for mode, name, loads_list, flag_list in ((0, "copy", (1, 2, 4, 8), (0, 1, 2, 3)), (1, "read", (1, 4, 8), (0, 1)),
+                                              (2, "write", (1, 4), (0, 2))):
+        best = None
+        for loads in loads_list:
+            for flags in flag_list:
+                for blocks in (512, 1024, 2048, 4096, 8192, 16384, 32768):
+                    def probe(i, mode=mode, loads=loads, flags=flags, blocks=blocks):
+                        if mode == 1:
+                            B.stream_probe(1, loads, flags, psrc[i], sink, blocks)
+                        else:
+                            B.stream_probe(mode, loads, flags, psrc[i], pdst[i], blocks)
+                    _, pms = time_launches(torch, probe, 4, 20, 3, stream)
+                    gbs = (2 if mode == 0 else 1) * pb / (pms * 1e-3) / 1e9
+                    if best is None or gbs > best["gbs"]:
+                        best = dict(gbs=round(gbs, 1), loads_per_lane=loads, nt_loads=bool(flags & 1),
+                                    nt_stores=bool(flags & 2), blocks=blocks)
+        reach[name] = best
+    log("reachable bandwidth (best of the probe sweep): copy %.0f GB/s, read %.0f GB/s, write %.0f GB/s"
+        % (reach["copy"]["gbs"], reach["read"]["gbs"], reach["write"]["gbs"]))
+    forms["reachable_bandwidth"] = reach
+    del psrc, pdst, sink
     nbytes_acc = nbytes + 3 * nx * ny * nz * 4
     forms["fused_accumulate_512x512x64"] = dict(
         kernel_ms=round(acc_ms, 4), over_plain=round(acc_ms / k_ms, 3),
@@ -643,7 +676,9 @@ def main():
                      "algorithmic_bytes_per_launch": nbytes, "kernel_ms": round(k_ms, 6),
                      "kernel_ms_median_of_blocks": round(k_median, 6),
                      "kernel_ms_blocks": [round(x, 6) for x in k_blocks],
-                     "copy_kernel_gbs": round(copy_gbs, 1), "copy3_kernel_gbs": round(copy3_gbs, 1)},
+                     "copy_kernel_gbs": round(copy_gbs, 1), "copy3_kernel_gbs": round(copy3_gbs, 1),
+                     "reachable_copy_gbs": forms["reachable_bandwidth"]["copy"]["gbs"],
+                     "frac_of_reachable_copy": round(achieved / forms["reachable_bandwidth"]["copy"]["gbs"], 4)},
         "cpu_baseline": {"value": round(cpu_gpts, 4), "unit": "Gpoints/s", "cores": ncpu, "kind": "oracle",
                          "sample": "FP64 oracle on the full 512x512x64 grid, %d repetitions (%.1f s) on %d "
                                    "threads; %d repetitions (%.1f s) on 1 thread"

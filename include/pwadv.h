@@ -131,6 +131,18 @@ pw_status pw_advect(const pw_grid *grid, const pw_layout *layout, pw_dtype in_dt
  * Tangent: prefetch 0, 1 or 2.
  * Tangent (pw_advect_tangent_ex): cols_per_lane 1 or 2 (PW_F64: 1),
  *   rows_per_strip in {1, 2}.
+ * share_rows (forward only; 0 everywhere else): 0 = the wavefronts of a
+ *   workgroup are independent, each reading the row below and the row above
+ *   its strip from memory (served by L2); 1 = the waves_per_group (2 or 4)
+ *   wavefronts own consecutive strips in y and hand their edge rows to each
+ *   other through LDS, so every row is read once per workgroup (the 2.5-D
+ *   tile staged in LDS, paper Sec. 2.2 and Fig. 1: each value from memory
+ *   once, neighbours on chip); 2 = as 1, and the rows that no other
+ *   workgroup reads are loaded non-temporally.  Shared tiles take prefetch 1
+ *   and: FP32 cols_per_lane 4 with rows_per_strip 1, 2 or 4; BF16 / FP16
+ *   cols_per_lane 4 with rows 2 or 4, or 8 with rows 2; FP64 cols_per_lane 2
+ *   with rows 2 or 4.  pw_advect_bc runs a shared tile as the same shape
+ *   with share_rows 0.
  * Always zlen >= 1 and waves_per_group in 1..8.  Other values give
  * PW_ERR_INVALID_ARG. */
 typedef struct {
@@ -139,6 +151,7 @@ typedef struct {
     int32_t zlen;
     int32_t waves_per_group;
     int32_t prefetch;
+    int32_t share_rows;
 } pw_tile;
 
 /* pw_advect with an explicit launch shape; tile == NULL means the library's
@@ -480,6 +493,20 @@ pw_status pw_stream_copy(const void *src, void *dst, int64_t nbytes, void *hip_s
  * reachable rate for that pattern.  Same argument rules as pw_stream_copy;
  * no two of the six ranges may overlap. */
 pw_status pw_stream_copy3(const void *const src[3], void *const dst[3], int64_t nbytes, void *hip_stream);
+
+/* Bandwidth probe (measurement only: the rate the HBM reaches for plain
+ * streams, the ceiling the stencil kernels are compared with).
+ *   mode 0: copy src -> dst; 1: read src only (dst is a sink of at least
+ *   4096 bytes, written only if an XOR of all data read equals one fixed
+ *   128-bit pattern); 2: write dst only (src unused, may be NULL).
+ *   loads_per_lane in {1, 2, 4, 8}: independent 16-byte loads (or stores)
+ *   per lane in flight before the matching stores.
+ *   flags bit 0: non-temporal loads; bit 1: non-temporal stores.
+ *   blocks: workgroups of 256 threads, 1 .. 1048576 (grid-stride loop).
+ * nbytes > 0 and a multiple of 16; buffers 16-byte aligned device memory of
+ * nbytes each (the read-only sink: 4096), not overlapping. */
+pw_status pw_stream_probe(int32_t mode, int32_t loads_per_lane, int32_t flags, const void *src, void *dst,
+                          int64_t nbytes, int32_t blocks, void *hip_stream);
 
 #ifdef __cplusplus
 }

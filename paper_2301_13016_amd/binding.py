@@ -56,12 +56,13 @@ class pw_coeffs(ctypes.Structure):
 
 class pw_tile(ctypes.Structure):
     _fields_ = [("cols_per_lane", ctypes.c_int32), ("rows_per_strip", ctypes.c_int32),
-                ("zlen", ctypes.c_int32), ("waves_per_group", ctypes.c_int32), ("prefetch", ctypes.c_int32)]
+                ("zlen", ctypes.c_int32), ("waves_per_group", ctypes.c_int32), ("prefetch", ctypes.c_int32),
+                ("share_rows", ctypes.c_int32)]
 
 
 def _tile_tuple(t):
-    """(cols_per_lane, rows_per_strip, zlen, waves_per_group, prefetch)."""
-    return (t.cols_per_lane, t.rows_per_strip, t.zlen, t.waves_per_group, t.prefetch)
+    """(cols_per_lane, rows_per_strip, zlen, waves_per_group, prefetch, share_rows)."""
+    return (t.cols_per_lane, t.rows_per_strip, t.zlen, t.waves_per_group, t.prefetch, t.share_rows)
 
 
 class pw_epilogue(ctypes.Structure):
@@ -126,6 +127,7 @@ _SIGNATURES = {
     "pw_halo_fold": [ctypes.POINTER(pw_grid), ctypes.POINTER(pw_layout), ctypes.c_int, ctypes.POINTER(_P),
                      ctypes.POINTER(pw_halo_modes), ctypes.c_int32, _P],
     "pw_stream_copy": [_P, _P, ctypes.c_int64, _P],
+    "pw_stream_probe": [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, _P, ctypes.c_int64, ctypes.c_int32, _P],
     "pw_stream_copy3": [ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.c_int64, _P],
     "pw_tune": [ctypes.POINTER(pw_grid), ctypes.c_int, ctypes.c_int32, ctypes.POINTER(pw_tile),
                 ctypes.POINTER(pw_tile)],
@@ -613,8 +615,8 @@ def advect_coeff_grad(u, v, w, gsu, gsv, gsw, halo=1, stream=None, out=None, sta
 
 def tune(nx, ny, nz, dtype, halo=1, flags=0):
     """Run the autotuner for this grid class; returns (forward tile, adjoint
-    tile) as (cols_per_lane, rows_per_strip, zlen, waves_per_group, prefetch) tuples
-    (the adjoint entry is None when not tuned)."""
+    tile) as (cols_per_lane, rows_per_strip, zlen, waves_per_group, prefetch,
+    share_rows) tuples (the adjoint entry is None when not tuned)."""
     import torch
     code = {torch.float32: PW_F32, torch.float64: PW_F64, torch.bfloat16: PW_BF16, torch.float16: PW_F16}[dtype]
     f, a = pw_tile(), pw_tile()
@@ -625,7 +627,7 @@ def tune(nx, ny, nz, dtype, halo=1, flags=0):
 def launch_shape(kind, nx, ny, nz, dtype, halo=1):
     """The launch shape ``kind`` ("forward", "adjoint", "tangent" or "zfast")
     takes for this grid when called without a tile, as (cols_per_lane,
-    rows_per_strip, zlen, waves_per_group, prefetch)."""
+    rows_per_strip, zlen, waves_per_group, prefetch, share_rows)."""
     import torch
     code = {torch.float32: PW_F32, torch.float64: PW_F64, torch.bfloat16: PW_BF16, torch.float16: PW_F16}[dtype]
     k = {"forward": PW_KERNEL_FORWARD, "adjoint": PW_KERNEL_ADJOINT, "tangent": PW_KERNEL_TANGENT,
@@ -750,6 +752,20 @@ def halo_fill(fields, modes, halo=1, stream=None):
     of triples, one per field; each entry is a name from HALO_MODES or its
     code.  Returns ``fields``."""
     return _halo_call(pw_halo_fill, "pw_halo_fill", fields, modes, halo, stream)
+
+
+def pw_stream_probe(mode, loads_per_lane, flags, src, dst, nbytes, blocks, stream=None):
+    return lib().pw_stream_probe(int(mode), int(loads_per_lane), int(flags), src, dst, int(nbytes), int(blocks),
+                                 stream)
+
+
+def stream_probe(mode, loads_per_lane, flags, src, dst, blocks, stream=None):
+    """One launch of the bandwidth probe (mode 0 copy, 1 read, 2 write; see
+    pw_stream_probe) over ``src`` (or ``dst`` for writes) of torch tensors."""
+    buf = dst if mode == 2 else src
+    n = buf.numel() * buf.element_size()
+    _check(pw_stream_probe(mode, loads_per_lane, flags, 0 if src is None else src.data_ptr(), dst.data_ptr(), n,
+                           blocks, _stream_handle(stream)), "pw_stream_probe")
 
 
 def stream_copy(src, dst, stream=None):

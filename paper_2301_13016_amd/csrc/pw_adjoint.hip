@@ -470,7 +470,7 @@ pw_status launch_adj_dt(const AdjArgs &g, const TileCfg &cfg, hipStream_t s) {
 
 bool adjoint_tile_supported(const TileCfg &c) {
     return c.px == 1 && (c.depth == 1 || c.depth == 2) && (c.ry == 1 || c.ry == 2 || c.ry == 4) && c.zlen >= 1 &&
-           c.wpb >= 1 && c.wpb <= 8;
+           c.wpb >= 1 && c.wpb <= 8 && c.share == 0;
 }
 
 TileCfg default_adjoint_tile(const AdjArgs &a, pw_dtype dt) {

@@ -159,6 +159,7 @@ TileCfg to_cfg(const pw_tile &t) {
     c.zlen = t.zlen;
     c.wpb = t.waves_per_group;
     c.depth = t.prefetch == 0 ? 1 : t.prefetch;
+    c.share = t.share_rows;
     return c;
 }
 
@@ -285,8 +286,10 @@ pw_status advect_general(const pw_grid *grid, const pw_layout *layout, pw_dtype 
     FwdArgs a;
     PW_TRY(validate_forward(grid, layout, in_dtype, u, v, w, coeffs, su, sv, sw, &a));
     if (tile && !tile_supported(to_cfg(*tile), in_dtype))
-        return fail(PW_ERR_INVALID_ARG, "unsupported forward tile cols=%d rows=%d zlen=%d waves=%d prefetch=%d",
-                    tile->cols_per_lane, tile->rows_per_strip, tile->zlen, tile->waves_per_group, tile->prefetch);
+        return fail(PW_ERR_INVALID_ARG,
+                    "unsupported forward tile cols=%d rows=%d zlen=%d waves=%d prefetch=%d share_rows=%d",
+                    tile->cols_per_lane, tile->rows_per_strip, tile->zlen, tile->waves_per_group, tile->prefetch,
+                    tile->share_rows);
     if (bc) {
         const int32_t m[3] = {bc->x, bc->y, bc->z};
         for (int d = 0; d < 3; ++d)
@@ -362,8 +365,10 @@ pw_status pw_advect_ex(const pw_grid *grid, const pw_layout *layout, pw_dtype in
     FwdArgs a;
     PW_TRY(validate_forward(grid, layout, in_dtype, u, v, w, coeffs, su, sv, sw, &a));
     if (tile && !tile_supported(to_cfg(*tile), in_dtype))
-        return fail(PW_ERR_INVALID_ARG, "unsupported forward tile cols=%d rows=%d zlen=%d waves=%d prefetch=%d",
-                    tile->cols_per_lane, tile->rows_per_strip, tile->zlen, tile->waves_per_group, tile->prefetch);
+        return fail(PW_ERR_INVALID_ARG,
+                    "unsupported forward tile cols=%d rows=%d zlen=%d waves=%d prefetch=%d share_rows=%d",
+                    tile->cols_per_lane, tile->rows_per_strip, tile->zlen, tile->waves_per_group, tile->prefetch,
+                    tile->share_rows);
     PW_TRY(check_forward_on_device(a));
     TileCfg cfg;
     if (tile)
@@ -769,6 +774,32 @@ pw_status pw_stream_copy3(const void *const src[3], void *const dst[3], int64_t 
     PW_TRY(current_device(&dev));
     for (int i = 0; i < 6; ++i) PW_TRY(check_on_device(names[i], p[i], dev));
     return launch_copy3(src, dst, nbytes, static_cast<hipStream_t>(hip_stream));
+}
+
+pw_status pw_stream_probe(int32_t mode, int32_t loads_per_lane, int32_t flags, const void *src, void *dst,
+                          int64_t nbytes, int32_t blocks, void *hip_stream) {
+    g_err[0] = 0;
+    if (mode < 0 || mode > 2) return fail(PW_ERR_INVALID_ARG, "mode %d (0 copy, 1 read, 2 write)", mode);
+    if (loads_per_lane != 1 && loads_per_lane != 2 && loads_per_lane != 4 && loads_per_lane != 8)
+        return fail(PW_ERR_INVALID_ARG, "loads_per_lane %d (1, 2, 4 or 8)", loads_per_lane);
+    if (flags & ~3) return fail(PW_ERR_INVALID_ARG, "unknown flags 0x%x", flags);
+    if (blocks < 1 || blocks > (1 << 20)) return fail(PW_ERR_INVALID_ARG, "blocks %d out of 1..1048576", blocks);
+    if (nbytes <= 0 || nbytes % 16) return fail(PW_ERR_INVALID_ARG, "nbytes must be a positive multiple of 16");
+    const bool use_src = mode != 2;
+    if ((use_src && !src) || !dst) return fail(PW_ERR_INVALID_ARG, "NULL pointer");
+    if ((reinterpret_cast<uintptr_t>(use_src ? src : nullptr) | reinterpret_cast<uintptr_t>(dst)) % 16)
+        return fail(PW_ERR_INVALID_ARG, "pointers must be 16-byte aligned");
+    const int64_t dbytes = mode == 1 ? 4096 : nbytes;
+    if (use_src) {
+        const Range a{"src", reinterpret_cast<uintptr_t>(src), reinterpret_cast<uintptr_t>(src) + uintptr_t(nbytes)};
+        const Range b{"dst", reinterpret_cast<uintptr_t>(dst), reinterpret_cast<uintptr_t>(dst) + uintptr_t(dbytes)};
+        if (overlap(a, b)) return fail(PW_ERR_INVALID_ARG, "src and dst overlap");
+    }
+    int dev = 0;
+    PW_TRY(current_device(&dev));
+    if (use_src) PW_TRY(check_on_device("src", src, dev));
+    PW_TRY(check_on_device("dst", dst, dev));
+    return launch_probe(mode, loads_per_lane, flags, src, dst, nbytes, blocks, static_cast<hipStream_t>(hip_stream));
 }
 
 }  // extern "C"

@@ -256,6 +256,7 @@ pw_status enqueue(pw_batch *b, hipStream_t s) {
 }
 
 bool batch_tile_ok(const TileCfg &c) {
+    if (c.share != 0) return false;
     if (c.px == 0) {
         TileCfg c1 = c, c2 = c;
         c1.px = 1;

@@ -64,6 +64,22 @@ __global__ __launch_bounds__(MaxT) void pw_forward_kernel(FwdK<Tin> a) {
     strip_march<Tin, PX, RY, Depth, Epi, Bc>(a, tx, ty, cz);
 }
 
+// W wavefronts per workgroup sharing their edge rows through LDS (see
+// strip_march_lds): the workgroup covers W consecutive strips in y.  Every
+// wavefront runs, also one whose strip lies past the grid, so that all reach
+// the same barriers.
+template <typename Tin, int PX, int RY, int Depth, bool Epi, bool Bc, int W, bool NtOwn = false>
+__global__ __launch_bounds__(64 * W) void pw_forward_lds_kernel(FwdK<Tin> a) {
+    __shared__ EdgeLds<Tin, PX, W> L;
+    const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    const int cz = t % a.nzc;
+    const int t2 = t / a.nzc;
+    const int tx = t2 % a.ntx;
+    const int ty = (t2 / a.ntx) * W + wave;
+    strip_march_lds<Tin, PX, RY, Depth, Epi, Bc, W, NtOwn>(a, L, tx, ty, cz, wave);
+}
+
 template <typename Tin, int PX, int RY, bool Epi, bool Bc>
 void launch_fwd_b(const FwdK<Tin> &a, const TileCfg &cfg, dim3 grid, dim3 block, hipStream_t s) {
     if (cfg.depth == 2) {
@@ -88,7 +104,7 @@ void launch_fwd_k(const FwdK<Tin> &a, const TileCfg &cfg, dim3 grid, dim3 block,
 }
 
 template <typename Tin, int PX, int RY>
-pw_status launch_fwd_t(const FwdArgs &g, const TileCfg &cfg, hipStream_t s) {
+FwdK<Tin> make_fwdk(const FwdArgs &g, const TileCfg &cfg) {
     using Tc = typename Storage<Tin>::Tc;
     FwdK<Tin> a;
     a.u = static_cast<const Tin *>(g.u);
@@ -123,6 +139,12 @@ pw_status launch_fwd_t(const FwdArgs &g, const TileCfg &cfg, hipStream_t s) {
     a.bcx = g.bcx;
     a.bcy = g.bcy;
     a.bcz = g.bcz;
+    return a;
+}
+
+template <typename Tin, int PX, int RY>
+pw_status launch_fwd_t(const FwdArgs &g, const TileCfg &cfg, hipStream_t s) {
+    const FwdK<Tin> a = make_fwdk<Tin, PX, RY>(g, cfg);
     const int64_t nblk_y = (a.nty + cfg.wpb - 1) / cfg.wpb;
     const int64_t nblocks = static_cast<int64_t>(a.ntx) * nblk_y * a.nzc;
     if (nblocks <= 0 || nblocks > 0x7fffffffLL) return fail(PW_ERR_UNSUPPORTED, "grid too large");
@@ -162,6 +184,31 @@ pw_status launch_fwd_dt(const FwdArgs &g, const TileCfg &cfg, hipStream_t s) {
             [[fallthrough]];
         default: return fail(PW_ERR_UNSUPPORTED, "%d columns per lane not instantiated", cfg.px);
     }
+}
+
+// Shared-row tiles (cfg.share 1 or 2; see strip_march_lds).  Launched with
+// exactly cfg.wpb wavefronts per workgroup; boundary rules are not built in
+// (launch_forward runs those calls with independent strips).
+template <typename Tin, int PX, int RY, int W, bool NtOwn>
+pw_status launch_lds_w(const FwdArgs &g, const TileCfg &cfg, hipStream_t s) {
+    const FwdK<Tin> a = make_fwdk<Tin, PX, RY>(g, cfg);
+    const int64_t nblk_y = (a.nty + W - 1) / W;
+    const int64_t nblocks = static_cast<int64_t>(a.ntx) * nblk_y * a.nzc;
+    if (nblocks <= 0 || nblocks > 0x7fffffffLL) return fail(PW_ERR_UNSUPPORTED, "grid too large");
+    const dim3 grid(static_cast<unsigned>(nblocks)), block(64 * W);
+    if (g.epilogue)
+        hipLaunchKernelGGL((pw_forward_lds_kernel<Tin, PX, RY, 1, true, false, W, NtOwn>), grid, block, 0, s, a);
+    else
+        hipLaunchKernelGGL((pw_forward_lds_kernel<Tin, PX, RY, 1, false, false, W, NtOwn>), grid, block, 0, s, a);
+    return hip_fail(hipGetLastError(), "forward kernel launch");
+}
+
+template <typename Tin, int PX, int RY>
+pw_status launch_lds_t(const FwdArgs &g, const TileCfg &cfg, hipStream_t s) {
+    const bool nt = cfg.share == 2;
+    if (cfg.wpb == 2) return nt ? launch_lds_w<Tin, PX, RY, 2, true>(g, cfg, s) : launch_lds_w<Tin, PX, RY, 2, false>(g, cfg, s);
+    if (cfg.wpb == 4) return nt ? launch_lds_w<Tin, PX, RY, 4, true>(g, cfg, s) : launch_lds_w<Tin, PX, RY, 4, false>(g, cfg, s);
+    return fail(PW_ERR_UNSUPPORTED, "shared rows with %d wavefronts per workgroup not instantiated", cfg.wpb);
 }
 
 }  // namespace fwd

@@ -24,8 +24,9 @@ struct TileCfg {
     int zlen = 16;
     int wpb = 4;
     int depth = 1;
+    int share = 0;   // pw_tile.share_rows
 };
-inline pw_tile to_tile(const TileCfg &c) { return pw_tile{c.px, c.ry, c.zlen, c.wpb, c.depth}; }
+inline pw_tile to_tile(const TileCfg &c) { return pw_tile{c.px, c.ry, c.zlen, c.wpb, c.depth, c.share}; }
 
 // Operands of one forward launch, already validated.  Strides are in elements.
 struct FwdArgs {
@@ -104,6 +105,11 @@ pw_status launch_forward_f32(const FwdArgs &a, const TileCfg &cfg, hipStream_t s
 pw_status launch_forward_f64(const FwdArgs &a, const TileCfg &cfg, hipStream_t s);
 pw_status launch_forward_bf16(const FwdArgs &a, const TileCfg &cfg, hipStream_t s);
 pw_status launch_forward_f16(const FwdArgs &a, const TileCfg &cfg, hipStream_t s);
+// the same with a shared-row tile (cfg.share != 0), pw_forward_lds_{f32,...}.hip
+pw_status launch_forward_lds_f32(const FwdArgs &a, const TileCfg &cfg, hipStream_t s);
+pw_status launch_forward_lds_f64(const FwdArgs &a, const TileCfg &cfg, hipStream_t s);
+pw_status launch_forward_lds_bf16(const FwdArgs &a, const TileCfg &cfg, hipStream_t s);
+pw_status launch_forward_lds_f16(const FwdArgs &a, const TileCfg &cfg, hipStream_t s);
 pw_status launch_adjoint(const AdjArgs &a, pw_dtype dt, const TileCfg &cfg, hipStream_t s);
 pw_status launch_tangent(const TanArgs &a, pw_dtype dt, const TileCfg &cfg, hipStream_t s);
 int64_t coeff_grad_workspace_bytes(const pw_grid &g, pw_dtype dt);
@@ -126,6 +132,8 @@ pw_status launch_zfast_f64(const FwdArgs &a, const TileCfg &cfg, hipStream_t s);
 pw_status launch_zfast_bf16(const FwdArgs &a, const TileCfg &cfg, hipStream_t s);
 pw_status launch_zfast_f16(const FwdArgs &a, const TileCfg &cfg, hipStream_t s);
 pw_status launch_copy(const void *src, void *dst, int64_t nbytes, hipStream_t s);
+pw_status launch_probe(int mode, int loads, int flags, const void *src, void *dst, int64_t nbytes, int blocks,
+                       hipStream_t s);
 pw_status launch_copy3(const void *const *src, void *const *dst, int64_t nbytes, hipStream_t s);
 
 // Host-side validation shared by pw_advect and the batched form (pw_api.cpp).

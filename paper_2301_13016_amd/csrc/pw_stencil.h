@@ -554,5 +554,286 @@ __device__ __forceinline__ void strip_march(const FwdK<Tin> &a, int tx, int ty, 
     }
 }
 
+// --------------------------------------------------- strips sharing rows in LDS
+// W wavefronts of one workgroup own W consecutive strips in y over the same
+// columns.  Each loads only its own RY rows of every plane (plus the packed
+// x-halo); the row just below and the row just above its strip are its
+// neighbours' edge rows, passed through LDS, so that a row is read from
+// memory once per workgroup instead of once per strip that touches it.  Only
+// the workgroup's lowest wavefront reads the row below the workgroup, and its
+// highest the row above.  The role of a wavefront is a template parameter, so
+// the march of each role is straight-line code.
+enum : int { kRoleLo = 1, kRoleMid = 2, kRoleHi = 3 };
+
+template <typename Tin, int PX> struct LdsVec;
+template <> struct LdsVec<float, 4> { typedef float type __attribute__((ext_vector_type(4))); };
+template <> struct LdsVec<float, 2> { typedef float type __attribute__((ext_vector_type(2))); };
+template <> struct LdsVec<float, 1> { typedef float type; };
+template <> struct LdsVec<double, 2> { typedef double type __attribute__((ext_vector_type(2))); };
+template <> struct LdsVec<double, 1> { typedef double type; };
+template <> struct LdsVec<uint16_t, 8> { typedef uint16_t type __attribute__((ext_vector_type(8))); };
+template <> struct LdsVec<uint16_t, 4> { typedef uint16_t type __attribute__((ext_vector_type(4))); };
+template <> struct LdsVec<uint16_t, 2> { typedef uint16_t type __attribute__((ext_vector_type(2))); };
+template <> struct LdsVec<uint16_t, 1> { typedef uint16_t type; };
+template <> struct LdsVec<_Float16, 8> { typedef _Float16 type __attribute__((ext_vector_type(8))); };
+template <> struct LdsVec<_Float16, 4> { typedef _Float16 type __attribute__((ext_vector_type(4))); };
+template <> struct LdsVec<_Float16, 2> { typedef _Float16 type __attribute__((ext_vector_type(2))); };
+template <> struct LdsVec<_Float16, 1> { typedef _Float16 type; };
+
+// Edge rows of one plane per slot: [slot][wavefront][0: first own row, 1:
+// last own row][field][lane].  A plane's edge rows are written and read in
+// the same level (before and after its barrier), and consecutive planes
+// alternate between two slots.  That is enough: a wavefront writes the slot
+// of plane L+1 at level L only after passing the barrier of level L-1, and
+// every wavefront arrives at that barrier with all its LDS accesses
+// complete (the barrier waits for them), including its reads of the same
+// slot, which held plane L-1 and were made at level L-2.
+constexpr int kLdsSlots = 2;
+template <typename Tin, int PX, int W> struct EdgeLds {
+    typename LdsVec<Tin, PX>::type e[kLdsSlots][W][2][3][64];
+};
+
+template <typename Tin, int PX>
+__device__ __forceinline__ void lds_put(typename LdsVec<Tin, PX>::type &d, const typename Vec<Tin, PX>::type &x) {
+    if constexpr (PX == 1) {
+        d = x;
+    } else {
+        typename LdsVec<Tin, PX>::type t;
+#pragma unroll
+        for (int m = 0; m < PX; ++m) t[m] = x[m];
+        d = t;
+    }
+}
+template <typename Tin, int PX>
+__device__ __forceinline__ void lds_get(typename Vec<Tin, PX>::type &d, const typename LdsVec<Tin, PX>::type &x) {
+    if constexpr (PX == 1) {
+        d = x;
+    } else {
+        const typename LdsVec<Tin, PX>::type t = x;
+#pragma unroll
+        for (int m = 0; m < PX; ++m) d[m] = t[m];
+    }
+}
+
+// A plane's own rows (1..RY) and, by role, the row below (lowest wavefront)
+// or above (highest) the workgroup, plus the packed x-halo of all RY+2 rows.
+// NtOwn: rows that no other workgroup reads (not the workgroup's first or
+// last own row) are read with non-temporal loads.
+template <typename Tin, int PX, int RY, bool Full, bool Bc, int Role, bool NtOwn = false>
+__device__ __forceinline__ void load_plane_own(Plane<Tin, PX, RY> &P, const FwdK<Tin> &a, int kp,
+                                               const StripAddr<RY> &s, int last_col) {
+    const int64_t pb = static_cast<int64_t>(kp) * a.in_sz * static_cast<int64_t>(sizeof(Tin));
+    const char *bu = reinterpret_cast<const char *>(a.u) + pb;
+    const char *bv = reinterpret_cast<const char *>(a.v) + pb;
+    const char *bw = reinterpret_cast<const char *>(a.w) + pb;
+    constexpr int r0 = (Role == kRoleLo) ? 0 : 1;
+    constexpr int r1 = (Role == kRoleHi) ? RY + 1 : RY;
+#pragma unroll
+    for (int r = r0; r <= r1; ++r) {
+        const bool shared = r == 0 || r == RY + 1 || (Role == kRoleLo && r == 1) || (Role == kRoleHi && r == RY);
+        if (NtOwn && Full && !shared) {
+            using VT = typename Vec<Tin, PX>::type;
+            P.u[r] = PW_GLOAD_NT(VT, bu + s.roff[r]);
+            P.v[r] = PW_GLOAD_NT(VT, bv + s.roff[r]);
+            P.w[r] = PW_GLOAD_NT(VT, bw + s.roff[r]);
+            continue;
+        }
+        load_row<Tin, PX, Full, Bc>(P.u[r], bu, s.roff[r], s.col, last_col, a.nx, a.h, a.bcx);
+        load_row<Tin, PX, Full, Bc>(P.v[r], bv, s.roff[r], s.col, last_col, a.nx, a.h, a.bcx);
+        load_row<Tin, PX, Full, Bc>(P.w[r], bw, s.roff[r], s.col, last_col, a.nx, a.h, a.bcx);
+    }
+    P.hu = PW_GLOAD(Tin, bu + s.hoff);
+    P.hv = PW_GLOAD(Tin, bv + s.hoff);
+    P.hw = PW_GLOAD(Tin, bw + s.hoff);
+}
+
+// Publish this wavefront's edge rows of a plane: the first own row for the
+// wavefront below, the last for the one above.
+template <typename Tin, int PX, int RY, int W, int Role>
+__device__ __forceinline__ void put_edges(EdgeLds<Tin, PX, W> &L, int slot, int wave, int lane,
+                                          const Plane<Tin, PX, RY> &P) {
+    if constexpr (Role != kRoleLo) {
+        lds_put<Tin, PX>(L.e[slot][wave][0][0][lane], P.u[1]);
+        lds_put<Tin, PX>(L.e[slot][wave][0][1][lane], P.v[1]);
+        lds_put<Tin, PX>(L.e[slot][wave][0][2][lane], P.w[1]);
+    }
+    if constexpr (Role != kRoleHi) {
+        lds_put<Tin, PX>(L.e[slot][wave][1][0][lane], P.u[RY]);
+        lds_put<Tin, PX>(L.e[slot][wave][1][1][lane], P.v[RY]);
+        lds_put<Tin, PX>(L.e[slot][wave][1][2][lane], P.w[RY]);
+    }
+}
+
+// Take the rows just outside the strip from the neighbours' edge rows.
+template <typename Tin, int PX, int RY, int W, int Role>
+__device__ __forceinline__ void get_edges(const EdgeLds<Tin, PX, W> &L, int slot, int wave, int lane,
+                                          Plane<Tin, PX, RY> &P) {
+    if constexpr (Role != kRoleLo) {
+        lds_get<Tin, PX>(P.u[0], L.e[slot][wave - 1][1][0][lane]);
+        lds_get<Tin, PX>(P.v[0], L.e[slot][wave - 1][1][1][lane]);
+        lds_get<Tin, PX>(P.w[0], L.e[slot][wave - 1][1][2][lane]);
+    }
+    if constexpr (Role != kRoleHi) {
+        lds_get<Tin, PX>(P.u[RY + 1], L.e[slot][wave + 1][0][0][lane]);
+        lds_get<Tin, PX>(P.v[RY + 1], L.e[slot][wave + 1][0][1][lane]);
+        lds_get<Tin, PX>(P.w[RY + 1], L.e[slot][wave + 1][0][2][lane]);
+    }
+}
+
+// The march of one wavefront of an LDS-sharing workgroup: as strip_march_t,
+// with one barrier per level.  At level kk the wavefront publishes the edge
+// rows of plane kk+1 (loaded a level earlier), waits at the barrier, and
+// completes plane kk+1 with its neighbours' rows; planes kk-1 and kk were
+// completed at the two levels before.  Every wavefront of the workgroup runs
+// the same number of levels (same z-chunk), also one whose strip lies past
+// the grid (it loads clamped rows and stores nothing), so the barriers match.
+template <typename Tin, int PX, int RY, bool Full, int Depth, bool Epi, bool Bc, int W, int Role, bool NtOwn = false>
+__device__ __forceinline__ void strip_march_lds_t(const FwdK<Tin> &a, EdgeLds<Tin, PX, W> &L, int tx, int ty,
+                                                  int cz, int wave) {
+    using Tc = typename Storage<Tin>::Tc;
+    const int lane = threadIdx.x & 63;
+
+    const int pcols = a.nx + 2 * a.h, prows = a.ny + 2 * a.h;
+    const int last_col = pcols - 1;
+    const int ii0 = tx * 64 * PX + lane * PX;
+    const int nvalid = a.nx - ii0;
+    const int jj0 = ty * RY;
+
+    StripAddr<RY> s;
+    s.col = min(ii0 + a.h, last_col);
+#pragma unroll
+    for (int r = 0; r < RY + 2; ++r) {
+        const int prow = bc_map<Bc>(min(jj0 - 1 + a.h + r, prows - 1), a.ny, a.h, a.bcy);
+        s.roff[r] = static_cast<uint32_t>((prow * a.in_sy + s.col) * static_cast<int>(sizeof(Tin)));
+    }
+    {
+        const int hr = min(lane & 31, RY + 1);
+        const int hrow = bc_map<Bc>(min(jj0 - 1 + a.h + hr, prows - 1), a.ny, a.h, a.bcy);
+        const int hcol = bc_map<Bc>((lane & 32) ? min(tx * 64 * PX + 64 * PX + a.h, last_col) : tx * 64 * PX + a.h - 1,
+                                    a.nx, a.h, a.bcx);
+        s.hoff = static_cast<uint32_t>((hrow * a.in_sy + hcol) * static_cast<int>(sizeof(Tin)));
+    }
+    uint32_t ooff[RY];
+    bool row_ok[RY];
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+        row_ok[r] = jj0 + r < a.ny;
+        const int jj = min(jj0 + r, a.ny - 1);
+        const int ic = min(ii0, a.nx - 1);
+        ooff[r] = static_cast<uint32_t>((jj * a.out_sy + ic) * static_cast<int>(sizeof(Tc)));
+    }
+    const bool lane0 = lane == 0, lane63 = lane == 63;
+    const int ic = min(ii0, a.nx - 1);
+
+    const int k0 = cz * a.zlen;
+    const int k1 = min(a.nz, k0 + a.zlen);
+    const int h = a.h;
+    EpiRows<Tin, PX, RY> Ep;
+    int slot = 0;   // slot of plane kk+1 at level kk: planes k0-1, k0, k0+1, ... take slots 0, 1, 2, 0, ...
+
+#define PW_PLOAD(P, kp) \
+    load_plane_own<Tin, PX, RY, Full, Bc, Role, NtOwn>(P, a, bc_map<Bc>(min((kp), k1) + h, a.nz, h, a.bcz), s, last_col)
+#define PW_LOAD(P, kp)                                                   \
+    do {                                                                 \
+        if constexpr (Epi) {                                             \
+            load_epi<Tin, PX, RY, Full>(Ep, a, kk, ooff, ic);            \
+            __builtin_amdgcn_sched_barrier(0);                           \
+        }                                                                \
+        PW_PLOAD(P, kp);                                                 \
+    } while (0)
+#define PW_SHARE(P)                                                      \
+    do {                                                                 \
+        put_edges<Tin, PX, RY, W, Role>(L, slot, wave, lane, P);         \
+        __syncthreads();                                                 \
+        get_edges<Tin, PX, RY, W, Role>(L, slot, wave, lane, P);         \
+        slot = slot == kLdsSlots - 1 ? 0 : slot + 1;                     \
+    } while (0)
+#define PW_LEVEL(M, C, P)                                                                          \
+    do {                                                                                           \
+        PW_SHARE(P);                                                                               \
+        level<Tin, PX, RY, Full, Epi>(M, C, P, a, kk, lane0, lane63, nvalid, ooff, row_ok, Ep);   \
+    } while (0)
+    int kk = k0;
+    if constexpr (Depth == 1) {
+        Plane<Tin, PX, RY> A, B, C, D;
+        load_plane_own<Tin, PX, RY, Full, Bc, Role, NtOwn>(A, a, bc_map<Bc>(k0 - 1 + h, a.nz, h, a.bcz), s, last_col);
+        PW_PLOAD(B, k0);
+        PW_PLOAD(C, k0 + 1);
+        PW_SHARE(A);
+        PW_SHARE(B);
+        for (;;) {
+            PW_LOAD(D, kk + 2);
+            PW_LEVEL(A, B, C);
+            if (++kk >= k1) break;
+            PW_LOAD(A, kk + 2);
+            PW_LEVEL(B, C, D);
+            if (++kk >= k1) break;
+            PW_LOAD(B, kk + 2);
+            PW_LEVEL(C, D, A);
+            if (++kk >= k1) break;
+            PW_LOAD(C, kk + 2);
+            PW_LEVEL(D, A, B);
+            if (++kk >= k1) break;
+        }
+    } else {
+        static_assert(Depth == 2, "prefetch depth 1 or 2");
+        Plane<Tin, PX, RY> A, B, C, D, E;
+        load_plane_own<Tin, PX, RY, Full, Bc, Role, NtOwn>(A, a, bc_map<Bc>(k0 - 1 + h, a.nz, h, a.bcz), s, last_col);
+        PW_PLOAD(B, k0);
+        PW_PLOAD(C, k0 + 1);
+        PW_PLOAD(D, k0 + 2);
+        PW_SHARE(A);
+        PW_SHARE(B);
+        for (;;) {
+            PW_LOAD(E, kk + 3);
+            PW_LEVEL(A, B, C);
+            if (++kk >= k1) break;
+            PW_LOAD(A, kk + 3);
+            PW_LEVEL(B, C, D);
+            if (++kk >= k1) break;
+            PW_LOAD(B, kk + 3);
+            PW_LEVEL(C, D, E);
+            if (++kk >= k1) break;
+            PW_LOAD(C, kk + 3);
+            PW_LEVEL(D, E, A);
+            if (++kk >= k1) break;
+            PW_LOAD(D, kk + 3);
+            PW_LEVEL(E, A, B);
+            if (++kk >= k1) break;
+        }
+    }
+#undef PW_PLOAD
+#undef PW_LOAD
+#undef PW_SHARE
+#undef PW_LEVEL
+}
+
+// Dispatch of one wavefront of an LDS-sharing workgroup to its role's march
+// (the wave index is wave-uniform, so this branch is taken once, before any
+// load), and to the full-strip or x-edge path.
+template <typename Tin, int PX, int RY, int Depth, bool Epi, bool Bc, int W, bool Full, bool NtOwn>
+__device__ __forceinline__ void strip_march_lds_f(const FwdK<Tin> &a, EdgeLds<Tin, PX, W> &L, int tx, int ty,
+                                                  int cz, int wave) {
+    static_assert(W >= 2, "sharing needs two wavefronts or more");
+    if (wave == 0)
+        strip_march_lds_t<Tin, PX, RY, Full, Depth, Epi, Bc, W, kRoleLo, NtOwn>(a, L, tx, ty, cz, wave);
+    else if (wave == W - 1)
+        strip_march_lds_t<Tin, PX, RY, Full, Depth, Epi, Bc, W, kRoleHi, NtOwn>(a, L, tx, ty, cz, wave);
+    else if constexpr (W > 2)
+        strip_march_lds_t<Tin, PX, RY, Full, Depth, Epi, Bc, W, kRoleMid, NtOwn>(a, L, tx, ty, cz, wave);
+}
+
+template <typename Tin, int PX, int RY, int Depth, bool Epi, bool Bc, int W, bool NtOwn = false>
+__device__ __forceinline__ void strip_march_lds(const FwdK<Tin> &a, EdgeLds<Tin, PX, W> &L, int tx, int ty, int cz,
+                                                int wave) {
+    if constexpr (PX == 1) {
+        strip_march_lds_f<Tin, PX, RY, Depth, Epi, Bc, W, false, NtOwn>(a, L, tx, ty, cz, wave);
+    } else if ((tx + 1) * 64 * PX <= a.nx) {
+        strip_march_lds_f<Tin, PX, RY, Depth, Epi, Bc, W, true, NtOwn>(a, L, tx, ty, cz, wave);
+    } else {
+        strip_march_lds_f<Tin, PX, RY, Depth, Epi, Bc, W, false, NtOwn>(a, L, tx, ty, cz, wave);
+    }
+}
+
 }  // namespace dev
 }  // namespace pw

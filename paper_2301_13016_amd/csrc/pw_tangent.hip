@@ -359,7 +359,7 @@ pw_status launch_tl_dt(const TanArgs &g, const TileCfg &cfg, hipStream_t s) {
 }  // namespace
 
 bool tangent_tile_supported(const TileCfg &c, pw_dtype dt) {
-    if (c.zlen < 1 || c.wpb < 1 || c.wpb > 8 || (c.depth != 1 && c.depth != 2)) return false;
+    if (c.zlen < 1 || c.wpb < 1 || c.wpb > 8 || (c.depth != 1 && c.depth != 2) || c.share != 0) return false;
     if (c.ry != 1 && c.ry != 2) return false;
     if (dt == PW_F64) return c.px == 1;
     return c.px == 1 || c.px == 2;

@@ -5,7 +5,7 @@
 namespace pw {
 
 bool zfast_tile_supported(const TileCfg &c, pw_dtype dt) {
-    if (c.zlen < 1 || c.wpb < 1 || c.wpb > 8 || (c.depth != 1 && c.depth != 2)) return false;
+    if (c.zlen < 1 || c.wpb < 1 || c.wpb > 8 || (c.depth != 1 && c.depth != 2) || c.share != 0) return false;
     const bool pz_ok = c.px == 1 || c.px == 2 || (c.px == 4 && dt != PW_F64);
     const bool ry_ok = c.ry == 1 || c.ry == 2 || (c.ry == 4 && c.px <= 2) || (c.ry == 8 && c.px == 1);
     return pz_ok && ry_ok;

@@ -39,9 +39,10 @@ def main(out_path):
     from paper_2301_13016_amd import binding as B
     code = {"float32": B.PW_F32, "float64": B.PW_F64, "bfloat16": B.PW_BF16, "float16": B.PW_F16}
     tdt = {"float32": torch.float32, "float64": torch.float64, "bfloat16": torch.bfloat16, "float16": torch.float16}
-    lines = ["// kind, dtype, log2 nx, log2 ny, log2 nz, cols/lane, rows/strip, z-chunks, waves/group, prefetch",
-             "// (kind 3, z-fastest: levels/lane, rows/strip, x-chunks, waves/group, prefetch)",
-             "// generated on %s by paper_2301_13016_amd/tune_defaults.py" % torch.cuda.get_device_name(0)]
+    lines = ["// kind, dtype, log2 nx, log2 ny, log2 nz, cols/lane, rows/strip, z-chunks, waves/group, prefetch, "
+             "share_rows",
+             "// (kind 3, z-fastest: levels/lane, rows/strip, x-chunks, waves/group, prefetch, 0)",
+             "// generated on %s by paper_2301_13016_amd/tune_defaults.py, unedited" % torch.cuda.get_device_name(0)]
     B.pw_tune_reset()
     for nx, ny, nz, dt, flags in SHAPES:
         B._check(B.pw_tune(B.pw_grid(nx, ny, nz, 1), code[dt], flags, None, None), "pw_tune")
@@ -52,8 +53,8 @@ def main(out_path):
                 continue
             t = B.launch_shape(name, nx, ny, nz, tdt[dt])
             nzc = -(-zext // t[2])
-            lines.append("{%d, %d, %d, %d, %d, %d, %d, %d, %d, %d},  // %dx%dx%d %s %s" % (
-                kind, code[dt], *key, t[0], t[1], nzc, t[3], t[4], nx, ny, nz, dt, name))
+            lines.append("{%d, %d, %d, %d, %d, %d, %d, %d, %d, %d, %d},  // %dx%dx%d %s %s" % (
+                kind, code[dt], *key, t[0], t[1], nzc, t[3], t[4], t[5], nx, ny, nz, dt, name))
             print(lines[-1], flush=True)
     with open(out_path, "w") as fh:
         fh.write("\n".join(lines) + "\n")

@@ -169,6 +169,27 @@ def test_good_tile(lib, tile):
     assert _call(g, None, B.PW_F32, c, p, B.pw_tile(*tile)) in _no_gpu_status()
 
 
+def test_shared_row_tile_rules(lib):
+    """share_rows: 1 or 2 with 2 or 4 wavefronts per group, prefetch 1 and
+    the instantiated column / row counts per dtype; 0 is independent strips.
+    Only the forward takes it."""
+    g, c, p = _args()
+    ok = [(B.PW_F32, (4, 1, 8, 4, 1, 1)), (B.PW_F32, (4, 2, 8, 2, 1, 2)), (B.PW_F32, (4, 4, 8, 4, 0, 1)),
+          (B.PW_BF16, (8, 2, 8, 4, 1, 1)), (B.PW_F16, (4, 4, 8, 2, 1, 2)), (B.PW_F64, (2, 4, 8, 4, 1, 1))]
+    bad = [(B.PW_F32, (4, 2, 8, 1, 1, 1)), (B.PW_F32, (4, 2, 8, 8, 1, 1)), (B.PW_F32, (4, 2, 8, 4, 2, 1)),
+           (B.PW_F32, (2, 2, 8, 4, 1, 1)), (B.PW_F32, (4, 2, 8, 4, 1, 3)), (B.PW_F32, (4, 2, 8, 4, 1, -1)),
+           (B.PW_BF16, (8, 4, 8, 4, 1, 1)), (B.PW_F64, (4, 2, 8, 4, 1, 1)), (B.PW_F64, (2, 1, 8, 4, 1, 1))]
+    for dt, t in ok:
+        assert _call(g, None, dt, c, p, B.pw_tile(*t)) in _no_gpu_status(), (dt, t)
+    for dt, t in bad:
+        assert _call(g, None, dt, c, p, B.pw_tile(*t)) == B.PW_ERR_INVALID_ARG, (dt, t)
+    q = [A + i * MB for i in range(9)]
+    st = B.pw_advect_adjoint_ex(g, None, B.PW_F32, *q[:3], c, *q[3:6], *q[6:9], B.pw_tile(1, 2, 8, 4, 1, 1))
+    assert st == B.PW_ERR_INVALID_ARG
+    st = B.pw_advect_tangent_ex(g, None, B.PW_F32, *q[:3], c, *q[3:6], *q[6:9], B.pw_tile(2, 2, 8, 4, 1, 1))
+    assert st == B.PW_ERR_INVALID_ARG
+
+
 def test_f64_tile_limits(lib):
     g, c, p = _args(dtype=B.PW_F64)
     for bad in [(4, 1, 8, 4), (1, 8, 8, 4), (2, 8, 8, 4)]:
@@ -258,7 +279,7 @@ def _table_row(kind, dt, nx, ny, nz):
         if m:
             row = tuple(int(x) for x in m.group(1).split(","))
             if row[:5] == key:
-                return row[5:]
+                return row[5:] + (0,) * (11 - len(row))   # rows without share_rows: 0
     return None
 
 
@@ -268,13 +289,15 @@ def test_launch_shape_query(lib):
     torch = pytest.importorskip("torch")
     row = _table_row(0, B.PW_F32, 512, 512, 64)
     assert row is not None
-    px, ry, nzc, wpb, depth = row
-    assert B.launch_shape("forward", 512, 512, 64, torch.float32) == (px, ry, -(-64 // nzc), wpb, depth)
+    px, ry, nzc, wpb, depth, share = row
+    assert B.launch_shape("forward", 512, 512, 64, torch.float32) == (px, ry, -(-64 // nzc), wpb, depth, share)
     row = _table_row(1, B.PW_F32, 256, 256, 128)
-    px, ry, nzc, wpb, depth = row
-    assert B.launch_shape("adjoint", 256, 256, 128, torch.float32) == (px, ry, -(-130 // nzc), wpb, 1)
+    px, ry, nzc, wpb, depth, share = row
+    assert share == 0
+    assert B.launch_shape("adjoint", 256, 256, 128, torch.float32) == (px, ry, -(-130 // nzc), wpb, depth, 0)
     shape = B.launch_shape("tangent", 100, 3, 5, torch.float64)   # no table entry: the default
     assert shape[0] == 1 and shape[1] in (1, 2) and 1 <= shape[2] <= 5 and 1 <= shape[3] <= 8 and shape[4] == 1
+    assert shape[5] == 0
     t = B.pw_tile()
     assert lib.pw_launch_shape(1, ctypes.byref(B.pw_grid(8, 8, 8, 1)), B.PW_BF16, ctypes.byref(t)) \
         == B.PW_ERR_UNSUPPORTED
@@ -286,9 +309,10 @@ def test_launch_shape_query(lib):
 
 
 def test_tune_cache_file_read_without_device(tmp_path):
-    """The cache file is read on first use, with no device: v2 lines carry the
-    prefetch depth, v1 lines mean depth 1, malformed lines are ignored, and a
-    file entry overrides the built-in table."""
+    """The cache file is read on first use, with no device: v3 lines carry
+    share_rows, v2 lines the prefetch depth (share_rows 0), v1 lines mean
+    depth 1, malformed lines are ignored, and a file entry overrides the
+    built-in table."""
     import os
     import subprocess
     import sys
@@ -297,21 +321,27 @@ def test_tune_cache_file_read_without_device(tmp_path):
     cache.write_text("pwadv-tune-v2 0 0 9 9 6 2 2 4 1 2\n"
                      "pwadv-tune-v1 1 0 7 7 4 1 4 2 1\n"
                      "garbage line\n"
-                     "pwadv-tune-v2 2 0 7 7 4 2 1 2 8 3\n")   # depth 3 is invalid: ignored
+                     "pwadv-tune-v2 2 0 7 7 4 2 1 2 8 3\n"    # depth 3 is invalid: ignored
+                     "pwadv-tune-v3 0 0 10 10 8 4 4 1 2 1 1\n"
+                     "pwadv-tune-v3 0 0 7 7 7 4 2 1 4 1 3\n")   # share_rows 3 is invalid: ignored
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
     code = ("import sys, torch; sys.path.insert(0, %r)\n"
             "from paper_2301_13016_amd import binding as B\n"
             "print(B.launch_shape('forward', 512, 512, 64, torch.float32))\n"
             "print(B.launch_shape('adjoint', 100, 100, 10, torch.float32))\n"
-            "print(B.launch_shape('tangent', 100, 100, 10, torch.float32))\n" % root)
+            "print(B.launch_shape('tangent', 100, 100, 10, torch.float32))\n"
+            "print(B.launch_shape('forward', 1024, 1024, 256, torch.float32))\n"
+            "print(B.launch_shape('forward', 128, 128, 128, torch.float32))\n" % root)
     r = subprocess.run([sys.executable, "-c", code], env=dict(os.environ, PWADV_TUNE_CACHE=str(cache)),
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 0, r.stderr[-2000:]
-    fwd, adj, tan = r.stdout.strip().splitlines()
-    assert fwd == str((2, 2, 16, 1, 2))
-    assert adj == str((1, 4, 6, 1, 1))       # 12 padded levels in 2 chunks
-    assert tan != str((2, 1, 5, 8, 3))       # the invalid line did not take effect
-    assert cache.read_text().count("\n") == 4   # reading never rewrites the file
+    fwd, adj, tan, big, mid = r.stdout.strip().splitlines()
+    assert fwd == str((2, 2, 16, 1, 2, 0))
+    assert adj == str((1, 4, 6, 1, 1, 0))       # 12 padded levels in 2 chunks
+    assert tan != str((2, 1, 5, 8, 3, 0))       # the invalid line did not take effect
+    assert big == str((4, 4, 256, 2, 1, 1))
+    assert mid != str((4, 2, 128, 4, 1, 3))
+    assert cache.read_text().count("\n") == 6   # reading never rewrites the file
 
 
 def test_stream_copy_validation(lib):
@@ -320,6 +350,22 @@ def test_stream_copy_validation(lib):
     assert B.pw_stream_copy(A + 4, A + MB, 16) == B.PW_ERR_INVALID_ARG
     assert B.pw_stream_copy(A, A + 8, 64) == B.PW_ERR_INVALID_ARG
     assert B.pw_stream_copy(A, A + MB, 64) in _no_gpu_status()
+
+
+def test_stream_probe_validation(lib):
+    ok = [(0, 1, 0), (0, 8, 3), (1, 4, 1), (2, 2, 2)]
+    for mode, loads, flags in ok:
+        assert B.pw_stream_probe(mode, loads, flags, A, A + MB, 4096, 64) in _no_gpu_status()
+    assert B.pw_stream_probe(2, 1, 0, None, A, 4096, 64) in _no_gpu_status()      # writes need no source
+    assert B.pw_stream_probe(3, 1, 0, A, A + MB, 4096, 64) == B.PW_ERR_INVALID_ARG
+    assert B.pw_stream_probe(0, 3, 0, A, A + MB, 4096, 64) == B.PW_ERR_INVALID_ARG
+    assert B.pw_stream_probe(0, 1, 4, A, A + MB, 4096, 64) == B.PW_ERR_INVALID_ARG
+    assert B.pw_stream_probe(0, 1, 0, A, A + MB, 4096, 0) == B.PW_ERR_INVALID_ARG
+    assert B.pw_stream_probe(0, 1, 0, A, A + MB, 4100, 64) == B.PW_ERR_INVALID_ARG
+    assert B.pw_stream_probe(0, 1, 0, A, A + 64, 4096, 64) == B.PW_ERR_INVALID_ARG     # overlap
+    assert B.pw_stream_probe(1, 1, 0, A, A + 8192, 1 << 20, 64) == B.PW_ERR_INVALID_ARG   # sink inside src
+    assert B.pw_stream_probe(0, 1, 0, A + 8, A + MB, 4096, 64) == B.PW_ERR_INVALID_ARG
+    assert B.pw_stream_probe(0, 1, 0, None, A + MB, 4096, 64) == B.PW_ERR_INVALID_ARG
 
 
 def test_epilogue_validation(lib):
@@ -549,8 +595,8 @@ def test_zfast_launch_shape(lib):
     torch = pytest.importorskip("torch")
     row = _table_row(3, B.PW_F32, 512, 512, 64)
     assert row is not None
-    pz, rj, nxc, wpb, depth = row
-    assert B.launch_shape("zfast", 512, 512, 64, torch.float32) == (pz, rj, -(-512 // nxc), wpb, depth)
+    pz, rj, nxc, wpb, depth, _ = row
+    assert B.launch_shape("zfast", 512, 512, 64, torch.float32) == (pz, rj, -(-512 // nxc), wpb, depth, 0)
     shape = B.launch_shape("zfast", 10, 3, 200, torch.bfloat16)
     assert shape[0] in (1, 2, 4) and 1 <= shape[2] <= 10
 

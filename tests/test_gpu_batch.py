@@ -177,7 +177,7 @@ print("OK")
     assert r.returncode == 0, r.stderr[-2000:]
     assert "OK" in r.stdout
     lines = cache.read_text().splitlines()
-    assert len(lines) == 3 and all(l.startswith("pwadv-tune-v2 ") for l in lines)
+    assert len(lines) == 3 and all(l.startswith("pwadv-tune-v3 ") for l in lines)
     assert sorted(int(l.split()[1]) for l in lines) == [0, 1, 2]
     shapes = [l for l in r.stdout.splitlines() if l.startswith("SHAPES")]
     r2 = subprocess.run([sys.executable, "-c", code, "read"], env=env, capture_output=True, text=True, timeout=300)

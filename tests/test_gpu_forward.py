@@ -264,6 +264,69 @@ def test_unread_cells_do_not_reach_any_output(shape, halo, storage):
         assert np.array_equal(x, y)
 
 
+SHARED_TILES = {
+    None: [(4, 1), (4, 2), (4, 4)],                          # FP32
+    "bfloat16": [(4, 2), (4, 4), (8, 2)],
+    "float16": [(4, 2), (8, 2)],
+    "float64": [(2, 2), (2, 4)],
+}
+
+
+@pytest.mark.parametrize("storage", [None, "bfloat16", "float16", "float64"])
+@pytest.mark.parametrize("shape,halo", [((130, 70, 20), 1), ((512, 9, 7), 1), ((300, 3, 5), 1), ((64, 1, 3), 1),
+                                        ((257, 37, 9), 2), ((1, 1, 1), 1), ((1030, 6, 4), 1)],
+                         ids=lambda x: "x".join(map(str, x)) if isinstance(x, tuple) else "h%d" % x)
+def test_shared_row_tiles_bitwise(shape, halo, storage):
+    """Workgroups whose wavefronts pass their edge rows through LDS give the
+    same outputs, bit for bit, as independent strips of the same shape: every
+    instantiated shape, 2 and 4 wavefronts per group, with and without
+    non-temporal own rows, one and several z-chunks, ragged y (wavefronts
+    past the grid) and x (edge strips), halo 1 and 2."""
+    nx, ny, nz = shape
+    g = wl.make_grid(nx, ny, nz, seed=41 + nx + ny, halo=halo,
+                     dtype=np.float64 if storage == "float64" else np.float32)
+    st = getattr(torch, storage) if storage in ("bfloat16", "float16") else None
+    for px, ry in SHARED_TILES[storage]:
+        ref = run(g, storage=st, tile=(px, ry, 3, 1, 1), halo=halo)
+        for wpb in (2, 4):
+            for share in (1, 2):
+                for zl in (nz, 2):
+                    got = run(g, storage=st, tile=(px, ry, zl, wpb, 1, share), halo=halo)
+                    for a, b in zip(ref, got):
+                        assert np.array_equal(a, b), (px, ry, zl, wpb, share)
+
+
+def test_shared_row_tiles_match_oracle(report):
+    """The shared-row FP32 shapes against the FP64 oracle at every point."""
+    g = wl.make_grid(300, 45, 13, seed=43)
+    worst = 0.0
+    for tile in [(4, 1, 13, 4, 1, 2), (4, 2, 7, 4, 1, 1), (4, 4, 13, 2, 1, 2)]:
+        errs = oracle_errors(run(g, tile=tile), g.u, g.v, g.w, g.coeffs)
+        worst = max(worst, max(e for e, _ in errs))
+    report["shared_rows_f32_300x45x13"] = dict(a_scaled_worst=worst)
+    assert worst <= 1e-6
+
+
+def test_shared_row_tiles_epilogue_and_bc():
+    """The fused epilogue runs in shared-row workgroups, bit-identical to
+    independent strips; boundary rules by addressing with a shared-row tile
+    run the same shape with independent strips (same result)."""
+    g = wl.make_grid(260, 19, 11, seed=44)
+    (u, v, w), c = dev_grid(g)
+    rng = np.random.default_rng(45)
+    add = [torch.from_numpy(rng.uniform(-1, 1, (11, 19, 260)).astype(np.float32)).to("cuda") for _ in range(3)]
+    ref = B.advect_epilogue(u, v, w, c, add, alpha=0.5, tile=(4, 2, 4, 1, 1))
+    for tile in [(4, 2, 11, 4, 1, 1), (4, 1, 5, 2, 1, 2), (4, 4, 11, 4, 1, 2)]:
+        got = B.advect_epilogue(u, v, w, c, add, alpha=0.5, tile=tile)
+        torch.cuda.synchronize()
+        assert all(torch.equal(a, b) for a, b in zip(ref, got)), tile
+    bc = ("periodic", "periodic", "copy")
+    rb = B.advect_bc(u, v, w, c, bc, tile=(4, 2, 11, 4, 1, 0))
+    gb = B.advect_bc(u, v, w, c, bc, tile=(4, 2, 11, 4, 1, 1))
+    torch.cuda.synchronize()
+    assert all(torch.equal(a, b) for a, b in zip(rb, gb))
+
+
 def test_host_pointer_rejected():
     """Host outputs: the binding refuses them (device mismatch), and the C
     entry point itself, called with host pointers, returns
@@ -276,6 +339,30 @@ def test_host_pointer_rejected():
     st = B.pw_advect(B.pw_grid(8, 8, 8, 1), None, B.PW_F32, u.data_ptr(), v.data_ptr(), w.data_ptr(),
                      c.c_struct(), *(o.data_ptr() for o in host_out))
     assert st == B.PW_ERR_INVALID_ARG
+
+
+def test_stream_probe_modes():
+    """The bandwidth probe copies bit for bit in every variant (sizes that
+    end mid-stride), its write mode stores its documented pattern, and its
+    read mode leaves the sink alone for ordinary data."""
+    n = 1_000_000 * 4                       # floats: 16 MB, not a multiple of any stride
+    src = torch.randn(n, device="cuda")
+    for loads in (1, 2, 4, 8):
+        for flags in range(4):
+            dst = torch.zeros_like(src)
+            B.stream_probe(0, loads, flags, src, dst, blocks=37)
+            torch.cuda.synchronize()
+            assert torch.equal(src, dst), (loads, flags)
+    w = torch.zeros(4096, dtype=torch.int32, device="cuda")
+    B.stream_probe(2, 4, 2, None, w, blocks=3)
+    idx = torch.arange(1024, device="cuda", dtype=torch.int32)
+    want = torch.stack([idx, torch.ones_like(idx), 2 * torch.ones_like(idx), 3 * torch.ones_like(idx)], 1).reshape(-1)
+    torch.cuda.synchronize()
+    assert torch.equal(w, want)
+    sink = torch.zeros(1024, dtype=torch.int32, device="cuda")
+    B.stream_probe(1, 8, 1, src, sink, blocks=64)
+    torch.cuda.synchronize()
+    assert int(sink.abs().sum()) == 0
 
 
 def test_stream_copies_are_exact():

@@ -127,7 +127,7 @@ pw_status pw_advect(const pw_grid *grid, const pw_layout *layout, pw_dtype in_dt
  * Batched form: as the forward with cols_per_lane <= 4 (FP32), prefetch 0, 1 or 2;
  *   or cols_per_lane 0: per subdomain 2 where that leaves no more lanes idle
  *   than 1 (nx rounded up to 128 equals nx rounded up to 64), else 1, with
- *   rows_per_strip in {1, 2, 4}.
+ *   rows_per_strip in {1, 2, 4}; share_rows 0.
  * Tangent: prefetch 0, 1 or 2.
  * Tangent (pw_advect_tangent_ex): cols_per_lane 1 or 2 (PW_F64: 1),
  *   rows_per_strip in {1, 2}.

@@ -119,6 +119,7 @@ template <int Depth, int MaxT> const void *batch_kernel_t(const TileCfg &c) {
 
 // The instantiation a tile runs (nullptr: none).
 const void *batch_kernel(const TileCfg &c) {
+    if (c.share != 0) return nullptr;   // independent wavefronts only
     if (c.depth == 2) return c.wpb <= 4 ? batch_kernel_t<2, 256>(c) : batch_kernel_t<2, 512>(c);
     if (c.depth == 1) return c.wpb <= 4 ? batch_kernel_t<1, 256>(c) : batch_kernel_t<1, 512>(c);
     return nullptr;
@@ -256,7 +257,7 @@ pw_status enqueue(pw_batch *b, hipStream_t s) {
 }
 
 bool batch_tile_ok(const TileCfg &c) {
-    if (c.share != 0) return false;
+    if (c.zlen < 1 || c.share != 0) return false;
     if (c.px == 0) {
         TileCfg c1 = c, c2 = c;
         c1.px = 1;
@@ -280,10 +281,11 @@ pw_status pw_batch_create(const pw_batch_item *items, int32_t n, pw_dtype dtype,
     TileCfg cfg = default_batch_tile();
     if (tile) {
         cfg = TileCfg{tile->cols_per_lane, tile->rows_per_strip, tile->zlen, tile->waves_per_group,
-                      tile->prefetch == 0 ? 1 : tile->prefetch};
+                      tile->prefetch == 0 ? 1 : tile->prefetch, tile->share_rows};
         if (!batch_tile_ok(cfg))
-            return fail(PW_ERR_INVALID_ARG, "unsupported batch tile cols=%d rows=%d zlen=%d waves=%d prefetch=%d",
-                        cfg.px, cfg.ry, cfg.zlen, cfg.wpb, tile->prefetch);
+            return fail(PW_ERR_INVALID_ARG,
+                        "unsupported batch tile cols=%d rows=%d zlen=%d waves=%d prefetch=%d share_rows=%d", cfg.px,
+                        cfg.ry, cfg.zlen, cfg.wpb, tile->prefetch, tile->share_rows);
     }
     std::vector<FwdArgs> subs(static_cast<size_t>(n));
     for (int32_t i = 0; i < n; ++i) {
@@ -416,41 +418,56 @@ pw_status pw_batch_tune(pw_batch *b, void *hip_stream, pw_tile *chosen) {
         (void)hipEventDestroy(e0);
         return hip_fail(hipGetLastError(), "hipEventCreate");
     }
+    // mean ms of `reps` runs of the batch under tile c, after one warm-up run
+    auto time_tile = [&](const TileCfg &c, int reps, float *ms) -> pw_status {
+        pw_status st = build_table(b, c);
+        if (st == PW_OK) st = enqueue(b, s);
+        if (st != PW_OK) return st;
+        if (hipEventRecord(e0, s) != hipSuccess) return hip_fail(hipGetLastError(), "hipEventRecord");
+        for (int r = 0; r < reps && st == PW_OK; ++r) st = enqueue(b, s);
+        if (st != PW_OK) return st;
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(ms, e0, e1) != hipSuccess)
+            return hip_fail(hipGetLastError(), "timing");
+        *ms /= reps;
+        return PW_OK;
+    };
     const TileCfg start = b->tile;
     TileCfg best = start;
-    float best_ms = -1.f;
+    std::vector<std::pair<float, TileCfg>> t;
     pw_status st = PW_OK;
     for (int px : {0, 1, 2, 4})
         for (int ry : {1, 2, 4})
             for (int zl : {32, 64, 128, 256})
                 for (int wpb : {1, 4})
-                  for (int depth : {1, 2}) {
-                    TileCfg c;
-                    c.px = px;
-                    c.ry = ry;
-                    c.zlen = zl;
-                    c.wpb = wpb;
-                    c.depth = depth;
-                    if (!batch_tile_ok(c)) continue;
-                    if ((st = build_table(b, c)) != PW_OK) break;
-                    if ((st = enqueue(b, s)) != PW_OK) break;   // warm-up
-                    float ms = -1.f;
-                    if (hipEventRecord(e0, s) != hipSuccess) {
-                        st = hip_fail(hipGetLastError(), "hipEventRecord");
-                        break;
-                    }
-                    for (int r = 0; r < 3 && st == PW_OK; ++r) st = enqueue(b, s);
-                    if (st != PW_OK) break;
-                    if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-                        hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
-                        st = hip_fail(hipGetLastError(), "timing");
-                        break;
-                    }
-                    if (best_ms < 0.f || ms < best_ms) {
-                        best_ms = ms;
-                        best = c;
-                    }
-                }
+                    for (int depth : {1, 2}) {
+                            if (st != PW_OK) break;
+                            TileCfg c;
+                            c.px = px;
+                            c.ry = ry;
+                            c.zlen = zl;
+                            c.wpb = wpb;
+                            c.depth = depth;
+                            if (!batch_tile_ok(c)) continue;
+                            float ms = -1.f;
+                            st = time_tile(c, 3, &ms);
+                            if (st == PW_OK && ms > 0.f) t.emplace_back(ms, c);
+                        }
+    // the three fastest again over more runs (less sensitive to noise)
+    if (st == PW_OK && !t.empty()) {
+        std::sort(t.begin(), t.end(), [](const std::pair<float, TileCfg> &x, const std::pair<float, TileCfg> &y) {
+            return x.first < y.first;
+        });
+        float best_ms = -1.f;
+        for (size_t r = 0; r < t.size() && r < 3 && st == PW_OK; ++r) {
+            float ms = -1.f;
+            st = time_tile(t[r].second, 10, &ms);
+            if (st == PW_OK && ms > 0.f && (best_ms < 0.f || ms < best_ms)) {
+                best_ms = ms;
+                best = t[r].second;
+            }
+        }
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     const pw_status st2 = build_table(b, st == PW_OK ? best : start);

@@ -491,6 +491,9 @@ def test_batch_argument_errors(lib):
     assert lib.pw_batch_create(_items(2), 2, B.PW_F32, None, None) == B.PW_ERR_INVALID_ARG
     assert B.pw_batch_create(_items(2), 2, B.PW_BF16, None, h) == B.PW_ERR_UNSUPPORTED
     assert B.pw_batch_create(_items(2), 2, B.PW_F32, B.pw_tile(4, 4, 8, 4), h) == B.PW_ERR_INVALID_ARG
+    # the batch runs independent wavefronts only (share_rows 0)
+    for bad in [(4, 2, 8, 4, 1, 1), (0, 2, 8, 4, 1, 2)]:
+        assert B.pw_batch_create(_items(2), 2, B.PW_F32, B.pw_tile(*bad), h) == B.PW_ERR_INVALID_ARG, bad
     # columns per lane 0 (chosen per subdomain): rows per strip as for 1 and 2 columns
     assert B.pw_batch_create(_items(2), 2, B.PW_F32, B.pw_tile(0, 8, 8, 4), h) == B.PW_ERR_INVALID_ARG
     assert B.pw_batch_create(_items(2), 2, B.PW_F32, B.pw_tile(0, 4, 8, 4, 3), h) == B.PW_ERR_INVALID_ARG

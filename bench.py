@@ -246,12 +246,13 @@ def prebuilt_zfast(B, ins, outs, coeffs, stream, accumulate=False):
 
 def prebuilt_bc(B, ins, outs, coeffs, bc, stream):
     """ctypes arguments of one pw_advect_bc call (boundary rules by
-    addressing, no epilogue), built once."""
+    addressing, one (x, y, z) triple per field, no epilogue), built once."""
     from paper_2301_13016_amd.binding import _dtype_code, _grid_from, _layout_from
     u, v, w = ins
-    keep = (_grid_from(u, 1), _layout_from(u, outs[0]), coeffs.c_struct(), B.pw_halo_modes(*bc))
+    rules = (B.pw_halo_modes * 3)(*(B.pw_halo_modes(*m) for m in bc))
+    keep = (_grid_from(u, 1), _layout_from(u, outs[0]), coeffs.c_struct(), rules)
     args = (ctypes.byref(keep[0]), ctypes.byref(keep[1]), _dtype_code(u), u.data_ptr(), v.data_ptr(), w.data_ptr(),
-            ctypes.byref(keep[2]), ctypes.byref(keep[3]), None, *(o.data_ptr() for o in outs), None,
+            ctypes.byref(keep[2]), keep[3], None, *(o.data_ptr() for o in outs), None,
             ctypes.c_void_p(stream.cuda_stream))
     fn = B.lib().pw_advect_bc
 
@@ -482,19 +483,22 @@ def main():
     forms["halo_fill_512x512x64"] = dict(kernel_ms=round(halo_ms, 4), over_plain=round(halo_ms / k_ms, 3),
                                          bytes=hb, hbm_gbs=round(hb / (halo_ms * 1e-3) / 1e9, 1))
     log("c1 halo fill (u, v, w): %.4f ms, %.3f x the plain step" % (halo_ms, halo_ms / k_ms))
-    # the same boundaries applied by addressing inside the forward (periodic
-    # x, y; zero-gradient z for all three fields): no fill step
-    bmodes = (1, 1, 2)
-    fill_calls = [prebuilt_halo(B, kp[0], [bmodes] * 3, stream) for kp in keep]
-    _, fill_ms = time_launches(torch, lambda i: fill_calls[i](), nsets, 200, 20, stream)
-    bc_calls = [prebuilt_bc(B, kp[0], kp[1], coeffs, bmodes, stream) for kp in keep]
-    _, bc_ms = time_launches(torch, lambda i: bc_calls[i](), nsets, 500, 100, stream)
-    del fill_calls, bc_calls
-    forms["boundaries_by_addressing_512x512x64"] = dict(
-        kernel_ms=round(bc_ms, 4), over_plain=round(bc_ms / k_ms, 3), fill_ms=round(fill_ms, 4),
-        fill_then_forward_ms=round(fill_ms + k_ms, 4), saved=round(1 - bc_ms / (fill_ms + k_ms), 3))
-    log("c1 forward with periodic / zero-gradient boundaries by addressing: %.4f ms (fill + forward %.4f ms)"
-        % (bc_ms, fill_ms + k_ms))
+    # boundaries applied by addressing inside the forward, no fill step:
+    # remapped reads only (periodic x, y; zero-gradient z for all three
+    # fields), and the free-slip lid above, whose w = 0 is a value rule
+    addressed = {}
+    for name, rules in (("periodic_copy", [(1, 1, 2)] * 3), ("free_slip_lid", hmodes)):
+        fill_calls = [prebuilt_halo(B, kp[0], rules, stream) for kp in keep]
+        _, fill_ms = time_launches(torch, lambda i: fill_calls[i](), nsets, 200, 20, stream)
+        bc_calls = [prebuilt_bc(B, kp[0], kp[1], coeffs, rules, stream) for kp in keep]
+        _, bc_ms = time_launches(torch, lambda i: bc_calls[i](), nsets, 500, 100, stream)
+        del fill_calls, bc_calls
+        addressed[name] = dict(rules=rules, kernel_ms=round(bc_ms, 4), over_plain=round(bc_ms / k_ms, 3),
+                               fill_ms=round(fill_ms, 4), fill_then_forward_ms=round(fill_ms + k_ms, 4),
+                               saved=round(1 - bc_ms / (fill_ms + k_ms), 3))
+        log("c1 forward with %s boundaries by addressing: %.4f ms (fill + forward %.4f ms)"
+            % (name.replace("_", " "), bc_ms, fill_ms + k_ms))
+    forms["boundaries_by_addressing_512x512x64"] = addressed
     # the same grid stored z-fastest (column-major, [i, j, k])
     zsets = [(tuple(x.permute(2, 1, 0).contiguous() for x in kp[0]),
               tuple(torch.empty((nx, ny, nz), device=dev) for _ in range(3))) for kp in keep]

@@ -461,17 +461,26 @@ pw_status pw_halo_fold(const pw_grid *grid, const pw_layout *layout, pw_dtype dt
 /* ------------------------------------------------ boundaries by addressing
  * The forward operator, optionally with the fused epilogue, with the halo's
  * boundary rules applied by addressing instead of a halo fill: the result is
- * bit for bit that of pw_halo_fill(u, v, w with rules *bc) followed by
- * pw_advect_ex / pw_advect_epilogue, but the halo is neither written nor (on
- * axes whose rule is not KEEP) read -- a read of a halo cell goes to its
- * periodic or nearest-interior source.  Rules per axis: PW_HALO_KEEP (read
- * the stored halo), PW_HALO_PERIODIC, PW_HALO_COPY; the others change values
- * (zero, negation) rather than addresses and return PW_ERR_UNSUPPORTED --
- * fill the halo for those.  A periodic x-y domain on one GPU then needs no
- * fill step at all.  ep == NULL: out = F; otherwise as pw_advect_epilogue.
- * Same layouts, dtypes, tiles, ownership and errors as pw_advect_ex. */
+ * bit for bit that of pw_halo_fill(u, v, w with rules bc[0], bc[1], bc[2])
+ * followed by pw_advect_ex / pw_advect_epilogue, but the halo is neither
+ * written nor (on axes whose rule is not KEEP) read.  bc[f] holds the x, y, z
+ * rules of field f (u, v, w), any of the six pw_halo_mode rules.  The
+ * stencil reads one layer of halo (Sec. 2.2), and for those cells the
+ * mirror image of REFLECT / REFLECT_NEG is the nearest interior cell; so a
+ * read of a halo cell goes to its periodic or nearest-interior source, and
+ * ZERO and REFLECT_NEG then replace the value by +0 or flip its sign, per
+ * field, in the fill's axis order (corner cells included).  A periodic
+ * x-y domain with a free-slip lid (u, v: z = COPY, w: z = ZERO) or a
+ * no-slip wall (REFLECT_NEG) then needs no fill step at all.  The read
+ * remapping is shared by the three fields: on each axis they must all be
+ * KEEP, all PERIODIC, or all nearest-cell rules (COPY, ZERO, REFLECT,
+ * REFLECT_NEG), else PW_ERR_UNSUPPORTED.  REFLECT / REFLECT_NEG on an axis
+ * with fewer interior cells than the halo width, or an unknown rule:
+ * PW_ERR_INVALID_ARG (as pw_halo_fill).  ep == NULL: out = F; otherwise as
+ * pw_advect_epilogue.  Same layouts, dtypes, tiles, ownership and errors as
+ * pw_advect_ex. */
 pw_status pw_advect_bc(const pw_grid *grid, const pw_layout *layout, pw_dtype in_dtype, const void *u,
-                       const void *v, const void *w, const pw_coeffs *coeffs, const pw_halo_modes *bc,
+                       const void *v, const void *w, const pw_coeffs *coeffs, const pw_halo_modes bc[3],
                        const pw_epilogue *ep, void *su, void *sv, void *sw, const pw_tile *tile, void *hip_stream);
 
 /* Library version string (static storage). */

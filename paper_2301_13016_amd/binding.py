@@ -430,9 +430,12 @@ def advect_zfast(u, v, w, coeffs: Coeffs, halo=1, out=None, tile=None, stream=No
 
 def advect_bc(u, v, w, coeffs: Coeffs, bc, halo=1, out=None, addends=None, alpha=1.0, tile=None, stream=None):
     """The forward (with ``addends``: out = addends + alpha * F) with boundary
-    rules applied by addressing: ``bc`` is an (x, y, z) triple of "keep",
-    "periodic" or "copy" (names or codes).  Equals halo_fill with the same
-    rules followed by advect / advect_epilogue, without touching the halo."""
+    rules applied by addressing: ``bc`` is one (x, y, z) triple of rules for
+    all three fields or a list of three triples (u, v, w), each entry a name
+    from HALO_MODES or its code.  Equals halo_fill with the same rules
+    followed by advect / advect_epilogue, without touching the halo.  On each
+    axis the three fields must all keep, all be periodic or all use
+    nearest-cell rules (copy, zero, reflect, reflect_neg)."""
     import torch
     _check_inputs(u, v, w)
     grid = _grid_from(u, halo)
@@ -443,7 +446,7 @@ def advect_bc(u, v, w, coeffs: Coeffs, bc, halo=1, out=None, addends=None, alpha
     su, sv, sw = out
     _check_group(out, "outputs", (grid.nz, grid.ny, grid.nx), odt, u.device)
     layout = _layout_from(u, su)
-    modes = pw_halo_modes(*(_halo_code(m) for m in bc))
+    modes = (pw_halo_modes * 3)(*(pw_halo_modes(*(_halo_code(m) for m in t)) for t in _per_field_modes(bc, 3)))
     ep = None
     if addends is not None:
         _check_group(list(addends) + list(out), "addends and outputs", (grid.nz, grid.ny, grid.nx), odt, u.device)
@@ -705,6 +708,17 @@ def _halo_code(m):
     return int(m)
 
 
+def _per_field_modes(modes, n):
+    """One (x, y, z) rule triple for each of n fields: ``modes`` is one triple
+    for all of them or a list of n triples."""
+    modes = list(modes)
+    if len(modes) == 3 and all(isinstance(m, (str, int)) for m in modes):
+        return [tuple(modes)] * n
+    if len(modes) != n or any(len(m) != 3 for m in modes):
+        raise ValueError("one (x, y, z) mode triple for all fields or one per field")
+    return [tuple(m) for m in modes]
+
+
 def _halo_call(fn, name, fields, modes, halo, stream):
     fields = list(fields)
     if not fields:
@@ -715,11 +729,7 @@ def _halo_call(fn, name, fields, modes, halo, stream):
         raise ValueError("fields must share shape, strides, dtype and device")
     if u.dim() != 3:
         raise ValueError("fields must be 3-D padded arrays")
-    if len(modes) == 3 and all(isinstance(m, (str, int)) for m in modes):
-        modes = [modes] * len(fields)
-    if len(modes) != len(fields):
-        raise ValueError("one (x, y, z) mode triple per field")
-    codes = [tuple(_halo_code(m) for m in mm) for mm in modes]
+    codes = [tuple(_halo_code(m) for m in mm) for mm in _per_field_modes(modes, len(fields))]
     grid = _grid_from(u, halo)
     if u.stride(-1) != 1:
         raise ValueError("x (last) dimension must be contiguous")

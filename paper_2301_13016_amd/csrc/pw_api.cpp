@@ -291,15 +291,38 @@ pw_status advect_general(const pw_grid *grid, const pw_layout *layout, pw_dtype 
                     tile->cols_per_lane, tile->rows_per_strip, tile->zlen, tile->waves_per_group, tile->prefetch,
                     tile->share_rows);
     if (bc) {
-        const int32_t m[3] = {bc->x, bc->y, bc->z};
-        for (int d = 0; d < 3; ++d)
-            if (m[d] != PW_HALO_KEEP && m[d] != PW_HALO_PERIODIC && m[d] != PW_HALO_COPY)
-                return fail(m[d] >= 0 && m[d] <= PW_HALO_REFLECT_NEG ? PW_ERR_UNSUPPORTED : PW_ERR_INVALID_ARG,
-                            "boundary rule %d on axis %c: only keep, periodic and copy are applied by addressing",
-                            m[d], "xyz"[d]);
-        a.bcx = m[0];
-        a.bcy = m[1];
-        a.bcz = m[2];
+        // bc[f] = rules of field f (u, v, w).  A depth-one read of a halo cell
+        // goes to its periodic source or to the nearest interior cell (which
+        // is also the mirror image of the cells next to the face); ZERO and
+        // REFLECT_NEG then change the value.  The remapping is shared by the
+        // three fields, so per axis they must agree on it.
+        const int64_t n[3] = {grid->nx, grid->ny, grid->nz};
+        int32_t addr[3] = {-1, -1, -1};
+        uint32_t bcv = 0;
+        for (int f = 0; f < 3; ++f) {
+            const int32_t m[3] = {bc[f].x, bc[f].y, bc[f].z};
+            for (int d = 0; d < 3; ++d) {
+                if (m[d] < PW_HALO_KEEP || m[d] > PW_HALO_REFLECT_NEG)
+                    return fail(PW_ERR_INVALID_ARG, "unknown boundary rule %d (field %c, axis %c)", m[d], "uvw"[f],
+                                "xyz"[d]);
+                if ((m[d] == PW_HALO_REFLECT || m[d] == PW_HALO_REFLECT_NEG) && n[d] < grid->halo)
+                    return fail(PW_ERR_INVALID_ARG, "reflect on axis %c needs at least %d interior cells",
+                                "xyz"[d], grid->halo);
+                const int32_t cls = m[d] == PW_HALO_KEEP ? PW_HALO_KEEP
+                                    : m[d] == PW_HALO_PERIODIC ? PW_HALO_PERIODIC : PW_HALO_COPY;
+                if (addr[d] >= 0 && addr[d] != cls)
+                    return fail(PW_ERR_UNSUPPORTED,
+                                "axis %c: u, v and w must all keep, all be periodic, or all use nearest-cell rules "
+                                "(copy, zero, reflect, reflect_neg)", "xyz"[d]);
+                addr[d] = cls;
+                const uint32_t code = m[d] == PW_HALO_REFLECT_NEG ? 1u : (m[d] == PW_HALO_ZERO ? 2u : 0u);
+                bcv |= code << (8 * d + 2 * f);
+            }
+        }
+        a.bcx = addr[0];
+        a.bcy = addr[1];
+        a.bcz = addr[2];
+        a.bcv = bcv;
     }
     int dev = 0;
     if (ep) {
@@ -388,7 +411,7 @@ pw_status pw_advect_epilogue(const pw_grid *grid, const pw_layout *layout, pw_dt
 }
 
 pw_status pw_advect_bc(const pw_grid *grid, const pw_layout *layout, pw_dtype in_dtype, const void *u,
-                       const void *v, const void *w, const pw_coeffs *coeffs, const pw_halo_modes *bc,
+                       const void *v, const void *w, const pw_coeffs *coeffs, const pw_halo_modes bc[3],
                        const pw_epilogue *ep, void *su, void *sv, void *sw, const pw_tile *tile, void *hip_stream) {
     g_err[0] = 0;
     if (!bc) return fail(PW_ERR_INVALID_ARG, "bc is NULL");

@@ -165,14 +165,15 @@ TileCfg default_forward_tile(const FwdArgs &a, pw_dtype dt) {
 
 pw_status launch_forward(const FwdArgs &a, pw_dtype dt, const TileCfg &cfg, hipStream_t s) {
     if (!tile_supported(cfg, dt)) return fail(PW_ERR_INVALID_ARG, "unsupported tile configuration");
+    const bool bc = a.bcx != PW_HALO_KEEP || a.bcy != PW_HALO_KEEP || a.bcz != PW_HALO_KEEP || a.bcv != 0;
+    if (bc && cfg.share == 0 && cfg.wpb > 4) {
+        // boundary rules are built for up to four wavefronts per workgroup;
+        // the strips are independent, so regrouping them changes no result
+        TileCfg c = cfg;
+        c.wpb = 4;
+        return launch_forward(a, dt, c, s);
+    }
     if (cfg.share != 0) {
-        if (a.bcx != PW_HALO_KEEP || a.bcy != PW_HALO_KEEP || a.bcz != PW_HALO_KEEP) {
-            // boundary rules by addressing are built for independent strips:
-            // the same shape without sharing (results are the same bit for bit)
-            TileCfg c = cfg;
-            c.share = 0;
-            return launch_forward(a, dt, c, s);
-        }
         switch (dt) {
             case PW_F32: return launch_forward_lds_f32(a, cfg, s);
             case PW_F64: return launch_forward_lds_f64(a, cfg, s);

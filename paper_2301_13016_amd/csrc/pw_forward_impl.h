@@ -45,13 +45,14 @@ using namespace dev;
 // Depth: planes in flight ahead of the level being computed (1 or 2).
 // Epi: fused epilogue, out = c + alpha * F (accumulation into the outputs
 // when c is the output itself, or a time update c + dt * F).
-// Bc: boundary rules applied by addressing (pw_advect_bc); the plain
-// instantiations carry no mapping code.
+// Bc: boundary rules applied by addressing (pw_advect_bc): 1 remaps reads
+// (periodic, nearest interior), 2 also applies the value rules (zero,
+// negation); the plain instantiations (0) carry no mapping code.
 // MaxT: the workgroup size bound the kernel is compiled for.  Every shape is
 // built twice: for up to 256 threads (four wavefronts, one per SIMD, so a
 // wavefront may use the whole 512-entry register file: the large strips keep
 // their planes in registers instead of spilling) and for up to 512.
-template <typename Tin, int PX, int RY, int Depth, bool Epi, bool Bc, int MaxT>
+template <typename Tin, int PX, int RY, int Depth, bool Epi, int Bc, int MaxT>
 __global__ __launch_bounds__(MaxT) void pw_forward_kernel(FwdK<Tin> a) {
     // wavefront index as a scalar, so that per-strip conditions stay scalar
     const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
@@ -68,7 +69,7 @@ __global__ __launch_bounds__(MaxT) void pw_forward_kernel(FwdK<Tin> a) {
 // strip_march_lds): the workgroup covers W consecutive strips in y.  Every
 // wavefront runs, also one whose strip lies past the grid, so that all reach
 // the same barriers.
-template <typename Tin, int PX, int RY, int Depth, bool Epi, bool Bc, int W, bool NtOwn = false>
+template <typename Tin, int PX, int RY, int Depth, bool Epi, int Bc, int W, bool NtOwn = false>
 __global__ __launch_bounds__(64 * W) void pw_forward_lds_kernel(FwdK<Tin> a) {
     __shared__ EdgeLds<Tin, PX, W> L;
     const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
@@ -80,9 +81,14 @@ __global__ __launch_bounds__(64 * W) void pw_forward_lds_kernel(FwdK<Tin> a) {
     strip_march_lds<Tin, PX, RY, Depth, Epi, Bc, W, NtOwn>(a, L, tx, ty, cz, wave);
 }
 
-template <typename Tin, int PX, int RY, bool Epi, bool Bc>
+template <typename Tin, int PX, int RY, bool Epi, int Bc>
 void launch_fwd_b(const FwdK<Tin> &a, const TileCfg &cfg, dim3 grid, dim3 block, hipStream_t s) {
-    if (cfg.depth == 2) {
+    if constexpr (Bc != 0) {   // boundary rules: built for up to four wavefronts per workgroup only
+        if (cfg.depth == 2)
+            hipLaunchKernelGGL((pw_forward_kernel<Tin, PX, RY, 2, Epi, Bc, 256>), grid, block, 0, s, a);
+        else
+            hipLaunchKernelGGL((pw_forward_kernel<Tin, PX, RY, 1, Epi, Bc, 256>), grid, block, 0, s, a);
+    } else if (cfg.depth == 2) {
         if (cfg.wpb <= 4)
             hipLaunchKernelGGL((pw_forward_kernel<Tin, PX, RY, 2, Epi, Bc, 256>), grid, block, 0, s, a);
         else
@@ -97,10 +103,12 @@ void launch_fwd_b(const FwdK<Tin> &a, const TileCfg &cfg, dim3 grid, dim3 block,
 
 template <typename Tin, int PX, int RY, bool Epi>
 void launch_fwd_k(const FwdK<Tin> &a, const TileCfg &cfg, dim3 grid, dim3 block, hipStream_t s) {
-    if (a.bcx != PW_HALO_KEEP || a.bcy != PW_HALO_KEEP || a.bcz != PW_HALO_KEEP)
-        launch_fwd_b<Tin, PX, RY, Epi, true>(a, cfg, grid, block, s);
+    if (a.bcv != 0)
+        launch_fwd_b<Tin, PX, RY, Epi, 2>(a, cfg, grid, block, s);
+    else if (a.bcx != PW_HALO_KEEP || a.bcy != PW_HALO_KEEP || a.bcz != PW_HALO_KEEP)
+        launch_fwd_b<Tin, PX, RY, Epi, 1>(a, cfg, grid, block, s);
     else
-        launch_fwd_b<Tin, PX, RY, Epi, false>(a, cfg, grid, block, s);
+        launch_fwd_b<Tin, PX, RY, Epi, 0>(a, cfg, grid, block, s);
 }
 
 template <typename Tin, int PX, int RY>
@@ -139,6 +147,7 @@ FwdK<Tin> make_fwdk(const FwdArgs &g, const TileCfg &cfg) {
     a.bcx = g.bcx;
     a.bcy = g.bcy;
     a.bcz = g.bcz;
+    a.bcv = g.bcv;
     return a;
 }
 
@@ -187,8 +196,15 @@ pw_status launch_fwd_dt(const FwdArgs &g, const TileCfg &cfg, hipStream_t s) {
 }
 
 // Shared-row tiles (cfg.share 1 or 2; see strip_march_lds).  Launched with
-// exactly cfg.wpb wavefronts per workgroup; boundary rules are not built in
-// (launch_forward runs those calls with independent strips).
+// exactly W wavefronts per workgroup.
+template <typename Tin, int PX, int RY, int W, bool NtOwn, int Bc>
+void launch_lds_b(const FwdK<Tin> &a, bool epi, dim3 grid, dim3 block, hipStream_t s) {
+    if (epi)
+        hipLaunchKernelGGL((pw_forward_lds_kernel<Tin, PX, RY, 1, true, Bc, W, NtOwn>), grid, block, 0, s, a);
+    else
+        hipLaunchKernelGGL((pw_forward_lds_kernel<Tin, PX, RY, 1, false, Bc, W, NtOwn>), grid, block, 0, s, a);
+}
+
 template <typename Tin, int PX, int RY, int W, bool NtOwn>
 pw_status launch_lds_w(const FwdArgs &g, const TileCfg &cfg, hipStream_t s) {
     const FwdK<Tin> a = make_fwdk<Tin, PX, RY>(g, cfg);
@@ -196,15 +212,25 @@ pw_status launch_lds_w(const FwdArgs &g, const TileCfg &cfg, hipStream_t s) {
     const int64_t nblocks = static_cast<int64_t>(a.ntx) * nblk_y * a.nzc;
     if (nblocks <= 0 || nblocks > 0x7fffffffLL) return fail(PW_ERR_UNSUPPORTED, "grid too large");
     const dim3 grid(static_cast<unsigned>(nblocks)), block(64 * W);
-    if (g.epilogue)
-        hipLaunchKernelGGL((pw_forward_lds_kernel<Tin, PX, RY, 1, true, false, W, NtOwn>), grid, block, 0, s, a);
-    else
-        hipLaunchKernelGGL((pw_forward_lds_kernel<Tin, PX, RY, 1, false, false, W, NtOwn>), grid, block, 0, s, a);
+    if constexpr (W == 4 && NtOwn) {   // the only instantiation that carries boundary rules
+        if (a.bcv != 0)
+            launch_lds_b<Tin, PX, RY, W, true, 2>(a, g.epilogue, grid, block, s);
+        else if (a.bcx != PW_HALO_KEEP || a.bcy != PW_HALO_KEEP || a.bcz != PW_HALO_KEEP)
+            launch_lds_b<Tin, PX, RY, W, true, 1>(a, g.epilogue, grid, block, s);
+        else
+            launch_lds_b<Tin, PX, RY, W, true, 0>(a, g.epilogue, grid, block, s);
+    } else {
+        launch_lds_b<Tin, PX, RY, W, NtOwn, 0>(a, g.epilogue, grid, block, s);
+    }
     return hip_fail(hipGetLastError(), "forward kernel launch");
 }
 
 template <typename Tin, int PX, int RY>
 pw_status launch_lds_t(const FwdArgs &g, const TileCfg &cfg, hipStream_t s) {
+    // boundary rules by addressing: four wavefronts, non-temporal own rows
+    // (the grouping of strips and the cache hint change no result)
+    if (g.bcx != PW_HALO_KEEP || g.bcy != PW_HALO_KEEP || g.bcz != PW_HALO_KEEP || g.bcv != 0)
+        return launch_lds_w<Tin, PX, RY, 4, true>(g, cfg, s);
     const bool nt = cfg.share == 2;
     if (cfg.wpb == 2) return nt ? launch_lds_w<Tin, PX, RY, 2, true>(g, cfg, s) : launch_lds_w<Tin, PX, RY, 2, false>(g, cfg, s);
     if (cfg.wpb == 4) return nt ? launch_lds_w<Tin, PX, RY, 4, true>(g, cfg, s) : launch_lds_w<Tin, PX, RY, 4, false>(g, cfg, s);

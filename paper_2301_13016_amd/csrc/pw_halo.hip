@@ -6,14 +6,20 @@
 // and its source lies in the interior of every such axis, so no cell is both
 // read and written: one kernel fills all three axes with no ordering between
 // its writes, and the result equals the sequential x, y, z fill.  The work of
-// one field is three segments: the z-halo planes (whole planes), the y-halo
+// one field is three segments: the z-halo planes (whole rows), the y-halo
 // rows of the remaining planes (whole rows) and the x-halo cells of the
-// remaining rows.  The first two are whole rows: one wavefront takes a row,
-// finds its source row once, and its lanes move consecutive cells (coalesced
-// loads and stores, per-cell work only on the x axis).  The x-halo cells are
-// scattered, one per thread.  Values move as raw bits (2, 4 or 8 bytes); a
-// negated mirror flips the sign bit, which is exact negation.
+// remaining rows.  A wavefront takes one piece of a whole row: its plane and
+// row, their sources and value rules are found once per wavefront in scalar
+// registers, and the lanes move consecutive cells, all loads before the
+// stores, so that every wavefront makes one round trip to memory.  The
+// x-halo cells go 64 to a wavefront in memory order (the right halo of a row
+// and the left halo of the next are neighbouring lanes); in a dense array
+// each row boundary still costs a cache line of its own, which only applying
+// the rules by addressing (pw_advect_bc) avoids.
+// Values move as raw bits (2, 4 or 8 bytes); a negated mirror flips the sign
+// bit, which is exact negation.
 #include <algorithm>
+#include <climits>
 
 #include "pw_internal.h"
 
@@ -21,111 +27,131 @@ namespace pw {
 namespace {
 
 struct HaloSeg {
-    int64_t nzs, nys, nxs;  // rows of the z and y segments, cells of the x segment
-    int64_t k0, kn;         // planes covered by the y and x segments
-    int64_t j0, jn;         // rows covered by the x segment
+    int32_t zrows, yrows;   // whole rows of the z and y segments
+    int32_t xwaves;         // wavefronts of the x segment (64 cells each)
+    int32_t xcells;         // cells of the x segment
+    int32_t k0;             // first plane of the y and x segments
+    int32_t j0, jn;         // rows covered by the x segment
     int32_t mode[3];        // x, y, z
 };
 
 struct HaloK {
     void *f[kMaxHaloFields];
     HaloSeg seg[kMaxHaloFields];
-    int64_t nx, ny, nz, sy, sz;
-    int32_t h;
+    int64_t sy, sz;
+    int32_t nx, ny, nz, h;
 };
 
-// Source coordinate of padded coordinate p on an axis of n interior cells;
-// `sign` becomes 0 for a zeroed cell and flips for a negated mirror.
-__device__ inline int64_t source(int64_t p, int64_t n, int64_t h, int mode, int &sign) {
+// Value code of a cell, built up axis by axis in the fill's order x, y, z:
+// bit 1 = the value is zero, bit 0 = the sign is flipped.  A ZERO axis sets
+// the cell to +0 and drops earlier flips; a REFLECT_NEG axis after it flips
+// that zero to -0, as the sequential fill does.
+constexpr int kCodeNeg = 1, kCodeZero = 2;
+
+// Source coordinate of padded coordinate p on an axis of n interior cells,
+// updating the value code for a halo cell.  Padded extents fit in 32 bits.
+__device__ inline int source(int p, int n, int h, int mode, int &code) {
     if (p >= h && p < n + h) return p;
     switch (mode) {
         case PW_HALO_PERIODIC: {
-            int64_t q = (p - h) % n;
-            return h + (q < 0 ? q + n : q);
+            int q = p - h;   // one step unless the halo is wider than the interior
+            while (q < 0) q += n;
+            while (q >= n) q -= n;
+            return h + q;
         }
         case PW_HALO_COPY: return p < h ? h : n + h - 1;
-        case PW_HALO_ZERO: sign = 0; return p;
-        case PW_HALO_REFLECT_NEG: sign = -sign; [[fallthrough]];
+        case PW_HALO_ZERO: code = kCodeZero; return p;
+        case PW_HALO_REFLECT_NEG: code ^= kCodeNeg; [[fallthrough]];
         case PW_HALO_REFLECT: return p < h ? 2 * h - 1 - p : 2 * (n + h) - 1 - p;
         default: return p;  // KEEP
     }
 }
 
-// I: index type of the work decomposition (32-bit when every count fits, to
-// keep the divisions cheap).  Grid: x strides over a field's work, y = field.
-template <typename U, typename I>
+// Composition of value codes: `first`, then `then` (see kCodeNeg).
+__device__ inline int compose(int first, int then) { return (then & kCodeZero) ? then : (first ^ then); }
+
+template <typename U> __device__ inline U coded(U x, int code) {
+    const U signbit = static_cast<U>(U(1) << (8 * sizeof(U) - 1));
+    const U v = (code & kCodeZero) ? U(0) : x;
+    return (code & kCodeNeg) ? static_cast<U>(v ^ signbit) : v;
+}
+
+constexpr int kHaloRowCells = 4;                  // cells per lane of a row piece
+constexpr int kHaloPiece = 64 * kHaloRowCells;    // cells of a row piece
+
+// Grid: x strides over a field's wavefronts, y = field.  Wavefront w < xwaves
+// takes 64 x-halo cells (first, so that their scattered round trips overlap
+// the row copies), the others one piece of kHaloPiece cells of a whole row:
+// one load per lane and cell, all issued before the stores.
+template <typename U>
 __global__ __launch_bounds__(256) void halo_kernel(HaloK a) {
+    constexpr int G = kHaloRowCells;
     const int f = blockIdx.y;
     U *const base = static_cast<U *>(a.f[f]);
     const HaloSeg &s = a.seg[f];
-    const I h = I(a.h), h2 = I(2 * a.h);
-    const I px = I(a.nx + 2 * a.h), py = I(a.ny + 2 * a.h);
-    const U signbit = U(1) << (8 * sizeof(U) - 1);
-
-    // whole rows: the z-halo planes (row index r < nzs) and the y-halo rows of
-    // the other planes; one wavefront per row
-    const I rows = I(s.nzs + s.nys), nzs = I(s.nzs);
+    const int h = a.h, h2 = 2 * a.h;
+    const int px = a.nx + 2 * a.h, py = a.ny + 2 * a.h;
+    const int pieces = (px + kHaloPiece - 1) / kHaloPiece;
     const int lane = static_cast<int>(threadIdx.x & 63);
-    const I nwaves = I(gridDim.x) * I(blockDim.x >> 6);
-    const I wave0 = I(blockIdx.x) * I(blockDim.x >> 6) + I(__builtin_amdgcn_readfirstlane(threadIdx.x >> 6));
-    for (I r = wave0; r < rows; r += nwaves) {
-        int64_t k, j;
-        if (r < nzs) {
-            const I q = r / py;
-            j = r - q * py;
-            k = q < h ? q : a.nz + q;
-        } else {
-            const I u = r - nzs, c = u / h2, q = u - c * h2;
-            k = s.k0 + c;
-            j = q < h ? q : a.ny + q;
-        }
-        int sign_kj = 1;
-        const int64_t sj = source(j, a.ny, a.h, s.mode[1], sign_kj);
-        const int64_t sk = source(k, a.nz, a.h, s.mode[2], sign_kj);
-        const U *src = base + sk * a.sz + sj * a.sy;
-        U *dst = base + k * a.sz + j * a.sy;
-        for (int64_t i = lane; i < int64_t(px); i += 64) {
-            int sign = sign_kj;
-            const int64_t si = source(i, a.nx, a.h, s.mode[0], sign);
-            U val = 0;
-            if (sign != 0) {
-                val = src[si];
-                if (sign < 0) val ^= signbit;
+    const int waves = s.xwaves + (s.zrows + s.yrows) * pieces;
+    const int nwaves = static_cast<int>(gridDim.x) * 4;
+    for (int wv = static_cast<int>(blockIdx.x) * 4 + __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+         wv < waves; wv += nwaves) {
+        if (wv < s.xwaves) {   // 64 x-halo cells
+            const int t = wv * 64 + lane;
+            if (t < s.xcells) {
+                const int r = t / h2, q = t - r * h2, c = r / s.jn;
+                const int i = q < h ? q : a.nx + q;
+                const int j = s.j0 + (r - c * s.jn), k = s.k0 + c;
+                int code = 0;
+                const int si = source(i, a.nx, h, s.mode[0], code);
+                const int sj = source(j, a.ny, h, s.mode[1], code);
+                const int sk = source(k, a.nz, h, s.mode[2], code);
+                const U val = (code & kCodeZero) ? U(0) : base[sk * a.sz + static_cast<int64_t>(sj) * a.sy + si];
+                base[k * a.sz + static_cast<int64_t>(j) * a.sy + i] = coded(val, code);
             }
-            dst[i] = val;
+        } else {               // a piece of one whole row: wave-uniform plane and row
+            const int u = wv - s.xwaves, row = u / pieces, i0 = (u - row * pieces) * kHaloPiece;
+            int k, j;
+            if (row < s.zrows) {
+                const int q = row / py;
+                j = row - q * py;
+                k = q < h ? q : a.nz + q;
+            } else {
+                const int v = row - s.zrows, c = v / h2, q = v - c * h2;
+                k = s.k0 + c;
+                j = q < h ? q : a.ny + q;
+            }
+            int cyz = 0;
+            const int sj = source(j, a.ny, h, s.mode[1], cyz);
+            const int sk = source(k, a.nz, h, s.mode[2], cyz);
+            const U *src = base + sk * a.sz + static_cast<int64_t>(sj) * a.sy;
+            U *dst = base + k * a.sz + static_cast<int64_t>(j) * a.sy;
+            U val[G];
+            int code[G];
+#pragma unroll
+            for (int m = 0; m < G; ++m) {
+                const int i = i0 + 64 * m + lane;
+                int cx = 0;
+                const int si = source(i, a.nx, h, s.mode[0], cx);
+                code[m] = cx ? compose(cx, cyz) : cyz;
+                val[m] = (i < px && !(code[m] & kCodeZero)) ? src[si] : U(0);
+            }
+#pragma unroll
+            for (int m = 0; m < G; ++m) {
+                const int i = i0 + 64 * m + lane;
+                if (i < px) dst[i] = coded(val[m], code[m]);
+            }
         }
-    }
-
-    // the x-halo cells of the remaining rows, one per thread
-    const I cells = I(s.nxs), jn = I(s.jn);
-    const I stride = I(gridDim.x) * I(blockDim.x);
-    for (I t = I(blockIdx.x) * I(blockDim.x) + I(threadIdx.x); t < cells; t += stride) {
-        const I r = t / h2, c = r / jn, q = t - r * h2;
-        const int64_t j = s.j0 + (r - c * jn);
-        const int64_t k = s.k0 + c;
-        const int64_t i = q < h ? q : a.nx + q;
-        int sign = 1;
-        const int64_t si = source(i, a.nx, a.h, s.mode[0], sign);
-        const int64_t sj = source(j, a.ny, a.h, s.mode[1], sign);
-        const int64_t sk = source(k, a.nz, a.h, s.mode[2], sign);
-        U val = 0;
-        if (sign != 0) {
-            val = base[sk * a.sz + sj * a.sy + si];
-            if (sign < 0) val ^= signbit;
-        }
-        base[k * a.sz + j * a.sy + i] = val;
     }
 }
 
-// `most`: the largest number of blocks any field's work asks for.
+// `most`: the largest number of wavefronts any field needs.
 template <typename U>
-hipError_t launch_u(const HaloK &k, int nf, int64_t most, bool small, hipStream_t s) {
-    const int64_t blocks = std::min<int64_t>(most, 2048);
+hipError_t launch_u(const HaloK &k, int nf, int64_t most, hipStream_t s) {
+    const int64_t blocks = std::min<int64_t>((most + 3) / 4, 16384);
     const dim3 grid(unsigned(std::max<int64_t>(blocks, 1)), unsigned(nf));
-    if (small)
-        hipLaunchKernelGGL((halo_kernel<U, uint32_t>), grid, dim3(256), 0, s, k);
-    else
-        hipLaunchKernelGGL((halo_kernel<U, uint64_t>), grid, dim3(256), 0, s, k);
+    hipLaunchKernelGGL(halo_kernel<U>, grid, dim3(256), 0, s, k);
     return hipGetLastError();
 }
 
@@ -160,10 +186,10 @@ __global__ __launch_bounds__(256) void fold_kernel(FoldK a) {
             const int64_t p = q < h ? q : n + q;
             T *const cell = line + p * a.s_axis;
             if (mode != PW_HALO_ZERO) {
-                int sign = 1;
-                const int64_t sp = source(p, n, h, mode, sign);
+                int code = 0;
+                const int64_t sp = source(static_cast<int>(p), static_cast<int>(n), static_cast<int>(h), mode, code);
                 T *const dst = line + sp * a.s_axis;
-                *dst = sign < 0 ? *dst - *cell : *dst + *cell;
+                *dst = (code & kCodeNeg) ? *dst - *cell : *dst + *cell;
             }
             *cell = T(0);
         }
@@ -208,11 +234,11 @@ pw_status launch_halo_fold(const HaloArgs &a, hipStream_t s) {
 
 pw_status launch_halo(const HaloArgs &a, hipStream_t s) {
     HaloK k{};
-    k.nx = a.nx;
-    k.ny = a.ny;
-    k.nz = a.nz;
     k.sy = a.sy;
     k.sz = a.sz;
+    k.nx = static_cast<int32_t>(a.nx);
+    k.ny = static_cast<int32_t>(a.ny);
+    k.nz = static_cast<int32_t>(a.nz);
     k.h = a.h;
     const int64_t h = a.h, px = a.nx + 2 * h, py = a.ny + 2 * h, pz = a.nz + 2 * h;
     int64_t most = 0;
@@ -220,32 +246,37 @@ pw_status launch_halo(const HaloArgs &a, hipStream_t s) {
     for (int f = 0; f < a.nf; ++f) {
         const int32_t *m = a.mode[f];
         if (m[0] == PW_HALO_KEEP && m[1] == PW_HALO_KEEP && m[2] == PW_HALO_KEEP) continue;
-        HaloSeg g{};
         const bool fz = m[2] != PW_HALO_KEEP, fy = m[1] != PW_HALO_KEEP, fx = m[0] != PW_HALO_KEEP;
-        g.k0 = fz ? h : 0;
-        g.kn = fz ? a.nz : pz;
-        g.j0 = fy ? h : 0;
-        g.jn = fy ? a.ny : py;
-        g.nzs = fz ? 2 * h * py : 0;        // rows
-        g.nys = fy ? g.kn * 2 * h : 0;      // rows
-        g.nxs = fx ? g.kn * g.jn * 2 * h : 0;   // cells
+        const int64_t kn = fz ? a.nz : pz;   // planes of the y and x segments
+        const int64_t jn = fy ? a.ny : py;
+        const int64_t zrows = fz ? 2 * h * py : 0, yrows = fy ? kn * 2 * h : 0;
+        const int64_t xcells = fx ? kn * jn * 2 * h : 0, xwaves = (xcells + 63) / 64;
+        const int64_t waves = (zrows + yrows) * ((px + kHaloPiece - 1) / kHaloPiece) + xwaves;
+        // 32-bit wavefront, cell and coordinate arithmetic (with room for the
+        // grid-stride step)
+        if (xcells + 64 > INT32_MAX || waves + 4 * 16384 > INT32_MAX || px > INT32_MAX / 2 || py > INT32_MAX / 2 ||
+            pz > INT32_MAX / 2)
+            return fail(PW_ERR_UNSUPPORTED, "halo fill: too many cells for 32-bit indexing");
+        HaloSeg g{};
+        g.zrows = static_cast<int32_t>(zrows);
+        g.yrows = static_cast<int32_t>(yrows);
+        g.xwaves = static_cast<int32_t>(xwaves);
+        g.xcells = static_cast<int32_t>(xcells);
+        g.k0 = static_cast<int32_t>(fz ? h : 0);
+        g.j0 = static_cast<int32_t>(fy ? h : 0);
+        g.jn = static_cast<int32_t>(jn);
         for (int d = 0; d < 3; ++d) g.mode[d] = m[d];
         k.f[nf] = a.f[f];
         k.seg[nf] = g;
-        // four rows per block (one per wavefront), 256 cells per block
-        most = std::max({most, (g.nzs + g.nys + 3) / 4, (g.nxs + 255) / 256});
+        most = std::max(most, waves);
         ++nf;
     }
     if (nf == 0) return PW_OK;
-    // 32-bit decomposition when every count and a loop's last increment fit
-    int64_t biggest = 0;
-    for (int f = 0; f < nf; ++f) biggest = std::max({biggest, k.seg[f].nzs + k.seg[f].nys, k.seg[f].nxs});
-    const bool small = biggest + 2048 * 256 < (int64_t(1) << 32) && px * py < (int64_t(1) << 32);
     hipError_t e = hipSuccess;
     switch (a.es) {
-        case 2: e = launch_u<uint16_t>(k, nf, most, small, s); break;
-        case 4: e = launch_u<uint32_t>(k, nf, most, small, s); break;
-        case 8: e = launch_u<uint64_t>(k, nf, most, small, s); break;
+        case 2: e = launch_u<uint16_t>(k, nf, most, s); break;
+        case 4: e = launch_u<uint32_t>(k, nf, most, s); break;
+        case 8: e = launch_u<uint64_t>(k, nf, most, s); break;
         default: return fail(PW_ERR_INVALID_ARG, "element size %d", a.es);
     }
     return hip_fail(e, "halo_kernel launch");

@@ -42,8 +42,12 @@ struct FwdArgs {
     bool epilogue = false;
     const void *cu = nullptr, *cv = nullptr, *cw = nullptr;
     double alpha = 1.0;
-    // boundary rules applied by addressing (pw_halo_mode per axis)
+    // boundary rules applied by addressing: the read remapping per axis
+    // (KEEP, PERIODIC, or COPY = nearest interior cell) and the value rules
+    // (byte d = axis x, y, z; 2 bits per field f = u, v, w at bit 2f:
+    // 1 negate, 2 zero)
     int32_t bcx = PW_HALO_KEEP, bcy = PW_HALO_KEEP, bcz = PW_HALO_KEEP;
+    uint32_t bcv = 0;
 };
 
 struct AdjArgs {

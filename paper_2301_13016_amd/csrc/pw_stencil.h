@@ -138,6 +138,10 @@ template <typename Tin> struct FwdK {
     // the stored halo): a read of a halo cell goes to its periodic or
     // nearest-interior source instead
     int32_t bcx = PW_HALO_KEEP, bcy = PW_HALO_KEEP, bcz = PW_HALO_KEEP;
+    // value rules on top of the addressing (kernels built with Bc == 2): byte
+    // d (axis x, y, z) holds a 2-bit code per field f (u, v, w) at bit 2f,
+    // see bc_apply
+    uint32_t bcv = 0;
 };
 
 // Padded index that a read of padded index p (0 <= p < n+2h) uses on an axis
@@ -155,7 +159,7 @@ __device__ __forceinline__ int bc_src(int p, int n, int h, int mode) {
 }
 // bc_src when the kernel is built for boundary rules (Bc), else p unchanged:
 // the plain kernels carry no mapping code at all.
-template <bool Bc> __device__ __forceinline__ int bc_map(int p, int n, int h, int mode) {
+template <int Bc> __device__ __forceinline__ int bc_map(int p, int n, int h, int mode) {
     if constexpr (Bc) {
         return bc_src(p, n, h, mode);
     } else {
@@ -166,6 +170,51 @@ template <bool Bc> __device__ __forceinline__ int bc_map(int p, int n, int h, in
     }
 }
 
+// Value rules by addressing (Bc == 2).  A halo cell's value is its source's
+// value passed through one code per axis, in the halo fill's order x, y, z:
+// 0 keeps it, 1 negates it (REFLECT_NEG), 2 replaces it by +0 (ZERO).  A code
+// describing several axes has bit 1 = zero, bit 0 = negate: a zero drops
+// what came before and a later negation turns it into -0, as the sequential
+// fill does.  Codes of the three fields sit side by side, two bits each.
+__device__ __forceinline__ uint32_t bc_compose(uint32_t first, uint32_t then) {   // one field
+    return (then & 2u) ? then : (first ^ then);
+}
+__device__ __forceinline__ uint32_t bc_compose3(uint32_t first, uint32_t then) {  // three fields
+    uint32_t z = then & 0x2Au;
+    z |= z >> 1;   // both bits of every field whose later code zeroes
+    return (then & z) | ((first ^ then) & ~z);
+}
+// Codes (three fields) of axis d for padded index p on an axis of n cells.
+template <int Bc>
+__device__ __forceinline__ uint32_t bc_axis_code(const uint32_t bcv, int d, int p, int n, int h) {
+    if constexpr (Bc == 2) {
+        const bool halo = p < h || p >= n + h;
+        return halo ? (bcv >> (8 * d)) & 0x3Fu : 0u;
+    } else {
+        (void)bcv;
+        (void)d;
+        (void)p;
+        (void)n;
+        (void)h;
+        return 0u;
+    }
+}
+template <typename T> struct Bits;
+template <> struct Bits<float> { using type = uint32_t; };
+template <> struct Bits<double> { using type = uint64_t; };
+template <> struct Bits<uint16_t> { using type = uint16_t; };
+template <> struct Bits<_Float16> { using type = uint16_t; };
+// x passed through code c (one field): sign-bit and zero operations on the
+// stored bits, exact in every storage type.
+template <typename T> __device__ __forceinline__ T bc_apply(T x, uint32_t c) {
+    using B = typename Bits<T>::type;
+    constexpr B sign = static_cast<B>(B(1) << (8 * sizeof(T) - 1));
+    B b = __builtin_bit_cast(B, x);
+    b = (c & 2u) ? B(0) : b;
+    b = (c & 1u) ? static_cast<B>(b ^ sign) : b;
+    return __builtin_bit_cast(T, b);
+}
+
 // One z-plane of the strip as loaded: rows 0..RY+1 are the strip's rows
 // jj0-1 .. jj0+RY (interior numbering), each the lane's PX columns in storage
 // precision (16-bit values stay packed two per register and are widened when
@@ -173,6 +222,7 @@ template <bool Bc> __device__ __forceinline__ int bc_map(int p, int n, int h, in
 template <typename Tin, int PX, int RY> struct Plane {
     typename Vec<Tin, PX>::type u[RY + 2], v[RY + 2], w[RY + 2];
     Tin hu, hv, hw;
+    uint32_t zcode;          // value rules: the plane's z codes (Bc == 2)
 };
 
 // Per-lane addressing of the strip, fixed for the whole march.
@@ -180,7 +230,79 @@ template <int RY> struct StripAddr {
     uint32_t roff[RY + 2];   // byte offset of this lane's first column in row r
     uint32_t hoff;           // byte offset of this lane's halo element
     int col;                 // padded column of the lane's first element
+    // value rules (Bc == 2): y codes of row r (wave-uniform), the x-then-y
+    // codes of this lane's halo element, and a bit per element m of the
+    // lane's columns that lies in the x halo (strips at the grid's x end)
+    uint32_t ycode[RY + 2];
+    uint32_t yany;           // OR of ycode (wave-uniform)
+    uint32_t hcode;
+    uint32_t xhalo;
 };
+
+// The value rules of one freshly loaded plane, applied in place before its
+// first use (Bc == 2): every row value of field f takes its x code (if its
+// column is a halo column), then the row's y code, then the plane's z code.
+template <typename Tin, int PX, int RY, bool Full>
+__device__ __forceinline__ void bc_values(Plane<Tin, PX, RY> &P, const StripAddr<RY> &s, uint32_t bcv) {
+    const uint32_t hc = bc_compose3(s.hcode, P.zcode);
+    P.hu = bc_apply(P.hu, hc & 3u);
+    P.hv = bc_apply(P.hv, (hc >> 2) & 3u);
+    P.hw = bc_apply(P.hw, (hc >> 4) & 3u);
+    // row values: only in planes or strips that reach a z or y halo, or at
+    // the grid's x end (a wave-uniform test; most planes skip it)
+    if (Full && (s.yany | P.zcode) == 0u) return;
+    const uint32_t vx = bcv & 0x3Fu;
+#pragma unroll
+    for (int r = 0; r < RY + 2; ++r) {
+        const uint32_t cyz = bc_compose3(s.ycode[r], P.zcode);   // wave-uniform
+#pragma unroll
+        for (int m = 0; m < PX; ++m) {
+            uint32_t c3 = cyz;
+            if constexpr (!Full) c3 = ((s.xhalo >> m) & 1u) ? bc_compose3(vx, cyz) : cyz;
+            if constexpr (PX == 1) {
+                P.u[r] = bc_apply(P.u[r], c3 & 3u);
+                P.v[r] = bc_apply(P.v[r], (c3 >> 2) & 3u);
+                P.w[r] = bc_apply(P.w[r], (c3 >> 4) & 3u);
+            } else {
+                P.u[r][m] = bc_apply(P.u[r][m], c3 & 3u);
+                P.v[r][m] = bc_apply(P.v[r][m], (c3 >> 2) & 3u);
+                P.w[r][m] = bc_apply(P.w[r][m], (c3 >> 4) & 3u);
+            }
+        }
+    }
+}
+
+// The value-rule codes of a strip (Bc == 2): y codes of its loaded rows
+// (padded rows jj0-1+h .. jj0+RY+h, clamped as the loads are), x-then-y codes
+// of the lane's packed halo element (padded row hrow_p, column hcol_p), and
+// the lane's elements that lie in the x halo.
+template <int Bc, int PX, int RY>
+__device__ __forceinline__ void bc_strip_codes(StripAddr<RY> &s, uint32_t bcv, int jj0, int prows, int last_col,
+                                               int hrow_p, int hcol_p, int nx, int ny, int h) {
+    if constexpr (Bc == 2) {
+        s.hcode = bc_compose3(bc_axis_code<Bc>(bcv, 0, hcol_p, nx, h), bc_axis_code<Bc>(bcv, 1, hrow_p, ny, h));
+        s.xhalo = 0;
+#pragma unroll
+        for (int m = 0; m < PX; ++m) s.xhalo |= (min(s.col + m, last_col) >= nx + h ? 1u : 0u) << m;
+        s.yany = 0;
+#pragma unroll
+        for (int r = 0; r < RY + 2; ++r) {
+            s.ycode[r] = bc_axis_code<Bc>(bcv, 1, min(jj0 - 1 + h + r, prows - 1), ny, h);
+            s.yany |= s.ycode[r];
+        }
+    } else {
+        (void)s;
+        (void)bcv;
+        (void)jj0;
+        (void)prows;
+        (void)last_col;
+        (void)hrow_p;
+        (void)hcol_p;
+        (void)nx;
+        (void)ny;
+        (void)h;
+    }
+}
 
 // PX consecutive elements of one row starting at padded column `col`.  In a
 // full strip (Full) every lane's vector lies inside the row and is read with
@@ -191,7 +313,7 @@ template <int RY> struct StripAddr {
 // axis' rule (bc_src over n interior columns, halo h).  One-column lanes need
 // no clamping beyond their start column unless mapped.  The choice is made
 // per wavefront, so neither path branches per lane.
-template <typename Tin, int PX, bool Full, bool Bc = false>
+template <typename Tin, int PX, bool Full, int Bc = 0>
 __device__ __forceinline__ void load_row(typename Vec<Tin, PX>::type &dst, const char *plane, uint32_t off, int col,
                                          int last_col, int n, int h, int bc) {
     if constexpr (Full || (PX == 1 && !Bc)) {
@@ -216,7 +338,7 @@ __device__ __forceinline__ void load_row(typename Vec<Tin, PX>::type &dst, const
     }
 }
 
-template <typename Tin, int PX, int RY, bool Full, bool Bc = false>
+template <typename Tin, int PX, int RY, bool Full, int Bc = 0>
 __device__ __forceinline__ void load_plane(Plane<Tin, PX, RY> &P, const FwdK<Tin> &a,
                                            int kp, const StripAddr<RY> &s, int last_col) {
     const int64_t pb = static_cast<int64_t>(kp) * a.in_sz * static_cast<int64_t>(sizeof(Tin));
@@ -430,7 +552,7 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
 // start of the level, before that level's plane prefetch (a scheduling
 // barrier keeps the compiler from moving them after it), so waiting for them
 // never waits for the prefetch.
-template <typename Tin, int PX, int RY, bool Full, int Depth, bool Epi, bool Bc>
+template <typename Tin, int PX, int RY, bool Full, int Depth, bool Epi, int Bc>
 __device__ __forceinline__ void strip_march_t(const FwdK<Tin> &a, int tx, int ty, int cz) {
     using Tc = typename Storage<Tin>::Tc;
     const int lane = threadIdx.x & 63;
@@ -452,10 +574,12 @@ __device__ __forceinline__ void strip_march_t(const FwdK<Tin> &a, int tx, int ty
     }
     {   // packed halo: lane r -> left halo of row r, lane 32+r -> right halo of row r
         const int hr = min(lane & 31, RY + 1);
-        const int hrow = bc_map<Bc>(min(jj0 - 1 + a.h + hr, prows - 1), a.ny, a.h, a.bcy);
-        const int hcol = bc_map<Bc>((lane & 32) ? min(tx * 64 * PX + 64 * PX + a.h, last_col) : tx * 64 * PX + a.h - 1,
-                                    a.nx, a.h, a.bcx);
+        const int hrow_p = min(jj0 - 1 + a.h + hr, prows - 1);
+        const int hcol_p = (lane & 32) ? min(tx * 64 * PX + 64 * PX + a.h, last_col) : tx * 64 * PX + a.h - 1;
+        const int hrow = bc_map<Bc>(hrow_p, a.ny, a.h, a.bcy);
+        const int hcol = bc_map<Bc>(hcol_p, a.nx, a.h, a.bcx);
         s.hoff = static_cast<uint32_t>((hrow * a.in_sy + hcol) * static_cast<int>(sizeof(Tin)));
+        bc_strip_codes<Bc, PX, RY>(s, a.bcv, jj0, prows, last_col, hrow_p, hcol_p, a.nx, a.ny, a.h);
     }
     uint32_t ooff[RY];
     bool row_ok[RY];
@@ -478,23 +602,46 @@ __device__ __forceinline__ void strip_march_t(const FwdK<Tin> &a, int tx, int ty
     // re-reads plane k1, a cache hit): a conditional load would merge two
     // paths with different loads in flight, and the wait inserted at such a
     // merge drains every outstanding load, prefetch included.
-#define PW_PLOAD(P, kp) load_plane<Tin, PX, RY, Full, Bc>(P, a, bc_map<Bc>(min((kp), k1) + h, a.nz, h, a.bcz), s, last_col)
+    // (value rules: a plane's z codes are set with its load, and the rules are
+    // applied to it just before the first level that reads it)
+#define PW_PLOAD(P, kp)                                                                                        \
+    do {                                                                                                       \
+        load_plane<Tin, PX, RY, Full, Bc>(P, a, bc_map<Bc>(min((kp), k1) + h, a.nz, h, a.bcz), s, last_col); \
+        P.zcode = bc_axis_code<Bc>(a.bcv, 2, min((kp), k1) + h, a.nz, h);                                      \
+    } while (0)
 #define PW_LOAD(P, kp)                                                   \
     do {                                                                 \
         if constexpr (Epi) {                                             \
             load_epi<Tin, PX, RY, Full>(Ep, a, kk, ooff, ic);            \
             __builtin_amdgcn_sched_barrier(0);                           \
         }                                                                \
-        load_plane<Tin, PX, RY, Full, Bc>(P, a, bc_map<Bc>(min((kp), k1) + h, a.nz, h, a.bcz), s, last_col); \
+        PW_PLOAD(P, kp);                                                 \
     } while (0)
-#define PW_LEVEL(M, C, P) level<Tin, PX, RY, Full, Epi>(M, C, P, a, kk, lane0, lane63, nvalid, ooff, row_ok, Ep)
+#define PW_LEVEL(M, C, P)                                                                      \
+    do {                                                                                       \
+        if constexpr (Bc == 2) bc_values<Tin, PX, RY, Full>(P, s, a.bcv);                      \
+        level<Tin, PX, RY, Full, Epi>(M, C, P, a, kk, lane0, lane63, nvalid, ooff, row_ok, Ep); \
+    } while (0)
+#define PW_FIRST(P, kp)                                                                            \
+    do {                                                                                           \
+        load_plane<Tin, PX, RY, Full, Bc>(P, a, bc_map<Bc>((kp) + h, a.nz, h, a.bcz), s, last_col); \
+        P.zcode = bc_axis_code<Bc>(a.bcv, 2, (kp) + h, a.nz, h);                                   \
+    } while (0)
+#define PW_FIX_FIRST(A, B)                                   \
+    do {                                                     \
+        if constexpr (Bc == 2) {                             \
+            bc_values<Tin, PX, RY, Full>(A, s, a.bcv);       \
+            bc_values<Tin, PX, RY, Full>(B, s, a.bcv);       \
+        }                                                    \
+    } while (0)
     int kk = k0;
     if constexpr (Depth == 1) {
         // four-plane ring: planes kk-1, kk, kk+1 feed level kk, kk+2 in flight
         Plane<Tin, PX, RY> A, B, C, D;
-        load_plane<Tin, PX, RY, Full, Bc>(A, a, bc_map<Bc>(k0 - 1 + h, a.nz, h, a.bcz), s, last_col);
+        PW_FIRST(A, k0 - 1);
         PW_PLOAD(B, k0);
         PW_PLOAD(C, k0 + 1);
+        PW_FIX_FIRST(A, B);
         for (;;) {
             PW_LOAD(D, kk + 2);
             PW_LEVEL(A, B, C);
@@ -513,10 +660,11 @@ __device__ __forceinline__ void strip_march_t(const FwdK<Tin> &a, int tx, int ty
         // five-plane ring: planes kk+2 and kk+3 in flight
         static_assert(Depth == 2, "prefetch depth 1 or 2");
         Plane<Tin, PX, RY> A, B, C, D, E;
-        load_plane<Tin, PX, RY, Full, Bc>(A, a, bc_map<Bc>(k0 - 1 + h, a.nz, h, a.bcz), s, last_col);
+        PW_FIRST(A, k0 - 1);
         PW_PLOAD(B, k0);
         PW_PLOAD(C, k0 + 1);
         PW_PLOAD(D, k0 + 2);
+        PW_FIX_FIRST(A, B);
         for (;;) {
             PW_LOAD(E, kk + 3);
             PW_LEVEL(A, B, C);
@@ -537,11 +685,13 @@ __device__ __forceinline__ void strip_march_t(const FwdK<Tin> &a, int tx, int ty
     }
 #undef PW_PLOAD
 #undef PW_LOAD
+#undef PW_FIRST
+#undef PW_FIX_FIRST
 #undef PW_LEVEL
 }
 
 // Bc: reads go through the boundary rules a.bcx/bcy/bcz (pw_advect_bc).
-template <typename Tin, int PX, int RY, int Depth, bool Epi = false, bool Bc = false>
+template <typename Tin, int PX, int RY, int Depth, bool Epi = false, int Bc = 0>
 __device__ __forceinline__ void strip_march(const FwdK<Tin> &a, int tx, int ty, int cz) {
     if constexpr (PX == 1) {
         // one-column lanes: loads never need clamping beyond the start column,
@@ -619,7 +769,7 @@ __device__ __forceinline__ void lds_get(typename Vec<Tin, PX>::type &d, const ty
 // or above (highest) the workgroup, plus the packed x-halo of all RY+2 rows.
 // NtOwn: rows that no other workgroup reads (not the workgroup's first or
 // last own row) are read with non-temporal loads.
-template <typename Tin, int PX, int RY, bool Full, bool Bc, int Role, bool NtOwn = false>
+template <typename Tin, int PX, int RY, bool Full, int Bc, int Role, bool NtOwn = false>
 __device__ __forceinline__ void load_plane_own(Plane<Tin, PX, RY> &P, const FwdK<Tin> &a, int kp,
                                                const StripAddr<RY> &s, int last_col) {
     const int64_t pb = static_cast<int64_t>(kp) * a.in_sz * static_cast<int64_t>(sizeof(Tin));
@@ -687,7 +837,7 @@ __device__ __forceinline__ void get_edges(const EdgeLds<Tin, PX, W> &L, int slot
 // completed at the two levels before.  Every wavefront of the workgroup runs
 // the same number of levels (same z-chunk), also one whose strip lies past
 // the grid (it loads clamped rows and stores nothing), so the barriers match.
-template <typename Tin, int PX, int RY, bool Full, int Depth, bool Epi, bool Bc, int W, int Role, bool NtOwn = false>
+template <typename Tin, int PX, int RY, bool Full, int Depth, bool Epi, int Bc, int W, int Role, bool NtOwn = false>
 __device__ __forceinline__ void strip_march_lds_t(const FwdK<Tin> &a, EdgeLds<Tin, PX, W> &L, int tx, int ty,
                                                   int cz, int wave) {
     using Tc = typename Storage<Tin>::Tc;
@@ -708,10 +858,12 @@ __device__ __forceinline__ void strip_march_lds_t(const FwdK<Tin> &a, EdgeLds<Ti
     }
     {
         const int hr = min(lane & 31, RY + 1);
-        const int hrow = bc_map<Bc>(min(jj0 - 1 + a.h + hr, prows - 1), a.ny, a.h, a.bcy);
-        const int hcol = bc_map<Bc>((lane & 32) ? min(tx * 64 * PX + 64 * PX + a.h, last_col) : tx * 64 * PX + a.h - 1,
-                                    a.nx, a.h, a.bcx);
+        const int hrow_p = min(jj0 - 1 + a.h + hr, prows - 1);
+        const int hcol_p = (lane & 32) ? min(tx * 64 * PX + 64 * PX + a.h, last_col) : tx * 64 * PX + a.h - 1;
+        const int hrow = bc_map<Bc>(hrow_p, a.ny, a.h, a.bcy);
+        const int hcol = bc_map<Bc>(hcol_p, a.nx, a.h, a.bcx);
         s.hoff = static_cast<uint32_t>((hrow * a.in_sy + hcol) * static_cast<int>(sizeof(Tin)));
+        bc_strip_codes<Bc, PX, RY>(s, a.bcv, jj0, prows, last_col, hrow_p, hcol_p, a.nx, a.ny, a.h);
     }
     uint32_t ooff[RY];
     bool row_ok[RY];
@@ -731,8 +883,14 @@ __device__ __forceinline__ void strip_march_lds_t(const FwdK<Tin> &a, EdgeLds<Ti
     EpiRows<Tin, PX, RY> Ep;
     int slot = 0;   // slot of plane kk+1 at level kk: planes k0-1, k0, k0+1, ... take slots 0, 1, 2, 0, ...
 
-#define PW_PLOAD(P, kp) \
-    load_plane_own<Tin, PX, RY, Full, Bc, Role, NtOwn>(P, a, bc_map<Bc>(min((kp), k1) + h, a.nz, h, a.bcz), s, last_col)
+    // (value rules: the raw rows go through LDS, and every wavefront applies
+    // the rules to its whole plane once the neighbours' rows are in)
+#define PW_PLOAD(P, kp)                                                                                            \
+    do {                                                                                                           \
+        load_plane_own<Tin, PX, RY, Full, Bc, Role, NtOwn>(P, a, bc_map<Bc>(min((kp), k1) + h, a.nz, h, a.bcz), s, \
+                                                           last_col);                                              \
+        P.zcode = bc_axis_code<Bc>(a.bcv, 2, min((kp), k1) + h, a.nz, h);                                          \
+    } while (0)
 #define PW_LOAD(P, kp)                                                   \
     do {                                                                 \
         if constexpr (Epi) {                                             \
@@ -747,6 +905,7 @@ __device__ __forceinline__ void strip_march_lds_t(const FwdK<Tin> &a, EdgeLds<Ti
         __syncthreads();                                                 \
         get_edges<Tin, PX, RY, W, Role>(L, slot, wave, lane, P);         \
         slot = slot == kLdsSlots - 1 ? 0 : slot + 1;                     \
+        if constexpr (Bc == 2) bc_values<Tin, PX, RY, Full>(P, s, a.bcv); \
     } while (0)
 #define PW_LEVEL(M, C, P)                                                                          \
     do {                                                                                           \
@@ -757,6 +916,7 @@ __device__ __forceinline__ void strip_march_lds_t(const FwdK<Tin> &a, EdgeLds<Ti
     if constexpr (Depth == 1) {
         Plane<Tin, PX, RY> A, B, C, D;
         load_plane_own<Tin, PX, RY, Full, Bc, Role, NtOwn>(A, a, bc_map<Bc>(k0 - 1 + h, a.nz, h, a.bcz), s, last_col);
+        A.zcode = bc_axis_code<Bc>(a.bcv, 2, k0 - 1 + h, a.nz, h);
         PW_PLOAD(B, k0);
         PW_PLOAD(C, k0 + 1);
         PW_SHARE(A);
@@ -779,6 +939,7 @@ __device__ __forceinline__ void strip_march_lds_t(const FwdK<Tin> &a, EdgeLds<Ti
         static_assert(Depth == 2, "prefetch depth 1 or 2");
         Plane<Tin, PX, RY> A, B, C, D, E;
         load_plane_own<Tin, PX, RY, Full, Bc, Role, NtOwn>(A, a, bc_map<Bc>(k0 - 1 + h, a.nz, h, a.bcz), s, last_col);
+        A.zcode = bc_axis_code<Bc>(a.bcv, 2, k0 - 1 + h, a.nz, h);
         PW_PLOAD(B, k0);
         PW_PLOAD(C, k0 + 1);
         PW_PLOAD(D, k0 + 2);
@@ -811,7 +972,7 @@ __device__ __forceinline__ void strip_march_lds_t(const FwdK<Tin> &a, EdgeLds<Ti
 // Dispatch of one wavefront of an LDS-sharing workgroup to its role's march
 // (the wave index is wave-uniform, so this branch is taken once, before any
 // load), and to the full-strip or x-edge path.
-template <typename Tin, int PX, int RY, int Depth, bool Epi, bool Bc, int W, bool Full, bool NtOwn>
+template <typename Tin, int PX, int RY, int Depth, bool Epi, int Bc, int W, bool Full, bool NtOwn>
 __device__ __forceinline__ void strip_march_lds_f(const FwdK<Tin> &a, EdgeLds<Tin, PX, W> &L, int tx, int ty,
                                                   int cz, int wave) {
     static_assert(W >= 2, "sharing needs two wavefronts or more");
@@ -823,7 +984,7 @@ __device__ __forceinline__ void strip_march_lds_f(const FwdK<Tin> &a, EdgeLds<Ti
         strip_march_lds_t<Tin, PX, RY, Full, Depth, Epi, Bc, W, kRoleMid, NtOwn>(a, L, tx, ty, cz, wave);
 }
 
-template <typename Tin, int PX, int RY, int Depth, bool Epi, bool Bc, int W, bool NtOwn = false>
+template <typename Tin, int PX, int RY, int Depth, bool Epi, int Bc, int W, bool NtOwn = false>
 __device__ __forceinline__ void strip_march_lds(const FwdK<Tin> &a, EdgeLds<Tin, PX, W> &L, int tx, int ty, int cz,
                                                 int wave) {
     if constexpr (PX == 1) {

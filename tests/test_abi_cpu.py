@@ -622,17 +622,33 @@ def test_advect_bc_validation(lib):
     g, c, p = _args()
     call = lambda bc, ep=None: lib.pw_advect_bc(ctypes.byref(g), None, B.PW_F32, *p[:3], ctypes.byref(c),  # noqa
                                                 bc, ep, *p[3:], None, None)
-    assert call(ctypes.byref(B.pw_halo_modes(1, 1, 2))) in _no_gpu_status()
-    assert call(ctypes.byref(B.pw_halo_modes(0, 0, 0))) in _no_gpu_status()
+
+    def rules(*triples):   # one triple for all three fields, or three
+        if len(triples) == 1:
+            triples = triples * 3
+        return (B.pw_halo_modes * 3)(*(B.pw_halo_modes(*t) for t in triples))
+    assert call(rules((1, 1, 2))) in _no_gpu_status()
+    assert call(rules((0, 0, 0))) in _no_gpu_status()
     assert call(None) == B.PW_ERR_INVALID_ARG
-    assert call(ctypes.byref(B.pw_halo_modes(3, 1, 1))) == B.PW_ERR_UNSUPPORTED      # zero: a value rule
-    assert "addressing" in B.pw_last_error()
-    assert call(ctypes.byref(B.pw_halo_modes(1, 5, 1))) == B.PW_ERR_UNSUPPORTED      # negated mirror
-    assert call(ctypes.byref(B.pw_halo_modes(1, 1, 9))) == B.PW_ERR_INVALID_ARG      # unknown rule
+    # value rules: free-slip lid, no-slip wall, zero / mirrored walls in x and y
+    assert call(rules((1, 1, 2), (1, 1, 2), (1, 1, 3))) in _no_gpu_status()
+    assert call(rules((1, 1, 5), (1, 1, 5), (1, 1, 3))) in _no_gpu_status()
+    assert call(rules((3, 5, 1), (4, 2, 1), (5, 3, 1))) in _no_gpu_status()
+    # the read remapping must agree across fields on each axis
+    assert call(rules((1, 1, 2), (1, 1, 2), (1, 1, 1))) == B.PW_ERR_UNSUPPORTED   # nearest vs periodic
+    assert "all keep" in B.pw_last_error()
+    assert call(rules((0, 1, 2), (2, 1, 2), (2, 1, 2))) == B.PW_ERR_UNSUPPORTED   # keep vs nearest
+    assert call(rules((1, 1, 9))) == B.PW_ERR_INVALID_ARG                          # unknown rule
+    assert call(rules((1, 1, 2), (1, 1, 2), (1, 1, -1))) == B.PW_ERR_INVALID_ARG
+    # mirror rules need n >= h, as for the fill
+    g3 = B.pw_grid(8, 8, 2, 3)
+    st = lib.pw_advect_bc(ctypes.byref(g3), None, B.PW_F32, *p[:3], ctypes.byref(c), rules((1, 1, 4)), None,
+                          *p[3:], None, None)
+    assert st == B.PW_ERR_INVALID_ARG and "reflect" in B.pw_last_error()
     q = [A + (20 + i) * MB for i in range(3)]
-    assert call(ctypes.byref(B.pw_halo_modes(1, 1, 1)), ctypes.byref(B.pw_epilogue(0.5, *q))) in _no_gpu_status()
-    assert call(ctypes.byref(B.pw_halo_modes(1, 1, 1)),
-                ctypes.byref(B.pw_epilogue(float("nan"), *q))) == B.PW_ERR_INVALID_ARG
+    assert call(rules((1, 1, 1)), ctypes.byref(B.pw_epilogue(0.5, *q))) in _no_gpu_status()
+    assert call(rules((1, 1, 5)), ctypes.byref(B.pw_epilogue(0.5, *q))) in _no_gpu_status()
+    assert call(rules((1, 1, 1)), ctypes.byref(B.pw_epilogue(float("nan"), *q))) == B.PW_ERR_INVALID_ARG
 
 
 def test_halo_fold_validation(lib):

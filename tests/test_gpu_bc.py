@@ -1,6 +1,8 @@
 """GPU tests of boundary rules applied by addressing (pw_advect_bc): the
-result equals halo fill + forward bit for bit, the halo is never written,
-and a periodic domain conserves energy exactly without any fill."""
+result equals halo fill + forward bit for bit (sign of zero included), for
+remapped reads (keep, periodic, nearest cell) and the value rules (zero,
+negated mirror) per field; the halo is never written, and a periodic domain
+conserves energy exactly without any fill."""
 import itertools
 import sys
 
@@ -27,6 +29,30 @@ def _announce(request):
 
 
 RULES = ["keep", "periodic", "copy"]
+# rules that read the same cells: on each axis all three fields take rules
+# of one class, and within the nearest-cell class each field its own
+CLASSES = {"keep": ["keep"], "periodic": ["periodic"], "nearest": ["copy", "zero", "reflect", "reflect_neg"]}
+LIDS = [
+    [("periodic", "periodic", "copy")] * 2 + [("periodic", "periodic", "zero")],         # free-slip lid
+    [("periodic", "periodic", "reflect_neg")] * 2 + [("periodic", "periodic", "zero")],  # no-slip lid
+    [("reflect_neg", "periodic", "copy"), ("zero", "periodic", "copy"), ("copy", "periodic", "zero")],
+    [("zero", "reflect_neg", "keep"), ("reflect", "zero", "keep"), ("reflect_neg", "copy", "keep")],
+]
+
+
+def rule_draws(seed, per_class=3):
+    """Per-field rule triples: every class combination of the three axes,
+    with `per_class` random choices of the per-field rules where an axis is
+    in the nearest-cell class."""
+    rng = np.random.default_rng(seed)
+    for cls in itertools.product(CLASSES, repeat=3):
+        for _ in range(per_class if "nearest" in cls else 1):
+            yield [tuple(str(rng.choice(CLASSES[c])) for c in cls) for _ in range(3)]
+
+
+def same_bits(a, b):
+    it = {torch.float32: torch.int32, torch.float64: torch.int64}[a.dtype]
+    return a.dtype == b.dtype and torch.equal(a.view(it), b.view(it))
 
 
 def _fill_then_advect(ins, c, bc, halo, tile, addends=None, alpha=1.0):
@@ -53,8 +79,40 @@ def test_every_rule_combination_bitwise(shape, storage):
         torch.cuda.synchronize()
         for a, b in zip(got, ref):
             assert torch.equal(a, b), bc
+    for bc in rule_draws(901 + nx, per_class=2 if storage else 4):
+        got = B.advect_bc(u, v, w, c, bc)
+        ref = _fill_then_advect((u, v, w), c, bc, 1, None)
+        torch.cuda.synchronize()
+        for a, b in zip(got, ref):
+            assert same_bits(a, b), bc
     for x, y in zip((u, v, w), before):   # inputs, halo included, untouched
         assert torch.equal(x, y)
+
+
+@pytest.mark.parametrize("storage", [None, "float64", "bfloat16"])
+def test_value_rules_never_read_the_halo(storage):
+    """NaN in every halo cell: where no axis keeps its halo, the addressed
+    forward reads none of them, for every per-field rule draw (bit for bit
+    against fill + forward, which overwrites them)."""
+    g = wl.make_grid(131, 6, 5, seed=905, dtype=np.float64 if storage == "float64" else np.float32)
+    sdt = None if storage in (None, "float64") else getattr(torch, storage)
+    (u, v, w), c = dev_grid(g, storage=sdt)
+    for x in (u, v, w):
+        inner = x[1:-1, 1:-1, 1:-1].clone()
+        x.fill_(float("nan"))
+        x[1:-1, 1:-1, 1:-1] = inner
+    n = 0
+    for bc in rule_draws(906, per_class=4):
+        if any("keep" in t for t in bc):
+            continue
+        got = B.advect_bc(u, v, w, c, bc)
+        ref = _fill_then_advect((u, v, w), c, bc, 1, None)
+        torch.cuda.synchronize()
+        for a, b in zip(got, ref):
+            assert bool(torch.isfinite(a).all()), bc
+            assert same_bits(a, b), bc
+        n += 1
+    assert n >= 16
 
 
 @pytest.mark.parametrize("tile", [(4, 2, 64, 1, 2), (1, 1, 5, 4, 1), (2, 4, 3, 8, 1), (4, 1, 7, 2, 2), (1, 2, 9, 1, 2)],
@@ -66,26 +124,57 @@ def test_launch_shapes_and_epilogue(tile):
     (u, v, w), c = dev_grid(g)
     rng = np.random.default_rng(911)
     adds = [torch.from_numpy(rng.uniform(-3, 3, (22, 13, 197)).astype(np.float32)).cuda() for _ in range(3)]
-    for bc in [("periodic", "periodic", "copy"), ("copy", "periodic", "periodic"), ("periodic", "keep", "copy")]:
+    for bc in [("periodic", "periodic", "copy"), ("copy", "periodic", "periodic"), ("periodic", "keep", "copy")] + LIDS:
         got = B.advect_bc(u, v, w, c, bc, tile=tile)
         ref = _fill_then_advect((u, v, w), c, bc, 1, tile)
         got_e = B.advect_bc(u, v, w, c, bc, addends=adds, alpha=-0.5, tile=tile)
         ref_e = _fill_then_advect((u, v, w), c, bc, 1, tile, addends=adds, alpha=-0.5)
         torch.cuda.synchronize()
         for a, b in zip(got + got_e, ref + ref_e):
-            assert torch.equal(a, b), (bc, tile)
+            assert same_bits(a, b), (bc, tile)
+
+
+SHARED = {None: [(4, 1, 5, 2, 1, 1), (4, 2, 7, 4, 1, 2), (4, 4, 64, 4, 1, 2)],
+          "float64": [(2, 2, 6, 4, 1, 2), (2, 4, 64, 2, 1, 1)],
+          "bfloat16": [(8, 2, 9, 4, 1, 2), (4, 4, 64, 2, 1, 1)],
+          "float16": [(4, 2, 64, 4, 1, 2)]}
+
+
+@pytest.mark.parametrize("storage", list(SHARED))
+def test_shared_row_tiles_with_rules(storage):
+    """Workgroups that share edge rows through LDS apply the rules too: the
+    raw rows pass through LDS and every wavefront applies the value rules to
+    its completed plane.  Grids with partial workgroups at the top, ragged x
+    ends and several z-chunks; with and without the epilogue."""
+    dt = np.float64 if storage == "float64" else np.float32
+    g = wl.make_grid(601, 19, 13, seed=916, dtype=dt)
+    sdt = None if storage in (None, "float64") else getattr(torch, storage)
+    (u, v, w), c = dev_grid(g, storage=sdt)
+    odt = torch.float64 if storage == "float64" else torch.float32
+    rng = np.random.default_rng(917)
+    adds = [torch.from_numpy(rng.uniform(-3, 3, (13, 19, 601))).to(odt).cuda() for _ in range(3)]
+    draws = list(rule_draws(918, per_class=1))[::3]
+    for tile in SHARED[storage]:
+        for bc in [("periodic", "periodic", "copy"), ("keep", "keep", "keep")] + LIDS + draws:
+            got = B.advect_bc(u, v, w, c, bc, tile=tile)
+            ref = _fill_then_advect((u, v, w), c, bc, 1, tile)
+            got_e = B.advect_bc(u, v, w, c, bc, addends=adds, alpha=0.25, tile=tile)
+            ref_e = _fill_then_advect((u, v, w), c, bc, 1, tile, addends=adds, alpha=0.25)
+            torch.cuda.synchronize()
+            for a, b in zip(got + got_e, ref + ref_e):
+                assert same_bits(a, b), (bc, tile)
 
 
 @pytest.mark.parametrize("halo", [2, 3])
 def test_wider_halo(halo):
     g = wl.make_grid(70, 9, 6, seed=912, halo=halo)
     (u, v, w), c = dev_grid(g)
-    for bc in [("periodic",) * 3, ("copy", "periodic", "keep")]:
+    for bc in [("periodic",) * 3, ("copy", "periodic", "keep")] + LIDS:
         got = B.advect_bc(u, v, w, c, bc, halo=halo)
         ref = _fill_then_advect((u, v, w), c, bc, halo, None)
         torch.cuda.synchronize()
         for a, b in zip(got, ref):
-            assert torch.equal(a, b), bc
+            assert same_bits(a, b), bc
 
 
 def test_periodic_domain_conserves_energy_without_a_fill():
@@ -114,13 +203,21 @@ def test_periodic_domain_conserves_energy_without_a_fill():
         assert np.array_equal(a.cpu().numpy(), b)
 
 
-def test_value_rules_are_unsupported():
+def test_rules_that_read_different_cells_are_rejected():
+    """The read remapping is shared: per axis the fields must all keep, all be
+    periodic or all use nearest-cell rules.  Mirror rules need n >= h."""
     g = wl.make_grid(20, 8, 4, seed=914)
     (u, v, w), c = dev_grid(g)
-    for bc in [("zero", "keep", "keep"), ("keep", "reflect", "keep"), ("keep", "keep", "reflect_neg")]:
+    for bc in [[("zero", "keep", "keep"), ("periodic", "keep", "keep"), ("zero", "keep", "keep")],
+               [("keep", "keep", "copy"), ("keep", "keep", "copy"), ("keep", "keep", "keep")]]:
         with pytest.raises(B.PWError) as ei:
             B.advect_bc(u, v, w, c, bc)
         assert ei.value.status == B.PW_ERR_UNSUPPORTED
+    g3 = wl.make_grid(20, 8, 2, seed=915, halo=3)
+    (u, v, w), c = dev_grid(g3)
+    with pytest.raises(B.PWError) as ei:
+        B.advect_bc(u, v, w, c, ("periodic", "periodic", "reflect"), halo=3)
+    assert ei.value.status == B.PW_ERR_INVALID_ARG
 
 
 def test_autograd_through_boundaries_gradcheck():
@@ -130,7 +227,7 @@ def test_autograd_through_boundaries_gradcheck():
     g = wl.make_grid(9, 5, 4, seed=930, dtype=np.float64)
     (u, v, w), c = dev_grid(g)
     ins = [x.clone().requires_grad_(True) for x in (u, v, w)]
-    for bc in [("periodic", "periodic", "copy"), ("copy", "keep", "periodic")]:
+    for bc in [("periodic", "periodic", "copy"), ("copy", "keep", "periodic"), LIDS[1], LIDS[3]]:
         f = lambda a, b, d: PW.apply(a, b, d, c, bc)  # noqa: E731
         assert torch.autograd.gradcheck(f, tuple(ins), eps=1e-6, atol=1e-8, rtol=1e-6, fast_mode=True,
                                         check_forward_ad=True)

@@ -1,7 +1,7 @@
 """GPU tests of the halo fill against the oracle's per-axis definition.
 
 The fill only moves and negates values, so the bar is exact: every cell of
-the GPU result equals the oracle's (zero compared as a value), for every
+the GPU result equals the oracle's, sign of zero included, for every
 storage type, mode combination and halo width, with strided layouts, and the
 interior and any cells outside the padded views stay untouched bit for bit.
 """
@@ -52,6 +52,8 @@ def _check(fields, modes, halo):
         ref = H.fill(b, halo, m)
         got = _host64(f)
         assert np.array_equal(got, ref), (m, np.argwhere(got != ref)[:5])
+        # signed zeros too: a zeroed cell that a later axis negates is -0
+        assert np.array_equal(np.signbit(got), np.signbit(ref)), (m, np.argwhere(np.signbit(got) != np.signbit(ref))[:5])
 
 
 MODES = [m for m in H.MODES]

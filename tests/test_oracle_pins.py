@@ -308,6 +308,24 @@ def test_halo_fill_reflect_neg_vanishes_on_the_face():
         H.fill(np.zeros((7, 7, 5)), 2, ("reflect", "keep", "keep"))
 
 
+def test_halo_fill_signed_zero_follows_the_axis_order():
+    """Edges and corners take the sequential x, y, z fill's value, sign of
+    zero included: a cell zeroed by an earlier axis and negated by a later
+    one is -0, a cell negated first and zeroed later is +0 (checked cell by
+    cell against the order of the two operations)."""
+    from oracle import halo as H
+    a = np.full((3, 4, 5), 7.0)
+    got = H.fill(a, 1, ("zero", "reflect_neg", "keep"))
+    corner = got[:, 0, 0]                      # x halo (zeroed), then y halo (negated)
+    assert np.all(corner == 0) and np.all(np.signbit(corner))
+    assert np.all(got[:, 1:-1, 0] == 0) and not np.any(np.signbit(got[:, 1:-1, 0]))
+    assert np.all(got[:, 0, 1:-1] == -7.0)
+    got = H.fill(a, 1, ("reflect_neg", "zero", "keep"))
+    assert np.all(got[:, 0, :] == 0) and not np.any(np.signbit(got[:, 0, :]))
+    got = H.fill(a, 1, ("zero", "reflect_neg", "reflect_neg"))
+    assert not np.any(np.signbit(got[0, 0, 0:1]))   # negated twice after the zero: +0
+
+
 def test_halo_fill_keep_and_wide_periodic():
     """keep leaves an axis' halo alone; a halo wider than the interior wraps
     more than once (brute-force index arithmetic)."""

@@ -343,6 +343,30 @@ def prebuilt_coeff_grad(B, ins, cots, stream, torch):
     return call
 
 
+def prebuilt_fused_backward(B, ins, cots, grads, coeffs, stream, torch):
+    """ctypes arguments of one pw_advect_adjoint_coeff_grad call (wind and
+    coefficient gradients in one pass; output and workspace allocated here)."""
+    from paper_2301_13016_amd.binding import _dtype_code, _grid_from, _layout_from
+    u, v, w = ins
+    grid = _grid_from(u, 1)
+    need = ctypes.c_int64()
+    B.lib().pw_advect_coeff_grad_workspace(ctypes.byref(grid), _dtype_code(u), ctypes.byref(need))
+    out = torch.empty(6 * int(grid.nz) + 2, dtype=torch.float64, device=u.device)
+    ws = torch.empty(max(1, need.value // 8), dtype=torch.float64, device=u.device)
+    keep = (grid, _layout_from(u, cots[0]), coeffs.c_struct(), out, ws)
+    args = (ctypes.byref(keep[0]), ctypes.byref(keep[1]), _dtype_code(u), u.data_ptr(), v.data_ptr(), w.data_ptr(),
+            ctypes.byref(keep[2]), *(x.data_ptr() for x in cots), *(x.data_ptr() for x in grads), out.data_ptr(),
+            ws.data_ptr(), need.value, ctypes.c_void_p(stream.cuda_stream))
+    fn = B.lib().pw_advect_adjoint_coeff_grad
+
+    def call():
+        st = fn(*args)
+        if st != B.PW_OK:
+            raise B.PWError(st, B.pw_last_error(), "pw_advect_adjoint_coeff_grad")
+    call.keep = keep
+    return call
+
+
 def prebuilt_adjoint(B, ins, cots, grads, coeffs, stream):
     """ctypes arguments of one pw_advect_adjoint_ex call, built once."""
     from paper_2301_13016_amd.binding import _dtype_code, _grid_from, _layout_from
@@ -578,7 +602,7 @@ def main():
     host4 = [torch.from_numpy(x) for x in (g4.u, g4.v, g4.w)]
     hcot4 = [torch.from_numpy(x) for x in wl.cotangents(*n4, c4["cot_seed"])]
     hdir4 = [torch.from_numpy(x.astype(np.float32)) for x in wl.direction(*n4, seed=46)]
-    fcalls, acalls, tcalls, ccalls, keep4 = [], [], [], [], []
+    fcalls, acalls, tcalls, ccalls, bcalls, keep4 = [], [], [], [], [], []
     for _ in range(4):
         ins4 = [x.to(dev) for x in host4]
         cot4 = [x.to(dev) for x in hcot4]
@@ -591,10 +615,12 @@ def main():
         acalls.append(prebuilt_adjoint(B, ins4, cot4, gr4, co4, stream))
         tcalls.append(prebuilt_tangent(B, ins4, dir4, t4, co4, stream))
         ccalls.append(prebuilt_coeff_grad(B, ins4, cot4, stream, torch))
+        bcalls.append(prebuilt_fused_backward(B, ins4, cot4, gr4, co4, stream, torch))
     _, fms = time_launches(torch, lambda i: fcalls[i](), 4, 100, 5, stream)
     _, ams = time_launches(torch, lambda i: acalls[i](), 4, 100, 5, stream)
     _, tms = time_launches(torch, lambda i: tcalls[i](), 4, 100, 5, stream)
     _, cms = time_launches(torch, lambda i: ccalls[i](), 4, 100, 5, stream)
+    _, bms = time_launches(torch, lambda i: bcalls[i](), 4, 100, 5, stream)
     pts4 = n4[0] * n4[1] * n4[2]
     forms["adjoint_256x256x128"] = dict(
         forward_ms=round(fms, 4), adjoint_ms=round(ams, 4), adjoint_over_forward=round(ams / fms, 3),
@@ -611,9 +637,14 @@ def main():
         coeff_grad_ms=round(cms, 4), coeff_grad_over_forward=round(cms / fms, 3),
         ideal_ratio_from_bytes=round(cbytes4 / algo_bytes(*n4, 1, 4), 3),
         coeff_grad_hbm_gbs=round(cbytes4 / (cms * 1e-3) / 1e9, 1))
+    forms["fused_backward_256x256x128"] = dict(
+        backward_ms=round(bms, 4), over_adjoint=round(bms / ams, 3), separate_ms=round(ams + cms, 4),
+        backward_over_forward=round(bms / fms, 3))
     log("c4: forward %.4f ms, adjoint %.4f ms (ratio %.3f), tangent %.4f ms (ratio %.3f), "
         "coefficient gradients %.4f ms (ratio %.3f)" % (fms, ams, ams / fms, tms, tms / fms, cms, cms / fms))
-    del keep4, fcalls, acalls, tcalls, ccalls
+    log("c4: wind and coefficient gradients in one pass %.4f ms (%.3f x the adjoint; separately %.4f ms)"
+        % (bms, bms / ams, ams + cms))
+    del keep4, fcalls, acalls, tcalls, ccalls, bcalls
     torch.cuda.empty_cache()
 
     # ------------------------------------------------------------ batched form: c3

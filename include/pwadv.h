@@ -243,10 +243,13 @@ pw_status pw_advect_tangent_ex(const pw_grid *grid, const pw_layout *layout, pw_
  *   each level's share of dL/dtcx [0..nz) and of dL/dtcy [0..nz),
  *   dL/dtcx, dL/dtcy.
  * Sums are accumulated in FP64 in a fixed order (the same result on every
- * run).  u, v, w padded (input layout), gsu/gsv/gsw interior (output
- * layout); dtype PW_F32 or PW_F64.  `workspace` is device memory of at least
- * pw_advect_coeff_grad_workspace() bytes, owned by the caller; it and grad
- * must be 8-byte aligned and overlap nothing else.  No allocation. */
+ * run): per point and strip of the adjoint's march (strips of 62 padded
+ * columns and a number of rows fixed by the grid's size), then over the
+ * strips, then (tcx, tcy) over the levels.  u, v, w padded (input
+ * layout), gsu/gsv/gsw interior (output layout); dtype PW_F32 or PW_F64.
+ * `workspace` is device memory of at least pw_advect_coeff_grad_workspace()
+ * bytes (6 nz ceil((nx+2h)/62) (ny+2h) doubles), owned by the caller; it and
+ * grad must be 8-byte aligned and overlap nothing else.  No allocation. */
 pw_status pw_advect_coeff_grad_workspace(const pw_grid *grid, pw_dtype dtype, int64_t *bytes);
 pw_status pw_advect_coeff_grad(const pw_grid *grid, const pw_layout *layout, pw_dtype dtype,
                                const void *u, const void *v, const void *w,
@@ -272,6 +275,24 @@ pw_status pw_advect_coeff_grad_static(const pw_grid *grid, const pw_layout *layo
                                       const void *u, const void *v, const void *w,
                                       const void *gsu, const void *gsv, const void *gsw,
                                       double *grad, void *hip_stream);
+
+/* The whole backward of L = <su, gsu> + <sv, gsv> + <sw, gsw> in one pass
+ * over u, v, w and the cotangents: the wind gradients of pw_advect_adjoint
+ * (gu, gv, gw) and the coefficient gradients of pw_advect_coeff_grad (grad),
+ * from the same adjoint march (Sec. 4's term structure: every term is one
+ * coefficient times a coefficient-free product, whose factors the adjoint
+ * already holds).  Both results equal, bit for bit, those of
+ * pw_advect_adjoint and pw_advect_coeff_grad called separately: the wind
+ * gradients do not depend on the launch shape, and the coefficient partials
+ * are per strip of one shape that depends on the grid's size alone, whether
+ * or not the wind gradients come with them.  Arguments, ownership and errors
+ * as the two calls; grad and the workspace must also overlap none of gu, gv,
+ * gw.  PW_F32 / PW_F64.  No allocation. */
+pw_status pw_advect_adjoint_coeff_grad(const pw_grid *grid, const pw_layout *layout, pw_dtype dtype,
+                                       const void *u, const void *v, const void *w, const pw_coeffs *coeffs,
+                                       const void *gsu, const void *gsv, const void *gsw,
+                                       void *gu, void *gv, void *gw, double *grad, void *workspace,
+                                       int64_t workspace_bytes, void *hip_stream);
 
 /* Autotuner for single-grid launches.  Times candidate launch shapes of the
  * forward kernel (flags & PW_TUNE_FORWARD), the z-fastest forward kernel

@@ -114,6 +114,9 @@ _SIGNATURES = {
                              _P, _P, _P, _P, _P, _P, _P, _P, ctypes.c_int64, _P],
     "pw_advect_coeff_grad_static": [ctypes.POINTER(pw_grid), ctypes.POINTER(pw_layout), ctypes.c_int,
                                     _P, _P, _P, _P, _P, _P, _P, _P],
+    "pw_advect_adjoint_coeff_grad": [ctypes.POINTER(pw_grid), ctypes.POINTER(pw_layout), ctypes.c_int,
+                                     _P, _P, _P, ctypes.POINTER(pw_coeffs), _P, _P, _P, _P, _P, _P, _P, _P,
+                                     ctypes.c_int64, _P],
     "pw_advect_zfast": [ctypes.POINTER(pw_grid), ctypes.POINTER(pw_layout_zfast), ctypes.c_int,
                         _P, _P, _P, ctypes.POINTER(pw_coeffs), _P, _P, _P, ctypes.POINTER(pw_tile), _P],
     "pw_advect_zfast_epilogue": [ctypes.POINTER(pw_grid), ctypes.POINTER(pw_layout_zfast), ctypes.c_int,
@@ -610,10 +613,52 @@ def advect_coeff_grad(u, v, w, gsu, gsv, gsw, halo=1, stream=None, out=None, sta
                                         v.data_ptr(), w.data_ptr(), *(g.data_ptr() for g in gs), out.data_ptr(),
                                         ws.data_ptr(), need.value, _stream_handle(stream))
         _check(st, "pw_advect_coeff_grad")
+    return _coeff_grad_dict(out, nz)
+
+
+def _coeff_grad_dict(out, nz):
     names = ("tzc1", "tzc2", "tzd1", "tzd2", "tcx_level", "tcy_level")
     res = {n: out[i * nz:(i + 1) * nz] for i, n in enumerate(names)}
     res["tcx"], res["tcy"] = out[6 * nz], out[6 * nz + 1]
     return res
+
+
+def advect_adjoint_coeff_grad(u, v, w, coeffs: Coeffs, gsu, gsv, gsw, halo=1, out=None, grad_out=None,
+                              stream=None):
+    """The whole backward in one pass (pw_advect_adjoint_coeff_grad): the wind
+    gradients (gu, gv, gw) as advect_adjoint and the coefficient gradients as
+    advect_coeff_grad (a dict of views of ``grad_out``), bit for bit."""
+    import torch
+    _check_inputs(u, v, w)
+    grid = _grid_from(u, halo)
+    _check_coeffs(coeffs, grid.nz, _compute_dtype(u), u.device)
+    if out is None:
+        out = tuple(torch.empty_like(u) for _ in range(3))
+    gu, gv, gw = out
+    for g in (gsu, gsv, gsw):
+        _check_group([g], "cotangents", (grid.nz, grid.ny, grid.nx), u.dtype, u.device)
+    gsu, gsv, gsw = (g.contiguous() if g.stride(-1) != 1 else g for g in (gsu, gsv, gsw))
+    if not (gsu.stride() == gsv.stride() == gsw.stride()):
+        gsu, gsv, gsw = (g.contiguous() for g in (gsu, gsv, gsw))
+    layout = _layout_from(u, gsu)
+    _check_group(out, "gradients", tuple(u.shape), u.dtype, u.device)
+    if gu.stride() != u.stride():
+        raise ValueError("gradients must share the inputs' strides")
+    nz = int(grid.nz)
+    if grad_out is None:
+        grad_out = torch.empty(6 * nz + 2, dtype=torch.float64, device=u.device)
+    _check_group([grad_out], "grad_out", (6 * nz + 2,), torch.float64, u.device)
+    need = ctypes.c_int64()
+    _check(lib().pw_advect_coeff_grad_workspace(ctypes.byref(grid), _dtype_code(u), ctypes.byref(need)),
+           "pw_advect_coeff_grad_workspace")
+    ws = torch.empty(max(1, need.value // 8), dtype=torch.float64, device=u.device)
+    st = lib().pw_advect_adjoint_coeff_grad(ctypes.byref(grid), ctypes.byref(layout), _dtype_code(u), u.data_ptr(),
+                                            v.data_ptr(), w.data_ptr(), ctypes.byref(coeffs.c_struct()),
+                                            gsu.data_ptr(), gsv.data_ptr(), gsw.data_ptr(), gu.data_ptr(),
+                                            gv.data_ptr(), gw.data_ptr(), grad_out.data_ptr(), ws.data_ptr(),
+                                            need.value, _stream_handle(stream))
+    _check(st, "pw_advect_adjoint_coeff_grad")
+    return (gu, gv, gw), _coeff_grad_dict(grad_out, nz)
 
 
 def tune(nx, ny, nz, dtype, halo=1, flags=0):
@@ -888,9 +933,9 @@ def _autograd_function_coeffs():
     class PWAdvectCoeffs(torch.autograd.Function):
         """PW advection differentiable in the winds and in the coefficients:
         apply(u, v, w, tcx, tcy, tzc1, tzc2, tzd1, tzd2, halo=1) with tcx, tcy
-        0-d tensors and tz* device tensors of length nz.  Backward runs the
-        adjoint kernel for the winds and the coefficient-gradient kernel for
-        the coefficients (each only when needed)."""
+        0-d tensors and tz* device tensors of length nz.  Backward runs one
+        adjoint march for both the winds and the coefficients when both are
+        needed (advect_adjoint_coeff_grad), else only the one needed."""
 
         @staticmethod
         def forward(ctx, u, v, w, tcx, tcy, tzc1, tzc2, tzd1, tzd2, halo=1):
@@ -905,11 +950,15 @@ def _autograd_function_coeffs():
             u, v, w = ctx.saved_tensors
             need = ctx.needs_input_grad
             gu = gv = gw = None
-            if any(need[:3]):
+            g = None
+            if any(need[:3]) and any(need[3:9]):   # one pass over the winds and cotangents
+                (gu, gv, gw), g = advect_adjoint_coeff_grad(u, v, w, ctx.coeffs, gsu, gsv, gsw, ctx.halo)
+            elif any(need[:3]):
                 gu, gv, gw = advect_adjoint(u, v, w, ctx.coeffs, gsu, gsv, gsw, ctx.halo)
-            cg = [None] * 6
-            if any(need[3:9]):
+            elif any(need[3:9]):
                 g = advect_coeff_grad(u, v, w, gsu, gsv, gsw, ctx.halo)
+            cg = [None] * 6
+            if g is not None:
                 c = ctx.coeffs
                 (d0, v0), (d1, v1) = ctx.cdtypes
                 cg = [g["tcx"].to(device=v0, dtype=d0), g["tcy"].to(device=v1, dtype=d1)] + \

@@ -23,6 +23,7 @@
 // meet zero cotangents, and zeroing them keeps a non-finite value there
 // (0 * NaN = NaN) out of the gradient.
 #include "pw_internal.h"
+#include "pw_reduce.h"
 
 namespace pw {
 namespace {
@@ -55,7 +56,13 @@ template <typename T> struct AdjK {
     int64_t in_sz, out_sz;
     int32_t in_sy, out_sy;
     int32_t ntx, nty, nzc, zlen, wpb;
+    // coefficient partials (modes with kModeCg): ws[q][level][strip], strip = ty * ntx + tx
+    double *ws;
 };
+
+// What a launch computes: the gradients of u, v, w (kModeGrad), the
+// per-strip coefficient partials (kModeCg; see cg_level), or both in one pass.
+constexpr int kModeGrad = 1, kModeCg = 2;
 
 // One padded z-plane of the strip: rows 0..RY+1 are padded rows jb-1 .. jb+RY.
 template <typename T, int RY> struct APlane {
@@ -187,7 +194,6 @@ template <typename T, int RY>
 __device__ __forceinline__ void adj_level(const APlane<T, RY> &m, const APlane<T, RY> &c, APlane<T, RY> &p,
                                           const AdjK<T> &a, const StripAddr<T, RY> &s, int kp, bool lane_ok,
                                           const uint32_t (&goff)[RY], const bool (&row_ok)[RY]) {
-    mask_aplane<T, RY>(p, s);   // first use of plane kp+1
     const int kq = kp - a.h;   // interior level index of this gradient plane
     const T tcx = a.tcx, tcy = a.tcy;
     const T c1p = coef(a.tzc1, kq + 1, a.nz), c2m = coef(a.tzc2, kq - 1, a.nz), c2 = coef(a.tzc2, kq, a.nz);
@@ -285,6 +291,66 @@ __device__ __forceinline__ void adj_level(const APlane<T, RY> &m, const APlane<T
     }
 }
 
+// Coefficient partials of level kp (an interior level kk = kp - h): each
+// coefficient multiplies a coefficient-free product in every term it enters,
+// so dL/dc sums, over the interior points, the cotangent times that product.
+// Per point the six groups (tzc1: z-lower u and v terms, tzc2: z-upper,
+// tzd1 / tzd2: the w terms, tcx / tcy: the x- and y-face terms) are formed
+// from the planes and rows the adjoint already holds, summed per lane over
+// the strip's rows in the compute type, then over the wavefront in FP64 in a
+// fixed order, and stored as ws[q][kk][strip].  The strips are the adjoint's
+// (62 columns x RY rows), so a partial does not depend on whether the
+// gradients are computed in the same pass.  Points outside the interior, and
+// lanes 0 and 63, are selected away (not multiplied by a zero cotangent: a
+// NaN there would survive).
+constexpr int kQ = 6;
+template <typename T, int RY>
+__device__ __forceinline__ void cg_level(const APlane<T, RY> &m, const APlane<T, RY> &c, const APlane<T, RY> &p,
+                                         const AdjK<T> &a, const StripAddr<T, RY> &s, int kp, bool lane_ok,
+                                         int strip, bool lane0) {
+    if (!c.zok) return;   // a halo level (wave-uniform)
+    T fy[RY + 1];
+#pragma unroll
+    for (int r = 0; r <= RY; ++r) fy[r] = c.v[r] + from_right(c.v[r]);
+    T sq[kQ] = {T(0), T(0), T(0), T(0), T(0), T(0)};
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+        const int q = r + 1;
+        const bool ok = lane_ok && (s.mask[q] & kCotOk);
+        const T ra = c.ru[q], rb = c.rv[q], re = c.rw[q];
+        // su term groups
+        const T uc = c.u[q], ul = from_left(c.u[q]), ur = from_right(c.u[q]);
+        const T ax = fma_(-ur, uc + ur, ul * (uc + ul));
+        const T ay = fma_(-c.u[q + 1], fy[q], c.u[q - 1] * fy[r]);
+        const T az1 = m.u[q] * (m.w[q] + from_right(m.w[q]));
+        const T az2 = p.u[q] * (c.w[q] + from_right(c.w[q]));
+        // sv term groups
+        const T vc = c.v[q], vl = from_left(c.v[q]), vr = from_right(c.v[q]);
+        const T bx = fma_(-vr, uc + c.u[q + 1], vl * (ul + from_left(c.u[q + 1])));
+        const T by = fma_(-c.v[q + 1], vc + c.v[q + 1], c.v[q - 1] * (vc + c.v[q - 1]));
+        const T bz1 = m.v[q] * (m.w[q] + m.w[q + 1]);
+        const T bz2 = p.v[q] * (c.w[q] + c.w[q + 1]);
+        // sw term groups
+        const T wc = c.w[q], wl = from_left(c.w[q]), wr = from_right(c.w[q]);
+        const T cx = fma_(-wr, uc + p.u[q], wl * (ul + from_left(p.u[q])));
+        const T cy = fma_(-c.w[q + 1], c.v[q] + p.v[q], c.w[q - 1] * (c.v[q - 1] + p.v[q - 1]));
+        const T cz1 = m.w[q] * (wc + m.w[q]);
+        const T cz2 = p.w[q] * (wc + p.w[q]);
+        sq[0] += ok ? fma_(ra, az1, rb * bz1) : T(0);
+        sq[1] -= ok ? fma_(ra, az2, rb * bz2) : T(0);
+        sq[2] += ok ? re * cz1 : T(0);
+        sq[3] -= ok ? re * cz2 : T(0);
+        sq[4] += ok ? fma_(ra, ax, fma_(rb, bx, re * cx)) : T(0);
+        sq[5] += ok ? fma_(ra, ay, fma_(rb, by, re * cy)) : T(0);
+    }
+    const int kk = kp - a.h;
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+        const double t = red::wave_sum(static_cast<double>(sq[q]));
+        if (lane0) a.ws[(static_cast<int64_t>(q) * a.nz + kk) * (static_cast<int64_t>(a.ntx) * a.nty) + strip] = t;
+    }
+}
+
 __device__ __forceinline__ int xcd_tile(int b, int nb) {
     const int q = nb >> 3, rem = nb & 7, x = b & 7, i = b >> 3;
     return x * q + min(x, rem) + i;
@@ -293,7 +359,7 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
 // Depth: planes in flight ahead of the three a level reads (1 or 2).
 // MaxT: workgroup size bound (built for 256 and 512 threads; see the forward
 // kernel).
-template <typename T, int RY, int Depth, int MaxT>
+template <typename T, int RY, int Depth, int MaxT, int Mode>
 __global__ __launch_bounds__(MaxT) void pw_adjoint_kernel(AdjK<T> a) {
     const int lane = threadIdx.x & 63;
     // wavefront index as a scalar, so that per-strip conditions stay scalar
@@ -351,7 +417,14 @@ __global__ __launch_bounds__(MaxT) void pw_adjoint_kernel(AdjK<T> a) {
     // k1, a cache hit, into a slot no level uses): a conditional load would
     // join two paths with different loads in flight, and the wait at the join
     // drains the prefetch.
-#define PW_ALEVEL(M, C, P) adj_level<T, RY>(M, C, P, a, s, k, lane_ok, goff, row_ok)
+    const int strip = ty * a.ntx + tx;
+    const bool lane0 = lane == 0;
+#define PW_ALEVEL(M, C, P)                                                                    \
+    do {                                                                                      \
+        mask_aplane<T, RY>(P, s);   /* first use of plane k+1 */                              \
+        if constexpr (Mode & kModeGrad) adj_level<T, RY>(M, C, P, a, s, k, lane_ok, goff, row_ok); \
+        if constexpr (Mode & kModeCg) cg_level<T, RY>(M, C, P, a, s, k, lane_ok, strip, lane0);    \
+    } while (0)
     int k = k0;
     if constexpr (Depth == 1) {
         // four-plane ring: planes k-1, k, k+1 feed level k, k+2 in flight
@@ -406,9 +479,10 @@ __global__ __launch_bounds__(MaxT) void pw_adjoint_kernel(AdjK<T> a) {
 #undef PW_ALEVEL
 }
 
-template <typename T, int RY>
-pw_status launch_adj_t(const AdjArgs &g, const TileCfg &cfg, hipStream_t s) {
+template <typename T, int RY, int Mode>
+pw_status launch_adj_t(const AdjArgs &g, const TileCfg &cfg, double *ws, hipStream_t s) {
     AdjK<T> a;
+    a.ws = ws;
     a.u = static_cast<const T *>(g.u);
     a.v = static_cast<const T *>(g.v);
     a.w = static_cast<const T *>(g.w);
@@ -442,28 +516,45 @@ pw_status launch_adj_t(const AdjArgs &g, const TileCfg &cfg, hipStream_t s) {
     const int64_t nblocks = static_cast<int64_t>(a.ntx) * nblk_y * a.nzc;
     if (nblocks <= 0 || nblocks > 0x7fffffffLL) return fail(PW_ERR_UNSUPPORTED, "grid too large");
     const dim3 grid(static_cast<unsigned>(nblocks)), block(64 * cfg.wpb);
-    if (cfg.depth == 2) {
-        if (cfg.wpb <= 4)
-            hipLaunchKernelGGL((pw_adjoint_kernel<T, RY, 2, 256>), grid, block, 0, s, a);
+    if constexpr (Mode != kModeGrad) {   // built for up to four wavefronts per workgroup
+        if (cfg.depth == 2)
+            hipLaunchKernelGGL((pw_adjoint_kernel<T, RY, 2, 256, Mode>), grid, block, 0, s, a);
         else
-            hipLaunchKernelGGL((pw_adjoint_kernel<T, RY, 2, 512>), grid, block, 0, s, a);
+            hipLaunchKernelGGL((pw_adjoint_kernel<T, RY, 1, 256, Mode>), grid, block, 0, s, a);
+    } else if (cfg.depth == 2) {
+        if (cfg.wpb <= 4)
+            hipLaunchKernelGGL((pw_adjoint_kernel<T, RY, 2, 256, Mode>), grid, block, 0, s, a);
+        else
+            hipLaunchKernelGGL((pw_adjoint_kernel<T, RY, 2, 512, Mode>), grid, block, 0, s, a);
     } else {
         if (cfg.wpb <= 4)
-            hipLaunchKernelGGL((pw_adjoint_kernel<T, RY, 1, 256>), grid, block, 0, s, a);
+            hipLaunchKernelGGL((pw_adjoint_kernel<T, RY, 1, 256, Mode>), grid, block, 0, s, a);
         else
-            hipLaunchKernelGGL((pw_adjoint_kernel<T, RY, 1, 512>), grid, block, 0, s, a);
+            hipLaunchKernelGGL((pw_adjoint_kernel<T, RY, 1, 512, Mode>), grid, block, 0, s, a);
     }
     return hip_fail(hipGetLastError(), "adjoint kernel launch");
 }
 
-template <typename T>
-pw_status launch_adj_dt(const AdjArgs &g, const TileCfg &cfg, hipStream_t s) {
+template <typename T, int Mode>
+pw_status launch_adj_dt(const AdjArgs &g, const TileCfg &cfg, double *ws, hipStream_t s) {
     switch (cfg.ry) {
-        case 1: return launch_adj_t<T, 1>(g, cfg, s);
-        case 2: return launch_adj_t<T, 2>(g, cfg, s);
-        case 4: return launch_adj_t<T, 4>(g, cfg, s);
+        case 1: return launch_adj_t<T, 1, Mode>(g, cfg, ws, s);
+        case 2: return launch_adj_t<T, 2, Mode>(g, cfg, ws, s);
+        case 4: return launch_adj_t<T, 4, Mode>(g, cfg, ws, s);
         default: return fail(PW_ERR_UNSUPPORTED, "adjoint rows per strip %d not instantiated", cfg.ry);
     }
+}
+
+template <typename T>
+pw_status launch_adj_mode(const AdjArgs &g, const TileCfg &cfg, int mode, double *ws, hipStream_t s) {
+    TileCfg c = cfg;
+    if (mode != kModeGrad && c.wpb > 4) c.wpb = 4;   // strips are independent: no result changes
+    switch (mode) {
+        case kModeGrad: return launch_adj_dt<T, kModeGrad>(g, c, ws, s);
+        case kModeCg: return launch_adj_dt<T, kModeCg>(g, c, ws, s);
+        case kModeGrad | kModeCg: return launch_adj_dt<T, kModeGrad | kModeCg>(g, c, ws, s);
+    }
+    return fail(PW_ERR_INVALID_ARG, "adjoint mode %d", mode);
 }
 
 }  // namespace
@@ -491,13 +582,24 @@ TileCfg default_adjoint_tile(const AdjArgs &a, pw_dtype dt) {
     return c;
 }
 
-pw_status launch_adjoint(const AdjArgs &a, pw_dtype dt, const TileCfg &cfg, hipStream_t s) {
+int64_t adjoint_strips(const pw_grid &g, int ry) {
+    const int64_t px = g.nx + 2 * g.halo, py = g.ny + 2 * g.halo;
+    return ((px + kWaveCols - 1) / kWaveCols) * ((py + ry - 1) / ry);
+}
+
+pw_status launch_adjoint_mode(const AdjArgs &a, pw_dtype dt, const TileCfg &cfg, bool grads, double *partials,
+                              hipStream_t s) {
     if (!adjoint_tile_supported(cfg)) return fail(PW_ERR_INVALID_ARG, "unsupported adjoint tile configuration");
+    const int mode = (grads ? kModeGrad : 0) | (partials ? kModeCg : 0);
     switch (dt) {
-        case PW_F32: return launch_adj_dt<float>(a, cfg, s);
-        case PW_F64: return launch_adj_dt<double>(a, cfg, s);
+        case PW_F32: return launch_adj_mode<float>(a, cfg, mode, partials, s);
+        case PW_F64: return launch_adj_mode<double>(a, cfg, mode, partials, s);
         default: return fail(PW_ERR_UNSUPPORTED, "adjoint dtype %d", static_cast<int>(dt));
     }
+}
+
+pw_status launch_adjoint(const AdjArgs &a, pw_dtype dt, const TileCfg &cfg, hipStream_t s) {
+    return launch_adjoint_mode(a, dt, cfg, true, nullptr, s);
 }
 
 }  // namespace pw

@@ -527,6 +527,65 @@ pw_status check_coeff_grad(const pw_grid *grid, const pw_layout *layout, pw_dtyp
 
 }  // namespace
 
+}  // extern "C"
+
+namespace pw {
+namespace {
+
+// Launch shape of every coefficient-gradient pass, fixed by the grid's size
+// alone, so that the partials -- and the gradients -- are the same bit for
+// bit whether the wind gradients are computed with them or not.  Measured on
+// MI355X (256x256x128 FP32, the three adjoint modes over rows per strip,
+// z-chunks, wavefronts per workgroup and prefetch depth): four-row strips
+// (FP64: one row, for registers), one wavefront per workgroup, and the march
+// cut into as many z-chunks as keep the wavefronts within one round of the
+// chip's 2048 slots (these kernels hold about 220 VGPRs: two wavefronts per
+// SIMD).  One round more with a short tail costs a quarter: 2275 wavefronts
+// took 139 us where 1950 took 113 us.
+TileCfg coeff_grad_tile(const pw_grid *grid, pw_dtype dtype) {
+    TileCfg c;
+    c.px = 1;
+    c.ry = dtype == PW_F64 ? 1 : 4;
+    c.wpb = 1;
+    c.depth = 1;
+    c.share = 0;
+    const int64_t pz = grid->nz + 2 * grid->halo;
+    const int64_t strips = adjoint_strips(*grid, c.ry);
+    int64_t chunks = 2048 / strips;
+    if (chunks < 1) chunks = 1;
+    int64_t zl = (pz + chunks - 1) / chunks;
+    if (zl < 8) zl = 8;
+    if (zl > pz) zl = pz;
+    c.zlen = static_cast<int>(zl);
+    return c;
+}
+
+AdjArgs coeff_grad_args(const pw_grid *grid, const Layout &L, const void *u, const void *v, const void *w,
+                        const void *gsu, const void *gsv, const void *gsw) {
+    AdjArgs a{};
+    a.u = u; a.v = v; a.w = w;
+    a.gsu = gsu; a.gsv = gsv; a.gsw = gsw;
+    a.gu = a.gv = a.gw = nullptr;
+    a.tzc1 = a.tzc2 = a.tzd1 = a.tzd2 = nullptr;
+    a.tcx = a.tcy = 0.0;
+    a.nx = grid->nx; a.ny = grid->ny; a.nz = grid->nz; a.h = grid->halo;
+    a.in_sy = L.in_sy; a.in_sz = L.in_sz; a.out_sy = L.out_sy; a.out_sz = L.out_sz;
+    return a;
+}
+
+pw_status run_coeff_grad(const pw_grid *grid, pw_dtype dtype, const AdjArgs &a, bool grads, double *grad,
+                         void *workspace, hipStream_t s) {
+    const TileCfg cfg = coeff_grad_tile(grid, dtype);
+    double *ws = static_cast<double *>(workspace);
+    PW_TRY(launch_adjoint_mode(a, dtype, cfg, grads, ws, s));
+    return launch_coeff_grad_reduce(ws, adjoint_strips(*grid, cfg.ry), grad, grid->nz, s);
+}
+
+}  // namespace
+}  // namespace pw
+
+extern "C" {
+
 pw_status pw_advect_coeff_grad_static(const pw_grid *grid, const pw_layout *layout, pw_dtype dtype,
                                       const void *u, const void *v, const void *w,
                                       const void *gsu, const void *gsv, const void *gsw,
@@ -536,13 +595,8 @@ pw_status pw_advect_coeff_grad_static(const pw_grid *grid, const pw_layout *layo
     PW_TRY(check_coeff_grad(grid, layout, dtype, u, v, w, gsu, gsv, gsw, grad, nullptr, 0, &L));
     void *ws = nullptr;
     PW_TRY(coeff_grad_scratch(&ws));
-    CgArgs a;
-    a.u = u; a.v = v; a.w = w;
-    a.gsu = gsu; a.gsv = gsv; a.gsw = gsw;
-    a.grad = grad; a.workspace = ws;
-    a.nx = grid->nx; a.ny = grid->ny; a.nz = grid->nz; a.h = grid->halo;
-    a.in_sy = L.in_sy; a.in_sz = L.in_sz; a.out_sy = L.out_sy; a.out_sz = L.out_sz;
-    return launch_coeff_grad(a, dtype, static_cast<hipStream_t>(hip_stream));
+    const AdjArgs a = coeff_grad_args(grid, L, u, v, w, gsu, gsv, gsw);
+    return run_coeff_grad(grid, dtype, a, false, grad, ws, static_cast<hipStream_t>(hip_stream));
 }
 
 pw_status pw_advect_coeff_grad(const pw_grid *grid, const pw_layout *layout, pw_dtype dtype,
@@ -553,13 +607,8 @@ pw_status pw_advect_coeff_grad(const pw_grid *grid, const pw_layout *layout, pw_
     if (!workspace) return fail(PW_ERR_INVALID_ARG, "workspace is NULL");
     Layout L;
     PW_TRY(check_coeff_grad(grid, layout, dtype, u, v, w, gsu, gsv, gsw, grad, workspace, workspace_bytes, &L));
-    CgArgs a;
-    a.u = u; a.v = v; a.w = w;
-    a.gsu = gsu; a.gsv = gsv; a.gsw = gsw;
-    a.grad = grad; a.workspace = workspace;
-    a.nx = grid->nx; a.ny = grid->ny; a.nz = grid->nz; a.h = grid->halo;
-    a.in_sy = L.in_sy; a.in_sz = L.in_sz; a.out_sy = L.out_sy; a.out_sz = L.out_sz;
-    return launch_coeff_grad(a, dtype, static_cast<hipStream_t>(hip_stream));
+    const AdjArgs a = coeff_grad_args(grid, L, u, v, w, gsu, gsv, gsw);
+    return run_coeff_grad(grid, dtype, a, false, grad, workspace, static_cast<hipStream_t>(hip_stream));
 }
 
 pw_status pw_advect_adjoint(const pw_grid *grid, const pw_layout *layout, pw_dtype dtype,
@@ -570,11 +619,13 @@ pw_status pw_advect_adjoint(const pw_grid *grid, const pw_layout *layout, pw_dty
                                 hip_stream);
 }
 
-pw_status pw_advect_adjoint_ex(const pw_grid *grid, const pw_layout *layout, pw_dtype dtype,
-                               const void *u, const void *v, const void *w, const pw_coeffs *coeffs,
-                               const void *gsu, const void *gsv, const void *gsw,
-                               void *gu, void *gv, void *gw, const pw_tile *tile, void *hip_stream) {
-    g_err[0] = 0;
+namespace {
+
+// Validation of the adjoint's operands; fills `a` and the resolved layout.
+pw_status check_adjoint(const pw_grid *grid, const pw_layout *layout, pw_dtype dtype,
+                        const void *u, const void *v, const void *w, const pw_coeffs *coeffs,
+                        const void *gsu, const void *gsv, const void *gsw,
+                        void *gu, void *gv, void *gw, const pw_tile *tile, AdjArgs *aout, Layout *Lout) {
     PW_TRY(check_grid(grid));
     if (dtype != PW_F32 && dtype != PW_F64) {
         if (elem_size(dtype)) return fail(PW_ERR_UNSUPPORTED, "adjoint supports PW_F32 and PW_F64 only");
@@ -614,12 +665,53 @@ pw_status pw_advect_adjoint_ex(const pw_grid *grid, const pw_layout *layout, pw_
     a.tcx = coeffs->tcx; a.tcy = coeffs->tcy;
     a.nx = grid->nx; a.ny = grid->ny; a.nz = grid->nz; a.h = grid->halo;
     a.in_sy = L.in_sy; a.in_sz = L.in_sz; a.out_sy = L.out_sy; a.out_sz = L.out_sz;
+    *aout = a;
+    *Lout = L;
+    return PW_OK;
+}
+
+}  // namespace
+
+pw_status pw_advect_adjoint_ex(const pw_grid *grid, const pw_layout *layout, pw_dtype dtype,
+                               const void *u, const void *v, const void *w, const pw_coeffs *coeffs,
+                               const void *gsu, const void *gsv, const void *gsw,
+                               void *gu, void *gv, void *gw, const pw_tile *tile, void *hip_stream) {
+    g_err[0] = 0;
+    AdjArgs a;
+    Layout L;
+    PW_TRY(check_adjoint(grid, layout, dtype, u, v, w, coeffs, gsu, gsv, gsw, gu, gv, gw, tile, &a, &L));
     TileCfg cfg;
     if (tile)
         cfg = to_cfg(*tile);
     else if (!lookup_tuned(TuneKind::Adjoint, grid, dtype, &cfg))
         cfg = default_adjoint_tile(a, dtype);
     return launch_adjoint(a, dtype, cfg, static_cast<hipStream_t>(hip_stream));
+}
+
+pw_status pw_advect_adjoint_coeff_grad(const pw_grid *grid, const pw_layout *layout, pw_dtype dtype,
+                                       const void *u, const void *v, const void *w, const pw_coeffs *coeffs,
+                                       const void *gsu, const void *gsv, const void *gsw,
+                                       void *gu, void *gv, void *gw, double *grad, void *workspace,
+                                       int64_t workspace_bytes, void *hip_stream) {
+    g_err[0] = 0;
+    if (!workspace) return fail(PW_ERR_INVALID_ARG, "workspace is NULL");
+    AdjArgs a;
+    Layout L;
+    PW_TRY(check_adjoint(grid, layout, dtype, u, v, w, coeffs, gsu, gsv, gsw, gu, gv, gw, nullptr, &a, &L));
+    Layout L2;
+    PW_TRY(check_coeff_grad(grid, layout, dtype, u, v, w, gsu, gsv, gsw, grad, workspace, workspace_bytes, &L2));
+    // grad and the workspace also stay apart from the wind gradients
+    const int64_t es = elem_size(dtype);
+    int64_t need = 0;
+    PW_TRY(pw_advect_coeff_grad_workspace(grid, dtype, &need));
+    const uintptr_t gb = reinterpret_cast<uintptr_t>(grad), wb = reinterpret_cast<uintptr_t>(workspace);
+    const Range rcg[2] = {{"grad", gb, gb + uintptr_t((6 * grid->nz + 2) * 8)}, {"workspace", wb, wb + uintptr_t(need)}};
+    const Range rg[3] = {in_range("gu", gu, grid, L, es), in_range("gv", gv, grid, L, es),
+                         in_range("gw", gw, grid, L, es)};
+    for (const Range &c : rcg)
+        for (const Range &o : rg)
+            if (overlap(c, o)) return fail(PW_ERR_INVALID_ARG, "%s overlaps %s", c.name, o.name);
+    return run_coeff_grad(grid, dtype, a, true, grad, workspace, static_cast<hipStream_t>(hip_stream));
 }
 
 }  // extern "C"

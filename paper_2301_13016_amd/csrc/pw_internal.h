@@ -68,16 +68,6 @@ struct TanArgs {
     const void *du, *dv, *dw;
 };
 
-// Operands of one coefficient-gradient call (validated).  grad: 6*nz + 2
-// doubles; workspace: coeff_grad_workspace_bytes() bytes.
-struct CgArgs {
-    const void *u, *v, *w;
-    const void *gsu, *gsv, *gsw;
-    void *grad, *workspace;
-    int64_t nx, ny, nz;
-    int32_t h;
-    int64_t in_sy, in_sz, out_sy, out_sz;
-};
 
 // Operands of one halo fill (validated): up to kMaxHaloFields distinct
 // padded arrays of element size es sharing one layout, with per-field x, y, z
@@ -115,9 +105,19 @@ pw_status launch_forward_lds_f64(const FwdArgs &a, const TileCfg &cfg, hipStream
 pw_status launch_forward_lds_bf16(const FwdArgs &a, const TileCfg &cfg, hipStream_t s);
 pw_status launch_forward_lds_f16(const FwdArgs &a, const TileCfg &cfg, hipStream_t s);
 pw_status launch_adjoint(const AdjArgs &a, pw_dtype dt, const TileCfg &cfg, hipStream_t s);
+// The adjoint march computing the wind gradients (grads), the per-strip
+// coefficient partials (partials != NULL: [6][nz][adjoint_strips(g, cfg.ry)]
+// doubles), or both in one pass; the coefficient fields of `a` are only read
+// for the gradients.
+pw_status launch_adjoint_mode(const AdjArgs &a, pw_dtype dt, const TileCfg &cfg, bool grads, double *partials,
+                              hipStream_t s);
+int64_t adjoint_strips(const pw_grid &g, int ry);
 pw_status launch_tangent(const TanArgs &a, pw_dtype dt, const TileCfg &cfg, hipStream_t s);
 int64_t coeff_grad_workspace_bytes(const pw_grid &g, pw_dtype dt);
-pw_status launch_coeff_grad(const CgArgs &a, pw_dtype dt, hipStream_t s);
+// Passes 2 and 3 of the coefficient gradients: grad (6*nz + 2 doubles) from
+// the partials of nstrips strips.
+pw_status launch_coeff_grad_reduce(const double *partials, int64_t nstrips, double *grad, int64_t nz,
+                                   hipStream_t s);
 // Size of the library's own coefficient-gradient scratch, and its address on
 // the current device (looked up once per device, no allocation).
 constexpr int64_t kCoeffGradScratchBytes = PW_COEFF_GRAD_STATIC_MAX_BYTES;

@@ -395,10 +395,14 @@ def test_coeff_grad_validation(lib):
     g, c, p = _args()
     need = ctypes.c_int64()
     assert lib.pw_advect_coeff_grad_workspace(ctypes.byref(g), B.PW_F32, ctypes.byref(need)) == B.PW_OK
-    # FP32: strips of 128 columns x 2 rows -> 1 x 4 strips; 6 quantities x 8 levels x 4 strips doubles
-    assert need.value == 6 * 8 * 4 * 8
+    # the adjoint's strips of 62 padded columns, for one-row strips (the most
+    # strips): 10 padded columns -> 1 x 10 strips; 6 quantities x 8 levels
+    assert need.value == 6 * 8 * 10 * 8
     assert lib.pw_advect_coeff_grad_workspace(ctypes.byref(g), B.PW_F64, ctypes.byref(need)) == B.PW_OK
-    assert need.value == 6 * 8 * 4 * 8
+    assert need.value == 6 * 8 * 10 * 8
+    g2 = B.pw_grid(123, 5, 3, 2)              # 127 padded columns -> 3 strips of 62; 9 padded rows
+    assert lib.pw_advect_coeff_grad_workspace(ctypes.byref(g2), B.PW_F32, ctypes.byref(need)) == B.PW_OK
+    assert need.value == 6 * 3 * 3 * 9 * 8
     assert lib.pw_advect_coeff_grad_workspace(ctypes.byref(g), B.PW_BF16, ctypes.byref(need)) == B.PW_ERR_UNSUPPORTED
     assert lib.pw_advect_coeff_grad_workspace(ctypes.byref(g), B.PW_F32, None) == B.PW_ERR_INVALID_ARG
     q = [A + i * MB for i in range(8)]   # u v w gsu gsv gsw grad workspace
@@ -428,14 +432,14 @@ def test_coeff_grad_static_validation(lib):
     bad = list(q); bad[6] = q[6] + 4          # grad not 8-byte aligned
     assert call(g, bad) == B.PW_ERR_INVALID_ARG
     assert call(g, q, B.PW_BF16) == B.PW_ERR_UNSUPPORTED
-    # 2048 x 2048 x 256 FP32: 16 x 1024 strips x 6 x 256 levels x 8 B = 192 MiB of partials
+    # 2048 x 2048 x 256 FP32: 34 x 2050 strips x 6 x 256 levels x 8 B = 816 MiB of partials
     big = B.pw_grid(2048, 2048, 256, 1)
     need = ctypes.c_int64()
     assert lib.pw_advect_coeff_grad_workspace(ctypes.byref(big), B.PW_F32, ctypes.byref(need)) == B.PW_OK
     assert need.value > 16 << 20
     assert call(big, q) == B.PW_ERR_UNSUPPORTED and "static scratch" in B.pw_last_error()
-    # the largest grid class that fits: 16 MiB / (6 * 8 B) partials per level and strip
-    edge = B.pw_grid(256, 256, 128 * 4, 1)    # 2 x 128 strips x 512 levels x 48 B = 6 MiB
+    # a grid that fits: 16 MiB / (6 * 8 B) partials per level and strip
+    edge = B.pw_grid(256, 256, 128 * 2, 1)    # 5 x 258 strips x 256 levels x 48 B = 15.1 MiB
     far = [A + i * (1 << 30) for i in range(7)]   # 1 GiB apart: no array overlaps another
     st = call(edge, far)
     assert st in _no_gpu_status() and "static scratch" not in B.pw_last_error()

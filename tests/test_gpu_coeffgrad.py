@@ -166,3 +166,113 @@ def test_coeff_grad_argument_errors():
     r = [torch.zeros((4, 8, 20), device="cuda") for _ in range(3)]
     with pytest.raises(B.PWError):
         B.advect_coeff_grad(*(x.to(torch.bfloat16) for x in (u, v, w)), *(x.to(torch.bfloat16) for x in r))
+
+
+# ------------------------------------------------- fused backward (one pass)
+
+def _same_bits(a, b):
+    it = {torch.float32: torch.int32, torch.float64: torch.int64}[a.dtype]
+    return a.dtype == b.dtype and a.shape == b.shape and torch.equal(a.view(it), b.view(it))
+
+
+@pytest.mark.parametrize("case", [(130, 70, 20, np.float32, 1), (1, 1, 1, np.float32, 1), (129, 5, 2, np.float32, 1),
+                                  (61, 9, 17, np.float64, 1), (70, 9, 6, np.float32, 2), (257, 3, 4, np.float64, 1)],
+                         ids=lambda c: "%dx%dx%d_%s_h%d" % (c[0], c[1], c[2], np.dtype(c[3]).name, c[4]))
+def test_fused_backward_equals_separate_calls(case):
+    """pw_advect_adjoint_coeff_grad: wind gradients bit for bit those of
+    advect_adjoint, coefficient gradients bit for bit those of
+    advect_coeff_grad, both within the oracle bounds."""
+    nx, ny, nz, dt, halo = case
+    g = wl.make_grid(nx, ny, nz, seed=980 + nx, dtype=dt, halo=halo)
+    r = wl.cotangents(nx, ny, nz, seed=981 + nx, dtype=dt)
+    (u, v, w), c = dev_grid(g)
+    rd = _dev(r, u.dtype)
+    (gu, gv, gw), cg = B.advect_adjoint_coeff_grad(u, v, w, c, *rd, halo=halo)
+    ref_w = B.advect_adjoint(u, v, w, c, *rd, halo=halo)
+    ref_c = B.advect_coeff_grad(u, v, w, *rd, halo=halo)
+    torch.cuda.synchronize()
+    for a, b in zip((gu, gv, gw), ref_w):
+        assert _same_bits(a, b)
+    for n in ("tcx", "tcy", "tcx_level", "tcy_level") + NAMES:
+        assert _same_bits(cg[n], ref_c[n]), n
+    # oracle: coefficients (as in check) and winds
+    rq = [np.asarray(x, dt).astype(np.float64) for x in r]
+    refc = oracle.coeff_grad(g.u, g.v, g.w, *rq, halo=halo)
+    mag = magnitudes(g, rq)
+    tol = 1e-6 if dt == np.float32 else 1e-13
+    for n in ("tcx", "tcy") + NAMES:
+        assert np.all(np.abs(cg[n].cpu().numpy() - refc[n]) <= tol * mag[n]), n
+    from gpu_util import adjoint_scale
+    refw = oracle.adjoint(g.u, g.v, g.w, g.coeffs, *rq, halo=halo)
+    scale = adjoint_scale(g.u, g.v, g.w, g.coeffs, rq, halo=halo)
+    for a, b, s in zip((gu, gv, gw), refw, scale):
+        assert np.all(np.abs(a.cpu().numpy() - b) <= tol * s)
+
+
+def test_fused_backward_tile_independent_winds_and_reproducible():
+    """Every adjoint launch shape gives the same wind gradients in the fused
+    pass as alone; two fused calls agree bit for bit."""
+    g = wl.make_grid(150, 21, 13, seed=990)
+    r = wl.cotangents(150, 21, 13, seed=991)
+    (u, v, w), c = dev_grid(g)
+    rd = _dev(r, u.dtype)
+    (a1, b1, c1), cg1 = B.advect_adjoint_coeff_grad(u, v, w, c, *rd)
+    (a2, b2, c2), cg2 = B.advect_adjoint_coeff_grad(u, v, w, c, *rd)
+    torch.cuda.synchronize()
+    for x, y in zip((a1, b1, c1), (a2, b2, c2)):
+        assert _same_bits(x, y)
+    for n in cg1:
+        assert _same_bits(cg1[n], cg2[n])
+    for tile in [(1, 1, 5, 1, 1), (1, 2, 9, 4, 2), (1, 4, 64, 8, 1)]:
+        alone = B.advect_adjoint(u, v, w, c, *rd, tile=tile)
+        torch.cuda.synchronize()
+        for x, y in zip((a1, b1, c1), alone):
+            assert _same_bits(x, y), tile
+
+
+def test_fused_backward_nan_in_unread_cells():
+    """Non-finite values in cells no output reads reach neither the wind nor
+    the coefficient gradients of the fused pass."""
+    from gpu_util import poison_unread
+    g = wl.make_grid(70, 11, 6, seed=992)
+    r = wl.cotangents(70, 11, 6, seed=993)
+    (u, v, w), c = dev_grid(g)
+    clean = B.advect_adjoint_coeff_grad(u, v, w, c, *_dev(r, u.dtype))
+    poison_unread(g)
+    (u, v, w), c = dev_grid(g)
+    dirty = B.advect_adjoint_coeff_grad(u, v, w, c, *_dev(r, u.dtype))
+    torch.cuda.synchronize()
+    for x, y in zip(clean[0], dirty[0]):
+        assert torch.equal(x, y)
+    for n in clean[1]:
+        assert torch.equal(clean[1][n], dirty[1][n])
+
+
+def test_c4_fused_backward_time(report):
+    """256 x 256 x 128 FP32: the fused backward against the adjoint alone and
+    the two separate calls (timed, reported)."""
+    cfg = wl.C4
+    g = wl.config_grid(cfg)
+    r = wl.cotangents(cfg["nx"], cfg["ny"], cfg["nz"], cfg["cot_seed"])
+    (u, v, w), c = dev_grid(g)
+    rd = _dev(r, u.dtype)
+    outs = tuple(torch.empty_like(u) for _ in range(3))
+    gout = torch.empty(6 * g.nz + 2, dtype=torch.float64, device="cuda")
+
+    def timed(fn, n=50):
+        for _ in range(5):
+            fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(n):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / n
+
+    t_fused = timed(lambda: B.advect_adjoint_coeff_grad(u, v, w, c, *rd, out=outs, grad_out=gout))
+    t_adj = timed(lambda: B.advect_adjoint(u, v, w, c, *rd, out=outs))
+    t_cg = timed(lambda: B.advect_coeff_grad(u, v, w, *rd, out=gout))
+    report["fused_backward_f32_256x256x128_ms"] = dict(fused=round(t_fused, 4), adjoint=round(t_adj, 4),
+                                                       coeff_grad=round(t_cg, 4),
+                                                       fused_over_adjoint=round(t_fused / t_adj, 3))

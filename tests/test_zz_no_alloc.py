@@ -111,7 +111,7 @@ def test_static_scratch_equals_workspace_entry_point(dtype):
 
 def test_static_scratch_rejects_oversized_grids():
     g, r, x, rd = _case(40, 8, 4, seed=970, dtype=np.float32)
-    grid = B.pw_grid(4096, 2048, 64, 1)   # 32 x 1024 strips x 64 levels x 48 B = 96 MiB of partials
+    grid = B.pw_grid(4096, 2048, 64, 1)   # 67 x 2050 strips x 64 levels x 48 B = 403 MiB of partials
     layout = B.pw_layout(4098, 4098 * 2050, 4096, 4096 * 2048)
     out = torch.empty(6 * 64 + 2, dtype=torch.float64, device="cuda")
     st = B.pw_advect_coeff_grad_static(grid, layout, B.PW_F32, *(t.data_ptr() for t in x),

@@ -23,28 +23,18 @@
 // meet zero cotangents, and zeroing them keeps a non-finite value there
 // (0 * NaN = NaN) out of the gradient.
 #include "pw_internal.h"
+#include "pw_lanes.h"
 #include "pw_reduce.h"
 
 namespace pw {
 namespace {
 
-constexpr int kWaveShr1 = 0x138;   // lane l <- lane l-1
-constexpr int kWaveShl1 = 0x130;   // lane l <- lane l+1
-
-template <int Ctrl> __device__ __forceinline__ float wave_shift(float x) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), Ctrl, 0xf, 0xf, true));
-}
-template <int Ctrl> __device__ __forceinline__ double wave_shift(double x) {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), Ctrl, 0xf, 0xf, true);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), Ctrl, 0xf, 0xf, true);
-    return __hiloint2double(hi, lo);
-}
-template <typename T> __device__ __forceinline__ T from_left(T x) { return wave_shift<kWaveShr1>(x); }
-template <typename T> __device__ __forceinline__ T from_right(T x) { return wave_shift<kWaveShl1>(x); }
-
-template <typename T> __device__ __forceinline__ T fma_(T a, T b, T c);
-template <> __device__ __forceinline__ float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
-template <> __device__ __forceinline__ double fma_(double a, double b, double c) { return __builtin_fma(a, b, c); }
+using lanes::fma_;
+using lanes::kWaveShl1;
+using lanes::kWaveShr1;
+using lanes::wave_shift;
+template <typename T> __device__ __forceinline__ T from_left(T x) { return wave_shift<kWaveShr1>(x); }   // lane l-1
+template <typename T> __device__ __forceinline__ T from_right(T x) { return wave_shift<kWaveShl1>(x); }  // lane l+1
 
 template <typename T> struct AdjK {
     const T *u, *v, *w;

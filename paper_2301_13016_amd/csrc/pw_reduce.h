@@ -5,6 +5,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include "pw_lanes.h"
+
 namespace pw {
 namespace red {
 
@@ -20,11 +22,7 @@ constexpr int kQuadXor2 = 0x4E;   // quad_perm [2,3,0,1]
 constexpr int kRowRor4 = 0x124;   // rotate by 4 within a row of 16 lanes
 constexpr int kRowRor8 = 0x128;   // rotate by 8
 
-__device__ __forceinline__ double lane_value(double x, int lane) {
-    const int lo = __builtin_amdgcn_readlane(__double2loint(x), lane);
-    const int hi = __builtin_amdgcn_readlane(__double2hiint(x), lane);
-    return __hiloint2double(hi, lo);
-}
+using lanes::lane_value;
 
 // Pairs and quads (quad permutations), the four quads of each 16-lane row
 // (row rotations), then the four row sums in a fixed order.  All register

@@ -4,6 +4,7 @@
 #pragma once
 
 #include "pw_internal.h"
+#include "pw_lanes.h"
 
 namespace pw {
 namespace dev {
@@ -55,28 +56,13 @@ __device__ __forceinline__ T comp(const typename Vec<T, N>::type &v, int m) {
 }
 
 // ------------------------------------------------------- cross-lane moves
-// DPP controls (GFX9 family): wave_shr:1 moves lane l-1 into lane l,
-// wave_shl:1 moves lane l+1 into lane l (bound_ctrl: the lane with no source
-// reads 0 and is patched from the halo).
-constexpr int kWaveShr1 = 0x138;
-constexpr int kWaveShl1 = 0x130;
+// Cross-lane moves (pw_lanes.h): wave_shr:1 / wave_shl:1 DPP shifts, in
+// which the lane with no source reads 0 and is patched from the halo.
+using lanes::kWaveShl1;
+using lanes::kWaveShr1;
+using lanes::lane_value;
+using lanes::wave_shift;
 
-template <int Ctrl> __device__ __forceinline__ float wave_shift(float x) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), Ctrl, 0xf, 0xf, true));
-}
-template <int Ctrl> __device__ __forceinline__ double wave_shift(double x) {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), Ctrl, 0xf, 0xf, true);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), Ctrl, 0xf, 0xf, true);
-    return __hiloint2double(hi, lo);
-}
-__device__ __forceinline__ float lane_value(float x, int lane) {
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), lane));
-}
-__device__ __forceinline__ double lane_value(double x, int lane) {
-    const int lo = __builtin_amdgcn_readlane(__double2loint(x), lane);
-    const int hi = __builtin_amdgcn_readlane(__double2hiint(x), lane);
-    return __hiloint2double(hi, lo);
-}
 // Column left of this lane's first column: the previous lane's last value,
 // or for lane 0 the strip's left halo (held by lane `row` of `halo`).
 template <typename T> __device__ __forceinline__ T left_of(T last, T halo, int row, bool lane0) {
@@ -116,9 +102,7 @@ template <typename T> __device__ __forceinline__ T uniform_load(const T *p, int 
 // it does not displace the y-halo rows that neighbouring strips re-read from L2.
 #define PW_GLOAD_NT(V, p) __builtin_nontemporal_load((const __attribute__((address_space(1))) V *)(p))
 
-template <typename T> __device__ __forceinline__ T fma_(T a, T b, T c);
-template <> __device__ __forceinline__ float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
-template <> __device__ __forceinline__ double fma_(double a, double b, double c) { return __builtin_fma(a, b, c); }
+using lanes::fma_;
 
 // --------------------------------------------------------- kernel operands
 template <typename Tin> struct FwdK {

@@ -508,7 +508,10 @@ pw_status pw_advect_bc(const pw_grid *grid, const pw_layout *layout, pw_dtype in
 const char *pw_version(void);
 
 /* Message for the last non-OK status returned on the calling thread
- * (static per-thread storage; "" if none). */
+ * (static per-thread storage; "" if none).  With the environment variable
+ * PWADV_LOG set (and not "0"), every launching call also prints one line on
+ * stderr: the entry point, grid, storage type, launch shape and whether the
+ * shape was given, tuned, the default or a fixed rule. */
 const char *pw_last_error(void);
 
 /* Measurement helper: a plain vectorised device-to-device copy of `nbytes`

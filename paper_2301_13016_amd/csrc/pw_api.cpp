@@ -3,6 +3,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 
 #include "pw_internal.h"
@@ -22,6 +23,30 @@ pw_status fail(pw_status st, const char *fmt, ...) {
 pw_status hip_fail(hipError_t e, const char *what) {
     if (e == hipSuccess) return PW_OK;
     return fail(PW_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+// PWADV_LOG (set and not "0"): one line on stderr per launch -- entry point,
+// grid, storage type, launch shape and where the shape came from.  Read once
+// per process.
+static bool log_enabled() {
+    static const bool on = [] {
+        const char *e = std::getenv("PWADV_LOG");
+        return e != nullptr && e[0] != '\0' && std::strcmp(e, "0") != 0;
+    }();
+    return on;
+}
+
+void log_launch(const char *entry, const pw_grid *g, pw_dtype dt, const TileCfg *c, const char *how) {
+    if (!log_enabled()) return;
+    static const char *names[] = {"f32", "f64", "bf16", "f16"};
+    const char *dn = (dt >= PW_F32 && dt <= PW_F16) ? names[dt] : "?";
+    if (c)
+        std::fprintf(stderr, "pwadv: %s %lldx%lldx%lld halo %d %s tile (%d, %d, %d, %d, %d, %d) %s\n", entry,
+                     (long long)g->nx, (long long)g->ny, (long long)g->nz, g->halo, dn, c->px, c->ry, c->zlen, c->wpb,
+                     c->depth, c->share, how);
+    else
+        std::fprintf(stderr, "pwadv: %s %lldx%lldx%lld halo %d %s %s\n", entry, (long long)g->nx, (long long)g->ny,
+                     (long long)g->nz, g->halo, dn, how);
 }
 
 namespace {
@@ -358,10 +383,14 @@ pw_status advect_general(const pw_grid *grid, const pw_layout *layout, pw_dtype 
         PW_TRY(check_forward_on_device(a));
     }
     TileCfg cfg;
+    const char *how = "given";
     if (tile)
         cfg = to_cfg(*tile);
-    else if (!lookup_tuned(TuneKind::Forward, grid, in_dtype, &cfg))
-        cfg = default_forward_tile(a, in_dtype);
+    else if (lookup_tuned(TuneKind::Forward, grid, in_dtype, &cfg))
+        how = "tuned";
+    else
+        cfg = default_forward_tile(a, in_dtype), how = "default";
+    log_launch(bc ? "pw_advect_bc" : "pw_advect_epilogue", grid, in_dtype, &cfg, how);
     return launch_forward(a, in_dtype, cfg, static_cast<hipStream_t>(hip_stream));
 }
 
@@ -394,10 +423,14 @@ pw_status pw_advect_ex(const pw_grid *grid, const pw_layout *layout, pw_dtype in
                     tile->share_rows);
     PW_TRY(check_forward_on_device(a));
     TileCfg cfg;
+    const char *how = "given";
     if (tile)
         cfg = to_cfg(*tile);
-    else if (!lookup_tuned(TuneKind::Forward, grid, in_dtype, &cfg))
-        cfg = default_forward_tile(a, in_dtype);
+    else if (lookup_tuned(TuneKind::Forward, grid, in_dtype, &cfg))
+        how = "tuned";
+    else
+        cfg = default_forward_tile(a, in_dtype), how = "default";
+    log_launch("pw_advect", grid, in_dtype, &cfg, how);
     return launch_forward(a, in_dtype, cfg, static_cast<hipStream_t>(hip_stream));
 }
 
@@ -462,10 +495,14 @@ pw_status pw_advect_tangent_ex(const pw_grid *grid, const pw_layout *layout, pw_
     a.dv = dv;
     a.dw = dw;
     TileCfg cfg;
+    const char *how = "given";
     if (tile)
         cfg = to_cfg(*tile);
-    else if (!lookup_tuned(TuneKind::Tangent, grid, dtype, &cfg))
-        cfg = default_tangent_tile(a, dtype);
+    else if (lookup_tuned(TuneKind::Tangent, grid, dtype, &cfg))
+        how = "tuned";
+    else
+        cfg = default_tangent_tile(a, dtype), how = "default";
+    log_launch("pw_advect_tangent", grid, dtype, &cfg, how);
     return launch_tangent(a, dtype, cfg, static_cast<hipStream_t>(hip_stream));
 }
 
@@ -576,6 +613,7 @@ AdjArgs coeff_grad_args(const pw_grid *grid, const Layout &L, const void *u, con
 pw_status run_coeff_grad(const pw_grid *grid, pw_dtype dtype, const AdjArgs &a, bool grads, double *grad,
                          void *workspace, hipStream_t s) {
     const TileCfg cfg = coeff_grad_tile(grid, dtype);
+    log_launch(grads ? "pw_advect_adjoint_coeff_grad" : "pw_advect_coeff_grad", grid, dtype, &cfg, "shape rule");
     double *ws = static_cast<double *>(workspace);
     PW_TRY(launch_adjoint_mode(a, dtype, cfg, grads, ws, s));
     return launch_coeff_grad_reduce(ws, adjoint_strips(*grid, cfg.ry), grad, grid->nz, s);
@@ -681,10 +719,14 @@ pw_status pw_advect_adjoint_ex(const pw_grid *grid, const pw_layout *layout, pw_
     Layout L;
     PW_TRY(check_adjoint(grid, layout, dtype, u, v, w, coeffs, gsu, gsv, gsw, gu, gv, gw, tile, &a, &L));
     TileCfg cfg;
+    const char *how = "given";
     if (tile)
         cfg = to_cfg(*tile);
-    else if (!lookup_tuned(TuneKind::Adjoint, grid, dtype, &cfg))
-        cfg = default_adjoint_tile(a, dtype);
+    else if (lookup_tuned(TuneKind::Adjoint, grid, dtype, &cfg))
+        how = "tuned";
+    else
+        cfg = default_adjoint_tile(a, dtype), how = "default";
+    log_launch("pw_advect_adjoint", grid, dtype, &cfg, how);
     return launch_adjoint(a, dtype, cfg, static_cast<hipStream_t>(hip_stream));
 }
 
@@ -778,10 +820,14 @@ pw_status launch_zfast_tuned(const pw_grid *grid, pw_dtype in_dtype, const FwdAr
                              void *hip_stream) {
     PW_TRY(check_forward_on_device(a));
     TileCfg cfg;
+    const char *how = "given";
     if (tile)
         cfg = to_cfg(*tile);
-    else if (!lookup_tuned(TuneKind::Zfast, grid, in_dtype, &cfg))
-        cfg = default_zfast_tile(a, in_dtype);
+    else if (lookup_tuned(TuneKind::Zfast, grid, in_dtype, &cfg))
+        how = "tuned";
+    else
+        cfg = default_zfast_tile(a, in_dtype), how = "default";
+    log_launch(a.epilogue ? "pw_advect_zfast_epilogue" : "pw_advect_zfast", grid, in_dtype, &cfg, how);
     return launch_zfast(a, in_dtype, cfg, static_cast<hipStream_t>(hip_stream));
 }
 
@@ -841,6 +887,7 @@ pw_status pw_halo_fill(const pw_grid *grid, const pw_layout *layout, pw_dtype dt
     g_err[0] = 0;
     HaloArgs a{};
     PW_TRY(validate_halo(grid, layout, dtype, fields, modes, nfields, &a));
+    log_launch("pw_halo_fill", grid, dtype, nullptr, nfields == 1 ? "1 field" : "several fields");
     return launch_halo(a, static_cast<hipStream_t>(hip_stream));
 }
 
@@ -851,6 +898,7 @@ pw_status pw_halo_fold(const pw_grid *grid, const pw_layout *layout, pw_dtype dt
         return fail(PW_ERR_UNSUPPORTED, "the halo fold (a gradient operation) supports PW_F32 and PW_F64 only");
     HaloArgs a{};
     PW_TRY(validate_halo(grid, layout, dtype, fields, modes, nfields, &a));
+    log_launch("pw_halo_fold", grid, dtype, nullptr, nfields == 1 ? "1 field" : "several fields");
     return launch_halo_fold(a, static_cast<hipStream_t>(hip_stream));
 }
 

@@ -159,5 +159,7 @@ void store_tuned(TuneKind kind, const pw_grid *grid, pw_dtype dt, const TileCfg 
 // Error plumbing (pw_api.cpp).
 pw_status fail(pw_status st, const char *fmt, ...);
 pw_status hip_fail(hipError_t e, const char *what);
+// Host-side logging (environment PWADV_LOG): one line per launch on stderr.
+void log_launch(const char *entry, const pw_grid *g, pw_dtype dt, const TileCfg *c, const char *how);
 
 }  // namespace pw

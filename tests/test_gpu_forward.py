@@ -11,6 +11,7 @@ which bounds the rounding error of any evaluation order):
 Integer winds with dyadic coefficients are exact in every dtype, so there the
 comparison is bit for bit.
 """
+import os
 import sys
 
 import numpy as np
@@ -20,6 +21,8 @@ import oracle
 from gpu_util import dev_grid, full_grid_errors, oracle_errors, poison_unread
 from paper_2301_13016_amd import binding as B
 from paper_2301_13016_amd import workloads as wl
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -378,3 +381,41 @@ def test_stream_copies_are_exact():
     for a, b in zip(src, dst):
         assert torch.equal(a, b)
     assert torch.equal(one, src[1])
+
+
+def test_pwadv_log_prints_one_line_per_launch():
+    """PWADV_LOG=1: each launching call prints its entry point, grid, storage
+    type, launch shape and the shape's source on stderr (in a child process,
+    since the switch is read once per process)."""
+    import subprocess
+    import textwrap
+    code = textwrap.dedent("""
+        import sys
+        sys.path.insert(0, %r)
+        import numpy as np, torch
+        from paper_2301_13016_amd import binding as B
+        from paper_2301_13016_amd import workloads as wl
+        g = wl.make_grid(70, 9, 5, seed=1)
+        x = [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in (g.u, g.v, g.w)]
+        c = B.Coeffs.from_host(g.coeffs, device="cuda")
+        B.advect(*x, c)
+        B.advect(*x, c, tile=(2, 2, 5, 4))
+        r = [torch.ones((5, 9, 70), device="cuda") for _ in range(3)]
+        B.advect_adjoint(*x, c, *r)
+        B.advect_coeff_grad(*x, *r)
+        B.halo_fill(x, ("periodic", "periodic", "copy"))
+        torch.cuda.synchronize()
+    """) % ROOT
+    env = dict(os.environ, PWADV_LOG="1")
+    p = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=120)
+    assert p.returncode == 0, p.stderr[-2000:]
+    lines = [ln for ln in p.stderr.splitlines() if ln.startswith("pwadv: ")]
+    assert any(ln.startswith("pwadv: pw_advect 70x9x5 halo 1 f32 tile (") and ln.endswith(("default", "tuned"))
+               for ln in lines), lines
+    assert any("pw_advect 70x9x5 halo 1 f32 tile (2, 2, 5, 4, 1, 0) given" in ln for ln in lines), lines
+    assert any(ln.startswith("pwadv: pw_advect_adjoint 70x9x5") for ln in lines), lines
+    assert any(ln.startswith("pwadv: pw_advect_coeff_grad 70x9x5") and ln.endswith("shape rule") for ln in lines)
+    assert any(ln.startswith("pwadv: pw_halo_fill 70x9x5 halo 1 f32") for ln in lines), lines
+    env.pop("PWADV_LOG")
+    q = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=120)
+    assert q.returncode == 0 and "pwadv: " not in q.stderr

@@ -288,7 +288,7 @@ __device__ __forceinline__ void adj_level(const APlane<T, RY> &m, const APlane<T
 // tzd1 / tzd2: the w terms, tcx / tcy: the x- and y-face terms) are formed
 // from the planes and rows the adjoint already holds, summed per lane over
 // the strip's rows in the compute type, then over the wavefront in FP64 in a
-// fixed order, and stored as ws[q][kk][strip].  The strips are the adjoint's
+// fixed order (red::wave_sum6), and stored as ws[q][kk][strip].  The strips are the adjoint's
 // (62 columns x RY rows), so a partial does not depend on whether the
 // gradients are computed in the same pass.  Points outside the interior, and
 // lanes 0 and 63, are selected away (not multiplied by a zero cotangent: a
@@ -297,7 +297,7 @@ constexpr int kQ = 6;
 template <typename T, int RY>
 __device__ __forceinline__ void cg_level(const APlane<T, RY> &m, const APlane<T, RY> &c, const APlane<T, RY> &p,
                                          const AdjK<T> &a, const StripAddr<T, RY> &s, int kp, bool lane_ok,
-                                         int strip, bool lane0) {
+                                         int strip) {
     if (!c.zok) return;   // a halo level (wave-uniform)
     T fy[RY + 1];
 #pragma unroll
@@ -334,11 +334,15 @@ __device__ __forceinline__ void cg_level(const APlane<T, RY> &m, const APlane<T,
         sq[5] += ok ? fma_(ra, ay, fma_(rb, by, re * cy)) : T(0);
     }
     const int kk = kp - a.h;
+    double qd[kQ];
 #pragma unroll
-    for (int q = 0; q < kQ; ++q) {
-        const double t = red::wave_sum(static_cast<double>(sq[q]));
-        if (lane0) a.ws[(static_cast<int64_t>(q) * a.nz + kk) * (static_cast<int64_t>(a.ntx) * a.nty) + strip] = t;
-    }
+    for (int q = 0; q < kQ; ++q) qd[q] = static_cast<double>(sq[q]);
+    // one wavefront sum for all six (every lane ends with one quantity's total)
+    const double t = red::wave_sum6(qd);
+    const int lane = static_cast<int>(threadIdx.x & 63);
+    const int q = red::sum6_quantity(lane);
+    if (lane < 8 && q < kQ)
+        a.ws[(static_cast<int64_t>(q) * a.nz + kk) * (static_cast<int64_t>(a.ntx) * a.nty) + strip] = t;
 }
 
 __device__ __forceinline__ int xcd_tile(int b, int nb) {
@@ -408,12 +412,11 @@ __global__ __launch_bounds__(MaxT) void pw_adjoint_kernel(AdjK<T> a) {
     // join two paths with different loads in flight, and the wait at the join
     // drains the prefetch.
     const int strip = ty * a.ntx + tx;
-    const bool lane0 = lane == 0;
 #define PW_ALEVEL(M, C, P)                                                                    \
     do {                                                                                      \
         mask_aplane<T, RY>(P, s);   /* first use of plane k+1 */                              \
         if constexpr (Mode & kModeGrad) adj_level<T, RY>(M, C, P, a, s, k, lane_ok, goff, row_ok); \
-        if constexpr (Mode & kModeCg) cg_level<T, RY>(M, C, P, a, s, k, lane_ok, strip, lane0);    \
+        if constexpr (Mode & kModeCg) cg_level<T, RY>(M, C, P, a, s, k, lane_ok, strip);           \
     } while (0)
     int k = k0;
     if constexpr (Depth == 1) {

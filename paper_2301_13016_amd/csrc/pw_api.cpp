@@ -526,7 +526,8 @@ namespace {
 pw_status check_coeff_grad(const pw_grid *grid, const pw_layout *layout, pw_dtype dtype,
                            const void *u, const void *v, const void *w,
                            const void *gsu, const void *gsv, const void *gsw,
-                           double *grad, void *workspace, int64_t workspace_bytes, Layout *Lout) {
+                           double *grad, void *workspace, int64_t workspace_bytes, Layout *Lout,
+                           bool device = true) {
     int64_t need = 0;
     PW_TRY(pw_advect_coeff_grad_workspace(grid, dtype, &need));
     const int64_t es = elem_size(dtype);
@@ -555,10 +556,11 @@ pw_status check_coeff_grad(const pw_grid *grid, const pw_layout *layout, pw_dtyp
         for (const Range &i : rin)
             if (overlap(rout[o], i)) return fail(PW_ERR_INVALID_ARG, "%s overlaps %s", rout[o].name, i.name);
     if (!own && overlap(rout[0], rout[1])) return fail(PW_ERR_INVALID_ARG, "grad overlaps workspace");
+    *Lout = L;
+    if (!device) return PW_OK;
     int dev = 0;
     PW_TRY(current_device(&dev));
     for (int i = 0; i < nptr; ++i) PW_TRY(check_on_device(names[i], ptrs[i], dev));
-    *Lout = L;
     return PW_OK;
 }
 
@@ -663,7 +665,8 @@ namespace {
 pw_status check_adjoint(const pw_grid *grid, const pw_layout *layout, pw_dtype dtype,
                         const void *u, const void *v, const void *w, const pw_coeffs *coeffs,
                         const void *gsu, const void *gsv, const void *gsw,
-                        void *gu, void *gv, void *gw, const pw_tile *tile, AdjArgs *aout, Layout *Lout) {
+                        void *gu, void *gv, void *gw, const pw_tile *tile, AdjArgs *aout, Layout *Lout,
+                        bool device = true) {
     PW_TRY(check_grid(grid));
     if (dtype != PW_F32 && dtype != PW_F64) {
         if (elem_size(dtype)) return fail(PW_ERR_UNSUPPORTED, "adjoint supports PW_F32 and PW_F64 only");
@@ -691,9 +694,11 @@ pw_status check_adjoint(const pw_grid *grid, const pw_layout *layout, pw_dtype d
     if (tile && !adjoint_tile_supported(to_cfg(*tile)))
         return fail(PW_ERR_INVALID_ARG, "unsupported adjoint tile cols=%d rows=%d zlen=%d waves=%d prefetch=%d",
                     tile->cols_per_lane, tile->rows_per_strip, tile->zlen, tile->waves_per_group, tile->prefetch);
-    int dev = 0;
-    PW_TRY(current_device(&dev));
-    for (int i = 0; i < 13; ++i) PW_TRY(check_on_device(names[i], ptrs[i], dev));
+    if (device) {
+        int dev = 0;
+        PW_TRY(current_device(&dev));
+        for (int i = 0; i < 13; ++i) PW_TRY(check_on_device(names[i], ptrs[i], dev));
+    }
 
     AdjArgs a;
     a.u = u; a.v = v; a.w = w;
@@ -737,11 +742,14 @@ pw_status pw_advect_adjoint_coeff_grad(const pw_grid *grid, const pw_layout *lay
                                        int64_t workspace_bytes, void *hip_stream) {
     g_err[0] = 0;
     if (!workspace) return fail(PW_ERR_INVALID_ARG, "workspace is NULL");
+    // every argument check first, then the device checks (so that the checks
+    // can be tested without a GPU)
     AdjArgs a;
     Layout L;
-    PW_TRY(check_adjoint(grid, layout, dtype, u, v, w, coeffs, gsu, gsv, gsw, gu, gv, gw, nullptr, &a, &L));
+    PW_TRY(check_adjoint(grid, layout, dtype, u, v, w, coeffs, gsu, gsv, gsw, gu, gv, gw, nullptr, &a, &L, false));
     Layout L2;
-    PW_TRY(check_coeff_grad(grid, layout, dtype, u, v, w, gsu, gsv, gsw, grad, workspace, workspace_bytes, &L2));
+    PW_TRY(check_coeff_grad(grid, layout, dtype, u, v, w, gsu, gsv, gsw, grad, workspace, workspace_bytes, &L2,
+                            false));
     // grad and the workspace also stay apart from the wind gradients
     const int64_t es = elem_size(dtype);
     int64_t need = 0;
@@ -753,6 +761,8 @@ pw_status pw_advect_adjoint_coeff_grad(const pw_grid *grid, const pw_layout *lay
     for (const Range &c : rcg)
         for (const Range &o : rg)
             if (overlap(c, o)) return fail(PW_ERR_INVALID_ARG, "%s overlaps %s", c.name, o.name);
+    PW_TRY(check_adjoint(grid, layout, dtype, u, v, w, coeffs, gsu, gsv, gsw, gu, gv, gw, nullptr, &a, &L));
+    PW_TRY(check_coeff_grad(grid, layout, dtype, u, v, w, gsu, gsv, gsw, grad, workspace, workspace_bytes, &L2));
     return run_coeff_grad(grid, dtype, a, true, grad, workspace, static_cast<hipStream_t>(hip_stream));
 }
 

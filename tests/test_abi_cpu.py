@@ -418,6 +418,31 @@ def test_coeff_grad_validation(lib):
     assert call(bad) == B.PW_ERR_INVALID_ARG
 
 
+def test_fused_backward_validation(lib):
+    """pw_advect_adjoint_coeff_grad: the adjoint's checks and the coefficient
+    gradients' checks, and grad / workspace apart from the wind gradients."""
+    g, c, p = _args()
+    need = ctypes.c_int64()
+    assert lib.pw_advect_coeff_grad_workspace(ctypes.byref(g), B.PW_F32, ctypes.byref(need)) == B.PW_OK
+    q = [A + i * MB for i in range(11)]   # u v w gsu gsv gsw gu gv gw grad workspace
+    call = lambda qq, nbytes=need.value, dt=B.PW_F32: lib.pw_advect_adjoint_coeff_grad(  # noqa: E731
+        ctypes.byref(g), None, dt, *qq[:3], ctypes.byref(c), *qq[3:9], qq[9], qq[10], nbytes, None)
+    assert call(q) in _no_gpu_status()
+    assert call(q, dt=B.PW_F64) in _no_gpu_status() or "coefficient" in B.pw_last_error()
+    assert call(q, dt=B.PW_BF16) == B.PW_ERR_UNSUPPORTED
+    assert call(q, need.value - 8) == B.PW_ERR_INVALID_ARG and "workspace" in B.pw_last_error()
+    bad = list(q); bad[10] = 0                # workspace NULL
+    assert call(bad) == B.PW_ERR_INVALID_ARG
+    bad = list(q); bad[9] = q[6] + 64         # grad inside gu
+    assert call(bad) == B.PW_ERR_INVALID_ARG and "overlaps" in B.pw_last_error()
+    bad = list(q); bad[10] = q[8] + 256       # workspace inside gw
+    assert call(bad) == B.PW_ERR_INVALID_ARG and "overlaps" in B.pw_last_error()
+    bad = list(q); bad[6] = q[0]              # gu on u
+    assert call(bad) == B.PW_ERR_INVALID_ARG
+    bad = list(q); bad[9] = q[9] + 4          # grad misaligned
+    assert call(bad) == B.PW_ERR_INVALID_ARG
+
+
 def test_coeff_grad_static_validation(lib):
     """The allocation-free coefficient-gradient entry point: the same checks
     as with a workspace, and grids whose partials exceed its static scratch

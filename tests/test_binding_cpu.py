@@ -57,6 +57,9 @@ def test_valid_calls_reach_the_library():
         lambda: B.advect_adjoint(u, v, w, c, *interior(), stream=STREAM),
         lambda: B.advect_tangent(u, v, w, c, *winds(), stream=STREAM),
         lambda: B.advect_coeff_grad(u, v, w, *interior(), stream=STREAM),
+        lambda: B.advect_adjoint_coeff_grad(u, v, w, c, *interior(), stream=STREAM),
+        lambda: B.advect_bc(u, v, w, c, [("periodic", "periodic", "copy")] * 2 + [("periodic", "periodic", "zero")],
+                            stream=STREAM),
         lambda: B.halo_fill([u, v, w], ("periodic",) * 3, stream=STREAM),
         lambda: B.Batch([(u, v, w, c, interior())]),
     ]
@@ -163,6 +166,35 @@ def test_tangent_arguments_checked(bad):
         out[2] = torch.zeros((NZ - 1, NY, NX))
     with pytest.raises(ValueError):
         B.advect_tangent(u, v, w, coeffs(), *d, out=out, stream=STREAM)
+
+
+@pytest.mark.parametrize("bad", ["cot_shape", "grad_dtype", "grad_out_len", "grad_out_dtype", "coeff_len"])
+def test_fused_backward_arguments_checked(bad):
+    u, v, w = winds()
+    r = interior()
+    g = [torch.zeros_like(u) for _ in range(3)]
+    c = coeffs()
+    go = torch.zeros(6 * NZ + 2, dtype=torch.float64)
+    if bad == "cot_shape":
+        r[0] = torch.zeros((NZ, NY, NX + 1))
+    elif bad == "grad_dtype":
+        g[2] = g[2].double()
+    elif bad == "grad_out_len":
+        go = torch.zeros(6 * NZ + 1, dtype=torch.float64)
+    elif bad == "grad_out_dtype":
+        go = torch.zeros(6 * NZ + 2, dtype=torch.float32)
+    else:
+        c = coeffs(nz=NZ - 1)
+    with pytest.raises(ValueError):
+        B.advect_adjoint_coeff_grad(u, v, w, c, *r, out=g, grad_out=go, stream=STREAM)
+
+
+def test_bc_rules_checked():
+    u, v, w = winds()
+    with pytest.raises(ValueError):
+        B.advect_bc(u, v, w, coeffs(), ("periodic", "sideways", "copy"), stream=STREAM)
+    with pytest.raises(ValueError):
+        B.advect_bc(u, v, w, coeffs(), [("periodic",) * 3] * 2, stream=STREAM)   # two triples for three fields
 
 
 def test_coeff_grad_cotangents_checked():

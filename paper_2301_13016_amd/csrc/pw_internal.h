@@ -124,6 +124,9 @@ constexpr int64_t kCoeffGradScratchBytes = PW_COEFF_GRAD_STATIC_MAX_BYTES;
 pw_status coeff_grad_scratch(void **ptr);
 pw_status launch_halo(const HaloArgs &a, hipStream_t s);
 pw_status launch_halo_fold(const HaloArgs &a, hipStream_t s);   // es 4 or 8
+// n elements of type dt set to seeded pseudo-random values uniform in
+// [lo, hi): the autotuner's timing inputs (pw_tune_data.hip).
+hipError_t fill_tuning_data(void *p, int64_t n, pw_dtype dt, uint32_t seed, float lo, float hi, hipStream_t s);
 // z-fastest forward (pw_zfast.hip): FwdArgs carry the column stride in
 // in_sy / out_sy and the x-plane stride in in_sz / out_sz; tile px = levels
 // per lane, ry = y-rows per strip, zlen = x-columns per work item.

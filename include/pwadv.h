@@ -299,9 +299,13 @@ pw_status pw_advect_adjoint_coeff_grad(const pw_grid *grid, const pw_layout *lay
  * (flags & PW_TUNE_ZFAST) and, for PW_F32 / PW_F64, of the adjoint
  * (flags & PW_TUNE_ADJOINT) and tangent (flags & PW_TUNE_TANGENT) kernels;
  * flags == 0 means forward, adjoint and tangent.  The candidates run on scratch grids
- * of this extent (allocated and freed here, contents zero), rotating over as
- * many copies as span about 1 GiB so that repeats are not served by the
- * MALL.  The fastest shape per shape class -- kernel, dtype and the
+ * of this extent (allocated and freed here; seeded pseudo-random winds in
+ * [-10, 10), which also serve as cotangents, directions in [-1, 1) and
+ * coefficients in [0.0025, 0.0075), since kernel times depend on the data),
+ * rotating over as many copies as span about 1 GiB so that repeats are not
+ * served by the MALL.  Each candidate is timed over 12 launches; the eight
+ * fastest are re-timed in three interleaved rounds of 40 and ranked by their
+ * median.  The fastest shape per shape class -- kernel, dtype and the
  * power-of-two ceilings of nx, ny, nz -- goes into a process-wide table that
  * the kernels consult when called without a tile.  The z-cut is kept as a
  * number of chunks, so an entry serves every nz of its class.  If the

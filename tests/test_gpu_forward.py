@@ -283,7 +283,8 @@ def test_shared_row_tiles_bitwise(shape, halo, storage):
     """Workgroups whose wavefronts pass their edge rows through LDS give the
     same outputs, bit for bit, as independent strips of the same shape: every
     instantiated shape, 2 and 4 wavefronts per group, with and without
-    non-temporal own rows, one and several z-chunks, ragged y (wavefronts
+    non-temporal own rows, one and several z-chunks (chunks of one, two and
+    three levels, a last chunk shorter than the rest), ragged y (wavefronts
     past the grid) and x (edge strips), halo 1 and 2."""
     nx, ny, nz = shape
     g = wl.make_grid(nx, ny, nz, seed=41 + nx + ny, halo=halo,
@@ -293,7 +294,7 @@ def test_shared_row_tiles_bitwise(shape, halo, storage):
         ref = run(g, storage=st, tile=(px, ry, 3, 1, 1), halo=halo)
         for wpb in (2, 4):
             for share in (1, 2):
-                for zl in (nz, 2):
+                for zl in sorted({nz, 3, 2, 1}):
                     got = run(g, storage=st, tile=(px, ry, zl, wpb, 1, share), halo=halo)
                     for a, b in zip(ref, got):
                         assert np.array_equal(a, b), (px, ry, zl, wpb, share)

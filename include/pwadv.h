@@ -144,7 +144,17 @@ pw_status pw_advect(const pw_grid *grid, const pw_layout *layout, pw_dtype in_dt
  *   with rows 2 or 4.  pw_advect_bc runs a shared tile as the same shape
  *   with share_rows 0.
  * Always zlen >= 1 and waves_per_group in 1..8.  Other values give
- * PW_ERR_INVALID_ARG. */
+ * PW_ERR_INVALID_ARG.
+ * The environment variable PWADV_TILE (an override for experiments) sets the
+ * shape of the x-fastest forward calls that pass no tile (pw_advect,
+ * pw_advect_ex, pw_advect_epilogue, pw_advect_bc) and what pw_launch_shape
+ * reports for the forward: the pw_tile fields in order separated by 'x' or
+ * ',', at least cols_per_lane, rows_per_strip and zlen (waves_per_group 4,
+ * prefetch 1 and share_rows 0 when left out), e.g. PWADV_TILE=4x2x32x4x1x2.
+ * It is read on every call and takes precedence over tuned and built-in
+ * shapes; a value that does not parse, or is not a forward shape for the
+ * call's storage type, makes those calls return PW_ERR_INVALID_ARG before
+ * any device work.  Results do not depend on the shape. */
 typedef struct {
     int32_t cols_per_lane;
     int32_t rows_per_strip;
@@ -515,7 +525,8 @@ const char *pw_version(void);
  * (static per-thread storage; "" if none).  With the environment variable
  * PWADV_LOG set (and not "0"), every launching call also prints one line on
  * stderr: the entry point, grid, storage type, launch shape and whether the
- * shape was given, tuned, the default or a fixed rule. */
+ * shape was given, came from PWADV_TILE, was tuned, the default or a fixed
+ * rule. */
 const char *pw_last_error(void);
 
 /* Measurement helper: a plain vectorised device-to-device copy of `nbytes`

@@ -177,17 +177,6 @@ pw_status check_on_device(const char *name, const void *p, int dev) {
     return PW_OK;
 }
 
-TileCfg to_cfg(const pw_tile &t) {
-    TileCfg c;
-    c.px = t.cols_per_lane;
-    c.ry = t.rows_per_strip;
-    c.zlen = t.zlen;
-    c.wpb = t.waves_per_group;
-    c.depth = t.prefetch == 0 ? 1 : t.prefetch;
-    c.share = t.share_rows;
-    return c;
-}
-
 #define PW_TRY(x)                            \
     do {                                     \
         pw_status st_ = (x);                 \
@@ -302,6 +291,40 @@ pw_status validate_halo(const pw_grid *grid, const pw_layout *layout, pw_dtype d
     return PW_OK;
 }
 
+// The forward's launch shape: the caller's tile, else PWADV_TILE, else the
+// tuned entry of the grid's class, else the default; `how` names the source
+// (for PWADV_LOG).  No device work, so a bad PWADV_TILE fails before any.
+pw_status forward_shape(const pw_grid *grid, const FwdArgs &a, pw_dtype dt, const pw_tile *tile, TileCfg *cfg,
+                        const char **how) {
+    if (tile) {
+        *cfg = to_cfg(*tile);
+        *how = "given";
+        return PW_OK;
+    }
+    pw_tile t;
+    const int e = env_forward_tile(&t);
+    if (e < 0)
+        return fail(PW_ERR_INVALID_ARG,
+                    "PWADV_TILE=\"%s\" is not a launch shape (cols_per_lane x rows_per_strip x zlen "
+                    "[x waves_per_group [x prefetch [x share_rows]]])",
+                    std::getenv("PWADV_TILE"));
+    if (e > 0) {
+        if (!tile_supported(to_cfg(t), dt))
+            return fail(PW_ERR_INVALID_ARG, "PWADV_TILE=\"%s\" is not a forward shape for this storage type",
+                        std::getenv("PWADV_TILE"));
+        *cfg = to_cfg(t);
+        *how = "PWADV_TILE";
+        return PW_OK;
+    }
+    if (lookup_tuned(TuneKind::Forward, grid, dt, cfg)) {
+        *how = "tuned";
+        return PW_OK;
+    }
+    *cfg = default_forward_tile(a, dt);
+    *how = "default";
+    return PW_OK;
+}
+
 // Forward with optional boundary rules (bc, NULL: read the stored halo) and
 // optional fused epilogue (ep, NULL: out = F): validation and launch.
 pw_status advect_general(const pw_grid *grid, const pw_layout *layout, pw_dtype in_dtype, const void *u,
@@ -315,6 +338,9 @@ pw_status advect_general(const pw_grid *grid, const pw_layout *layout, pw_dtype 
                     "unsupported forward tile cols=%d rows=%d zlen=%d waves=%d prefetch=%d share_rows=%d",
                     tile->cols_per_lane, tile->rows_per_strip, tile->zlen, tile->waves_per_group, tile->prefetch,
                     tile->share_rows);
+    TileCfg cfg;
+    const char *how = "given";
+    PW_TRY(forward_shape(grid, a, in_dtype, tile, &cfg, &how));
     if (bc) {
         // bc[f] = rules of field f (u, v, w).  A depth-one read of a halo cell
         // goes to its periodic source or to the nearest interior cell (which
@@ -382,14 +408,6 @@ pw_status advect_general(const pw_grid *grid, const pw_layout *layout, pw_dtype 
     } else {
         PW_TRY(check_forward_on_device(a));
     }
-    TileCfg cfg;
-    const char *how = "given";
-    if (tile)
-        cfg = to_cfg(*tile);
-    else if (lookup_tuned(TuneKind::Forward, grid, in_dtype, &cfg))
-        how = "tuned";
-    else
-        cfg = default_forward_tile(a, in_dtype), how = "default";
     log_launch(bc ? "pw_advect_bc" : "pw_advect_epilogue", grid, in_dtype, &cfg, how);
     return launch_forward(a, in_dtype, cfg, static_cast<hipStream_t>(hip_stream));
 }
@@ -421,15 +439,10 @@ pw_status pw_advect_ex(const pw_grid *grid, const pw_layout *layout, pw_dtype in
                     "unsupported forward tile cols=%d rows=%d zlen=%d waves=%d prefetch=%d share_rows=%d",
                     tile->cols_per_lane, tile->rows_per_strip, tile->zlen, tile->waves_per_group, tile->prefetch,
                     tile->share_rows);
-    PW_TRY(check_forward_on_device(a));
     TileCfg cfg;
     const char *how = "given";
-    if (tile)
-        cfg = to_cfg(*tile);
-    else if (lookup_tuned(TuneKind::Forward, grid, in_dtype, &cfg))
-        how = "tuned";
-    else
-        cfg = default_forward_tile(a, in_dtype), how = "default";
+    PW_TRY(forward_shape(grid, a, in_dtype, tile, &cfg, &how));
+    PW_TRY(check_forward_on_device(a));
     log_launch("pw_advect", grid, in_dtype, &cfg, how);
     return launch_forward(a, in_dtype, cfg, static_cast<hipStream_t>(hip_stream));
 }

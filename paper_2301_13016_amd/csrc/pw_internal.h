@@ -27,6 +27,17 @@ struct TileCfg {
     int share = 0;   // pw_tile.share_rows
 };
 inline pw_tile to_tile(const TileCfg &c) { return pw_tile{c.px, c.ry, c.zlen, c.wpb, c.depth, c.share}; }
+// A public launch shape as the kernels take it (prefetch 0 means 1).
+inline TileCfg to_cfg(const pw_tile &t) {
+    TileCfg c;
+    c.px = t.cols_per_lane;
+    c.ry = t.rows_per_strip;
+    c.zlen = t.zlen;
+    c.wpb = t.waves_per_group;
+    c.depth = t.prefetch == 0 ? 1 : t.prefetch;
+    c.share = t.share_rows;
+    return c;
+}
 
 // Operands of one forward launch, already validated.  Strides are in elements.
 struct FwdArgs {
@@ -156,6 +167,12 @@ void forward_ranges(const FwdArgs &a, uintptr_t (*in)[2], uintptr_t (*out)[2]);
 // Autotune cache (pw_tune.cpp): best launch shape per kernel kind, dtype and
 // shape class, filled by pw_tune and consulted when no tile is given.
 enum class TuneKind { Forward = 0, Adjoint = 1, Tangent = 2, Zfast = 3 };
+// PWADV_TILE: a forward launch shape for calls that give none (an override
+// for experiments), the pw_tile fields in order separated by 'x' or ','; at
+// least cols_per_lane, rows_per_strip and zlen (waves_per_group 4, prefetch 1
+// and share_rows 0 when left out).  Read on every call.  Returns 0 when unset
+// or empty, 1 with the shape, -1 when malformed.
+int env_forward_tile(pw_tile *t);
 bool lookup_tuned(TuneKind kind, const pw_grid *grid, pw_dtype dt, TileCfg *cfg);
 void store_tuned(TuneKind kind, const pw_grid *grid, pw_dtype dt, const TileCfg &cfg);
 

@@ -308,6 +308,49 @@ def test_launch_shape_query(lib):
         == B.PW_ERR_INVALID_ARG
 
 
+def test_pwadv_tile_override(lib, monkeypatch):
+    """PWADV_TILE sets the forward's shape for calls without a tile and what
+    pw_launch_shape reports; a malformed or unsupported value fails those
+    calls before any device work, naming the variable; an explicit tile and
+    the other kernels ignore it."""
+    torch = pytest.importorskip("torch")
+    g, c, p = _args()
+    ep = B.pw_epilogue(1.0, A + 20 * MB, A + 21 * MB, A + 22 * MB)
+    bc = (B.pw_halo_modes * 3)(*[B.pw_halo_modes(1, 1, 2)] * 3)
+    calls = {
+        "pw_advect": lambda: _call(g, None, B.PW_F32, c, p),
+        "pw_advect_epilogue": lambda: lib.pw_advect_epilogue(ctypes.byref(g), None, B.PW_F32, *p[:3], ctypes.byref(c),
+                                                             ctypes.byref(ep), *p[3:], None, None),
+        "pw_advect_bc": lambda: lib.pw_advect_bc(ctypes.byref(g), None, B.PW_F32, *p[:3], ctypes.byref(c), bc,
+                                                 None, *p[3:], None, None),
+    }
+    for bad in ("garbage", "4x2", "4x2x", "4x2x32x4x1x2x9", "4;2;32", "3x1x8", "4x1x0", "8x2x16"):
+        monkeypatch.setenv("PWADV_TILE", bad)
+        for name, call in calls.items():
+            assert call() == B.PW_ERR_INVALID_ARG, (bad, name)
+            assert "PWADV_TILE" in B.pw_last_error(), (bad, name)
+        t = B.pw_tile()
+        assert lib.pw_launch_shape(0, ctypes.byref(B.pw_grid(8, 8, 8, 1)), B.PW_F32, ctypes.byref(t)) \
+            == B.PW_ERR_INVALID_ARG, bad
+        # an explicit tile and the adjoint's shape query do not read it
+        assert _call(g, None, B.PW_F32, c, p, tile=B.pw_tile(1, 2, 8, 4)) in _no_gpu_status()
+        assert "PWADV_TILE" not in B.pw_last_error()
+        assert lib.pw_launch_shape(1, ctypes.byref(B.pw_grid(8, 8, 8, 1)), B.PW_F32, ctypes.byref(t)) == B.PW_OK
+    for val, want in (("4x2x32x4x1x2", (4, 2, 32, 4, 1, 2)), ("4,2,32", (4, 2, 32, 4, 1, 0)),
+                      ("2x4x5x2x2", (2, 4, 5, 2, 2, 0)), ("1x1x1x1x0", (1, 1, 1, 1, 1, 0))):
+        monkeypatch.setenv("PWADV_TILE", val)
+        assert B.launch_shape("forward", 512, 512, 64, torch.float32) == want, val
+        for name, call in calls.items():
+            assert call() in _no_gpu_status(), (val, name)
+            assert "PWADV_TILE" not in B.pw_last_error(), (val, name)
+    monkeypatch.setenv("PWADV_TILE", "8x2x16")      # a 16-bit shape: fine for BF16, not for FP32
+    assert B.launch_shape("forward", 64, 64, 64, torch.bfloat16) == (8, 2, 16, 4, 1, 0)
+    assert _call(g, None, B.PW_BF16, c, p) in _no_gpu_status() and "PWADV_TILE" not in B.pw_last_error()
+    monkeypatch.setenv("PWADV_TILE", "")             # empty: as if unset
+    row = _table_row(0, B.PW_F32, 512, 512, 64)
+    assert B.launch_shape("forward", 512, 512, 64, torch.float32)[:2] == row[:2]
+
+
 def test_tune_cache_file_read_without_device(tmp_path):
     """The cache file is read on first use, with no device: v3 lines carry
     share_rows, v2 lines the prefetch depth (share_rows 0), v1 lines mean

@@ -420,3 +420,32 @@ def test_pwadv_log_prints_one_line_per_launch():
     env.pop("PWADV_LOG")
     q = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=120)
     assert q.returncode == 0 and "pwadv: " not in q.stderr
+    # a shape from PWADV_TILE is named as such; an explicit tile still wins
+    env.update(PWADV_LOG="1", PWADV_TILE="2x1x3x2x2")
+    t = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=120)
+    assert t.returncode == 0, t.stderr[-2000:]
+    lines = [ln for ln in t.stderr.splitlines() if ln.startswith("pwadv: ")]
+    assert any("pw_advect 70x9x5 halo 1 f32 tile (2, 1, 3, 2, 2, 0) PWADV_TILE" in ln for ln in lines), lines
+    assert any("pw_advect 70x9x5 halo 1 f32 tile (2, 2, 5, 4, 1, 0) given" in ln for ln in lines), lines
+
+
+def test_pwadv_tile_override_bitwise(monkeypatch):
+    """Forward calls without a tile take PWADV_TILE's shape: the outputs equal
+    those of the same shape given explicitly, bit for bit, for the plain, the
+    epilogue and the boundary-rule forward; shape changes no result."""
+    g = wl.make_grid(130, 21, 9, seed=57)
+    (u, v, w), c = dev_grid(g)
+    add = [torch.full((9, 21, 130), 0.5, device="cuda") for _ in range(3)]
+    bc = ("periodic", "periodic", "copy")
+    for tile in [(4, 2, 5, 4, 1, 2), (2, 1, 3, 2, 2, 0), (1, 4, 9, 1, 1, 0)]:
+        want = [B.advect(u, v, w, c, tile=tile), B.advect_epilogue(u, v, w, c, add, alpha=0.25, tile=tile),
+                B.advect_bc(u, v, w, c, bc, tile=tile)]
+        monkeypatch.setenv("PWADV_TILE", "x".join(map(str, tile)))
+        got = [B.advect(u, v, w, c), B.advect_epilogue(u, v, w, c, add, alpha=0.25), B.advect_bc(u, v, w, c, bc)]
+        monkeypatch.delenv("PWADV_TILE")
+        torch.cuda.synchronize()
+        for wt, gt in zip(want, got):
+            assert all(torch.equal(a, b) for a, b in zip(wt, gt)), tile
+    monkeypatch.setenv("PWADV_TILE", "5x1x1")
+    with pytest.raises(B.PWError):
+        B.advect(u, v, w, c)

@@ -396,7 +396,18 @@ def main():
                     help="approximate host time spent timing the oracle on all cores (half of it again on 1)")
     ap.add_argument("--prewarm-ms", type=float, default=150.0,
                     help="wall time of untimed headline launches before the counted warm-up")
+    ap.add_argument("--forms", default="all",
+                    help="comma-separated forms to time besides the headline step, the bandwidth probe and the "
+                         "CPU baseline (which always run): c1 (more forms on the headline grid: halo fill, "
+                         "boundaries by addressing, z-fastest layout), precision (1024x1024x256 FP32, "
+                         "BF16, FP16, FP64), differentiation (256x256x128 adjoint, tangent, coefficient "
+                         "gradients, fused backward), batched (64 subdomains); default all")
     args = ap.parse_args()
+    known = ("c1", "precision", "differentiation", "batched")
+    forms_sel = set(known) if args.forms == "all" else {f.strip() for f in args.forms.split(",") if f.strip()}
+    if not forms_sel <= set(known):
+        ap.error("--forms: unknown %s (choose from all, %s)" % (", ".join(sorted(forms_sel - set(known))),
+                                                                 ", ".join(known)))
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: libpwadv runs on one GPU (the stencil's multi-GPU halo exchange is a "
               "design, not an implementation); use --gpus 1", file=sys.stderr)
@@ -497,49 +508,50 @@ def main():
         kernel_ms=round(acc_ms, 4), over_plain=round(acc_ms / k_ms, 3),
         ideal_ratio_from_bytes=round(nbytes_acc / nbytes, 3), hbm_gbs=round(nbytes_acc / (acc_ms * 1e-3) / 1e9, 1))
     log("c1 fused accumulate (out += F): %.4f ms, %.3f x the plain step" % (acc_ms, acc_ms / k_ms))
-    # the step before: halo fill of u, v, w (periodic x, y; free-slip lid:
-    # u, v zero-gradient, w zero), on the same buffers
-    hmodes = [(1, 1, 2), (1, 1, 2), (1, 1, B_HALO_ZERO)]
-    halo_calls = [prebuilt_halo(B, kp[0], hmodes, stream) for kp in keep]
-    _, halo_ms = time_launches(torch, lambda i: halo_calls[i](), nsets, 200, 20, stream)
-    del halo_calls
-    hb = halo_bytes(nx, ny, nz, h, 4, hmodes)
-    forms["halo_fill_512x512x64"] = dict(kernel_ms=round(halo_ms, 4), over_plain=round(halo_ms / k_ms, 3),
-                                         bytes=hb, hbm_gbs=round(hb / (halo_ms * 1e-3) / 1e9, 1))
-    log("c1 halo fill (u, v, w): %.4f ms, %.3f x the plain step" % (halo_ms, halo_ms / k_ms))
-    # boundaries applied by addressing inside the forward, no fill step:
-    # remapped reads only (periodic x, y; zero-gradient z for all three
-    # fields), and the free-slip lid above, whose w = 0 is a value rule
-    addressed = {}
-    for name, rules in (("periodic_copy", [(1, 1, 2)] * 3), ("free_slip_lid", hmodes)):
-        fill_calls = [prebuilt_halo(B, kp[0], rules, stream) for kp in keep]
-        _, fill_ms = time_launches(torch, lambda i: fill_calls[i](), nsets, 200, 20, stream)
-        bc_calls = [prebuilt_bc(B, kp[0], kp[1], coeffs, rules, stream) for kp in keep]
-        _, bc_ms = time_launches(torch, lambda i: bc_calls[i](), nsets, 500, 100, stream)
-        del fill_calls, bc_calls
-        addressed[name] = dict(rules=rules, kernel_ms=round(bc_ms, 4), over_plain=round(bc_ms / k_ms, 3),
-                               fill_ms=round(fill_ms, 4), fill_then_forward_ms=round(fill_ms + k_ms, 4),
-                               saved=round(1 - bc_ms / (fill_ms + k_ms), 3))
-        log("c1 forward with %s boundaries by addressing: %.4f ms (fill + forward %.4f ms)"
-            % (name.replace("_", " "), bc_ms, fill_ms + k_ms))
-    forms["boundaries_by_addressing_512x512x64"] = addressed
-    # the same grid stored z-fastest (column-major, [i, j, k])
-    zsets = [(tuple(x.permute(2, 1, 0).contiguous() for x in kp[0]),
-              tuple(torch.empty((nx, ny, nz), device=dev) for _ in range(3))) for kp in keep]
-    zf_calls = [prebuilt_zfast(B, zi, zo, coeffs, stream) for zi, zo in zsets]
-    _, zf_ms = time_launches(torch, lambda i: zf_calls[i](), nsets, 500, 100, stream)
-    # the x-fastest step again, under the same conditions
-    _, xf_ms = time_launches(torch, lambda i: calls[i](), nsets, 500, 100, stream)
-    zacc_calls = [prebuilt_zfast(B, zi, zo, coeffs, stream, accumulate=True) for zi, zo in zsets]
-    _, zacc_ms = time_launches(torch, lambda i: zacc_calls[i](), nsets, 200, 20, stream)
-    zshape = B.launch_shape("zfast", nx, ny, nz, torch.float32)
-    del zf_calls, zacc_calls, zsets
-    forms["zfast_512x512x64"] = dict(kernel_ms=round(zf_ms, 4), over_xfast=round(zf_ms / xf_ms, 3),
-                                     accumulate_ms=round(zacc_ms, 4),
-                                     gpts=round(pts / (zf_ms * 1e-3) / 1e9, 2),
-                                     hbm_gbs=round(nbytes / (zf_ms * 1e-3) / 1e9, 1), tile=list(zshape))
-    log("c1 z-fastest layout: %.4f ms, %.3f x the x-fastest step timed after it (%.4f ms; tile %s)"
-        % (zf_ms, zf_ms / xf_ms, xf_ms, zshape))
+    if "c1" in forms_sel:
+        # the step before: halo fill of u, v, w (periodic x, y; free-slip lid:
+        # u, v zero-gradient, w zero), on the same buffers
+        hmodes = [(1, 1, 2), (1, 1, 2), (1, 1, B_HALO_ZERO)]
+        halo_calls = [prebuilt_halo(B, kp[0], hmodes, stream) for kp in keep]
+        _, halo_ms = time_launches(torch, lambda i: halo_calls[i](), nsets, 200, 20, stream)
+        del halo_calls
+        hb = halo_bytes(nx, ny, nz, h, 4, hmodes)
+        forms["halo_fill_512x512x64"] = dict(kernel_ms=round(halo_ms, 4), over_plain=round(halo_ms / k_ms, 3),
+                                             bytes=hb, hbm_gbs=round(hb / (halo_ms * 1e-3) / 1e9, 1))
+        log("c1 halo fill (u, v, w): %.4f ms, %.3f x the plain step" % (halo_ms, halo_ms / k_ms))
+        # boundaries applied by addressing inside the forward, no fill step:
+        # remapped reads only (periodic x, y; zero-gradient z for all three
+        # fields), and the free-slip lid above, whose w = 0 is a value rule
+        addressed = {}
+        for name, rules in (("periodic_copy", [(1, 1, 2)] * 3), ("free_slip_lid", hmodes)):
+            fill_calls = [prebuilt_halo(B, kp[0], rules, stream) for kp in keep]
+            _, fill_ms = time_launches(torch, lambda i: fill_calls[i](), nsets, 200, 20, stream)
+            bc_calls = [prebuilt_bc(B, kp[0], kp[1], coeffs, rules, stream) for kp in keep]
+            _, bc_ms = time_launches(torch, lambda i: bc_calls[i](), nsets, 500, 100, stream)
+            del fill_calls, bc_calls
+            addressed[name] = dict(rules=rules, kernel_ms=round(bc_ms, 4), over_plain=round(bc_ms / k_ms, 3),
+                                   fill_ms=round(fill_ms, 4), fill_then_forward_ms=round(fill_ms + k_ms, 4),
+                                   saved=round(1 - bc_ms / (fill_ms + k_ms), 3))
+            log("c1 forward with %s boundaries by addressing: %.4f ms (fill + forward %.4f ms)"
+                % (name.replace("_", " "), bc_ms, fill_ms + k_ms))
+        forms["boundaries_by_addressing_512x512x64"] = addressed
+        # the same grid stored z-fastest (column-major, [i, j, k])
+        zsets = [(tuple(x.permute(2, 1, 0).contiguous() for x in kp[0]),
+                  tuple(torch.empty((nx, ny, nz), device=dev) for _ in range(3))) for kp in keep]
+        zf_calls = [prebuilt_zfast(B, zi, zo, coeffs, stream) for zi, zo in zsets]
+        _, zf_ms = time_launches(torch, lambda i: zf_calls[i](), nsets, 500, 100, stream)
+        # the x-fastest step again, under the same conditions
+        _, xf_ms = time_launches(torch, lambda i: calls[i](), nsets, 500, 100, stream)
+        zacc_calls = [prebuilt_zfast(B, zi, zo, coeffs, stream, accumulate=True) for zi, zo in zsets]
+        _, zacc_ms = time_launches(torch, lambda i: zacc_calls[i](), nsets, 200, 20, stream)
+        zshape = B.launch_shape("zfast", nx, ny, nz, torch.float32)
+        del zf_calls, zacc_calls, zsets
+        forms["zfast_512x512x64"] = dict(kernel_ms=round(zf_ms, 4), over_xfast=round(zf_ms / xf_ms, 3),
+                                         accumulate_ms=round(zacc_ms, 4),
+                                         gpts=round(pts / (zf_ms * 1e-3) / 1e9, 2),
+                                         hbm_gbs=round(nbytes / (zf_ms * 1e-3) / 1e9, 1), tile=list(zshape))
+        log("c1 z-fastest layout: %.4f ms, %.3f x the x-fastest step timed after it (%.4f ms; tile %s)"
+            % (zf_ms, zf_ms / xf_ms, xf_ms, zshape))
     del keep, calls, sets3
     torch.cuda.empty_cache()
 
@@ -556,138 +568,141 @@ def main():
     del f64
 
     # ------------------------------------------------------------ precision form: c2
-    c2 = wl.C2
-    n2 = (c2["nx"], c2["ny"], c2["nz"])
-    log("generating the 1024x1024x256 grid ...")
-    g2 = wl.config_grid(c2)
-    co2 = B.Coeffs.from_host(g2.coeffs, device=dev)
-    co2_64 = B.Coeffs.from_host(g2.coeffs, device=dev, dtype=torch.float64)
-    f32 = [torch.from_numpy(x).to(dev) for x in (g2.u, g2.v, g2.w)]
-    del g2
-    outs2 = tuple(torch.empty((n2[2], n2[1], n2[0]), device=dev) for _ in range(3))
-    pts2 = n2[0] * n2[1] * n2[2]
-    res2 = {}
-    for name, dt in (("fp32", torch.float32), ("bf16", torch.bfloat16), ("fp16", torch.float16)):
-        ins = f32 if dt == torch.float32 else [x.to(dt) for x in f32]
-        call = prebuilt_forward(B, ins, outs2, co2, stream)
-        _, kms2 = time_launches(torch, lambda i: call(), 1, 30, 3, stream)
-        eb = 2 if dt != torch.float32 else 4
-        res2[name] = dict(gpts=round(pts2 / (kms2 * 1e-3) / 1e9, 2), kernel_ms=round(kms2, 4),
-                          hbm_gbs=round(algo_bytes(*n2, 1, eb) / (kms2 * 1e-3) / 1e9, 1))
-        log("c2 %s: kernel %.4f ms, %.1f Gpt/s" % (name, kms2, res2[name]["gpts"]))
-        if dt != torch.float32:
-            del ins
-    # FP64 storage and arithmetic (the FP32 values widened exactly)
-    del outs2
-    outs64 = tuple(torch.empty((n2[2], n2[1], n2[0]), device=dev, dtype=torch.float64) for _ in range(3))
-    ins64 = [x.double() for x in f32]
-    call = prebuilt_forward(B, ins64, outs64, co2_64, stream)
-    _, kms64 = time_launches(torch, lambda i: call(), 1, 30, 3, stream)
-    res2["fp64"] = dict(gpts=round(pts2 / (kms64 * 1e-3) / 1e9, 2), kernel_ms=round(kms64, 4),
-                        hbm_gbs=round(algo_bytes(*n2, 1, 8, 8) / (kms64 * 1e-3) / 1e9, 1))
-    log("c2 fp64: kernel %.4f ms, %.1f Gpt/s" % (kms64, res2["fp64"]["gpts"]))
-    del call, ins64, outs64
-    for name in ("bf16", "fp16", "fp64"):
-        res2[name]["speed_vs_fp32"] = round(res2["fp32"]["kernel_ms"] / res2[name]["kernel_ms"], 3)
-    forms["precision_1024x1024x256"] = res2
-    del f32
-    torch.cuda.empty_cache()
+    if "precision" in forms_sel:
+        c2 = wl.C2
+        n2 = (c2["nx"], c2["ny"], c2["nz"])
+        log("generating the 1024x1024x256 grid ...")
+        g2 = wl.config_grid(c2)
+        co2 = B.Coeffs.from_host(g2.coeffs, device=dev)
+        co2_64 = B.Coeffs.from_host(g2.coeffs, device=dev, dtype=torch.float64)
+        f32 = [torch.from_numpy(x).to(dev) for x in (g2.u, g2.v, g2.w)]
+        del g2
+        outs2 = tuple(torch.empty((n2[2], n2[1], n2[0]), device=dev) for _ in range(3))
+        pts2 = n2[0] * n2[1] * n2[2]
+        res2 = {}
+        for name, dt in (("fp32", torch.float32), ("bf16", torch.bfloat16), ("fp16", torch.float16)):
+            ins = f32 if dt == torch.float32 else [x.to(dt) for x in f32]
+            call = prebuilt_forward(B, ins, outs2, co2, stream)
+            _, kms2 = time_launches(torch, lambda i: call(), 1, 30, 3, stream)
+            eb = 2 if dt != torch.float32 else 4
+            res2[name] = dict(gpts=round(pts2 / (kms2 * 1e-3) / 1e9, 2), kernel_ms=round(kms2, 4),
+                              hbm_gbs=round(algo_bytes(*n2, 1, eb) / (kms2 * 1e-3) / 1e9, 1))
+            log("c2 %s: kernel %.4f ms, %.1f Gpt/s" % (name, kms2, res2[name]["gpts"]))
+            if dt != torch.float32:
+                del ins
+        # FP64 storage and arithmetic (the FP32 values widened exactly)
+        del outs2
+        outs64 = tuple(torch.empty((n2[2], n2[1], n2[0]), device=dev, dtype=torch.float64) for _ in range(3))
+        ins64 = [x.double() for x in f32]
+        call = prebuilt_forward(B, ins64, outs64, co2_64, stream)
+        _, kms64 = time_launches(torch, lambda i: call(), 1, 30, 3, stream)
+        res2["fp64"] = dict(gpts=round(pts2 / (kms64 * 1e-3) / 1e9, 2), kernel_ms=round(kms64, 4),
+                            hbm_gbs=round(algo_bytes(*n2, 1, 8, 8) / (kms64 * 1e-3) / 1e9, 1))
+        log("c2 fp64: kernel %.4f ms, %.1f Gpt/s" % (kms64, res2["fp64"]["gpts"]))
+        del call, ins64, outs64
+        for name in ("bf16", "fp16", "fp64"):
+            res2[name]["speed_vs_fp32"] = round(res2["fp32"]["kernel_ms"] / res2[name]["kernel_ms"], 3)
+        forms["precision_1024x1024x256"] = res2
+        del f32
+        torch.cuda.empty_cache()
 
     # ------------------------------------------------------------ differentiation form: c4
-    c4 = wl.C4
-    n4 = (c4["nx"], c4["ny"], c4["nz"])
-    g4 = wl.config_grid(c4)
-    co4 = B.Coeffs.from_host(g4.coeffs, device=dev)
-    # 4 buffer sets (about 4 x 540 MB) so that the MALL cannot serve repeats
-    host4 = [torch.from_numpy(x) for x in (g4.u, g4.v, g4.w)]
-    hcot4 = [torch.from_numpy(x) for x in wl.cotangents(*n4, c4["cot_seed"])]
-    hdir4 = [torch.from_numpy(x.astype(np.float32)) for x in wl.direction(*n4, seed=46)]
-    fcalls, acalls, tcalls, ccalls, bcalls, keep4 = [], [], [], [], [], []
-    for _ in range(4):
-        ins4 = [x.to(dev) for x in host4]
-        cot4 = [x.to(dev) for x in hcot4]
-        dir4 = [x.to(dev) for x in hdir4]
-        o4 = tuple(torch.empty((n4[2], n4[1], n4[0]), device=dev) for _ in range(3))
-        t4 = tuple(torch.empty((n4[2], n4[1], n4[0]), device=dev) for _ in range(3))
-        gr4 = tuple(torch.empty_like(x) for x in ins4)
-        keep4.append((ins4, cot4, dir4, o4, t4, gr4))
-        fcalls.append(prebuilt_forward(B, ins4, o4, co4, stream))
-        acalls.append(prebuilt_adjoint(B, ins4, cot4, gr4, co4, stream))
-        tcalls.append(prebuilt_tangent(B, ins4, dir4, t4, co4, stream))
-        ccalls.append(prebuilt_coeff_grad(B, ins4, cot4, stream, torch))
-        bcalls.append(prebuilt_fused_backward(B, ins4, cot4, gr4, co4, stream, torch))
-    _, fms = time_launches(torch, lambda i: fcalls[i](), 4, 100, 5, stream)
-    _, ams = time_launches(torch, lambda i: acalls[i](), 4, 100, 5, stream)
-    _, tms = time_launches(torch, lambda i: tcalls[i](), 4, 100, 5, stream)
-    _, cms = time_launches(torch, lambda i: ccalls[i](), 4, 100, 5, stream)
-    _, bms = time_launches(torch, lambda i: bcalls[i](), 4, 100, 5, stream)
-    pts4 = n4[0] * n4[1] * n4[2]
-    forms["adjoint_256x256x128"] = dict(
-        forward_ms=round(fms, 4), adjoint_ms=round(ams, 4), adjoint_over_forward=round(ams / fms, 3),
-        ideal_ratio_from_bytes=round(adjoint_bytes(*n4, 1) / algo_bytes(*n4, 1, 4), 3),
-        adjoint_gpts=round(pts4 / (ams * 1e-3) / 1e9, 2),
-        adjoint_hbm_gbs=round(adjoint_bytes(*n4, 1) / (ams * 1e-3) / 1e9, 1))
-    tbytes = tangent_bytes(*n4, 1)
-    forms["tangent_256x256x128"] = dict(
-        tangent_ms=round(tms, 4), tangent_over_forward=round(tms / fms, 3),
-        ideal_ratio_from_bytes=round(tbytes / algo_bytes(*n4, 1, 4), 3),
-        tangent_gpts=round(pts4 / (tms * 1e-3) / 1e9, 2), tangent_hbm_gbs=round(tbytes / (tms * 1e-3) / 1e9, 1))
-    cbytes4 = adjoint_bytes(*n4, 1) - 3 * (n4[0] + 2) * (n4[1] + 2) * (n4[2] + 2) * 4   # its reads only
-    forms["coeff_grad_256x256x128"] = dict(
-        coeff_grad_ms=round(cms, 4), coeff_grad_over_forward=round(cms / fms, 3),
-        ideal_ratio_from_bytes=round(cbytes4 / algo_bytes(*n4, 1, 4), 3),
-        coeff_grad_hbm_gbs=round(cbytes4 / (cms * 1e-3) / 1e9, 1))
-    forms["fused_backward_256x256x128"] = dict(
-        backward_ms=round(bms, 4), over_adjoint=round(bms / ams, 3), separate_ms=round(ams + cms, 4),
-        backward_over_forward=round(bms / fms, 3))
-    log("c4: forward %.4f ms, adjoint %.4f ms (ratio %.3f), tangent %.4f ms (ratio %.3f), "
-        "coefficient gradients %.4f ms (ratio %.3f)" % (fms, ams, ams / fms, tms, tms / fms, cms, cms / fms))
-    log("c4: wind and coefficient gradients in one pass %.4f ms (%.3f x the adjoint; separately %.4f ms)"
-        % (bms, bms / ams, ams + cms))
-    del keep4, fcalls, acalls, tcalls, ccalls, bcalls
-    torch.cuda.empty_cache()
+    if "differentiation" in forms_sel:
+        c4 = wl.C4
+        n4 = (c4["nx"], c4["ny"], c4["nz"])
+        g4 = wl.config_grid(c4)
+        co4 = B.Coeffs.from_host(g4.coeffs, device=dev)
+        # 4 buffer sets (about 4 x 540 MB) so that the MALL cannot serve repeats
+        host4 = [torch.from_numpy(x) for x in (g4.u, g4.v, g4.w)]
+        hcot4 = [torch.from_numpy(x) for x in wl.cotangents(*n4, c4["cot_seed"])]
+        hdir4 = [torch.from_numpy(x.astype(np.float32)) for x in wl.direction(*n4, seed=46)]
+        fcalls, acalls, tcalls, ccalls, bcalls, keep4 = [], [], [], [], [], []
+        for _ in range(4):
+            ins4 = [x.to(dev) for x in host4]
+            cot4 = [x.to(dev) for x in hcot4]
+            dir4 = [x.to(dev) for x in hdir4]
+            o4 = tuple(torch.empty((n4[2], n4[1], n4[0]), device=dev) for _ in range(3))
+            t4 = tuple(torch.empty((n4[2], n4[1], n4[0]), device=dev) for _ in range(3))
+            gr4 = tuple(torch.empty_like(x) for x in ins4)
+            keep4.append((ins4, cot4, dir4, o4, t4, gr4))
+            fcalls.append(prebuilt_forward(B, ins4, o4, co4, stream))
+            acalls.append(prebuilt_adjoint(B, ins4, cot4, gr4, co4, stream))
+            tcalls.append(prebuilt_tangent(B, ins4, dir4, t4, co4, stream))
+            ccalls.append(prebuilt_coeff_grad(B, ins4, cot4, stream, torch))
+            bcalls.append(prebuilt_fused_backward(B, ins4, cot4, gr4, co4, stream, torch))
+        _, fms = time_launches(torch, lambda i: fcalls[i](), 4, 100, 5, stream)
+        _, ams = time_launches(torch, lambda i: acalls[i](), 4, 100, 5, stream)
+        _, tms = time_launches(torch, lambda i: tcalls[i](), 4, 100, 5, stream)
+        _, cms = time_launches(torch, lambda i: ccalls[i](), 4, 100, 5, stream)
+        _, bms = time_launches(torch, lambda i: bcalls[i](), 4, 100, 5, stream)
+        pts4 = n4[0] * n4[1] * n4[2]
+        forms["adjoint_256x256x128"] = dict(
+            forward_ms=round(fms, 4), adjoint_ms=round(ams, 4), adjoint_over_forward=round(ams / fms, 3),
+            ideal_ratio_from_bytes=round(adjoint_bytes(*n4, 1) / algo_bytes(*n4, 1, 4), 3),
+            adjoint_gpts=round(pts4 / (ams * 1e-3) / 1e9, 2),
+            adjoint_hbm_gbs=round(adjoint_bytes(*n4, 1) / (ams * 1e-3) / 1e9, 1))
+        tbytes = tangent_bytes(*n4, 1)
+        forms["tangent_256x256x128"] = dict(
+            tangent_ms=round(tms, 4), tangent_over_forward=round(tms / fms, 3),
+            ideal_ratio_from_bytes=round(tbytes / algo_bytes(*n4, 1, 4), 3),
+            tangent_gpts=round(pts4 / (tms * 1e-3) / 1e9, 2), tangent_hbm_gbs=round(tbytes / (tms * 1e-3) / 1e9, 1))
+        cbytes4 = adjoint_bytes(*n4, 1) - 3 * (n4[0] + 2) * (n4[1] + 2) * (n4[2] + 2) * 4   # its reads only
+        forms["coeff_grad_256x256x128"] = dict(
+            coeff_grad_ms=round(cms, 4), coeff_grad_over_forward=round(cms / fms, 3),
+            ideal_ratio_from_bytes=round(cbytes4 / algo_bytes(*n4, 1, 4), 3),
+            coeff_grad_hbm_gbs=round(cbytes4 / (cms * 1e-3) / 1e9, 1))
+        forms["fused_backward_256x256x128"] = dict(
+            backward_ms=round(bms, 4), over_adjoint=round(bms / ams, 3), separate_ms=round(ams + cms, 4),
+            backward_over_forward=round(bms / fms, 3))
+        log("c4: forward %.4f ms, adjoint %.4f ms (ratio %.3f), tangent %.4f ms (ratio %.3f), "
+            "coefficient gradients %.4f ms (ratio %.3f)" % (fms, ams, ams / fms, tms, tms / fms, cms, cms / fms))
+        log("c4: wind and coefficient gradients in one pass %.4f ms (%.3f x the adjoint; separately %.4f ms)"
+            % (bms, bms / ams, ams + cms))
+        del keep4, fcalls, acalls, tcalls, ccalls, bcalls
+        torch.cuda.empty_cache()
 
     # ------------------------------------------------------------ batched form: c3
-    log("generating the 64 subdomains ...")
-    grids3 = wl.batch_grids()
-    subs, plain = [], []
-    for gg in grids3:
-        ins = [torch.from_numpy(x).to(dev) for x in (gg.u, gg.v, gg.w)]
-        cc = B.Coeffs.from_host(gg.coeffs, device=dev)
-        outs = tuple(torch.empty((gg.nz, gg.ny, gg.nx), device=dev) for _ in range(3))
-        subs.append((*ins, cc, outs))
-        plain.append(prebuilt_forward(B, ins, outs, cc, stream))
-    pts3 = sum(gg.points for gg in grids3)
-    bytes3 = sum(algo_bytes(gg.nx, gg.ny, gg.nz, 1, 4) for gg in grids3)
-    del grids3
-    batch = B.Batch(subs)
-    btile = batch.tune()
-    gstream = torch.cuda.Stream()
-    batch.capture(gstream)
-    torch.cuda.synchronize()
+    if "batched" in forms_sel:
+        log("generating the 64 subdomains ...")
+        grids3 = wl.batch_grids()
+        subs, plain = [], []
+        for gg in grids3:
+            ins = [torch.from_numpy(x).to(dev) for x in (gg.u, gg.v, gg.w)]
+            cc = B.Coeffs.from_host(gg.coeffs, device=dev)
+            outs = tuple(torch.empty((gg.nz, gg.ny, gg.nx), device=dev) for _ in range(3))
+            subs.append((*ins, cc, outs))
+            plain.append(prebuilt_forward(B, ins, outs, cc, stream))
+        pts3 = sum(gg.points for gg in grids3)
+        bytes3 = sum(algo_bytes(gg.nx, gg.ny, gg.nz, 1, 4) for gg in grids3)
+        del grids3
+        batch = B.Batch(subs)
+        btile = batch.tune()
+        gstream = torch.cuda.Stream()
+        batch.capture(gstream)
+        torch.cuda.synchronize()
 
-    def all_plain(i):
-        for c in plain:
-            c()
-    pms_step, _ = time_launches(torch, all_plain, 1, 20, 2, stream)
-    gev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(20)]
-    for _ in range(2):
-        batch.replay(gstream)
-    torch.cuda.synchronize()
-    for a_, b_ in gev:
-        a_.record(gstream)
-        batch.replay(gstream)
-        b_.record(gstream)
-    torch.cuda.synchronize()
-    bms = float(np.mean([a_.elapsed_time(b_) for a_, b_ in gev]))
-    tile3, items3, groups3 = batch.info()
-    forms["batched_64_subdomains"] = dict(
-        points=pts3, graph_replay_ms=round(bms, 4), plain_64_launches_ms=round(pms_step, 4),
-        speedup_vs_plain=round(pms_step / bms, 3), gpts=round(pts3 / (bms * 1e-3) / 1e9, 2),
-        hbm_gbs=round(bytes3 / (bms * 1e-3) / 1e9, 1), tile=tile3, work_items=items3, workgroups=groups3)
-    log("c3: graph replay %.4f ms vs 64 plain launches %.4f ms (tile %s)" % (bms, pms_step, btile))
-    batch.close()
-    del subs, plain
+        def all_plain(i):
+            for c in plain:
+                c()
+        pms_step, _ = time_launches(torch, all_plain, 1, 20, 2, stream)
+        gev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(20)]
+        for _ in range(2):
+            batch.replay(gstream)
+        torch.cuda.synchronize()
+        for a_, b_ in gev:
+            a_.record(gstream)
+            batch.replay(gstream)
+            b_.record(gstream)
+        torch.cuda.synchronize()
+        bms = float(np.mean([a_.elapsed_time(b_) for a_, b_ in gev]))
+        tile3, items3, groups3 = batch.info()
+        forms["batched_64_subdomains"] = dict(
+            points=pts3, graph_replay_ms=round(bms, 4), plain_64_launches_ms=round(pms_step, 4),
+            speedup_vs_plain=round(pms_step / bms, 3), gpts=round(pts3 / (bms * 1e-3) / 1e9, 2),
+            hbm_gbs=round(bytes3 / (bms * 1e-3) / 1e9, 1), tile=tile3, work_items=items3, workgroups=groups3)
+        log("c3: graph replay %.4f ms vs 64 plain launches %.4f ms (tile %s)" % (bms, pms_step, btile))
+        batch.close()
+        del subs, plain
 
     line = {
         "metric": "PW advection Gpoints/s + % HBM roofline; FP32 vs BF16-store vs adjoint",

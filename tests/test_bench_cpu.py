@@ -95,3 +95,9 @@ def test_fingerprint_follows_the_sources(monkeypatch, tmp_path):
     inc.write_text(text)
     (fake / "pw_stencil.h").write_text((fake / "pw_stencil.h").read_text() + "\n// x\n")
     assert bench.kernel_fingerprint() != base
+
+
+def test_unknown_form_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--forms", "precision,bogus"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2 and "bogus" in r.stderr and r.stdout == ""

@@ -7,6 +7,11 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+# The tests check the library's own shape choice (built-in table, defaults);
+# an override left in the caller's environment would replace it.  Tests that
+# exercise PWADV_TILE set it themselves.
+os.environ.pop("PWADV_TILE", None)
+
 
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
